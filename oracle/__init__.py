@@ -1,0 +1,248 @@
+"""CPU oracle for subspace culling -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow reference implementation of what the HIP path computes (BVH
+build, ray-mask LUT, object masks, traversal with culling, codebook,
+requirement LUTs and the mask search of Alg. 3, plus brute-force checks).
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The product path never does, and the
+oracle shares no code with the HIP library.
+
+The arithmetic lives in ``sc_oracle.c`` (plain C, ``gcc -O2
+-ffp-contract=off``); this module only builds it, loads it and marshals
+numpy arrays. ``mlp.py`` holds the float64 reference of the placement MLP.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+MODES = {"none": 0, "raw": 1, "lut": 2}
+FLAG_CULL = 1
+FLAG_SHADOW = 2
+LEAF_BIT = 0x80000000
+EMPTY_REF = 0xFFFFFFFF
+NO_HIT = 0xFFFFFFFF
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = C.CDLL(_LIB)
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with status {rc}")
+
+
+def words_for(R: int) -> int:
+    return (R * R * R + 63) // 64
+
+
+@dataclass
+class BVH:
+    n_inner: int
+    root: int
+    depth: int
+    cbox: np.ndarray   # float32 [n_inner, 12]: child0 lo, child0 hi, child1 lo, child1 hi
+    cref: np.ndarray   # uint32 [n_inner, 2]
+    range: np.ndarray  # uint32 [n_inner, 2]: first, count of the subtree
+    perm: np.ndarray   # uint32 [n]: original triangle id at each leaf-order position
+
+    def slot_boxes(self) -> np.ndarray:
+        """[2*n_inner, 6] lo/hi of every child slot."""
+        return self.cbox.reshape(-1, 6)
+
+
+def bvh_build(tris: np.ndarray, leaf_max: int = 4, bins: int = 32, depth_cap: int = 64) -> BVH:
+    tris = np.ascontiguousarray(tris, np.float32)
+    n = tris.shape[0]
+    m = max(n, 1)
+    cbox = np.zeros((m, 12), np.float32)
+    cref = np.zeros((m, 2), np.uint32)
+    rng = np.zeros((m, 2), np.uint32)
+    perm = np.zeros(m, np.uint32)
+    info = np.zeros(3, np.uint32)
+    L = lib()
+    L.orc_bvh_build.restype = C.c_int
+    rc = L.orc_bvh_build(_p(tris), C.c_uint32(n), C.c_uint32(leaf_max), C.c_uint32(bins),
+                         C.c_uint32(depth_cap), _p(cbox), _p(cref), _p(rng), _p(perm), _p(info))
+    _check(rc, "bvh_build")
+    ni = int(info[0])
+    return BVH(ni, int(info[1]), int(info[2]), cbox[:ni].copy(), cref[:ni].copy(),
+               rng[:ni].copy(), perm[:n].copy())
+
+
+def raymask_lut(R: int) -> np.ndarray:
+    W = words_for(R)
+    out = np.zeros((R ** 6, W), np.uint64)
+    _check(lib().orc_raymask_lut(C.c_uint32(R), _p(out)), "raymask_lut")
+    return out
+
+
+def default_bounds(tris: np.ndarray):
+    """(origin_bound, delta) defaults: M = max |vertex coordinate|,
+    origin_bound = 4 * max(1, M), delta = (max(1, M) + origin_bound) * 2^-16,
+    all in float32."""
+    M = np.float32(np.abs(tris).max()) if tris.size else np.float32(0)
+    m1 = np.float32(max(np.float32(1.0), M))
+    ob = np.float32(np.float32(4.0) * m1)
+    delta = np.float32(np.float32(m1 + ob) * np.float32(2.0 ** -16))
+    return float(ob), float(delta)
+
+
+def object_masks(tris: np.ndarray, bvh: BVH, R: int, delta: float, nthreads: int = 0) -> np.ndarray:
+    tris = np.ascontiguousarray(tris, np.float32)
+    W = words_for(R)
+    out = np.zeros((max(2 * bvh.n_inner, 1), W), np.uint64)
+    L = lib()
+    rc = L.orc_object_masks(_p(tris), _p(bvh.perm), C.c_uint32(bvh.n_inner), _p(bvh.cbox),
+                            _p(bvh.cref), _p(bvh.range), C.c_uint32(R), C.c_float(delta),
+                            _p(out), C.c_int(nthreads))
+    _check(rc, "object_masks")
+    return out[:2 * bvh.n_inner]
+
+
+@dataclass
+class Hits:
+    prim: np.ndarray        # uint32, NO_HIT on a miss
+    t: np.ndarray           # float32, +inf on a miss
+    box_tests: np.ndarray
+    tri_tests: np.ndarray
+    mask_tests: np.ndarray
+    mask_culls: np.ndarray
+    slot_fp: np.ndarray | None = None
+
+
+def trace(tris, bvh: BVH, rays, *, mode="none", R=6, masks=None, codebook=None, cidx=None,
+          lut=None, origin_bound=None, cull=True, shadow=False, nthreads=0) -> Hits:
+    tris = np.ascontiguousarray(tris, np.float32)
+    rays = np.ascontiguousarray(rays, np.float32)
+    n = rays.shape[0]
+    if origin_bound is None:
+        origin_bound = default_bounds(tris)[0]
+    mcode = MODES[mode]
+    if mcode and lut is None:
+        lut = raymask_lut(R)
+    hits = np.zeros((max(n, 1), 4), np.uint32)
+    extra = np.zeros((max(n, 1), 2), np.uint32)
+    fp = np.zeros(max(2 * bvh.n_inner, 1), np.uint32) if shadow else None
+    flags = (FLAG_CULL if cull else 0) | (FLAG_SHADOW if shadow else 0)
+    masks = None if masks is None else np.ascontiguousarray(masks, np.uint64)
+    codebook = None if codebook is None else np.ascontiguousarray(codebook, np.uint64)
+    cidx = None if cidx is None else np.ascontiguousarray(cidx, np.uint16)
+    rc = lib().orc_trace(_p(tris), _p(bvh.perm), _p(bvh.cbox), _p(bvh.cref), C.c_uint32(bvh.root),
+                         C.c_uint32(bvh.depth), C.c_uint32(R), C.c_uint32(mcode), _p(masks),
+                         _p(codebook), _p(cidx), _p(lut), C.c_float(origin_bound),
+                         C.c_uint32(flags), _p(rays), C.c_uint32(n), _p(hits), _p(extra), _p(fp),
+                         C.c_int(nthreads))
+    _check(rc, "trace")
+    hits, extra = hits[:n], extra[:n]
+    return Hits(hits[:, 0].copy(), hits[:, 1].view(np.float32).copy(), hits[:, 2].copy(),
+                hits[:, 3].copy(), extra[:, 0].copy(), extra[:, 1].copy(),
+                None if fp is None else fp[:2 * bvh.n_inner])
+
+
+def brute_closest(tris, rays, nthreads=0):
+    tris = np.ascontiguousarray(tris, np.float32)
+    rays = np.ascontiguousarray(rays, np.float32)
+    n = rays.shape[0]
+    out = np.zeros((max(n, 1), 2), np.uint32)
+    _check(lib().orc_brute_closest(_p(tris), C.c_uint32(tris.shape[0]), _p(rays), C.c_uint32(n),
+                                   _p(out), C.c_int(nthreads)), "brute_closest")
+    return out[:n, 0].copy(), out[:n, 1].view(np.float32).copy()
+
+
+def codebook(masks, slot_boxes, R, K):
+    masks = np.ascontiguousarray(masks, np.uint64)
+    boxes = np.ascontiguousarray(slot_boxes, np.float32)
+    cb = np.zeros((K, words_for(R)), np.uint64)
+    _check(lib().orc_codebook(_p(masks), _p(boxes), C.c_uint32(masks.shape[0]), C.c_uint32(R),
+                              C.c_uint32(K), _p(cb)), "codebook")
+    return cb
+
+
+def req_luts(cb, R):
+    K = cb.shape[0]
+    nch = (R ** 3 + 7) // 8
+    req = np.zeros((nch, 256, K // 64), np.uint64)
+    _check(lib().orc_req_luts(_p(np.ascontiguousarray(cb, np.uint64)), C.c_uint32(K),
+                              C.c_uint32(R), _p(req)), "req_luts")
+    return req
+
+
+def alg3(masks, req, K, R):
+    masks = np.ascontiguousarray(masks, np.uint64)
+    out = np.zeros(max(masks.shape[0], 1), np.uint16)
+    _check(lib().orc_alg3(_p(masks), C.c_uint32(masks.shape[0]), _p(req), C.c_uint32(K),
+                          C.c_uint32(R), _p(out)), "alg3")
+    return out[:masks.shape[0]]
+
+
+def naive_search(masks, cb, R):
+    masks = np.ascontiguousarray(masks, np.uint64)
+    out = np.zeros(max(masks.shape[0], 1), np.uint16)
+    _check(lib().orc_naive_search(_p(masks), C.c_uint32(masks.shape[0]),
+                                  _p(np.ascontiguousarray(cb, np.uint64)), C.c_uint32(cb.shape[0]),
+                                  C.c_uint32(R), _p(out)), "naive_search")
+    return out[:masks.shape[0]]
+
+
+def compress(masks, slot_boxes, R, K):
+    """Codebook + indices the way the compressed node layout stores them."""
+    cb = codebook(masks, slot_boxes, R, K)
+    req = req_luts(cb, R)
+    return cb, alg3(masks, req, K, R)
+
+
+def voxelize_tri(tri, lo, hi, R, delta):
+    """Mask bits of one triangle in the box (lo, hi) -> uint64 [W]."""
+    out = np.zeros(words_for(R), np.uint64)
+    _check(lib().orc_voxelize_tri(_p(np.ascontiguousarray(tri, np.float32)),
+                                  _p(np.ascontiguousarray(lo, np.float32)),
+                                  _p(np.ascontiguousarray(hi, np.float32)), C.c_uint32(R),
+                                  C.c_float(delta), _p(out)), "voxelize_tri")
+    return out
+
+
+def mask_bits(m, R) -> np.ndarray:
+    """uint64 [..., W] -> bool [..., R^3] (bit x + R*y + R^2*z)."""
+    m = np.asarray(m, np.uint64)
+    bits = ((m[..., :, None] >> np.arange(64, dtype=np.uint64)) & np.uint64(1)).astype(bool)
+    return bits.reshape(*m.shape[:-1], -1)[..., :R ** 3]
+
+
+def ray_mask(lo, hi, o, d, t0, t1, R, lut):
+    """Alg. 1 for one box and segment -> uint64 [W]."""
+    out = np.zeros(words_for(R), np.uint64)
+    f = lambda a: np.ascontiguousarray(a, np.float32)
+    _check(lib().orc_ray_mask(_p(f(lo)), _p(f(hi)), _p(f(o)), _p(f(d)), C.c_float(t0),
+                              C.c_float(t1), C.c_uint32(R), _p(lut), _p(out)), "ray_mask")
+    return out
