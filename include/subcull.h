@@ -1,0 +1,194 @@
+/*
+ * subcull.h - C ABI of the MI355X subspace-culling ray tracer.
+ *
+ * Method: Yoshimura & Harada, "Subspace Culling for Ray-Box Intersection"
+ * (PACMCGIT 6(1), 2023). Every BVH child box carries an R x R x R occupancy
+ * bit mask (the "object mask", Sect. 3.1.1); a ray that passes the slab test
+ * of the box is converted into a "ray mask" of the same grid by a lookup
+ * keyed by the voxels of its entry and exit points (Alg. 1), and the child is
+ * culled when the two masks share no bit (Sect. 3.1.2, Alg. 4). Masks may be
+ * stored raw or as indices into a conservative codebook (Sect. 3.2.2-3.2.3,
+ * Alg. 3).
+ *
+ * Conventions for every function:
+ *  - The return value is an sc_status; no C++ exception crosses the ABI.
+ *  - Argument checks happen before any HIP call, so a bad argument returns
+ *    SC_ERR_INVALID_ARG on any machine; sc_last_error() then holds a
+ *    thread-local message.
+ *  - "device" pointers are HIP device memory (for instance a torch tensor's
+ *    data_ptr); "host" pointers are ordinary memory. Callers own every buffer
+ *    they pass in; a scene owns the memory it allocates.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Traces are asynchronous on that stream and never synchronise the host;
+ *    scene builds synchronise (the BVH and the codebook are built on the
+ *    host).
+ *  - An asynchronous HIP failure is reported as SC_ERR_HIP by the call that
+ *    observes it.
+ */
+#ifndef SUBCULL_H
+#define SUBCULL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SC_OK = 0,
+    SC_ERR_INVALID_ARG = 1,  /* null pointer, size or parameter out of range */
+    SC_ERR_NO_DEVICE = 2,    /* no HIP device with that ordinal */
+    SC_ERR_OOM = 3,          /* an allocation (device or host) failed */
+    SC_ERR_DEPTH = 4,        /* the BVH would exceed depth_cap */
+    SC_ERR_HIP = 5,          /* a HIP runtime call failed */
+    SC_ERR_UNSUPPORTED = 6   /* valid request this build does not implement */
+} sc_status;
+
+/* How object masks are stored (Sect. 3.2.2, 3.2.4). */
+typedef enum {
+    SC_MASK_NONE = 0,   /* plain BVH, no culling (the baseline of Tables 1-2)  */
+    SC_MASK_RAW = 1,    /* R^3 bits per child, stored in the node             */
+    SC_MASK_LUT = 2,    /* 16-bit index into a K-entry conservative codebook  */
+    SC_MASK_SPARSE = 3  /* raw masks on a chosen subset of child slots only    */
+} sc_mask_mode;
+
+/* sc_trace flags */
+enum {
+    SC_TRACE_CULL = 1u,    /* apply the mask test (else masks are ignored)        */
+    SC_TRACE_SHADOW = 2u,  /* evaluate masks without culling; count would-be culls
+                              per child slot into d_slot_fp                      */
+    SC_TRACE_SORT = 4u     /* reserved                                             */
+};
+
+typedef struct sc_ctx sc_ctx;
+typedef struct sc_scene sc_scene;
+
+/* Optional device allocator. alloc returns device memory of `bytes` bytes
+ * usable on `stream`, or NULL; free releases it. With no allocator the
+ * library uses hipMalloc/hipFree. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* stream, void* user);
+    void (*free)(void* ptr, size_t bytes, void* stream, void* user);
+    void* user;
+} sc_allocator;
+
+typedef struct {
+    uint32_t R;             /* mask resolution: 4 (64 bits) or 6 (216 bits)      */
+    uint32_t leaf_max;      /* triangles per leaf, 1..4 (default 4)               */
+    uint32_t sah_bins;      /* SAH bins per axis, 2..256 (default 32)             */
+    uint32_t depth_cap;     /* max inner nodes on a root-to-leaf path, 1..64      */
+    uint32_t mode;          /* sc_mask_mode                                       */
+    uint32_t codebook_size; /* K for SC_MASK_LUT: multiple of 64, 64..4096        */
+    float delta;            /* voxel dilation; <= 0 selects the default           */
+    float origin_bound;     /* masks are skipped for rays with max|o| above this;
+                               <= 0 selects the default                          */
+    const uint8_t* mask_placement; /* SC_MASK_SPARSE: host [2*n_inner] 0/1 per child
+                               slot (slot = 2*node + child); else NULL            */
+    uint32_t placement_len; /* length of mask_placement                            */
+} sc_build_params;
+
+typedef struct {
+    uint32_t n_tris, n_inner, depth, root_ref;
+    uint32_t R, mode, codebook_size, words;  /* words = 64-bit words per mask  */
+    uint32_t node_bytes;                     /* stride of one inner node        */
+    uint32_t n_masked;                       /* slots that carry a mask         */
+    float delta, origin_bound;
+    uint64_t device_bytes;                   /* scene-owned device memory       */
+    double ms_bvh, ms_masks, ms_codebook, ms_compress;  /* build phases (host clock) */
+} sc_scene_info;
+
+/* One result per ray. prim = original triangle index or 0xFFFFFFFF on a
+ * miss; t = hit distance or +inf; box_tests = ray-box slab tests executed;
+ * tri_tests = ray-triangle tests executed. */
+typedef struct {
+    uint32_t prim;
+    float t;
+    uint32_t box_tests;
+    uint32_t tri_tests;
+} sc_hit;
+
+/* Host buffers for sc_scene_export, each sized from sc_scene_info; any
+ * pointer may be NULL to skip that array. */
+typedef struct {
+    float* cbox;        /* [n_inner][12]: child0 lo xyz, hi xyz, child1 lo, hi   */
+    uint32_t* cref;     /* [n_inner][2]: child refs (bit31 leaf: bits0-28 first
+                           triangle, bits29-30 count-1; else inner node index) */
+    uint32_t* range;    /* [n_inner][2]: first triangle, count of the subtree  */
+    uint32_t* perm;     /* [n_tris]: original index of each leaf-order triangle */
+    uint64_t* masks;    /* [2*n_inner][words]: exact object masks (RAW, LUT)    */
+    uint64_t* codebook; /* [K][words] (LUT)                                      */
+    uint16_t* cidx;     /* [2*n_inner] codebook index per child slot (LUT)       */
+} sc_scene_host;
+
+/* Fill `p` with the defaults: R 6, leaf_max 4, 32 bins, depth cap 64, RAW,
+ * K 4096, default delta and origin bound. */
+void sc_build_params_default(sc_build_params* p);
+
+/* Create a context on HIP device `device`. `alloc` may be NULL. The context
+ * caches the ray-mask LUTs and must outlive its scenes. */
+sc_status sc_create(int device, const sc_allocator* alloc, sc_ctx** out);
+sc_status sc_destroy(sc_ctx* ctx); /* NULL-safe */
+
+/*
+ * Build a scene from `n` triangles (device float32 [n][3][3], vertex-major).
+ *  1. copies the triangles to the host and builds a binary BVH by binned SAH
+ *     (the builder named in Sect. 4; split cost of Eq. 1 with a size-based
+ *     leaf rule), DFS pre-order, triangles reordered into leaf order;
+ *  2. builds the ray-mask LUT of resolution R (Sect. 3.1.1, Alg. 1) on the
+ *     device if the context lacks it;
+ *  3. (RAW, LUT, SPARSE) builds exact object masks for every child slot on
+ *     the device: voxels of the child box that a descendant triangle
+ *     overlaps, dilated by delta (Sect. 3.1.1, 3.2.1 with L = infinity);
+ *  4. (LUT) selects the codebook by the importance SA(N) O_m(N) / R^3 of Eq. 2
+ *     on the host, builds the requirement LUTs and compresses every mask with
+ *     Alg. 3 on the device (Sect. 3.2.2-3.2.3);
+ *  5. packs the device node array.
+ * Errors: SC_ERR_INVALID_ARG (null pointers, n >= 2^29, R not 4 or 6, bad
+ * K, non-finite vertex), SC_ERR_DEPTH, SC_ERR_OOM, SC_ERR_HIP. n = 0 gives an
+ * empty scene whose traces all miss. Synchronises `stream`.
+ */
+sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_build_params* params,
+                         void* stream, sc_scene** out);
+sc_status sc_scene_destroy(sc_scene* scene); /* NULL-safe */
+sc_status sc_scene_get_info(const sc_scene* scene, sc_scene_info* out);
+
+/* Copy the scene's BVH, masks and codebook into caller host buffers
+ * (synchronous). Used to check the build against an independent reference. */
+sc_status sc_scene_export(const sc_scene* scene, sc_scene_host* out);
+
+/*
+ * Trace `n` rays (device float32 [n][8]: ox oy oz tmin dx dy dz tmax) with
+ * Alg. 4 (d_rays and d_hits 16-byte aligned, d_extra 8-byte aligned):
+ * stack traversal, nearer child first, mask test after every slab
+ * hit when SC_TRACE_CULL is set and the scene has masks, leaf triangles by
+ * the Moller-Trumbore test; closest hit in [tmin, tmax], equal t resolved to
+ * the lower triangle index.
+ *  d_hits   device sc_hit[n] (written)
+ *  d_extra  device uint32 [n][2] = mask tests, mask culls per ray, or NULL
+ *  d_slot_fp device uint32 [2*n_inner], or NULL; with SC_TRACE_SHADOW the
+ *           per-slot count of slab hits whose mask test fails is added
+ * A ray with a non-finite origin or direction, a zero direction, a NaN tmax
+ * or tmin > tmax misses with zero counts. Asynchronous on `stream`.
+ */
+sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags,
+                   sc_hit* d_hits, uint32_t* d_extra, uint32_t* d_slot_fp, void* stream);
+
+/* The ray-mask LUT of resolution R as built on the device (Sect. 3.1.1):
+ * d_out receives R^6 entries of words(R) uint64 (words = 1 for R=4, 4 for
+ * R=6); entry key ((((bx*R+by)*R+bz)*R+ex)*R+ey)*R+ez, voxel bit x+R*y+R^2*z. */
+sc_status sc_raymask_lut(sc_ctx* ctx, uint32_t R, uint64_t* d_out, void* stream);
+
+/* Alg. 3 on the device for arbitrary masks and codebook (checks and tools):
+ * d_masks [n][words], d_codebook [K][words] sorted by set-bit count, output
+ * d_idx [n] uint16 = index of the tightest superset. K multiple of 64, <= 4096. */
+sc_status sc_compress_masks(sc_ctx* ctx, uint32_t R, const uint64_t* d_codebook, uint32_t K,
+                            const uint64_t* d_masks, uint32_t n, uint16_t* d_idx, void* stream);
+
+const char* sc_status_string(sc_status s);
+const char* sc_last_error(void);  /* thread-local detail of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SUBCULL_H */

@@ -1,0 +1,270 @@
+"""Python binding of libsubcull (ctypes; argument marshalling only).
+
+Every computation runs in the HIP library; torch supplies device memory and
+streams. The names follow the C ABI in ``include/subcull.h``. Importing this
+module on a machine without the built library raises immediately -- there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsubcull.so")
+
+SC_OK = 0
+SC_MASK_NONE, SC_MASK_RAW, SC_MASK_LUT, SC_MASK_SPARSE = 0, 1, 2, 3
+SC_TRACE_CULL, SC_TRACE_SHADOW, SC_TRACE_SORT = 1, 2, 4
+MODES = {"none": SC_MASK_NONE, "raw": SC_MASK_RAW, "lut": SC_MASK_LUT, "sparse": SC_MASK_SPARSE}
+NO_HIT = 0xFFFFFFFF
+
+
+class SubcullError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (status {status})")
+        self.status = status
+
+
+class sc_allocator(C.Structure):
+    _fields_ = [("alloc", C.c_void_p), ("free", C.c_void_p), ("user", C.c_void_p)]
+
+
+class sc_build_params(C.Structure):
+    _fields_ = [("R", C.c_uint32), ("leaf_max", C.c_uint32), ("sah_bins", C.c_uint32),
+                ("depth_cap", C.c_uint32), ("mode", C.c_uint32), ("codebook_size", C.c_uint32),
+                ("delta", C.c_float), ("origin_bound", C.c_float),
+                ("mask_placement", C.c_void_p), ("placement_len", C.c_uint32)]
+
+
+class sc_scene_info(C.Structure):
+    _fields_ = [("n_tris", C.c_uint32), ("n_inner", C.c_uint32), ("depth", C.c_uint32),
+                ("root_ref", C.c_uint32), ("R", C.c_uint32), ("mode", C.c_uint32),
+                ("codebook_size", C.c_uint32), ("words", C.c_uint32), ("node_bytes", C.c_uint32),
+                ("n_masked", C.c_uint32), ("delta", C.c_float), ("origin_bound", C.c_float),
+                ("device_bytes", C.c_uint64), ("ms_bvh", C.c_double), ("ms_masks", C.c_double),
+                ("ms_codebook", C.c_double), ("ms_compress", C.c_double)]
+
+
+class sc_scene_host(C.Structure):
+    _fields_ = [("cbox", C.c_void_p), ("cref", C.c_void_p), ("range", C.c_void_p),
+                ("perm", C.c_void_p), ("masks", C.c_void_p), ("codebook", C.c_void_p),
+                ("cidx", C.c_void_p)]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+# Every symbol the header declares, with its ctypes signature.
+_SIGS = {
+    "sc_build_params_default": (None, [C.POINTER(sc_build_params)]),
+    "sc_create": (C.c_int, [C.c_int, C.POINTER(sc_allocator), C.POINTER(C.c_void_p)]),
+    "sc_destroy": (C.c_int, [C.c_void_p]),
+    "sc_scene_build": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(sc_build_params),
+                                 C.c_void_p, C.POINTER(C.c_void_p)]),
+    "sc_scene_destroy": (C.c_int, [C.c_void_p]),
+    "sc_scene_get_info": (C.c_int, [C.c_void_p, C.POINTER(sc_scene_info)]),
+    "sc_scene_export": (C.c_int, [C.c_void_p, C.POINTER(sc_scene_host)]),
+    "sc_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p,
+                           C.c_void_p, C.c_void_p]),
+    "sc_raymask_lut": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "sc_compress_masks": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
+                                    C.c_uint32, C.c_void_p, C.c_void_p]),
+    "sc_status_string": (C.c_char_p, [C.c_int]),
+    "sc_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load libsubcull.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2305_08343_amd.build` (ROCm hipcc, gfx950)")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != SC_OK:
+        lib = load()
+        raise SubcullError(status, where, lib.sc_last_error().decode() or
+                           lib.sc_status_string(status).decode())
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """An sc_ctx on one device; scene memory comes from torch's allocator."""
+
+    def __init__(self, device: int = 0, torch_memory: bool = True):
+        import torch
+        lib = load()
+        self.device = device
+        self._keep = []
+        alloc_p = None
+        if torch_memory:
+            def _alloc(nbytes, stream, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream or 0)
+                except Exception:
+                    return None
+
+            def _free(ptr, nbytes, stream, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            fa, ff = _ALLOC_FN(_alloc), _FREE_FN(_free)
+            self._keep += [fa, ff]
+            self._alloc = sc_allocator(C.cast(fa, C.c_void_p), C.cast(ff, C.c_void_p), None)
+            alloc_p = C.byref(self._alloc)
+        h = C.c_void_p()
+        torch.cuda.set_device(device)
+        _check(lib.sc_create(device, alloc_p, C.byref(h)), "sc_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().sc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def raymask_lut(self, R: int, stream=None):
+        """Device ray-mask LUT as uint64 numpy array [R^6, W] (copies back)."""
+        import torch
+        W = (R ** 3 + 63) // 64
+        out = torch.empty((R ** 6, W), dtype=torch.int64, device=f"cuda:{self.device}")
+        _check(load().sc_raymask_lut(self.handle, R, _ptr(out), _stream_ptr(stream)), "sc_raymask_lut")
+        torch.cuda.synchronize(self.device)
+        return out.cpu().numpy().view(np.uint64)
+
+    def compress_masks(self, R: int, codebook: np.ndarray, masks: np.ndarray, stream=None):
+        """Alg. 3 on the device for given masks and codebook -> uint16 indices."""
+        import torch
+        dev = f"cuda:{self.device}"
+        cb = torch.from_numpy(np.ascontiguousarray(codebook, np.uint64).view(np.int64)).to(dev)
+        m = torch.from_numpy(np.ascontiguousarray(masks, np.uint64).view(np.int64)).to(dev)
+        n = masks.shape[0]
+        idx = torch.empty(max(n, 1), dtype=torch.int16, device=dev)
+        _check(load().sc_compress_masks(self.handle, R, _ptr(cb), codebook.shape[0], _ptr(m), n,
+                                        _ptr(idx), _stream_ptr(stream)), "sc_compress_masks")
+        return idx[:n].cpu().numpy().view(np.uint16)
+
+
+@dataclass
+class TraceResult:
+    hits: "object"            # torch.int32 [n, 4]: prim, t bits, box tests, tri tests
+    extra: "object" = None    # torch.int32 [n, 2]: mask tests, mask culls
+
+    def numpy(self):
+        h = self.hits.cpu().numpy()
+        out = {"prim": h[:, 0].view(np.uint32).copy(), "t": h[:, 1].view(np.float32).copy(),
+               "box_tests": h[:, 2].view(np.uint32).copy(), "tri_tests": h[:, 3].view(np.uint32).copy()}
+        if self.extra is not None:
+            e = self.extra.cpu().numpy()
+            out["mask_tests"] = e[:, 0].view(np.uint32).copy()
+            out["mask_culls"] = e[:, 1].view(np.uint32).copy()
+        return out
+
+
+class Scene:
+    """A built scene (BVH + masks + codebook) on the context's device."""
+
+    def __init__(self, ctx: Context, tris, *, R: int = 6, mode: str = "raw", K: int = 4096,
+                 leaf_max: int = 4, bins: int = 32, depth_cap: int = 64, delta: float = 0.0,
+                 origin_bound: float = 0.0, placement=None, stream=None):
+        import torch
+        lib = load()
+        self.ctx = ctx
+        if not isinstance(tris, torch.Tensor):
+            tris = torch.from_numpy(np.ascontiguousarray(tris, np.float32))
+        tris = tris.to(device=f"cuda:{ctx.device}", dtype=torch.float32).contiguous()
+        n = tris.shape[0]
+        p = sc_build_params()
+        lib.sc_build_params_default(C.byref(p))
+        p.R, p.leaf_max, p.sah_bins, p.depth_cap = R, leaf_max, bins, depth_cap
+        p.mode, p.codebook_size = MODES[mode], K
+        p.delta, p.origin_bound = delta, origin_bound
+        self._placement = None
+        if placement is not None:
+            self._placement = np.ascontiguousarray(placement, np.uint8)
+            p.mask_placement = self._placement.ctypes.data_as(C.c_void_p)
+            p.placement_len = self._placement.size
+        h = C.c_void_p()
+        _check(lib.sc_scene_build(ctx.handle, _ptr(tris) if n else None, n, C.byref(p),
+                                  _stream_ptr(stream), C.byref(h)), "sc_scene_build")
+        self.handle = h
+        info = sc_scene_info()
+        _check(lib.sc_scene_get_info(h, C.byref(info)), "sc_scene_get_info")
+        self.info = {f: getattr(info, f) for f, _ in sc_scene_info._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().sc_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def export(self) -> dict:
+        """Host copies of the BVH, exact masks, codebook and indices."""
+        I = self.info
+        ni, n, W, K = I["n_inner"], I["n_tris"], I["words"], I["codebook_size"]
+        out = {
+            "cbox": np.zeros((max(ni, 1), 12), np.float32), "cref": np.zeros((max(ni, 1), 2), np.uint32),
+            "range": np.zeros((max(ni, 1), 2), np.uint32), "perm": np.zeros(max(n, 1), np.uint32),
+            "masks": np.zeros((max(2 * ni, 1), W), np.uint64),
+            "codebook": np.zeros((max(K, 1), W), np.uint64), "cidx": np.zeros(max(2 * ni, 1), np.uint16),
+        }
+        hs = sc_scene_host(*(out[k].ctypes.data_as(C.c_void_p) for k in
+                             ("cbox", "cref", "range", "perm", "masks", "codebook", "cidx")))
+        _check(load().sc_scene_export(self.handle, C.byref(hs)), "sc_scene_export")
+        out["cbox"], out["cref"], out["range"] = out["cbox"][:ni], out["cref"][:ni], out["range"][:ni]
+        out["perm"], out["masks"], out["cidx"] = out["perm"][:n], out["masks"][:2 * ni], out["cidx"][:2 * ni]
+        out["codebook"] = out["codebook"][:K]
+        return out
+
+    def trace(self, rays, *, cull: bool = True, shadow: bool = False, extra: bool = True,
+              slot_fp=None, hits=None, extra_out=None, stream=None) -> TraceResult:
+        """Trace device rays [n, 8] float32; results stay on the device."""
+        import torch
+        dev = f"cuda:{self.ctx.device}"
+        if not isinstance(rays, torch.Tensor):
+            rays = torch.from_numpy(np.ascontiguousarray(rays, np.float32))
+        rays = rays.to(device=dev, dtype=torch.float32).contiguous()
+        n = rays.shape[0]
+        if hits is None:
+            hits = torch.empty((max(n, 1), 4), dtype=torch.int32, device=dev)
+        if extra and extra_out is None:
+            extra_out = torch.empty((max(n, 1), 2), dtype=torch.int32, device=dev)
+        flags = (SC_TRACE_CULL if cull else 0) | (SC_TRACE_SHADOW if shadow else 0)
+        _check(load().sc_trace(self.handle, _ptr(rays), n, flags, _ptr(hits),
+                               _ptr(extra_out) if extra else None, _ptr(slot_fp),
+                               _stream_ptr(stream)), "sc_trace")
+        return TraceResult(hits[:n], extra_out[:n] if extra else None)

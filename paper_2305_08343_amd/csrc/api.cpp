@@ -1,0 +1,476 @@
+// C ABI of libsubcull (include/subcull.h): contexts, scene builds, traces.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace sc;
+
+struct sc_ctx {
+    int device = 0;
+    sc_allocator alloc{};
+    bool has_alloc = false;
+    uint64_t* lut[7] = {nullptr};  // ray-mask LUT per resolution, built on first use
+    std::mutex lut_mu;
+};
+
+struct sc_scene {
+    sc_ctx* ctx = nullptr;
+    sc_scene_info info{};
+    HostBVH bvh;                          // host copy for export
+    unsigned char* nodes = nullptr;
+    float* tris = nullptr;
+    uint64_t* masks = nullptr;            // exact masks [2*n_inner][W]
+    uint64_t* codebook = nullptr;         // LUT mode
+    uint16_t* cidx = nullptr;             // LUT mode
+    uint64_t* side_masks = nullptr;       // SPARSE mode
+    std::vector<std::pair<void*, size_t>> owned;
+};
+
+namespace {
+
+thread_local std::string g_error;
+
+sc_status fail(sc_status s, const std::string& msg) {
+    g_error = msg;
+    return s;
+}
+
+sc_status hip_fail(hipError_t e, const char* what) {
+    return fail(SC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void* dev_alloc(sc_ctx* ctx, size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 256;
+    if (ctx->has_alloc) return ctx->alloc.alloc(bytes, (void*)s, ctx->alloc.user);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void dev_free(sc_ctx* ctx, void* p, size_t bytes, hipStream_t s) {
+    if (!p) return;
+    if (ctx->has_alloc) ctx->alloc.free(p, bytes, (void*)s, ctx->alloc.user);
+    else (void)hipFree(p);
+}
+
+// Device allocation owned by a scene.
+template <typename T>
+T* scene_alloc(sc_scene* sc, size_t bytes, hipStream_t s) {
+    void* p = dev_alloc(sc->ctx, bytes, s);
+    if (p) {
+        sc->owned.emplace_back(p, bytes);
+        sc->info.device_bytes += bytes;
+    }
+    return static_cast<T*>(p);
+}
+
+void scene_free_all(sc_scene* sc, hipStream_t s) {
+    for (auto& pb : sc->owned) dev_free(sc->ctx, pb.first, pb.second, s);
+    sc->owned.clear();
+}
+
+sc_status use_device(int dev) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(SC_ERR_NO_DEVICE, "no HIP device");
+    if (cur != dev) {
+        const hipError_t e = hipSetDevice(dev);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    }
+    return SC_OK;
+}
+
+sc_status ensure_lut(sc_ctx* ctx, uint32_t R, hipStream_t s) {
+    std::lock_guard<std::mutex> g(ctx->lut_mu);
+    if (ctx->lut[R]) return SC_OK;
+    const size_t bytes = (size_t)R * R * R * R * R * R * words_for(R) * 8;
+    auto* p = static_cast<uint64_t*>(dev_alloc(ctx, bytes, s));
+    if (!p) return fail(SC_ERR_OOM, "ray-mask LUT allocation failed");
+    const hipError_t e = launch_raymask_lut(R, p, s);
+    if (e != hipSuccess) {
+        dev_free(ctx, p, bytes, s);
+        return hip_fail(e, "ray-mask LUT kernel");
+    }
+    ctx->lut[R] = p;
+    return SC_OK;
+}
+
+bool check_params(const sc_build_params& p, std::string& why) {
+    if (p.R != 4 && p.R != 6) { why = "R must be 4 or 6"; return false; }
+    if (p.leaf_max < 1 || p.leaf_max > 4) { why = "leaf_max must be 1..4"; return false; }
+    if (p.sah_bins < 2 || p.sah_bins > 256) { why = "sah_bins must be 2..256"; return false; }
+    if (p.depth_cap < 1 || p.depth_cap > kMaxDepth) { why = "depth_cap must be 1..64"; return false; }
+    if (p.mode > SC_MASK_SPARSE) { why = "unknown mask mode"; return false; }
+    if (p.mode == SC_MASK_LUT && (p.codebook_size < 64 || p.codebook_size > 4096 || p.codebook_size % 64)) {
+        why = "codebook_size must be a multiple of 64 in [64, 4096]";
+        return false;
+    }
+    if (p.mode == SC_MASK_SPARSE && !p.mask_placement) { why = "SPARSE needs mask_placement"; return false; }
+    if (!std::isfinite(p.delta) || !std::isfinite(p.origin_bound)) { why = "non-finite delta/origin_bound"; return false; }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sc_build_params_default(sc_build_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->R = 6;
+    p->leaf_max = 4;
+    p->sah_bins = 32;
+    p->depth_cap = kMaxDepth;
+    p->mode = SC_MASK_RAW;
+    p->codebook_size = 4096;
+    p->delta = 0.0f;
+    p->origin_bound = 0.0f;
+}
+
+const char* sc_status_string(sc_status s) {
+    switch (s) {
+        case SC_OK: return "ok";
+        case SC_ERR_INVALID_ARG: return "invalid argument";
+        case SC_ERR_NO_DEVICE: return "no device";
+        case SC_ERR_OOM: return "out of memory";
+        case SC_ERR_DEPTH: return "BVH depth cap exceeded";
+        case SC_ERR_HIP: return "HIP error";
+        case SC_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* sc_last_error(void) { return g_error.c_str(); }
+
+sc_status sc_create(int device, const sc_allocator* alloc, sc_ctx** out) {
+    if (!out) return fail(SC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(SC_ERR_INVALID_ARG, "allocator needs alloc and free");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(SC_ERR_NO_DEVICE, "no HIP device");
+    if (device < 0 || device >= count) return fail(SC_ERR_NO_DEVICE, "device ordinal out of range");
+    sc_status st = use_device(device);
+    if (st != SC_OK) return st;
+    auto* ctx = new (std::nothrow) sc_ctx();
+    if (!ctx) return fail(SC_ERR_OOM, "context allocation failed");
+    ctx->device = device;
+    if (alloc) {
+        ctx->alloc = *alloc;
+        ctx->has_alloc = true;
+    }
+    *out = ctx;
+    return SC_OK;
+}
+
+sc_status sc_destroy(sc_ctx* ctx) {
+    if (!ctx) return SC_OK;
+    (void)use_device(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (uint32_t R = 0; R < 7; ++R)
+        if (ctx->lut[R]) dev_free(ctx, ctx->lut[R], (size_t)R * R * R * R * R * R * words_for(R) * 8, nullptr);
+    delete ctx;
+    return SC_OK;
+}
+
+sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_build_params* params,
+                         void* stream, sc_scene** out) {
+    if (!ctx || !params || !out) return fail(SC_ERR_INVALID_ARG, "ctx, params and out must be non-NULL");
+    *out = nullptr;
+    if (n > 0 && !d_tris) return fail(SC_ERR_INVALID_ARG, "d_tris is NULL");
+    if (n >= (1u << 29)) return fail(SC_ERR_INVALID_ARG, "at most 2^29-1 triangles");
+    std::string why;
+    if (!check_params(*params, why)) return fail(SC_ERR_INVALID_ARG, why);
+    sc_status st = use_device(ctx->device);
+    if (st != SC_OK) return st;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const sc_build_params& P = *params;
+    const uint32_t R = P.R, W = words_for(R);
+
+    std::vector<float> host;
+    try {
+        host.resize(9 * (size_t)n);
+    } catch (const std::bad_alloc&) {
+        return fail(SC_ERR_OOM, "host triangle copy");
+    }
+    if (n) {
+        hipError_t e = hipMemcpyAsync(host.data(), d_tris, host.size() * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "triangle download");
+    }
+    float M = 0.0f;
+    for (float x : host) {
+        if (!std::isfinite(x)) return fail(SC_ERR_INVALID_ARG, "non-finite triangle vertex");
+        const float ax = std::fabs(x);
+        M = (ax > M) ? ax : M;
+    }
+    const float m1 = (M > 1.0f) ? M : 1.0f;
+    const float ob = (P.origin_bound > 0.0f) ? P.origin_bound : 4.0f * m1;
+    const float delta = (P.delta > 0.0f) ? P.delta : (m1 + ob) * 0x1p-16f;
+
+    auto* sc = new (std::nothrow) sc_scene();
+    if (!sc) return fail(SC_ERR_OOM, "scene allocation failed");
+    sc->ctx = ctx;
+    auto bail = [&](sc_status code, const std::string& msg) {
+        (void)hipStreamSynchronize(s);
+        scene_free_all(sc, s);
+        delete sc;
+        return fail(code, msg);
+    };
+
+    auto t0 = std::chrono::steady_clock::now();
+    st = build_bvh(host.data(), n, P.leaf_max, P.sah_bins, P.depth_cap, sc->bvh);
+    if (st != SC_OK) {
+        delete sc;
+        return fail(st, st == SC_ERR_DEPTH ? "BVH deeper than depth_cap" : "BVH build failed");
+    }
+    const HostBVH& B = sc->bvh;
+    sc->info.ms_bvh = ms_since(t0);
+    sc_scene_info& I = sc->info;
+    I.n_tris = n;
+    I.n_inner = B.n_inner;
+    I.depth = B.depth;
+    I.root_ref = B.root;
+    I.R = R;
+    I.mode = P.mode;
+    I.words = W;
+    I.codebook_size = (P.mode == SC_MASK_LUT) ? P.codebook_size : 0;
+    I.node_bytes = (P.mode == SC_MASK_RAW) ? kRawNodeBytes : kNodeBytes;
+    I.delta = delta;
+    I.origin_bound = ob;
+    const uint32_t S = 2 * B.n_inner;
+    if (P.mode == SC_MASK_SPARSE && P.placement_len != S)
+        return bail(SC_ERR_INVALID_ARG, "mask_placement length must be 2*n_inner = " + std::to_string(S));
+
+    // triangle records in leaf order: v0, e1 = v1 - v0, e2 = v2 - v0, id
+    std::vector<float> rec(12 * (size_t)(n ? n : 1), 0.0f);
+    for (uint32_t k = 0; k < n; ++k) {
+        const uint32_t id = B.perm[k];
+        const float* v = &host[9 * (size_t)id];
+        float* r = &rec[12 * (size_t)k];
+        r[0] = v[0]; r[1] = v[1]; r[2] = v[2];
+        r[3] = v[3] - v[0]; r[4] = v[4] - v[1]; r[5] = v[5] - v[2];
+        r[6] = v[6] - v[0]; r[7] = v[7] - v[1]; r[8] = v[8] - v[2];
+        std::memcpy(&r[9], &id, 4);
+    }
+    // nodes
+    const uint32_t stride = I.node_bytes;
+    std::vector<unsigned char> nodes((size_t)stride * (B.n_inner ? B.n_inner : 1), 0);
+    std::vector<uint32_t> side_of_slot;
+    uint32_t n_masked = (P.mode == SC_MASK_NONE) ? 0 : S;
+    if (P.mode == SC_MASK_SPARSE) {
+        side_of_slot.assign(S, kNoMask);
+        n_masked = 0;
+        for (uint32_t q = 0; q < S; ++q)
+            if (P.mask_placement[q]) side_of_slot[q] = n_masked++;
+    }
+    I.n_masked = n_masked;
+    for (uint32_t i = 0; i < B.n_inner; ++i) {
+        unsigned char* np = &nodes[(size_t)i * stride];
+        std::memcpy(np, &B.cbox[12 * (size_t)i], 48);
+        std::memcpy(np + 48, &B.cref[2 * (size_t)i], 8);
+        uint32_t aux[2] = {0, 0};
+        if (P.mode == SC_MASK_SPARSE) {
+            aux[0] = side_of_slot[2 * i];
+            aux[1] = side_of_slot[2 * i + 1];
+        }
+        std::memcpy(np + 56, aux, 8);
+    }
+
+    sc->nodes = scene_alloc<unsigned char>(sc, nodes.size(), s);
+    sc->tris = scene_alloc<float>(sc, rec.size() * 4, s);
+    if (!sc->nodes || !sc->tris) return bail(SC_ERR_OOM, "scene allocation failed");
+    hipError_t e = hipMemcpyAsync(sc->nodes, nodes.data(), nodes.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(sc->tris, rec.data(), rec.size() * 4, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("scene upload: ") + hipGetErrorString(e));
+
+    if (P.mode != SC_MASK_NONE) {
+        st = ensure_lut(ctx, R, s);
+        if (st != SC_OK) return bail(st, g_error);
+    }
+    if (P.mode != SC_MASK_NONE && B.n_inner > 0) {
+        t0 = std::chrono::steady_clock::now();
+        const size_t mask_bytes = (size_t)S * W * 8;
+        sc->masks = scene_alloc<uint64_t>(sc, mask_bytes, s);
+        auto* d_perm = static_cast<uint32_t*>(dev_alloc(ctx, (size_t)n * 4, s));
+        auto* d_range = static_cast<uint32_t*>(dev_alloc(ctx, B.range.size() * 4, s));
+        if (!sc->masks || !d_perm || !d_range) {
+            dev_free(ctx, d_perm, (size_t)n * 4, s);
+            dev_free(ctx, d_range, B.range.size() * 4, s);
+            return bail(SC_ERR_OOM, "mask build allocation failed");
+        }
+        e = hipMemsetAsync(sc->masks, 0, mask_bytes, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_perm, B.perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_range, B.range.data(), B.range.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = launch_object_masks(R, d_tris, d_perm, n, sc->nodes, stride, d_range, B.root, delta,
+                                    sc->masks, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        dev_free(ctx, d_perm, (size_t)n * 4, s);
+        dev_free(ctx, d_range, B.range.size() * 4, s);
+        if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("object masks: ") + hipGetErrorString(e));
+        I.ms_masks = ms_since(t0);
+
+        if (P.mode == SC_MASK_RAW) {
+            e = launch_pack_raw(R, sc->masks, B.n_inner, sc->nodes, s);
+            if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("pack: ") + hipGetErrorString(e));
+        } else {
+            std::vector<uint64_t> hmasks((size_t)S * W);
+            e = hipMemcpyAsync(hmasks.data(), sc->masks, mask_bytes, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("mask download: ") + hipGetErrorString(e));
+            if (P.mode == SC_MASK_LUT) {
+                const uint32_t K = P.codebook_size;
+                t0 = std::chrono::steady_clock::now();
+                std::vector<uint64_t> cb;
+                select_codebook(hmasks.data(), B.cbox.data(), S, R, K, cb);
+                I.ms_codebook = ms_since(t0);
+                t0 = std::chrono::steady_clock::now();
+                const uint32_t nch = (R * R * R + 7) / 8;
+                const size_t req_bytes = (size_t)nch * 256 * (K / 64) * 8;
+                sc->codebook = scene_alloc<uint64_t>(sc, cb.size() * 8, s);
+                sc->cidx = scene_alloc<uint16_t>(sc, (size_t)S * 2, s);
+                auto* d_req = static_cast<uint64_t*>(dev_alloc(ctx, req_bytes, s));
+                if (!sc->codebook || !sc->cidx || !d_req) {
+                    dev_free(ctx, d_req, req_bytes, s);
+                    return bail(SC_ERR_OOM, "codebook allocation failed");
+                }
+                e = hipMemcpyAsync(sc->codebook, cb.data(), cb.size() * 8, hipMemcpyHostToDevice, s);
+                if (e == hipSuccess) e = launch_req_luts(R, sc->codebook, K, d_req, s);
+                if (e == hipSuccess) e = launch_compress(R, sc->masks, S, d_req, K, sc->cidx, s);
+                if (e == hipSuccess) e = launch_pack_lut(sc->cidx, B.n_inner, sc->nodes, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                dev_free(ctx, d_req, req_bytes, s);
+                if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("compression: ") + hipGetErrorString(e));
+                I.ms_compress = ms_since(t0);
+            } else {  // SPARSE: gather the placed masks
+                std::vector<uint64_t> side((size_t)(n_masked ? n_masked : 1) * W, 0);
+                for (uint32_t q = 0; q < S; ++q)
+                    if (side_of_slot[q] != kNoMask)
+                        std::memcpy(&side[(size_t)side_of_slot[q] * W], &hmasks[(size_t)q * W], W * 8);
+                sc->side_masks = scene_alloc<uint64_t>(sc, side.size() * 8, s);
+                if (!sc->side_masks) return bail(SC_ERR_OOM, "sparse mask allocation failed");
+                e = hipMemcpyAsync(sc->side_masks, side.data(), side.size() * 8, hipMemcpyHostToDevice, s);
+                if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("sparse upload: ") + hipGetErrorString(e));
+            }
+        }
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("scene build: ") + hipGetErrorString(e));
+    *out = sc;
+    return SC_OK;
+}
+
+sc_status sc_scene_destroy(sc_scene* scene) {
+    if (!scene) return SC_OK;
+    (void)use_device(scene->ctx->device);
+    (void)hipDeviceSynchronize();
+    scene_free_all(scene, nullptr);
+    delete scene;
+    return SC_OK;
+}
+
+sc_status sc_scene_get_info(const sc_scene* scene, sc_scene_info* out) {
+    if (!scene || !out) return fail(SC_ERR_INVALID_ARG, "scene and out must be non-NULL");
+    *out = scene->info;
+    return SC_OK;
+}
+
+sc_status sc_scene_export(const sc_scene* scene, sc_scene_host* out) {
+    if (!scene || !out) return fail(SC_ERR_INVALID_ARG, "scene and out must be non-NULL");
+    const HostBVH& B = scene->bvh;
+    const sc_scene_info& I = scene->info;
+    if (out->cbox && !B.cbox.empty()) std::memcpy(out->cbox, B.cbox.data(), B.cbox.size() * 4);
+    if (out->cref && !B.cref.empty()) std::memcpy(out->cref, B.cref.data(), B.cref.size() * 4);
+    if (out->range && !B.range.empty()) std::memcpy(out->range, B.range.data(), B.range.size() * 4);
+    if (out->perm && !B.perm.empty()) std::memcpy(out->perm, B.perm.data(), B.perm.size() * 4);
+    sc_status st = use_device(scene->ctx->device);
+    if (st != SC_OK) return st;
+    const size_t S = 2 * (size_t)I.n_inner;
+    hipError_t e = hipSuccess;
+    if (out->masks && scene->masks && S)
+        e = hipMemcpy(out->masks, scene->masks, S * I.words * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && out->codebook && scene->codebook)
+        e = hipMemcpy(out->codebook, scene->codebook, (size_t)I.codebook_size * I.words * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && out->cidx && scene->cidx && S)
+        e = hipMemcpy(out->cidx, scene->cidx, S * 2, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "export");
+    return SC_OK;
+}
+
+sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags, sc_hit* d_hits,
+                   uint32_t* d_extra, uint32_t* d_slot_fp, void* stream) {
+    if (!scene) return fail(SC_ERR_INVALID_ARG, "scene is NULL");
+    if (n > 0 && (!d_rays || !d_hits)) return fail(SC_ERR_INVALID_ARG, "d_rays and d_hits must be non-NULL");
+    if (flags & ~(uint32_t)(SC_TRACE_CULL | SC_TRACE_SHADOW | SC_TRACE_SORT))
+        return fail(SC_ERR_INVALID_ARG, "unknown trace flag");
+    if (flags & SC_TRACE_SORT) return fail(SC_ERR_UNSUPPORTED, "SC_TRACE_SORT is not implemented");
+    if (((uintptr_t)d_rays & 15) || ((uintptr_t)d_hits & 15) || ((uintptr_t)d_extra & 7) ||
+        ((uintptr_t)d_slot_fp & 3))
+        return fail(SC_ERR_INVALID_ARG, "d_rays and d_hits must be 16-byte aligned, d_extra 8-byte");
+    if (n == 0) return SC_OK;
+    sc_status st = use_device(scene->ctx->device);
+    if (st != SC_OK) return st;
+    const sc_scene_info& I = scene->info;
+    TraceLaunch a{};
+    a.rays = d_rays;
+    a.n = n;
+    a.nodes = scene->nodes;
+    a.tris = scene->tris;
+    a.lut = (I.mode != SC_MASK_NONE) ? scene->ctx->lut[I.R] : nullptr;
+    a.codebook = scene->codebook;
+    a.side_masks = scene->side_masks;
+    a.root = I.root_ref;
+    a.R = I.R;
+    a.mode = (I.n_inner == 0) ? (uint32_t)SC_MASK_NONE : I.mode;
+    a.flags = flags;
+    a.origin_bound = I.origin_bound;
+    a.hits = d_hits;
+    a.extra = d_extra;
+    a.slot_fp = d_slot_fp;
+    if (a.mode == SC_MASK_SPARSE && I.n_masked == 0) a.mode = SC_MASK_NONE;
+    const hipError_t e = launch_trace(a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "trace launch");
+    return SC_OK;
+}
+
+sc_status sc_raymask_lut(sc_ctx* ctx, uint32_t R, uint64_t* d_out, void* stream) {
+    if (!ctx || !d_out) return fail(SC_ERR_INVALID_ARG, "ctx and d_out must be non-NULL");
+    if (R != 4 && R != 6) return fail(SC_ERR_INVALID_ARG, "R must be 4 or 6");
+    sc_status st = use_device(ctx->device);
+    if (st != SC_OK) return st;
+    const hipError_t e = launch_raymask_lut(R, d_out, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SC_OK : hip_fail(e, "ray-mask LUT kernel");
+}
+
+sc_status sc_compress_masks(sc_ctx* ctx, uint32_t R, const uint64_t* d_codebook, uint32_t K,
+                            const uint64_t* d_masks, uint32_t n, uint16_t* d_idx, void* stream) {
+    if (!ctx || !d_codebook || (n && (!d_masks || !d_idx)))
+        return fail(SC_ERR_INVALID_ARG, "NULL argument");
+    if (R != 4 && R != 6) return fail(SC_ERR_INVALID_ARG, "R must be 4 or 6");
+    if (K < 64 || K > 4096 || K % 64) return fail(SC_ERR_INVALID_ARG, "K must be a multiple of 64 in [64, 4096]");
+    sc_status st = use_device(ctx->device);
+    if (st != SC_OK) return st;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint32_t nch = (R * R * R + 7) / 8;
+    const size_t req_bytes = (size_t)nch * 256 * (K / 64) * 8;
+    auto* d_req = static_cast<uint64_t*>(dev_alloc(ctx, req_bytes, s));
+    if (!d_req) return fail(SC_ERR_OOM, "requirement LUT allocation failed");
+    hipError_t e = launch_req_luts(R, d_codebook, K, d_req, s);
+    if (e == hipSuccess) e = launch_compress(R, d_masks, n, d_req, K, d_idx, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(ctx, d_req, req_bytes, s);
+    return e == hipSuccess ? SC_OK : hip_fail(e, "compression");
+}
+
+}  // extern "C"

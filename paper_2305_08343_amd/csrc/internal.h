@@ -1,0 +1,87 @@
+// Internal declarations shared by the host code and the kernel launchers of
+// libsubcull. Not part of the public ABI (include/subcull.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/subcull.h"
+
+namespace sc {
+
+constexpr uint32_t kLeafBit = 0x80000000u;
+constexpr uint32_t kEmptyRef = 0xFFFFFFFFu;
+constexpr uint32_t kNoHit = 0xFFFFFFFFu;
+constexpr uint32_t kMaxDepth = 64;       // stack entries needed <= depth
+constexpr uint32_t kNoMask = 0xFFFFFFFFu;
+
+// Node layout (bytes). Every node holds its two children's boxes and refs in
+// the first 64 bytes (one half of a 128-byte L2 line):
+//   [0,24)  child 0 lo.xyz hi.xyz     [24,48) child 1 lo.xyz hi.xyz
+//   [48,52) ref 0   [52,56) ref 1     [56,60) aux   [60,64) aux2
+// aux  : LUT mode -> codebook index of child 0 | index of child 1 << 16
+//        SPARSE   -> mask slot of child 0 (kNoMask = none); aux2 -> child 1
+// RAW nodes are 128 bytes: the raw masks follow at [64, 64 + 2*words*8).
+constexpr uint32_t kNodeBytes = 64;
+constexpr uint32_t kRawNodeBytes = 128;
+constexpr uint32_t kTriBytes = 48;  // v0.xyz e1.xyz e2.xyz id pad pad
+
+inline uint32_t words_for(uint32_t R) { return (R * R * R + 63u) / 64u; }
+
+// -------------------------------------------------------------- host BVH
+struct HostBVH {
+    uint32_t n_inner = 0;
+    uint32_t root = kEmptyRef;
+    uint32_t depth = 0;
+    std::vector<float> cbox;      // [n_inner][12]
+    std::vector<uint32_t> cref;   // [n_inner][2]
+    std::vector<uint32_t> range;  // [n_inner][2] first, count
+    std::vector<uint32_t> perm;   // [n] original id per leaf-order position
+};
+
+// Binned SAH build; returns SC_OK, SC_ERR_DEPTH or SC_ERR_OOM.
+sc_status build_bvh(const float* tris, uint32_t n, uint32_t leaf_max, uint32_t bins,
+                    uint32_t depth_cap, HostBVH& out);
+
+// Codebook of K masks (Eq. 2 importance, Sect. 3.2.2), sorted by set-bit
+// count then value. slot_boxes [S][6] lo.xyz hi.xyz.
+void select_codebook(const uint64_t* masks, const float* slot_boxes, size_t S, uint32_t R,
+                     uint32_t K, std::vector<uint64_t>& cb);
+
+// ------------------------------------------------------ kernel launchers
+struct TraceLaunch {
+    const float* rays;
+    uint32_t n;
+    const unsigned char* nodes;
+    const float* tris;          // kTriBytes records in leaf order
+    const uint64_t* lut;        // ray-mask LUT
+    const uint64_t* codebook;   // LUT mode
+    const uint64_t* side_masks; // SPARSE mode
+    uint32_t root;
+    uint32_t R;
+    uint32_t mode;
+    uint32_t flags;
+    float origin_bound;
+    sc_hit* hits;
+    uint32_t* extra;
+    uint32_t* slot_fp;
+};
+
+hipError_t launch_trace(const TraceLaunch& a, hipStream_t s);
+hipError_t launch_raymask_lut(uint32_t R, uint64_t* out, hipStream_t s);
+hipError_t launch_object_masks(uint32_t R, const float* tris_orig, const uint32_t* perm, uint32_t n,
+                               const unsigned char* nodes, uint32_t node_stride,
+                               const uint32_t* range, uint32_t root, float delta, uint64_t* masks,
+                               hipStream_t s);
+hipError_t launch_req_luts(uint32_t R, const uint64_t* cb, uint32_t K, uint64_t* req, hipStream_t s);
+hipError_t launch_compress(uint32_t R, const uint64_t* masks, uint32_t n, const uint64_t* req,
+                           uint32_t K, uint16_t* idx, hipStream_t s);
+hipError_t launch_pack_raw(uint32_t R, const uint64_t* masks, uint32_t n_inner, unsigned char* nodes,
+                           hipStream_t s);
+hipError_t launch_pack_lut(const uint16_t* idx, uint32_t n_inner, unsigned char* nodes, hipStream_t s);
+
+}  // namespace sc

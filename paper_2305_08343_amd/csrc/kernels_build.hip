@@ -1,0 +1,371 @@
+// Build-time kernels for gfx950: ray-mask LUT, exact object masks,
+// requirement LUTs, Alg. 3 compression and node packing.
+//
+// All float32 arithmetic follows the exact expression order stated at each
+// kernel; the library is compiled with -ffp-contract=off so no product is
+// fused into an add, and divisions are correctly rounded.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace sc {
+namespace {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Ray-mask LUT (Sect. 3.1.1, Alg. 1). Entry (beg, end) holds voxel v iff a
+// unit cell swept from cell beg to cell end overlaps v with positive volume
+// at some time s in [0,1]: per axis the overlap time set is the open
+// interval between (v-1-beg)/D and (v+1-beg)/D (D = end-beg != 0), or all
+// time when D = 0 and v = beg. Times are scaled by 60 so every bound is an
+// integer for R <= 6. One thread per key.
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ void raymask_lut_kernel(uint64_t* __restrict__ out) {
+    constexpr int R3 = R * R * R;
+    constexpr int W = (R3 + 63) / 64;
+    constexpr int T = 60;
+    constexpr int kBig = 1 << 20;
+    const int key = blockIdx.x * blockDim.x + threadIdx.x;
+    if (key >= R3 * R3) return;
+    const int kb = key / R3, ke = key % R3;
+    const int beg[3] = {kb / (R * R), (kb / R) % R, kb % R};
+    const int end[3] = {ke / (R * R), (ke / R) % R, ke % R};
+    int tlo[3][R], thi[3][R];
+    bool ok[3][R];
+    for (int i = 0; i < 3; ++i) {
+        const int D = end[i] - beg[i];
+        for (int v = 0; v < R; ++v) {
+            if (D == 0) {
+                ok[i][v] = (v == beg[i]);
+                tlo[i][v] = -kBig;
+                thi[i][v] = kBig;
+            } else {
+                int a = T * (v - 1 - beg[i]) / D;
+                int b = T * (v + 1 - beg[i]) / D;
+                tlo[i][v] = a < b ? a : b;
+                thi[i][v] = a < b ? b : a;
+                ok[i][v] = true;
+            }
+        }
+    }
+    uint64_t m[W];
+    for (int w = 0; w < W; ++w) m[w] = 0;
+    for (int z = 0; z < R; ++z)
+        for (int y = 0; y < R; ++y)
+            for (int x = 0; x < R; ++x) {
+                if (!(ok[0][x] && ok[1][y] && ok[2][z])) continue;
+                int lo = tlo[0][x];
+                lo = tlo[1][y] > lo ? tlo[1][y] : lo;
+                lo = tlo[2][z] > lo ? tlo[2][z] : lo;
+                int hi = thi[0][x];
+                hi = thi[1][y] < hi ? thi[1][y] : hi;
+                hi = thi[2][z] < hi ? thi[2][z] : hi;
+                if (lo < hi && lo < T && hi > 0) {
+                    const int bit = x + R * y + R * R * z;
+                    m[bit >> 6] |= 1ull << (bit & 63);
+                }
+            }
+    for (int w = 0; w < W; ++w) out[(size_t)key * W + w] = m[w];
+}
+
+// ---------------------------------------------------------------------------
+// Triangle / voxel overlap: separating axis test on the triangle translated
+// to the voxel centre c with half-size h (3 box normals, the 9 products of a
+// box axis with an edge, the triangle normal). On each axis the three
+// projected vertices are compared with +-r, r the box's projected radius;
+// separated iff all three lie above r or all below -r.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float mn2(float a, float b) { return (a < b) ? a : b; }
+__device__ __forceinline__ float mx2(float a, float b) { return (a > b) ? a : b; }
+__device__ __forceinline__ bool outside(float p0, float p1, float p2, float r) {
+    return mn2(mn2(p0, p1), p2) > r || mx2(mx2(p0, p1), p2) < -r;
+}
+
+__device__ __forceinline__ bool tri_voxel_overlap(const float* v, float cx, float cy, float cz,
+                                                  const float* h) {
+    const float ax = v[0] - cx, ay = v[1] - cy, az = v[2] - cz;
+    const float bx = v[3] - cx, by = v[4] - cy, bz = v[5] - cz;
+    const float qx = v[6] - cx, qy = v[7] - cy, qz = v[8] - cz;
+    if (outside(ax, bx, qx, h[0]) || outside(ay, by, qy, h[1]) || outside(az, bz, qz, h[2]))
+        return false;
+    const float ex[3] = {bx - ax, qx - bx, ax - qx};
+    const float ey[3] = {by - ay, qy - by, ay - qy};
+    const float ez[3] = {bz - az, qz - bz, az - qz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float fx = ex[k], fy = ey[k], fz = ez[k];
+        float r = h[1] * fabsf(fz) + h[2] * fabsf(fy);
+        if (outside(fy * az - fz * ay, fy * bz - fz * by, fy * qz - fz * qy, r)) return false;
+        r = h[0] * fabsf(fz) + h[2] * fabsf(fx);
+        if (outside(fz * ax - fx * az, fz * bx - fx * bz, fz * qx - fx * qz, r)) return false;
+        r = h[0] * fabsf(fy) + h[1] * fabsf(fx);
+        if (outside(fx * ay - fy * ax, fx * by - fy * bx, fx * qy - fy * qx, r)) return false;
+    }
+    const float nx = ey[0] * ez[1] - ez[0] * ey[1];
+    const float ny = ez[0] * ex[1] - ex[0] * ez[1];
+    const float nz = ex[0] * ey[1] - ey[0] * ex[1];
+    const float r = (h[0] * fabsf(nx) + h[1] * fabsf(ny)) + h[2] * fabsf(nz);
+    const float p0 = (nx * ax + ny * ay) + nz * az;
+    const float p1 = (nx * bx + ny * by) + nz * bz;
+    const float p2 = (nx * qx + ny * qy) + nz * qz;
+    return !outside(p0, p1, p2, r);
+}
+
+// Voxels of box (lo, hi) that triangle v overlaps; voxel k on axis j has
+// centre lo + (k + 0.5f) * w and half-size 0.5f * w + delta, w = (hi-lo)/R.
+// Candidate voxels are those passing the box-normal tests of the same
+// overlap test (separable per axis), so the result is the full test's.
+template <int R>
+__device__ void voxelize(const float* v, const float* lo, const float* hi, float delta,
+                         uint64_t* bits) {
+    float w[3], h[3];
+    uint32_t pass[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        w[j] = (hi[j] - lo[j]) / (float)R;
+        h[j] = 0.5f * w[j] + delta;
+        pass[j] = 0;
+        for (int k = 0; k < R; ++k) {
+            const float c = lo[j] + ((float)k + 0.5f) * w[j];
+            if (!outside(v[j] - c, v[3 + j] - c, v[6 + j] - c, h[j])) pass[j] |= 1u << k;
+        }
+    }
+    for (uint32_t pz = pass[2]; pz; pz &= pz - 1) {
+        const int z = __builtin_ctz(pz);
+        const float cz = lo[2] + ((float)z + 0.5f) * w[2];
+        for (uint32_t py = pass[1]; py; py &= py - 1) {
+            const int y = __builtin_ctz(py);
+            const float cy = lo[1] + ((float)y + 0.5f) * w[1];
+            for (uint32_t px = pass[0]; px; px &= px - 1) {
+                const int x = __builtin_ctz(px);
+                const float cx = lo[0] + ((float)x + 0.5f) * w[0];
+                if (tri_voxel_overlap(v, cx, cy, cz, h)) {
+                    const int bit = x + R * y + R * R * z;
+                    bits[bit >> 6] |= 1ull << (bit & 63);
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t shfl_down64(uint64_t x, int off) {
+    const uint32_t lo = __shfl_down((uint32_t)x, off, kWave);
+    const uint32_t hi = __shfl_down((uint32_t)(x >> 32), off, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// ---------------------------------------------------------------------------
+// Exact object masks (L = infinity, Sect. 3.2.1): one thread per triangle
+// in leaf order. The thread walks from the root to its leaf; at every level
+// it voxelizes its triangle into the child box that contains it. Threads of
+// a wave hold consecutive triangles, so the lanes sharing a child slot are
+// contiguous: a segmented OR across the wave leaves one value per slot, and
+// the first lane of each segment ORs it into global memory.
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(256) void object_mask_kernel(
+    const float* __restrict__ tris, const uint32_t* __restrict__ perm, uint32_t n,
+    const unsigned char* __restrict__ nodes, uint32_t stride, const uint32_t* __restrict__ range,
+    uint32_t root, float delta, unsigned long long* __restrict__ masks) {
+    constexpr int W = (R * R * R + 63) / 64;
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    bool active = (j < n) && !(root & kLeafBit);
+    float v[9];
+    if (active) {
+        const float* src = tris + 9 * (size_t)perm[j];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v[k] = src[k];
+    }
+    uint32_t node = root;
+    while (__ballot(active) != 0) {
+        uint32_t slot = 0xFFFFFFFFu;
+        uint64_t bits[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) bits[w] = 0;
+        uint32_t next = 0;
+        bool leaf = true;
+        if (active) {
+            const float* nf = reinterpret_cast<const float*>(nodes + (size_t)node * stride);
+            const uint32_t* nu = reinterpret_cast<const uint32_t*>(nf);
+            const uint32_t ref0 = nu[12];
+            const uint32_t lcount = (ref0 & kLeafBit) ? ((ref0 >> 29) & 3u) + 1u : range[2 * (size_t)ref0 + 1];
+            const int c = (j < range[2 * (size_t)node] + lcount) ? 0 : 1;
+            slot = 2u * node + (uint32_t)c;
+            voxelize<R>(v, nf + 6 * c, nf + 6 * c + 3, delta, bits);
+            const uint32_t ref = nu[12 + c];
+            leaf = (ref & kLeafBit) != 0;
+            next = ref;
+        }
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t s2 = __shfl_down(slot, off, kWave);
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint64_t b2 = shfl_down64(bits[w], off);
+                if (lane + off < kWave && s2 == slot) bits[w] |= b2;
+            }
+        }
+        const uint32_t prev = __shfl_up(slot, 1, kWave);
+        if (slot != 0xFFFFFFFFu && (lane == 0 || prev != slot)) {
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                if (bits[w]) atomicOr(&masks[(size_t)slot * W + w], (unsigned long long)bits[w]);
+        }
+        active = active && !leaf;
+        node = next;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Requirement LUTs (Sect. 3.2.3): table i, row p, word w has bit b set iff
+// codebook entry k = 64w + b contains every bit of p in its chunk i (mask
+// bits [8i, 8i+8)). One thread per (table, row, word).
+// ---------------------------------------------------------------------------
+__global__ void req_lut_kernel(const uint64_t* __restrict__ cb, uint32_t K, uint32_t W,
+                               uint32_t nch, uint64_t* __restrict__ req) {
+    const uint32_t KW = K / 64;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)nch * 256 * KW) return;
+    const uint32_t w = gid % KW;
+    const uint32_t p = (gid / KW) % 256;
+    const uint32_t i = (uint32_t)(gid / ((size_t)KW * 256));
+    const uint32_t bit = 8 * i;
+    uint64_t out = 0;
+    for (uint32_t b = 0; b < 64; ++b) {
+        const uint32_t k = 64 * w + b;
+        const uint32_t chunk = (uint32_t)((cb[(size_t)k * W + (bit >> 6)] >> (bit & 63)) & 0xFFu);
+        if ((chunk & p) == p) out |= 1ull << b;
+    }
+    req[gid] = out;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 3 (Sect. 3.2.3): one wave per mask; lane l owns the 64 codebook
+// entries of word l. The rows picked by the mask's 8-bit chunks are ANDed,
+// the first lane with a non-zero word is found by a ballot, and its lowest
+// set bit is the index of the tightest conservative entry.
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(256) void compress_kernel(const uint64_t* __restrict__ masks, uint32_t n,
+                                                       const uint64_t* __restrict__ req, uint32_t K,
+                                                       uint16_t* __restrict__ idx) {
+    constexpr int W = (R * R * R + 63) / 64;
+    constexpr int NCH = (R * R * R + 7) / 8;
+    const uint32_t KW = K / 64;
+    const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    if (wave >= n) return;
+    uint64_t m[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) m[w] = masks[wave * W + w];
+    uint64_t acc = ~0ull;
+    if (lane < KW) {
+#pragma unroll
+        for (int i = 0; i < NCH; ++i) {
+            const uint32_t bit = 8 * i;
+            const uint32_t p = (uint32_t)((m[bit >> 6] >> (bit & 63)) & 0xFFu);
+            acc &= req[((size_t)i * 256 + p) * KW + lane];
+        }
+    }
+    const uint64_t nz = __ballot(lane < KW && acc != 0);
+    if (nz == 0) {
+        if (lane == 0) idx[wave] = 0xFFFFu;
+        return;
+    }
+    const int first = __builtin_ctzll(nz);
+    const uint32_t lo = __shfl((uint32_t)acc, first, kWave);
+    const uint32_t hi = __shfl((uint32_t)(acc >> 32), first, kWave);
+    const uint64_t word = ((uint64_t)hi << 32) | lo;
+    if (lane == 0) idx[wave] = (uint16_t)(first * 64 + __builtin_ctzll(word));
+}
+
+// Copy each inner node's two raw masks into bytes [64, 64 + 2*W*8) of its
+// 128-byte node.
+template <int R>
+__global__ void pack_raw_kernel(const uint64_t* __restrict__ masks, uint32_t n_inner,
+                                unsigned char* __restrict__ nodes) {
+    constexpr int W = (R * R * R + 63) / 64;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)n_inner * 2 * W) return;
+    const size_t node = gid / (2 * W);
+    const size_t k = gid % (2 * W);
+    reinterpret_cast<uint64_t*>(nodes + node * kRawNodeBytes + 64)[k] = masks[node * 2 * W + k];
+}
+
+__global__ void pack_lut_kernel(const uint16_t* __restrict__ idx, uint32_t n_inner,
+                                unsigned char* __restrict__ nodes) {
+    const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= n_inner) return;
+    const uint32_t v = (uint32_t)idx[2 * node] | ((uint32_t)idx[2 * node + 1] << 16);
+    reinterpret_cast<uint32_t*>(nodes + node * kNodeBytes)[14] = v;
+}
+
+inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_raymask_lut(uint32_t R, uint64_t* out, hipStream_t s) {
+    const size_t n = (size_t)R * R * R * R * R * R;
+    if (R == 4) hipLaunchKernelGGL(raymask_lut_kernel<4>, dim3(blocks_for(n, 256)), dim3(256), 0, s, out);
+    else if (R == 6) hipLaunchKernelGGL(raymask_lut_kernel<6>, dim3(blocks_for(n, 256)), dim3(256), 0, s, out);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_object_masks(uint32_t R, const float* tris_orig, const uint32_t* perm, uint32_t n,
+                               const unsigned char* nodes, uint32_t node_stride,
+                               const uint32_t* range, uint32_t root, float delta, uint64_t* masks,
+                               hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    auto* m = reinterpret_cast<unsigned long long*>(masks);
+    if (R == 4)
+        hipLaunchKernelGGL(object_mask_kernel<4>, dim3(blocks_for(n, 256)), dim3(256), 0, s, tris_orig,
+                           perm, n, nodes, node_stride, range, root, delta, m);
+    else if (R == 6)
+        hipLaunchKernelGGL(object_mask_kernel<6>, dim3(blocks_for(n, 256)), dim3(256), 0, s, tris_orig,
+                           perm, n, nodes, node_stride, range, root, delta, m);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_req_luts(uint32_t R, const uint64_t* cb, uint32_t K, uint64_t* req, hipStream_t s) {
+    const uint32_t W = words_for(R), nch = (R * R * R + 7) / 8;
+    const size_t n = (size_t)nch * 256 * (K / 64);
+    hipLaunchKernelGGL(req_lut_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, cb, K, W, nch, req);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress(uint32_t R, const uint64_t* masks, uint32_t n, const uint64_t* req,
+                           uint32_t K, uint16_t* idx, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const size_t threads = (size_t)n * kWave;
+    if (R == 4)
+        hipLaunchKernelGGL(compress_kernel<4>, dim3(blocks_for(threads, 256)), dim3(256), 0, s, masks, n,
+                           req, K, idx);
+    else if (R == 6)
+        hipLaunchKernelGGL(compress_kernel<6>, dim3(blocks_for(threads, 256)), dim3(256), 0, s, masks, n,
+                           req, K, idx);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_raw(uint32_t R, const uint64_t* masks, uint32_t n_inner, unsigned char* nodes,
+                           hipStream_t s) {
+    if (n_inner == 0) return hipSuccess;
+    const size_t n = (size_t)n_inner * 2 * words_for(R);
+    if (R == 4) hipLaunchKernelGGL(pack_raw_kernel<4>, dim3(blocks_for(n, 256)), dim3(256), 0, s, masks, n_inner, nodes);
+    else if (R == 6) hipLaunchKernelGGL(pack_raw_kernel<6>, dim3(blocks_for(n, 256)), dim3(256), 0, s, masks, n_inner, nodes);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_lut(const uint16_t* idx, uint32_t n_inner, unsigned char* nodes, hipStream_t s) {
+    if (n_inner == 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_lut_kernel, dim3(blocks_for(n_inner, 256)), dim3(256), 0, s, idx, n_inner, nodes);
+    return hipGetLastError();
+}
+
+}  // namespace sc

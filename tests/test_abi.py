@@ -1,0 +1,92 @@
+"""The C-ABI library loads and exports every symbol include/subcull.h declares;
+argument checks that happen before any HIP call (CPU-only)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2305_08343_amd import binding as B
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "subcull.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sc_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_api():
+    names = _declared()
+    for must in ("sc_create", "sc_destroy", "sc_scene_build", "sc_scene_destroy", "sc_scene_get_info",
+                 "sc_scene_export", "sc_trace", "sc_raymask_lut", "sc_compress_masks",
+                 "sc_status_string", "sc_last_error", "sc_build_params_default"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+        assert name in B._SIGS, f"binding lacks a signature for {name}"
+
+
+def test_params_default_and_status_strings():
+    lib = B.load()
+    p = B.sc_build_params()
+    lib.sc_build_params_default(C.byref(p))
+    assert (p.R, p.leaf_max, p.sah_bins, p.depth_cap, p.mode, p.codebook_size) == (6, 4, 32, 64, 1, 4096)
+    assert p.delta == 0.0 and p.origin_bound == 0.0 and not p.mask_placement
+    for s, txt in [(0, b"ok"), (1, b"invalid argument"), (4, b"BVH depth cap exceeded")]:
+        assert lib.sc_status_string(s) == txt
+
+
+def test_struct_sizes_match_header_layout():
+    # 10 uint32, 2 float, uint64, 4 double
+    assert C.sizeof(B.sc_scene_info) == 40 + 8 + 8 + 32
+    assert C.sizeof(B.sc_build_params) == 48
+    assert C.sizeof(B.sc_scene_host) == 7 * 8
+
+
+def test_null_arguments_rejected_before_hip():
+    lib = B.load()
+    assert lib.sc_create(0, None, None) == 1
+    assert lib.sc_scene_build(None, None, 0, None, None, None) == 1
+    assert b"non-NULL" in lib.sc_last_error()
+    assert lib.sc_trace(None, None, 0, 0, None, None, None, None) == 1
+    assert lib.sc_scene_get_info(None, None) == 1
+    assert lib.sc_scene_export(None, None) == 1
+    assert lib.sc_raymask_lut(None, 6, None, None) == 1
+    assert lib.sc_compress_masks(None, 6, None, 64, None, 0, None, None) == 1
+    assert lib.sc_destroy(None) == 0 and lib.sc_scene_destroy(None) == 0
+
+
+def test_bad_build_params_rejected_before_hip():
+    lib = B.load()
+    p = B.sc_build_params()
+    lib.sc_build_params_default(C.byref(p))
+    fake_ctx = C.c_void_p(1)  # never dereferenced: parameter checks come first
+    out = C.c_void_p()
+    for field, value in [("R", 5), ("leaf_max", 0), ("leaf_max", 5), ("sah_bins", 1), ("depth_cap", 65),
+                         ("mode", 9)]:
+        q = B.sc_build_params.from_buffer_copy(p)
+        setattr(q, field, value)
+        assert lib.sc_scene_build(fake_ctx, None, 0, C.byref(q), None, C.byref(out)) == 1, field
+    q = B.sc_build_params.from_buffer_copy(p)
+    q.mode, q.codebook_size = 2, 100
+    assert lib.sc_scene_build(fake_ctx, None, 0, C.byref(q), None, C.byref(out)) == 1
+    q = B.sc_build_params.from_buffer_copy(p)
+    q.mode = 3
+    assert lib.sc_scene_build(fake_ctx, None, 0, C.byref(q), None, C.byref(out)) == 1
+    assert b"mask_placement" in lib.sc_last_error()
+    assert lib.sc_scene_build(fake_ctx, None, 1 << 29, C.byref(p), None, C.byref(out)) == 1
+
+
+def test_no_device_is_reported(monkeypatch):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    assert B.load().sc_create(0, None, C.byref(h)) == 2

@@ -1,0 +1,224 @@
+"""GPU parity: every product of the HIP path against the oracle.
+
+Bar (integer work bit-exact; the float32 hit distance is bit-exact too,
+which is within the stated 1e-5 relative tolerance): ray-mask LUT, BVH
+topology/boxes/permutation, object masks, codebook, Alg. 3 indices, and per
+ray the hit id, t, box/triangle/mask test counts and mask culls. Sizes span
+many 128-ray blocks with a ragged tail, plus the degenerate cases.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_08343_amd import scenes
+
+pytestmark = pytest.mark.gpu
+NO_HIT = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2305_08343_amd import binding
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _compare_hits(dev, ora, with_masks=True):
+    bad = np.flatnonzero((dev["prim"] != ora.prim) |
+                         (dev["t"].view(np.uint32) != ora.t.view(np.uint32)) |
+                         (dev["box_tests"] != ora.box_tests) | (dev["tri_tests"] != ora.tri_tests))
+    assert bad.size == 0, f"{bad.size} rays differ, first {bad[:5]}"
+    if with_masks:
+        assert (dev["mask_tests"] == ora.mask_tests).all()
+        assert (dev["mask_culls"] == ora.mask_culls).all()
+
+
+def _aimed(tris, n, seed):
+    rng = np.random.default_rng(seed)
+    lo, hi = tris.reshape(-1, 3).min(0), tris.reshape(-1, 3).max(0)
+    c, ext = 0.5 * (lo + hi), np.maximum(hi - lo, 1e-3)
+    o = c + (rng.random((n, 3)) - 0.5) * ext * 2.2
+    t = rng.integers(0, tris.shape[0], n)
+    w = rng.dirichlet([1, 1, 1], n)
+    d = np.einsum("nk,nkj->nj", w, tris[t].astype(np.float64)) - o
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    r = np.zeros((n, 8), np.float32)
+    r[:, :3], r[:, 4:7], r[:, 7] = o, d, np.inf
+    return r
+
+
+def _check_bvh(exp, ob):
+    assert exp["cbox"].shape == ob.cbox.shape
+    assert (exp["cbox"].view(np.uint32) == ob.cbox.view(np.uint32)).all()
+    assert (exp["cref"] == ob.cref).all() and (exp["range"] == ob.range).all()
+    assert (exp["perm"] == ob.perm).all()
+
+
+@pytest.mark.parametrize("R", [4, 6])
+def test_raymask_lut_bit_exact(ctx, R):
+    print(f"[gpu] raymask LUT R={R}", flush=True)
+    assert (ctx.raymask_lut(R) == oracle.raymask_lut(R)).all()
+
+
+def test_small_scene_build_bit_exact(ctx, small_scene, small_oracle):
+    from paper_2305_08343_amd import binding
+    tris, _ = small_scene
+    for R in (4, 6):
+        print(f"[gpu] small scene build R={R}", flush=True)
+        s = binding.Scene(ctx, tris, R=R, mode="raw")
+        assert s.info["delta"] == np.float32(small_oracle["delta"])
+        assert s.info["origin_bound"] == np.float32(small_oracle["origin_bound"])
+        assert s.info["depth"] == small_oracle["bvh"].depth
+        exp = s.export()
+        _check_bvh(exp, small_oracle["bvh"])
+        assert (exp["masks"] == small_oracle[f"masks{R}"]).all()
+        s.close()
+
+
+@pytest.mark.parametrize("mode,R,K", [("none", 6, 0), ("raw", 4, 0), ("raw", 6, 0),
+                                      ("lut", 6, 256), ("lut", 6, 4096), ("lut", 4, 256)])
+def test_small_scene_trace_bit_exact(ctx, small_scene, small_oracle, mode, R, K):
+    from paper_2305_08343_amd import binding
+    tris, rays = small_scene
+    rays = np.concatenate([rays, _aimed(tris, 30001, 7)])  # ragged tail
+    print(f"[gpu] small trace mode={mode} R={R} K={K} rays={rays.shape[0]}", flush=True)
+    s = binding.Scene(ctx, tris, R=R, mode=mode, K=K or 4096)
+    bvh = small_oracle["bvh"]
+    kw = dict(origin_bound=small_oracle["origin_bound"])
+    if mode == "raw":
+        kw.update(mode="raw", R=R, masks=small_oracle[f"masks{R}"])
+    elif mode == "lut":
+        exp = s.export()
+        cb, idx = oracle.compress(small_oracle[f"masks{R}"], bvh.slot_boxes(), R, K)
+        assert (exp["codebook"] == cb).all()
+        assert (exp["cidx"] == idx).all()
+        kw.update(mode="lut", R=R, codebook=cb, cidx=idx)
+    for cull in (True, False):
+        ora = oracle.trace(tris, bvh, rays, cull=cull, **kw)
+        dev = s.trace(rays, cull=cull).numpy()
+        _compare_hits(dev, ora)
+    s.close()
+
+
+def test_shadow_counts_bit_exact(ctx, small_scene, small_oracle):
+    import torch
+    from paper_2305_08343_amd import binding
+    tris, rays = small_scene
+    rays = np.concatenate([rays, _aimed(tris, 20000, 8)])
+    print("[gpu] shadow-mode per-slot counts", flush=True)
+    s = binding.Scene(ctx, tris, R=6, mode="raw")
+    fp = torch.zeros(2 * s.info["n_inner"], dtype=torch.int32, device="cuda:0")
+    dev = s.trace(rays, cull=False, shadow=True, slot_fp=fp).numpy()
+    ora = oracle.trace(tris, small_oracle["bvh"], rays, mode="raw", R=6, masks=small_oracle["masks6"],
+                       origin_bound=small_oracle["origin_bound"], cull=False, shadow=True)
+    _compare_hits(dev, ora)
+    assert (fp.cpu().numpy().view(np.uint32) == ora.slot_fp).all()
+    assert ora.slot_fp.sum() > 0
+    s.close()
+
+
+def test_device_alg3_matches_oracle(ctx, small_oracle):
+    rng = np.random.default_rng(3)
+    for R, K in ((6, 4096), (6, 256), (4, 256), (4, 1024)):
+        print(f"[gpu] Alg. 3 R={R} K={K}", flush=True)
+        masks = small_oracle[f"masks{R}"]
+        cb = oracle.codebook(masks, small_oracle["bvh"].slot_boxes(), R, K)
+        req = oracle.req_luts(cb, R)
+        bits = rng.random((5000, R ** 3)) < 0.1
+        extra = np.zeros((5000, oracle.words_for(R)), np.uint64)
+        for b in range(R ** 3):
+            extra[:, b >> 6] |= bits[:, b].astype(np.uint64) << np.uint64(b & 63)
+        q = np.concatenate([masks, extra])
+        assert (ctx.compress_masks(R, cb, q) == oracle.alg3(q, req, K, R)).all()
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_micro_scenes_bit_exact(ctx, seed):
+    from paper_2305_08343_amd import binding
+    n = 1 + (seed * 11) % 64
+    tris = scenes.micro_scene(seed, n)
+    rays = np.concatenate([_aimed(tris, 257, seed), scenes.random_rays(63, seed)])
+    print(f"[gpu] micro scene seed={seed} n={n}", flush=True)
+    bvh = oracle.bvh_build(tris)
+    ob, delta = oracle.default_bounds(tris)
+    for mode, R in (("none", 6), ("raw", 4), ("raw", 6), ("lut", 6)):
+        s = binding.Scene(ctx, tris, R=R, mode=mode, K=64)
+        exp = s.export()
+        _check_bvh(exp, bvh)
+        kw = dict(origin_bound=ob)
+        if mode != "none" and bvh.n_inner:
+            m = oracle.object_masks(tris, bvh, R, delta)
+            assert (exp["masks"] == m).all()
+            if mode == "raw":
+                kw.update(mode="raw", R=R, masks=m)
+            else:
+                cb, idx = oracle.compress(m, bvh.slot_boxes(), R, 64)
+                kw.update(mode="lut", R=R, codebook=cb, cidx=idx)
+        _compare_hits(s.trace(rays).numpy(), oracle.trace(tris, bvh, rays, **kw))
+        s.close()
+
+
+def test_degenerate_inputs(ctx, small_scene):
+    import torch
+    from paper_2305_08343_amd import binding
+    tris, rays = small_scene
+    print("[gpu] degenerate inputs", flush=True)
+    # empty scene: every ray misses with zero counts
+    s = binding.Scene(ctx, np.zeros((0, 3, 3), np.float32), mode="raw")
+    d = s.trace(rays[:1000]).numpy()
+    assert (d["prim"] == NO_HIT).all() and np.isinf(d["t"]).all() and (d["box_tests"] == 0).all()
+    s.close()
+    # single leaf (no inner node)
+    t3 = scenes.micro_scene(2, 3)
+    s = binding.Scene(ctx, t3, mode="raw")
+    r = _aimed(t3, 500, 1)
+    ora = oracle.trace(t3, oracle.bvh_build(t3), r)
+    _compare_hits(s.trace(r).numpy(), ora)
+    s.close()
+    # zero rays, one ray, invalid rays
+    s = binding.Scene(ctx, tris, mode="raw")
+    res = s.trace(rays[:0])
+    assert res.hits.shape[0] == 0
+    one = s.trace(rays[:1]).numpy()
+    assert one["box_tests"].shape == (1,)
+    bad = np.repeat(rays[:1], 6, 0)
+    bad[0, 0] = np.nan
+    bad[1, 4:7] = 0
+    bad[2, 3], bad[2, 7] = 2.0, 1.0
+    bad[3, 7] = np.nan
+    bad[4, 5] = np.inf
+    bad[5, 3] = -np.inf
+    d = s.trace(bad).numpy()
+    assert (d["prim"] == NO_HIT).all() and (d["box_tests"] == 0).all() and (d["tri_tests"] == 0).all()
+    # a failed call leaves the scene usable
+    with pytest.raises(binding.SubcullError):
+        binding.load()
+        from paper_2305_08343_amd.binding import _check, load
+        _check(load().sc_trace(s.handle, None, 5, 1, None, None, None, None), "sc_trace")
+    d2 = s.trace(rays[:300]).numpy()
+    assert d2["box_tests"].sum() > 0
+    # depth cap is reported, non-finite vertices are rejected
+    with pytest.raises(binding.SubcullError) as e:
+        binding.Scene(ctx, tris, depth_cap=3)
+    assert e.value.status == 4
+    t_bad = tris.copy()
+    t_bad[5, 1, 2] = np.inf
+    with pytest.raises(binding.SubcullError) as e:
+        binding.Scene(ctx, t_bad)
+    assert e.value.status == 1
+    s.close()
+    torch.cuda.synchronize()
+
+
+def test_repeat_trace_is_deterministic(ctx, small_scene):
+    from paper_2305_08343_amd import binding
+    tris, rays = small_scene
+    print("[gpu] determinism", flush=True)
+    s = binding.Scene(ctx, tris, mode="lut", K=256)
+    a = s.trace(rays).hits.cpu().numpy()
+    b = s.trace(rays).hits.cpu().numpy()
+    assert (a == b).all()
+    s.close()
