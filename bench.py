@@ -133,6 +133,7 @@ def main():
     ap.add_argument("--modes", default="raw6,none,raw4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--tune", default="", help="block,stack,chunk of the traversal launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
@@ -149,6 +150,9 @@ def main():
     rays = scenes.rays_hair_1m(tris, 1)
     log(f"generated {tris.shape[0]} tris, {rays.shape[0]} rays in {time.perf_counter() - t0:.1f}s")
     ctx = binding.Context(0)
+    if args.tune:
+        b, s_, c = (int(x) for x in args.tune.split(","))
+        ctx.set_tune(b, s_, c)
     rays_dev = torch.from_numpy(rays).cuda()
     modes = [m for m in args.modes.split(",") if m]
     results, raw = {}, {}
@@ -183,6 +187,7 @@ def main():
                      "kernel": "trace_kernel", "kernel_ms": r["kernel_ms_mean"],
                      "alg_bytes_per_launch": r["alg_bytes_per_launch"]},
         "modes": results,
+        "tune": ctx.get_tune(),
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

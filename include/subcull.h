@@ -121,6 +121,16 @@ typedef struct {
     uint16_t* cidx;     /* [2*n_inner] codebook index per child slot (LUT)       */
 } sc_scene_host;
 
+/* Launch shape of the traversal: threads per block, LDS stack entries per
+ * lane (deeper entries spill to private memory) and rays per queue fetch
+ * (64 * chunk). Results never depend on it. Supported (block, stack) pairs:
+ * (256,8) (128,8) (256,12) (256,4) (128,16); chunk 1..64. */
+typedef struct {
+    uint32_t block;
+    uint32_t stack;
+    uint32_t chunk;
+} sc_tune;
+
 /* Fill `p` with the defaults: R 6, leaf_max 4, 32 bins, depth cap 64, RAW,
  * K 4096, default delta and origin bound. */
 void sc_build_params_default(sc_build_params* p);
@@ -169,10 +179,17 @@ sc_status sc_scene_export(const sc_scene* scene, sc_scene_host* out);
  *  d_slot_fp device uint32 [2*n_inner], or NULL; with SC_TRACE_SHADOW the
  *           per-slot count of slab hits whose mask test fails is added
  * A ray with a non-finite origin or direction, a zero direction, a NaN tmax
- * or tmin > tmax misses with zero counts. Asynchronous on `stream`.
+ * or tmin > tmax misses with zero counts. Asynchronous on `stream`. Each
+ * call takes one of 1024 per-context queue counters in turn, so at most 1024
+ * traces of one context may run at the same time (on different streams).
  */
 sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags,
                    sc_hit* d_hits, uint32_t* d_extra, uint32_t* d_slot_fp, void* stream);
+
+/* Select the traversal launch shape for later sc_trace calls on this
+ * context (default 256, 8, 1). SC_ERR_UNSUPPORTED for an uncompiled pair. */
+sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune);
+sc_status sc_get_tune(const sc_ctx* ctx, sc_tune* out);
 
 /* The ray-mask LUT of resolution R as built on the device (Sect. 3.1.1):
  * d_out receives R^6 entries of words(R) uint64 (words = 1 for R=4, 4 for

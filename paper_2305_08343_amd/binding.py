@@ -49,6 +49,10 @@ class sc_scene_info(C.Structure):
                 ("ms_codebook", C.c_double), ("ms_compress", C.c_double)]
 
 
+class sc_tune(C.Structure):
+    _fields_ = [("block", C.c_uint32), ("stack", C.c_uint32), ("chunk", C.c_uint32)]
+
+
 class sc_scene_host(C.Structure):
     _fields_ = [("cbox", C.c_void_p), ("cref", C.c_void_p), ("range", C.c_void_p),
                 ("perm", C.c_void_p), ("masks", C.c_void_p), ("codebook", C.c_void_p),
@@ -70,6 +74,8 @@ _SIGS = {
     "sc_scene_export": (C.c_int, [C.c_void_p, C.POINTER(sc_scene_host)]),
     "sc_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
+    "sc_set_tune": (C.c_int, [C.c_void_p, C.POINTER(sc_tune)]),
+    "sc_get_tune": (C.c_int, [C.c_void_p, C.POINTER(sc_tune)]),
     "sc_raymask_lut": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "sc_compress_masks": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
                                     C.c_uint32, C.c_void_p, C.c_void_p]),
@@ -151,6 +157,15 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_tune(self, block: int = 256, stack: int = 8, chunk: int = 1):
+        """Traversal launch shape for later traces (results never depend on it)."""
+        _check(load().sc_set_tune(self.handle, C.byref(sc_tune(block, stack, chunk))), "sc_set_tune")
+
+    def get_tune(self) -> dict:
+        t = sc_tune()
+        _check(load().sc_get_tune(self.handle, C.byref(t)), "sc_get_tune")
+        return {"block": t.block, "stack": t.stack, "chunk": t.chunk}
 
     def raymask_lut(self, R: int, stream=None):
         """Device ray-mask LUT as uint64 numpy array [R^6, W] (copies back)."""

@@ -1,6 +1,7 @@
 // C ABI of libsubcull (include/subcull.h): contexts, scene builds, traces.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -16,8 +17,12 @@ struct sc_ctx {
     int device = 0;
     sc_allocator alloc{};
     bool has_alloc = false;
-    uint64_t* lut[7] = {nullptr};  // ray-mask LUT per resolution, built on first use
+    uint64_t* lut[7] = {nullptr};       // full ray-mask LUT per resolution, built on first use
+    uint64_t* patterns[7] = {nullptr};  // its displacement patterns (what the traversal reads)
     std::mutex lut_mu;
+    uint32_t* counters = nullptr;           // kQueueRing ray-queue counters
+    std::atomic<uint32_t> next_counter{0};
+    sc_tune tune{256, 8, 1};
 };
 
 struct sc_scene {
@@ -90,18 +95,30 @@ sc_status use_device(int dev) {
     return SC_OK;
 }
 
+size_t lut_bytes(uint32_t R) { return (size_t)R * R * R * R * R * R * words_for(R) * 8; }
+size_t pattern_bytes(uint32_t R) { return pattern_count(R) * words_for(R) * 8; }
+
+// Ray-mask patterns and the full LUT of resolution R, built once per context.
 sc_status ensure_lut(sc_ctx* ctx, uint32_t R, hipStream_t s) {
     std::lock_guard<std::mutex> g(ctx->lut_mu);
     if (ctx->lut[R]) return SC_OK;
-    const size_t bytes = (size_t)R * R * R * R * R * R * words_for(R) * 8;
-    auto* p = static_cast<uint64_t*>(dev_alloc(ctx, bytes, s));
-    if (!p) return fail(SC_ERR_OOM, "ray-mask LUT allocation failed");
-    const hipError_t e = launch_raymask_lut(R, p, s);
-    if (e != hipSuccess) {
-        dev_free(ctx, p, bytes, s);
-        return hip_fail(e, "ray-mask LUT kernel");
+    auto* pat = static_cast<uint64_t*>(dev_alloc(ctx, pattern_bytes(R), s));
+    auto* lut = static_cast<uint64_t*>(dev_alloc(ctx, lut_bytes(R), s));
+    if (!pat || !lut) {
+        dev_free(ctx, pat, pattern_bytes(R), s);
+        dev_free(ctx, lut, lut_bytes(R), s);
+        return fail(SC_ERR_OOM, "ray-mask table allocation failed");
     }
-    ctx->lut[R] = p;
+    hipError_t e = launch_raymask_patterns(R, pat, s);
+    if (e == hipSuccess) e = launch_raymask_lut(R, pat, lut, s);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        dev_free(ctx, pat, pattern_bytes(R), s);
+        dev_free(ctx, lut, lut_bytes(R), s);
+        return hip_fail(e, "ray-mask table kernels");
+    }
+    ctx->patterns[R] = pat;
+    ctx->lut[R] = lut;
     return SC_OK;
 }
 
@@ -168,6 +185,11 @@ sc_status sc_create(int device, const sc_allocator* alloc, sc_ctx** out) {
         ctx->alloc = *alloc;
         ctx->has_alloc = true;
     }
+    ctx->counters = static_cast<uint32_t*>(dev_alloc(ctx, kQueueRing * 4, nullptr));
+    if (!ctx->counters) {
+        delete ctx;
+        return fail(SC_ERR_OOM, "queue counter allocation failed");
+    }
     *out = ctx;
     return SC_OK;
 }
@@ -176,8 +198,11 @@ sc_status sc_destroy(sc_ctx* ctx) {
     if (!ctx) return SC_OK;
     (void)use_device(ctx->device);
     (void)hipDeviceSynchronize();
-    for (uint32_t R = 0; R < 7; ++R)
-        if (ctx->lut[R]) dev_free(ctx, ctx->lut[R], (size_t)R * R * R * R * R * R * words_for(R) * 8, nullptr);
+    for (uint32_t R = 0; R < 7; ++R) {
+        if (ctx->lut[R]) dev_free(ctx, ctx->lut[R], lut_bytes(R), nullptr);
+        if (ctx->patterns[R]) dev_free(ctx, ctx->patterns[R], pattern_bytes(R), nullptr);
+    }
+    dev_free(ctx, ctx->counters, kQueueRing * 4, nullptr);
     delete ctx;
     return SC_OK;
 }
@@ -428,6 +453,7 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     a.nodes = scene->nodes;
     a.tris = scene->tris;
     a.lut = (I.mode != SC_MASK_NONE) ? scene->ctx->lut[I.R] : nullptr;
+    a.patterns = (I.mode != SC_MASK_NONE) ? scene->ctx->patterns[I.R] : nullptr;
     a.codebook = scene->codebook;
     a.side_masks = scene->side_masks;
     a.root = I.root_ref;
@@ -439,8 +465,28 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     a.extra = d_extra;
     a.slot_fp = d_slot_fp;
     if (a.mode == SC_MASK_SPARSE && I.n_masked == 0) a.mode = SC_MASK_NONE;
+    sc_ctx* ctx = scene->ctx;
+    a.queue = ctx->counters + (ctx->next_counter.fetch_add(1, std::memory_order_relaxed) % kQueueRing);
+    a.chunk = ctx->tune.chunk;
+    a.block = ctx->tune.block;
+    a.stack = ctx->tune.stack;
     const hipError_t e = launch_trace(a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "trace launch");
+    return SC_OK;
+}
+
+sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune) {
+    if (!ctx || !tune) return fail(SC_ERR_INVALID_ARG, "ctx and tune must be non-NULL");
+    if (!trace_config_supported(tune->block, tune->stack))
+        return fail(SC_ERR_UNSUPPORTED, "no traversal kernel for this (block, stack) pair");
+    if (tune->chunk < 1 || tune->chunk > 64) return fail(SC_ERR_INVALID_ARG, "chunk must be 1..64");
+    ctx->tune = *tune;
+    return SC_OK;
+}
+
+sc_status sc_get_tune(const sc_ctx* ctx, sc_tune* out) {
+    if (!ctx || !out) return fail(SC_ERR_INVALID_ARG, "ctx and out must be non-NULL");
+    *out = ctx->tune;
     return SC_OK;
 }
 
@@ -449,7 +495,10 @@ sc_status sc_raymask_lut(sc_ctx* ctx, uint32_t R, uint64_t* d_out, void* stream)
     if (R != 4 && R != 6) return fail(SC_ERR_INVALID_ARG, "R must be 4 or 6");
     sc_status st = use_device(ctx->device);
     if (st != SC_OK) return st;
-    const hipError_t e = launch_raymask_lut(R, d_out, static_cast<hipStream_t>(stream));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    st = ensure_lut(ctx, R, s);
+    if (st != SC_OK) return st;
+    const hipError_t e = launch_raymask_lut(R, ctx->patterns[R], d_out, s);
     return e == hipSuccess ? SC_OK : hip_fail(e, "ray-mask LUT kernel");
 }
 

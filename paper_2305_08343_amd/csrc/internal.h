@@ -58,7 +58,8 @@ struct TraceLaunch {
     uint32_t n;
     const unsigned char* nodes;
     const float* tris;          // kTriBytes records in leaf order
-    const uint64_t* lut;        // ray-mask LUT
+    const uint64_t* lut;        // full ray-mask LUT [R^6][W]
+    const uint64_t* patterns;   // displacement patterns [R(2R-1)^2][W]
     const uint64_t* codebook;   // LUT mode
     const uint64_t* side_masks; // SPARSE mode
     uint32_t root;
@@ -69,10 +70,20 @@ struct TraceLaunch {
     sc_hit* hits;
     uint32_t* extra;
     uint32_t* slot_fp;
+    uint32_t* queue;            // ray-queue counter for this launch (zeroed on the stream first)
+    uint32_t chunk;             // rays per queue fetch = 64 * chunk
+    uint32_t block, stack;      // threads per block, LDS stack entries per lane
 };
 
+// (block, stack) pairs with compiled traversal kernels.
+constexpr uint32_t kTraceConfigs[][2] = {{256, 8}, {128, 8}, {256, 12}, {256, 4}, {128, 16}};
+bool trace_config_supported(uint32_t block, uint32_t stack);
+constexpr uint32_t kQueueRing = 1024;  // launch counters per context
+
 hipError_t launch_trace(const TraceLaunch& a, hipStream_t s);
-hipError_t launch_raymask_lut(uint32_t R, uint64_t* out, hipStream_t s);
+hipError_t launch_raymask_patterns(uint32_t R, uint64_t* patterns, hipStream_t s);
+hipError_t launch_raymask_lut(uint32_t R, const uint64_t* patterns, uint64_t* out, hipStream_t s);
+inline size_t pattern_count(uint32_t R) { return (size_t)R * (2 * R - 1) * (2 * R - 1); }
 hipError_t launch_object_masks(uint32_t R, const float* tris_orig, const uint32_t* perm, uint32_t n,
                                const unsigned char* nodes, uint32_t node_stride,
                                const uint32_t* range, uint32_t root, float delta, uint64_t* masks,

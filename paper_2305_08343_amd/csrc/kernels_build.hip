@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "raymask.h"
 
 namespace sc {
 namespace {
@@ -14,24 +15,18 @@ namespace {
 constexpr int kWave = 64;
 
 // ---------------------------------------------------------------------------
-// Ray-mask LUT (Sect. 3.1.1, Alg. 1). Entry (beg, end) holds voxel v iff a
-// unit cell swept from cell beg to cell end overlaps v with positive volume
-// at some time s in [0,1]: per axis the overlap time set is the open
-// interval between (v-1-beg)/D and (v+1-beg)/D (D = end-beg != 0), or all
-// time when D = 0 and v = beg. Times are scaled by 60 so every bound is an
-// integer for R <= 6. One thread per key.
+// Ray masks (Sect. 3.1.1, Alg. 1). The LUT entry for cells (beg, end) holds
+// voxel v iff a unit cell swept from cell beg to cell end overlaps v with
+// positive volume at some time s in [0,1]: per axis the overlap times form
+// the open interval between (v-1-beg)/D and (v+1-beg)/D (D = end-beg != 0),
+// or all of [0,1] when D = 0 and v = beg. Times are scaled by 60 so every
+// bound is an integer for R <= 6.
 // ---------------------------------------------------------------------------
 template <int R>
-__global__ void raymask_lut_kernel(uint64_t* __restrict__ out) {
-    constexpr int R3 = R * R * R;
-    constexpr int W = (R3 + 63) / 64;
+__device__ void sweep_mask(const int* beg, const int* end, uint64_t* m) {
+    constexpr int W = (R * R * R + 63) / 64;
     constexpr int T = 60;
     constexpr int kBig = 1 << 20;
-    const int key = blockIdx.x * blockDim.x + threadIdx.x;
-    if (key >= R3 * R3) return;
-    const int kb = key / R3, ke = key % R3;
-    const int beg[3] = {kb / (R * R), (kb / R) % R, kb % R};
-    const int end[3] = {ke / (R * R), (ke / R) % R, ke % R};
     int tlo[3][R], thi[3][R];
     bool ok[3][R];
     for (int i = 0; i < 3; ++i) {
@@ -42,15 +37,14 @@ __global__ void raymask_lut_kernel(uint64_t* __restrict__ out) {
                 tlo[i][v] = -kBig;
                 thi[i][v] = kBig;
             } else {
-                int a = T * (v - 1 - beg[i]) / D;
-                int b = T * (v + 1 - beg[i]) / D;
+                const int a = T * (v - 1 - beg[i]) / D;
+                const int b = T * (v + 1 - beg[i]) / D;
                 tlo[i][v] = a < b ? a : b;
                 thi[i][v] = a < b ? b : a;
                 ok[i][v] = true;
             }
         }
     }
-    uint64_t m[W];
     for (int w = 0; w < W; ++w) m[w] = 0;
     for (int z = 0; z < R; ++z)
         for (int y = 0; y < R; ++y)
@@ -67,6 +61,39 @@ __global__ void raymask_lut_kernel(uint64_t* __restrict__ out) {
                     m[bit >> 6] |= 1ull << (bit & 63);
                 }
             }
+}
+
+// One thread per displacement (dx in [0,R-1], dy, dz in [-(R-1), R-1]):
+// the sweep of the cell pair with that displacement whose minimum corner is
+// the origin.
+template <int R>
+__global__ void raymask_pattern_kernel(uint64_t* __restrict__ out) {
+    constexpr int W = (R * R * R + 63) / 64;
+    constexpr int S = 2 * R - 1;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kPatterns<R>) return;
+    const int D[3] = {p / (S * S), (p / S) % S - (R - 1), p % S - (R - 1)};
+    int beg[3], end[3];
+    for (int i = 0; i < 3; ++i) {
+        beg[i] = D[i] < 0 ? -D[i] : 0;
+        end[i] = beg[i] + D[i];
+    }
+    uint64_t m[W];
+    sweep_mask<R>(beg, end, m);
+    for (int w = 0; w < W; ++w) out[(size_t)p * W + w] = m[w];
+}
+
+// The full R^6 table, expanded through the traversal's own pattern lookup;
+// key ((((bx*R+by)*R+bz)*R+ex)*R+ey)*R+ez.
+template <int R>
+__global__ void raymask_lut_kernel(const uint64_t* __restrict__ pat, uint64_t* __restrict__ out) {
+    constexpr int R3 = R * R * R;
+    constexpr int W = (R3 + 63) / 64;
+    const int key = blockIdx.x * blockDim.x + threadIdx.x;
+    if (key >= R3 * R3) return;
+    const int kb = key / R3, ke = key % R3;
+    uint64_t m[W];
+    ray_mask_from_patterns<R>(pat, kb / (R * R), (kb / R) % R, kb % R, ke / (R * R), (ke / R) % R, ke % R, m);
     for (int w = 0; w < W; ++w) out[(size_t)key * W + w] = m[w];
 }
 
@@ -307,10 +334,17 @@ inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n + b - 1)
 
 }  // namespace
 
-hipError_t launch_raymask_lut(uint32_t R, uint64_t* out, hipStream_t s) {
+hipError_t launch_raymask_patterns(uint32_t R, uint64_t* patterns, hipStream_t s) {
+    if (R == 4) hipLaunchKernelGGL(raymask_pattern_kernel<4>, dim3(blocks_for(kPatterns<4>, 64)), dim3(64), 0, s, patterns);
+    else if (R == 6) hipLaunchKernelGGL(raymask_pattern_kernel<6>, dim3(blocks_for(kPatterns<6>, 64)), dim3(64), 0, s, patterns);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_raymask_lut(uint32_t R, const uint64_t* patterns, uint64_t* out, hipStream_t s) {
     const size_t n = (size_t)R * R * R * R * R * R;
-    if (R == 4) hipLaunchKernelGGL(raymask_lut_kernel<4>, dim3(blocks_for(n, 256)), dim3(256), 0, s, out);
-    else if (R == 6) hipLaunchKernelGGL(raymask_lut_kernel<6>, dim3(blocks_for(n, 256)), dim3(256), 0, s, out);
+    if (R == 4) hipLaunchKernelGGL(raymask_lut_kernel<4>, dim3(blocks_for(n, 256)), dim3(256), 0, s, patterns, out);
+    else if (R == 6) hipLaunchKernelGGL(raymask_lut_kernel<6>, dim3(blocks_for(n, 256)), dim3(256), 0, s, patterns, out);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -1,17 +1,16 @@
 // Traversal with subspace culling (Alg. 4 with Alg. 1 and the mask AND of
 // Sect. 3.1.2) for gfx950.
 //
-// One lane per ray in wave64. Every ray runs the same canonical sequence as
-// the plain reference traversal, so hits and the per-ray test counts are
-// reproducible bit for bit:
+// Every ray runs the same canonical sequence as the plain reference
+// traversal, so hits and the per-ray test counts are reproducible bit for
+// bit:
 //  slab test of child box [lo, hi]: per axis x, y, z
 //      a = (lo - o) * inv, b = (hi - o) * inv, swap if a > b,
 //      b = b * (1 + 3*2^-23) (robust far value), t0 = (a > t0) ? a : t0,
 //      t1 = (b < t1) ? b : t1, from t0 = tmin, t1 = best_t; hit iff t0 <= t1
 //  ray mask (Alg. 1): for p = o + t*d at t0 and at t1, per axis
 //      s = R / (hi - lo) (0 if the extent is not positive or s is infinite),
-//      u = (p - lo) * s clamped to [0, R-1] (NaN -> 0), cell = (int)u;
-//      ray mask = LUT[(((((bx*R+by)*R+bz)*R+ex)*R+ey)*R+ez)]
+//      u = (p - lo) * s clamped to [0, R-1] (NaN -> 0), cell = (int)u
 //  culling: child survives iff (ray mask AND object mask) != 0; skipped for
 //      rays whose max|o| exceeds the scene's origin bound
 //  order: both children survive -> the one with the smaller t0 (tie: child
@@ -20,21 +19,34 @@
 //  leaf: Moller-Trumbore, two-sided, det == 0 rejects; accept t in
 //      [tmin, best_t]; replace iff t < best_t or (t == best_t and the
 //      original id is lower)
-// The next node of a lane is carried in registers instead of being pushed
-// and popped (its pop test could never fail: its t0 <= best_t by the slab
-// test), so the stack holds only postponed far children; it lives in LDS
-// (kLdsStack entries per lane) and spills the rest to private memory.
+//
+// Ray masks: R = 6 reads the R^6-entry table (1.42 MiB, resident in each
+// XCD's L2). R = 4 uses the table's translation invariance instead: the
+// entry for cells (b, e) is the pattern of the displacement e - b (x made
+// non-negative by the symmetry of the sweep) moved to the componentwise
+// minimum corner, so the 196 patterns (1.5 KiB) sit in LDS and the test is
+// ((object mask >> corner bit) AND pattern) != 0. Both give the table's bits.
+//
+// Scheduling: persistent waves fed by a global ray queue. A wave takes
+// 64*chunk consecutive rays at a time with one atomic add; whenever lanes
+// finish their ray they take the next unstarted ray (ballot + prefix count),
+// so lanes stay busy while the slowest rays of a wave finish. This changes
+// which lane runs a ray, never the ray's own sequence. The next node of a
+// lane stays in registers; postponed far children go to an LDS stack of
+// STACK entries per lane and spill to private memory beyond that.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "raymask.h"
 
 namespace sc {
 namespace {
 
-constexpr int kBlock = 128;
-constexpr int kLdsStack = 16;
+constexpr int kWave = 64;
 constexpr uint32_t kModeNone = SC_MASK_NONE, kModeRaw = SC_MASK_RAW, kModeLut = SC_MASK_LUT,
                    kModeSparse = SC_MASK_SPARSE;
+
+__global__ void reset_counter_kernel(uint32_t* c) { *c = 0u; }
 
 __device__ __forceinline__ float mx(float a, float b) { return (a > b) ? a : b; }
 
@@ -46,10 +58,14 @@ __device__ __forceinline__ bool ray_is_valid(float4 r0, float4 r1) {
 }
 
 template <int R>
-__device__ __forceinline__ int cell_of(float lo, float hi, float o, float d, float t) {
+__device__ __forceinline__ float grid_scale(float lo, float hi) {
     const float ext = hi - lo;
     float s = (ext > 0.0f) ? (float)R / ext : 0.0f;
-    if (isinf(s)) s = 0.0f;
+    return isinf(s) ? 0.0f : s;
+}
+
+template <int R>
+__device__ __forceinline__ int cell_of(float lo, float s, float o, float d, float t) {
     const float p = o + t * d;
     float u = (p - lo) * s;
     u = (u > 0.0f) ? u : 0.0f;
@@ -60,18 +76,6 @@ __device__ __forceinline__ int cell_of(float lo, float hi, float o, float d, flo
 struct Ray {
     float ox, oy, oz, dx, dy, dz, ix, iy, iz, tmin;
 };
-
-template <int R>
-__device__ __forceinline__ uint32_t lut_key(const float* lo, const float* hi, const Ray& r, float t0,
-                                            float t1) {
-    const int bx = cell_of<R>(lo[0], hi[0], r.ox, r.dx, t0);
-    const int by = cell_of<R>(lo[1], hi[1], r.oy, r.dy, t0);
-    const int bz = cell_of<R>(lo[2], hi[2], r.oz, r.dz, t0);
-    const int ex = cell_of<R>(lo[0], hi[0], r.ox, r.dx, t1);
-    const int ey = cell_of<R>(lo[1], hi[1], r.oy, r.dy, t1);
-    const int ez = cell_of<R>(lo[2], hi[2], r.oz, r.dz, t1);
-    return (uint32_t)(((((bx * R + by) * R + bz) * R + ex) * R + ey) * R + ez);
-}
 
 __device__ __forceinline__ void slab(const float* lo, const float* hi, const Ray& r, float tmax,
                                      float& t0, float& t1) {
@@ -94,57 +98,92 @@ __device__ __forceinline__ void slab(const float* lo, const float* hi, const Ray
     }
 }
 
-// Loads the W words of a mask; the layout keeps every mask 8-byte aligned
-// and, for W = 4, 32-byte aligned.
-template <int W>
-__device__ __forceinline__ void load_mask(const uint64_t* p, uint64_t* m) {
-    if constexpr (W == 4) {
-        const uint4 a = reinterpret_cast<const uint4*>(p)[0];
-        const uint4 b = reinterpret_cast<const uint4*>(p)[1];
-        m[0] = ((uint64_t)a.y << 32) | a.x;
-        m[1] = ((uint64_t)a.w << 32) | a.z;
-        m[2] = ((uint64_t)b.y << 32) | b.x;
-        m[3] = ((uint64_t)b.w << 32) | b.z;
-    } else {
-#pragma unroll
-        for (int w = 0; w < W; ++w) m[w] = p[w];
-    }
-}
-
-template <uint32_t MODE, int R>
-__global__ __launch_bounds__(kBlock) void trace_kernel(TraceLaunch a) {
+template <uint32_t MODE, int R, int BLOCK, int STACK>
+__global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
     constexpr int W = (R * R * R + 63) / 64;
     constexpr uint32_t kStride = (MODE == kModeRaw) ? kRawNodeBytes : kNodeBytes;
-    __shared__ uint2 lds_stack[kLdsStack * kBlock];
+    constexpr int kWavesPerBlock = BLOCK / kWave;
+    constexpr bool kPatLds = (R == 4) && (MODE != kModeNone);
+    __shared__ uint2 lds_stack[STACK * BLOCK];
+    __shared__ uint64_t lds_pat[kPatLds ? kPatterns<4> : 1];
 
     const uint32_t tid = threadIdx.x;
-    const uint32_t i = blockIdx.x * kBlock + tid;
-    if (i >= a.n) return;
-    const float4 r0 = reinterpret_cast<const float4*>(a.rays)[2 * (size_t)i];
-    const float4 r1 = reinterpret_cast<const float4*>(a.rays)[2 * (size_t)i + 1];
+    const uint32_t lane = tid & (kWave - 1);
+    if constexpr (kPatLds) {
+        for (int k = tid; k < kPatterns<4>; k += BLOCK) lds_pat[k] = a.patterns[k];
+        __syncthreads();
+    }
+    const uint64_t lanes_below = (1ull << lane) - 1ull;
+    const uint32_t chunk_rays = kWave * a.chunk;
+    const bool use_flags = (a.flags & (SC_TRACE_CULL | SC_TRACE_SHADOW)) != 0;
+    const bool cull = (a.flags & SC_TRACE_CULL) != 0;
+    const bool shadow = (a.flags & SC_TRACE_SHADOW) != 0 && a.slot_fp != nullptr;
 
-    uint32_t box_tests = 0, tri_tests = 0, mask_tests = 0, mask_culls = 0;
-    uint32_t best = kNoHit;
-    float best_t = __builtin_inff();
+    uint2 spill[kMaxDepth - STACK + 1];
 
-    if (ray_is_valid(r0, r1) && a.root != kEmptyRef) {
+    uint32_t cursor = 0, end = 0;  // wave-uniform range of unstarted rays
+    bool more = true;
+    // next range of rays for this wave from the queue; false when none is left
+    auto fetch = [&]() -> bool {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(a.queue, chunk_rays);
+        base = __shfl(base, 0, kWave);
+        if (base >= a.n) return false;
+        cursor = base;
+        end = min(a.n, base + chunk_rays);
+        return true;
+    };
+    {
+        bool has = false;
+        uint32_t ray_id = 0;
         Ray r;
-        r.ox = r0.x; r.oy = r0.y; r.oz = r0.z; r.tmin = r0.w;
-        r.dx = r1.x; r.dy = r1.y; r.dz = r1.z;
-        r.ix = 1.0f / r.dx; r.iy = 1.0f / r.dy; r.iz = 1.0f / r.dz;
-        best_t = r1.w;
+        float best_t = 0.0f;
+        uint32_t best = kNoHit, box_tests = 0, tri_tests = 0, mask_tests = 0, mask_culls = 0;
         bool use_mask = false;
-        if constexpr (MODE != kModeNone) {
-            use_mask = (a.flags & (SC_TRACE_CULL | SC_TRACE_SHADOW)) != 0 &&
-                       !(mx(mx(fabsf(r.ox), fabsf(r.oy)), fabsf(r.oz)) > a.origin_bound);
-        }
-        const bool cull = (a.flags & SC_TRACE_CULL) != 0;
-        const bool shadow = (a.flags & SC_TRACE_SHADOW) != 0 && a.slot_fp != nullptr;
-
-        uint2 spill[kMaxDepth - kLdsStack + 1];
         int sp = 0;
-        uint32_t ref = a.root;
+        uint32_t ref = 0;
         while (true) {
+            // refill idle lanes with unstarted rays
+            const uint64_t idle = __ballot(!has);
+            if (idle != 0) {
+                if (cursor >= end && more) more = fetch();
+                if (cursor < end) {
+                    if (!has) {
+                        const uint32_t id = cursor + (uint32_t)__popcll(idle & lanes_below);
+                        if (id < end) {
+                            const float4 r0 = reinterpret_cast<const float4*>(a.rays)[2 * (size_t)id];
+                            const float4 r1 = reinterpret_cast<const float4*>(a.rays)[2 * (size_t)id + 1];
+                            ray_id = id;
+                            if (ray_is_valid(r0, r1) && a.root != kEmptyRef) {
+                                r.ox = r0.x; r.oy = r0.y; r.oz = r0.z; r.tmin = r0.w;
+                                r.dx = r1.x; r.dy = r1.y; r.dz = r1.z;
+                                r.ix = 1.0f / r.dx; r.iy = 1.0f / r.dy; r.iz = 1.0f / r.dz;
+                                best_t = r1.w;
+                                best = kNoHit;
+                                box_tests = tri_tests = mask_tests = mask_culls = 0;
+                                use_mask = (MODE != kModeNone) && use_flags &&
+                                           !(mx(mx(fabsf(r.ox), fabsf(r.oy)), fabsf(r.oz)) > a.origin_bound);
+                                sp = 0;
+                                ref = a.root;
+                                has = true;
+                            } else {
+                                reinterpret_cast<uint4*>(a.hits)[id] =
+                                    make_uint4(kNoHit, __float_as_uint(__builtin_inff()), 0u, 0u);
+                                if (a.extra) reinterpret_cast<uint2*>(a.extra)[id] = make_uint2(0u, 0u);
+                            }
+                        }
+                    }
+                    cursor += (uint32_t)__popcll(idle);
+                }
+            }
+            if (__ballot(has) == 0) {
+                if (!more && cursor >= end) break;  // no ray left for this wave
+                continue;                           // every refilled ray finished at once (invalid rays)
+            }
+            if (!has) continue;
+
+            // one traversal step of this lane's ray
+            bool pop = true;
             if (ref & kLeafBit) {
                 const uint32_t first = ref & 0x1FFFFFFFu;
                 const uint32_t count = ((ref >> 29) & 3u) + 1u;
@@ -209,15 +248,40 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceLaunch a) {
                                 om = a.side_masks + (size_t)ms * W;
                             }
                             ++mask_tests;
-                            const uint32_t key = c ? lut_key<R>(lo1, hi1, r, t01, t11)
-                                                   : lut_key<R>(lo0, hi0, r, t00, t10);
-                            uint64_t rm[W], ob[W];
-                            load_mask<W>(a.lut + (size_t)key * W, rm);
+                            const float* lo = c ? lo1 : lo0;
+                            const float* hi = c ? hi1 : hi0;
+                            const float t0 = c ? t01 : t00, t1 = c ? t11 : t10;
+                            const float sx = grid_scale<R>(lo[0], hi[0]);
+                            const float sy = grid_scale<R>(lo[1], hi[1]);
+                            const float sz = grid_scale<R>(lo[2], hi[2]);
+                            const int bx = cell_of<R>(lo[0], sx, r.ox, r.dx, t0);
+                            const int by = cell_of<R>(lo[1], sy, r.oy, r.dy, t0);
+                            const int bz = cell_of<R>(lo[2], sz, r.oz, r.dz, t0);
+                            const int ex = cell_of<R>(lo[0], sx, r.ox, r.dx, t1);
+                            const int ey = cell_of<R>(lo[1], sy, r.oy, r.dy, t1);
+                            const int ez = cell_of<R>(lo[2], sz, r.oz, r.dz, t1);
+                            uint64_t ob[W];
                             load_mask<W>(om, ob);
-                            uint64_t any = 0;
+                            bool any;
+                            if constexpr (R == 4) {
+                                // displacement pattern (LDS) against the mask moved to its corner
+                                int qx = bx, qy = by, qz = bz, fx = ex, fy = ey, fz = ez;
+                                if (fx < qx) {
+                                    qx = ex; qy = ey; qz = ez; fx = bx; fy = by; fz = bz;
+                                }
+                                const int pidx = ((fx - qx) * 7 + (fy - qy + 3)) * 7 + (fz - qz + 3);
+                                const int my = qy < fy ? qy : fy, mz = qz < fz ? qz : fz;
+                                any = ((ob[0] >> (uint32_t)(qx + 4 * my + 16 * mz)) & lds_pat[pidx]) != 0;
+                            } else {
+                                const uint32_t key = (uint32_t)(((((bx * R + by) * R + bz) * R + ex) * R + ey) * R + ez);
+                                uint64_t rm[W];
+                                load_mask<W>(a.lut + (size_t)key * W, rm);
+                                uint64_t acc = 0;
 #pragma unroll
-                            for (int w = 0; w < W; ++w) any |= rm[w] & ob[w];
-                            if (any == 0) {
+                                for (int w = 0; w < W; ++w) acc |= rm[w] & ob[w];
+                                any = acc != 0;
+                            }
+                            if (!any) {
                                 ++mask_culls;
                                 if (shadow) atomicAdd(&a.slot_fp[2 * (size_t)ref + c], 1u);
                                 if (cull) {
@@ -230,61 +294,89 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceLaunch a) {
                 }
                 if (h0 && h1) {
                     const bool near1 = t01 < t00;
-                    const uint32_t far_ref = near1 ? n3.x : n3.y;
-                    const float far_t = near1 ? t00 : t01;
-                    const uint2 e = make_uint2(far_ref, __float_as_uint(far_t));
-                    if (sp < kLdsStack) lds_stack[sp * kBlock + tid] = e;
-                    else spill[sp - kLdsStack] = e;
+                    const uint2 e = make_uint2(near1 ? n3.x : n3.y, __float_as_uint(near1 ? t00 : t01));
+                    if (sp < STACK) lds_stack[sp * BLOCK + tid] = e;
+                    else spill[sp - STACK] = e;
                     ++sp;
                     ref = near1 ? n3.y : n3.x;
-                    continue;
+                    pop = false;
+                } else if (h0 || h1) {
+                    ref = h0 ? n3.x : n3.y;
+                    pop = false;
                 }
-                if (h0) { ref = n3.x; continue; }
-                if (h1) { ref = n3.y; continue; }
             }
-            // pop, dropping entries that start beyond the current closest hit
-            bool found = false;
-            while (sp > 0) {
-                --sp;
-                const uint2 e = (sp < kLdsStack) ? lds_stack[sp * kBlock + tid] : spill[sp - kLdsStack];
-                if (__uint_as_float(e.y) > best_t) continue;
-                ref = e.x;
-                found = true;
-                break;
+            if (pop) {
+                bool found = false;
+                while (sp > 0) {
+                    --sp;
+                    const uint2 e = (sp < STACK) ? lds_stack[sp * BLOCK + tid] : spill[sp - STACK];
+                    if (__uint_as_float(e.y) > best_t) continue;
+                    ref = e.x;
+                    found = true;
+                    break;
+                }
+                if (!found) {
+                    const float tout = (best == kNoHit) ? __builtin_inff() : best_t;
+                    reinterpret_cast<uint4*>(a.hits)[ray_id] =
+                        make_uint4(best, __float_as_uint(tout), box_tests, tri_tests);
+                    if (a.extra) reinterpret_cast<uint2*>(a.extra)[ray_id] = make_uint2(mask_tests, mask_culls);
+                    has = false;
+                }
             }
-            if (!found) break;
         }
     }
-    const float tout = (best == kNoHit) ? __builtin_inff() : best_t;
-    reinterpret_cast<uint4*>(a.hits)[i] = make_uint4(best, __float_as_uint(tout), box_tests, tri_tests);
-    if (a.extra) reinterpret_cast<uint2*>(a.extra)[i] = make_uint2(mask_tests, mask_culls);
+}
+
+template <uint32_t MODE, int R, int BLOCK, int STACK>
+hipError_t launch_one(const TraceLaunch& a, hipStream_t s) {
+    static int resident = 0;  // blocks resident on the whole device, computed once per instance
+    if (resident == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_kernel<MODE, R, BLOCK, STACK>, BLOCK, 0);
+        resident = (cus > 0 && per_cu > 0) ? cus * per_cu : 1024;
+    }
+    const uint32_t waves = (a.n + kWave - 1) / kWave;
+    uint32_t blocks = (waves + BLOCK / kWave - 1) / (BLOCK / kWave);
+    blocks = blocks < (uint32_t)resident ? blocks : (uint32_t)resident;
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, a.queue);
+    hipLaunchKernelGGL((trace_kernel<MODE, R, BLOCK, STACK>), dim3(blocks), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int BLOCK, int STACK>
+hipError_t launch_cfg(const TraceLaunch& a, hipStream_t s) {
+    switch (a.mode) {
+        case SC_MASK_NONE: return launch_one<kModeNone, 6, BLOCK, STACK>(a, s);
+        case SC_MASK_RAW:
+            return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK>(a, s) : launch_one<kModeRaw, 6, BLOCK, STACK>(a, s);
+        case SC_MASK_LUT:
+            return a.R == 4 ? launch_one<kModeLut, 4, BLOCK, STACK>(a, s) : launch_one<kModeLut, 6, BLOCK, STACK>(a, s);
+        case SC_MASK_SPARSE:
+            return a.R == 4 ? launch_one<kModeSparse, 4, BLOCK, STACK>(a, s)
+                            : launch_one<kModeSparse, 6, BLOCK, STACK>(a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
+bool trace_config_supported(uint32_t block, uint32_t stack) {
+    for (const auto& c : kTraceConfigs)
+        if (c[0] == block && c[1] == stack) return true;
+    return false;
+}
+
 hipError_t launch_trace(const TraceLaunch& a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    const dim3 grid((a.n + kBlock - 1) / kBlock), block(kBlock);
-    switch (a.mode) {
-        case SC_MASK_NONE:
-            hipLaunchKernelGGL((trace_kernel<kModeNone, 6>), grid, block, 0, s, a);
-            break;
-        case SC_MASK_RAW:
-            if (a.R == 4) hipLaunchKernelGGL((trace_kernel<kModeRaw, 4>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((trace_kernel<kModeRaw, 6>), grid, block, 0, s, a);
-            break;
-        case SC_MASK_LUT:
-            if (a.R == 4) hipLaunchKernelGGL((trace_kernel<kModeLut, 4>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((trace_kernel<kModeLut, 6>), grid, block, 0, s, a);
-            break;
-        case SC_MASK_SPARSE:
-            if (a.R == 4) hipLaunchKernelGGL((trace_kernel<kModeSparse, 4>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((trace_kernel<kModeSparse, 6>), grid, block, 0, s, a);
-            break;
-        default:
-            return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (a.chunk < 1 || !a.queue) return hipErrorInvalidValue;
+    if (a.block == 256 && a.stack == 8) return launch_cfg<256, 8>(a, s);
+    if (a.block == 128 && a.stack == 8) return launch_cfg<128, 8>(a, s);
+    if (a.block == 256 && a.stack == 12) return launch_cfg<256, 12>(a, s);
+    if (a.block == 256 && a.stack == 4) return launch_cfg<256, 4>(a, s);
+    if (a.block == 128 && a.stack == 16) return launch_cfg<128, 16>(a, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace sc

@@ -213,6 +213,51 @@ def test_degenerate_inputs(ctx, small_scene):
     torch.cuda.synchronize()
 
 
+def test_long_runs_of_invalid_rays(ctx, small_scene, small_oracle):
+    """Whole chunks of rays that finish at once must not end a wave early."""
+    from paper_2305_08343_amd import binding
+    tris, rays = small_scene
+    print("[gpu] runs of invalid rays", flush=True)
+    r = np.concatenate([_aimed(tris, 3000, 9), rays[:3000]])
+    bad = np.zeros(len(r), bool)
+    bad[100:1400] = True          # > 2 chunks of consecutive invalid rays
+    bad[2000:2070] = True
+    bad[4500::7] = True
+    r[bad, 4:7] = 0.0
+    s = binding.Scene(ctx, tris, mode="raw")
+    dev = s.trace(r).numpy()
+    ora = oracle.trace(tris, small_oracle["bvh"], r, mode="raw", R=6, masks=small_oracle["masks6"],
+                       origin_bound=small_oracle["origin_bound"])
+    _compare_hits(dev, ora)
+    assert (dev["box_tests"][bad] == 0).all() and (dev["box_tests"][~bad] > 0).any()
+    s.close()
+
+
+def test_every_launch_shape_gives_the_same_results(ctx, small_scene, small_oracle):
+    from paper_2305_08343_amd import binding
+    tris, rays = small_scene
+    r = np.concatenate([rays, _aimed(tris, 20000, 10)])
+    ora = oracle.trace(tris, small_oracle["bvh"], r, mode="raw", R=6, masks=small_oracle["masks6"],
+                       origin_bound=small_oracle["origin_bound"])
+    ora4 = oracle.trace(tris, small_oracle["bvh"], r, mode="raw", R=4, masks=small_oracle["masks4"],
+                        origin_bound=small_oracle["origin_bound"])
+    s6 = binding.Scene(ctx, tris, R=6, mode="raw")
+    s4 = binding.Scene(ctx, tris, R=4, mode="raw")
+    try:
+        for block, stack in ((256, 8), (128, 8), (256, 12), (256, 4), (128, 16)):
+            for chunk in (1, 3, 64):
+                print(f"[gpu] tune block={block} stack={stack} chunk={chunk}", flush=True)
+                ctx.set_tune(block, stack, chunk)
+                _compare_hits(s6.trace(r).numpy(), ora)
+                _compare_hits(s4.trace(r).numpy(), ora4)
+        with pytest.raises(binding.SubcullError):
+            ctx.set_tune(64, 8, 1)
+    finally:
+        ctx.set_tune(256, 8, 1)
+        s6.close()
+        s4.close()
+
+
 def test_repeat_trace_is_deterministic(ctx, small_scene):
     from paper_2305_08343_amd import binding
     tris, rays = small_scene
