@@ -161,6 +161,14 @@ sc_status sc_destroy(sc_ctx* ctx); /* NULL-safe */
 sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_build_params* params,
                          void* stream, sc_scene** out);
 sc_status sc_scene_destroy(sc_scene* scene); /* NULL-safe */
+
+/* Step 1 of sc_scene_build alone, on the host (no device needed): the binned
+ * SAH BVH of `n` host triangles (float32 [n][3][3]) under params' leaf_max,
+ * sah_bins and depth_cap. out->cbox/cref/range must hold max(n,1) nodes and
+ * out->perm n entries (masks, codebook, cidx are ignored). info receives
+ * n_inner, depth and root_ref (other fields zero). Errors as sc_scene_build. */
+sc_status sc_bvh_build_host(const float* h_tris, uint32_t n, const sc_build_params* params,
+                            sc_scene_host* out, sc_scene_info* info);
 sc_status sc_scene_get_info(const sc_scene* scene, sc_scene_info* out);
 
 /* Copy the scene's BVH, masks and codebook into caller host buffers

@@ -246,3 +246,18 @@ def ray_mask(lo, hi, o, d, t0, t1, R, lut):
     _check(lib().orc_ray_mask(_p(f(lo)), _p(f(hi)), _p(f(o)), _p(f(d)), C.c_float(t0),
                               C.c_float(t1), C.c_uint32(R), _p(lut), _p(out)), "ray_mask")
     return out
+
+
+def slot_masks(tris, bvh: BVH, slots, R, delta, nthreads=0):
+    """Object masks of the given child slots only -> uint64 [len(slots), W]."""
+    slots = np.ascontiguousarray(slots, np.uint32)
+    out = np.zeros((max(slots.size, 1), words_for(R)), np.uint64)
+    _check(lib().orc_slot_masks(_p(np.ascontiguousarray(tris, np.float32)), _p(bvh.perm), _p(bvh.cbox),
+                                _p(bvh.cref), _p(bvh.range), _p(slots), C.c_uint32(slots.size),
+                                C.c_uint32(R), C.c_float(delta), _p(out), C.c_int(nthreads)), "slot_masks")
+    return out[:slots.size]
+
+
+def cpu_threads() -> int:
+    import os as _os
+    return len(_os.sched_getaffinity(0))

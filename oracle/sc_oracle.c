@@ -843,3 +843,26 @@ int orc_ray_mask(const float* lo, const float* hi, const float* o, const float* 
     for (uint32_t w = 0; w < W; ++w) out[w] = lut[key * W + w];
     return ORC_OK;
 }
+
+/* Object masks of selected child slots only: out[i*W..] for slots[i]. */
+int orc_slot_masks(const float* tris, const uint32_t* perm, const float* cbox, const uint32_t* cref,
+                   const uint32_t* range, const uint32_t* slots, uint32_t nslots, uint32_t R, float delta,
+                   uint64_t* out, int nthreads) {
+    if (R < 1 || R > 6) return ORC_ERR_ARG;
+    uint32_t W = words_for(R);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t i = 0; i < (int64_t)nslots; ++i) {
+        uint32_t s = slots[i];
+        uint64_t* m = &out[(size_t)i * W];
+        for (uint32_t w = 0; w < W; ++w) m[w] = 0;
+        const float* bx = &cbox[12 * (size_t)(s >> 1) + 6 * (size_t)(s & 1)];
+        uint32_t first, count;
+        slot_range(cref, range, s, &first, &count);
+        for (uint32_t j = first; j < first + count; ++j)
+            voxelize_tri(&tris[9 * (size_t)perm[j]], bx, bx + 3, R, delta, m);
+    }
+    return ORC_OK;
+}

@@ -70,6 +70,8 @@ _SIGS = {
     "sc_scene_build": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(sc_build_params),
                                  C.c_void_p, C.POINTER(C.c_void_p)]),
     "sc_scene_destroy": (C.c_int, [C.c_void_p]),
+    "sc_bvh_build_host": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(sc_build_params),
+                                    C.POINTER(sc_scene_host), C.POINTER(sc_scene_info)]),
     "sc_scene_get_info": (C.c_int, [C.c_void_p, C.POINTER(sc_scene_info)]),
     "sc_scene_export": (C.c_int, [C.c_void_p, C.POINTER(sc_scene_host)]),
     "sc_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p,
@@ -187,6 +189,27 @@ class Context:
         _check(load().sc_compress_masks(self.handle, R, _ptr(cb), codebook.shape[0], _ptr(m), n,
                                         _ptr(idx), _stream_ptr(stream)), "sc_compress_masks")
         return idx[:n].cpu().numpy().view(np.uint16)
+
+
+def bvh_build_host(tris, leaf_max: int = 4, bins: int = 32, depth_cap: int = 64) -> dict:
+    """The library's host BVH builder alone (no device): cbox, cref, range, perm, depth, root."""
+    lib = load()
+    tris = np.ascontiguousarray(tris, np.float32)
+    n = tris.shape[0]
+    m = max(n, 1)
+    out = {"cbox": np.zeros((m, 12), np.float32), "cref": np.zeros((m, 2), np.uint32),
+           "range": np.zeros((m, 2), np.uint32), "perm": np.zeros(m, np.uint32)}
+    hs = sc_scene_host(*(out[k].ctypes.data_as(C.c_void_p) for k in ("cbox", "cref", "range", "perm")),
+                       None, None, None)
+    p = sc_build_params()
+    lib.sc_build_params_default(C.byref(p))
+    p.leaf_max, p.sah_bins, p.depth_cap = leaf_max, bins, depth_cap
+    info = sc_scene_info()
+    _check(lib.sc_bvh_build_host(tris.ctypes.data_as(C.c_void_p), n, C.byref(p), C.byref(hs),
+                                 C.byref(info)), "sc_bvh_build_host")
+    ni = info.n_inner
+    return {"cbox": out["cbox"][:ni], "cref": out["cref"][:ni], "range": out["range"][:ni],
+            "perm": out["perm"][:n], "n_inner": ni, "depth": info.depth, "root": info.root_ref}
 
 
 @dataclass

@@ -396,6 +396,31 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
     return SC_OK;
 }
 
+sc_status sc_bvh_build_host(const float* h_tris, uint32_t n, const sc_build_params* params,
+                            sc_scene_host* out, sc_scene_info* info) {
+    if (!params || !out || !info || (n > 0 && !h_tris)) return fail(SC_ERR_INVALID_ARG, "NULL argument");
+    if (n > 0 && (!out->cbox || !out->cref || !out->range || !out->perm))
+        return fail(SC_ERR_INVALID_ARG, "cbox, cref, range and perm are required");
+    if (n >= (1u << 29)) return fail(SC_ERR_INVALID_ARG, "at most 2^29-1 triangles");
+    std::string why;
+    if (!check_params(*params, why)) return fail(SC_ERR_INVALID_ARG, why);
+    for (size_t i = 0; i < 9 * (size_t)n; ++i)
+        if (!std::isfinite(h_tris[i])) return fail(SC_ERR_INVALID_ARG, "non-finite triangle vertex");
+    HostBVH B;
+    const sc_status st = build_bvh(h_tris, n, params->leaf_max, params->sah_bins, params->depth_cap, B);
+    if (st != SC_OK) return fail(st, st == SC_ERR_DEPTH ? "BVH deeper than depth_cap" : "BVH build failed");
+    std::memset(info, 0, sizeof(*info));
+    info->n_tris = n;
+    info->n_inner = B.n_inner;
+    info->depth = B.depth;
+    info->root_ref = B.root;
+    if (!B.cbox.empty()) std::memcpy(out->cbox, B.cbox.data(), B.cbox.size() * 4);
+    if (!B.cref.empty()) std::memcpy(out->cref, B.cref.data(), B.cref.size() * 4);
+    if (!B.range.empty()) std::memcpy(out->range, B.range.data(), B.range.size() * 4);
+    if (!B.perm.empty()) std::memcpy(out->perm, B.perm.data(), B.perm.size() * 4);
+    return SC_OK;
+}
+
 sc_status sc_scene_destroy(sc_scene* scene) {
     if (!scene) return SC_OK;
     (void)use_device(scene->ctx->device);

@@ -21,9 +21,16 @@
 //  - no candidate: split at count/2 in current order
 //  - stable partition, left child first, inner nodes numbered in DFS
 //    pre-order, triangles end in leaf order
+// Large right subtrees are built on other threads into fragments with local
+// node numbers and appended after the left subtree, which reproduces the
+// sequential numbering exactly.
 #include <cmath>
 #include <cstring>
+#include <future>
 #include <limits>
+#include <system_error>
+#include <thread>
+#include <atomic>
 
 #include "internal.h"
 
@@ -57,15 +64,37 @@ struct Aabb {
     }
 };
 
+// Nodes of one subtree, numbered from 0 in DFS pre-order.
+struct Fragment {
+    uint32_t n_inner = 0;
+    uint32_t depth = 0;
+    std::vector<float> cbox;
+    std::vector<uint32_t> cref, range;
+
+    // Append `g` (a subtree built separately); returns its root ref renumbered.
+    uint32_t append(Fragment&& g, uint32_t g_root) {
+        const uint32_t off = n_inner;
+        for (uint32_t& r : g.cref)
+            if (!(r & kLeafBit)) r += off;
+        cbox.insert(cbox.end(), g.cbox.begin(), g.cbox.end());
+        cref.insert(cref.end(), g.cref.begin(), g.cref.end());
+        range.insert(range.end(), g.range.begin(), g.range.end());
+        n_inner += g.n_inner;
+        depth = depth > g.depth ? depth : g.depth;
+        return (g_root & kLeafBit) ? g_root : g_root + off;
+    }
+};
+
 class Builder {
   public:
-    Builder(uint32_t leaf_max, uint32_t bins, uint32_t depth_cap, HostBVH& out)
-        : leaf_max_(leaf_max), bins_(bins), depth_cap_(depth_cap), out_(out) {}
+    Builder(uint32_t leaf_max, uint32_t bins, uint32_t depth_cap)
+        : leaf_max_(leaf_max), bins_(bins), depth_cap_(depth_cap) {}
 
     std::vector<Item> items, scratch;
-    sc_status status = SC_OK;
+    std::atomic<int> status{SC_OK};
+    std::atomic<int> spare_threads{0};
 
-    uint32_t build(uint32_t b, uint32_t e, uint32_t level, Aabb& box) {
+    uint32_t build(Fragment& F, uint32_t b, uint32_t e, uint32_t level, Aabb& box) {
         box.reset();
         for (uint32_t i = b; i < e; ++i) box.grow(items[i].lo, items[i].hi);
         const uint32_t count = e - b;
@@ -74,31 +103,43 @@ class Builder {
             status = SC_ERR_DEPTH;
             return 0;
         }
-        if (level > out_.depth) out_.depth = level;
-        const uint32_t node = out_.n_inner++;
-        out_.range.push_back(b);
-        out_.range.push_back(count);
-        out_.cbox.resize(12 * (size_t)out_.n_inner);
-        out_.cref.resize(2 * (size_t)out_.n_inner);
+        if (level > F.depth) F.depth = level;
+        const uint32_t node = F.n_inner++;
+        F.range.push_back(b);
+        F.range.push_back(count);
+        F.cbox.resize(12 * (size_t)F.n_inner);
+        F.cref.resize(2 * (size_t)F.n_inner);
 
         const uint32_t mid = choose_and_partition(b, e);
 
         Aabb lb, rb;
-        const uint32_t l = build(b, mid, level + 1, lb);
-        if (status != SC_OK) return 0;
-        const uint32_t r = build(mid, e, level + 1, rb);
-        if (status != SC_OK) return 0;
-        float* dst = &out_.cbox[12 * (size_t)node];
+        uint32_t l, r;
+        if (e - mid >= kParallelMin && spare_threads.fetch_sub(1) > 0) {
+            Fragment G;
+            auto right = std::async(std::launch::async, [&] { return build(G, mid, e, level + 1, rb); });
+            l = build(F, b, mid, level + 1, lb);
+            const uint32_t g_root = right.get();
+            if (status != SC_OK) return 0;
+            r = F.append(std::move(G), g_root);
+        } else {
+            l = build(F, b, mid, level + 1, lb);
+            if (status != SC_OK) return 0;
+            r = build(F, mid, e, level + 1, rb);
+            if (status != SC_OK) return 0;
+        }
+        float* dst = &F.cbox[12 * (size_t)node];
         std::memcpy(dst, lb.lo, 12);
         std::memcpy(dst + 3, lb.hi, 12);
         std::memcpy(dst + 6, rb.lo, 12);
         std::memcpy(dst + 9, rb.hi, 12);
-        out_.cref[2 * (size_t)node] = l;
-        out_.cref[2 * (size_t)node + 1] = r;
+        F.cref[2 * (size_t)node] = l;
+        F.cref[2 * (size_t)node + 1] = r;
         return node;
     }
 
   private:
+    static constexpr uint32_t kParallelMin = 1u << 16;
+
     uint32_t bin_of(float c, float lo, float scale) const {
         const float f = (c - lo) * scale;
         if (f >= (float)(bins_ - 1)) return bins_ - 1;
@@ -173,7 +214,6 @@ class Builder {
     }
 
     uint32_t leaf_max_, bins_, depth_cap_;
-    HostBVH& out_;
 };
 
 }  // namespace
@@ -183,10 +223,11 @@ sc_status build_bvh(const float* tris, uint32_t n, uint32_t leaf_max, uint32_t b
     out = HostBVH();
     if (n == 0) return SC_OK;
     try {
-        Builder B(leaf_max, bins, depth_cap, out);
+        Builder B(leaf_max, bins, depth_cap);
+        const unsigned hw = std::thread::hardware_concurrency();
+        B.spare_threads = (int)(hw > 1 ? (hw < 64 ? hw : 64) - 1 : 0);
         B.items.resize(n);
         B.scratch.resize(n);
-        out.range.reserve(2 * (size_t)n / 2);
         for (uint32_t t = 0; t < n; ++t) {
             const float* v = tris + 9 * (size_t)t;
             Item& it = B.items[t];
@@ -202,16 +243,25 @@ sc_status build_bvh(const float* tris, uint32_t n, uint32_t leaf_max, uint32_t b
             }
             it.id = t;
         }
+        Fragment F;
         Aabb root_box;
-        const uint32_t root = B.build(0, n, 1, root_box);
+        const uint32_t root = B.build(F, 0, n, 1, root_box);
         if (B.status != SC_OK) {
             out = HostBVH();
-            return B.status;
+            return (sc_status)B.status.load();
         }
+        out.n_inner = F.n_inner;
+        out.depth = F.depth;
         out.root = root;
+        out.cbox = std::move(F.cbox);
+        out.cref = std::move(F.cref);
+        out.range = std::move(F.range);
         out.perm.resize(n);
         for (uint32_t i = 0; i < n; ++i) out.perm[i] = B.items[i].id;
     } catch (const std::bad_alloc&) {
+        out = HostBVH();
+        return SC_ERR_OOM;
+    } catch (const std::system_error&) {
         out = HostBVH();
         return SC_ERR_OOM;
     }

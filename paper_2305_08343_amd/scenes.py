@@ -134,10 +134,10 @@ def strands_helical(seed: int, n_strands: int, n_seg: int, width: float, curl: f
     bn = _unit(np.cross(_unit(tan), radial))
     half = 0.5 * width
     pa, pb = c + half * bn, c - half * bn
-    t0 = np.stack([pa[:, :-1], pb[:, :-1], pa[:, 1:]], 2)
-    t1 = np.stack([pb[:, :-1], pb[:, 1:], pa[:, 1:]], 2)
-    tri = np.stack([t0, t1], 2)  # [S, K, 2, 3, 3]
-    return tri.reshape(-1, 3, 3).astype(np.float32)
+    tri = np.empty((n_strands, n_seg, 2, 3, 3), np.float32)  # rounded once on assignment
+    tri[:, :, 0, 0], tri[:, :, 0, 1], tri[:, :, 0, 2] = pa[:, :-1], pb[:, :-1], pa[:, 1:]
+    tri[:, :, 1, 0], tri[:, :, 1, 1], tri[:, :, 1, 2] = pb[:, :-1], pb[:, 1:], pa[:, 1:]
+    return tri.reshape(-1, 3, 3)
 
 
 def ground_plane(y: float = 0.0, lo: float = -1.0, hi: float = 2.0) -> np.ndarray:
@@ -213,14 +213,15 @@ def surface_bounce_rays(tris: np.ndarray, n: int, seed: int, offset: float = 2.0
     Degenerate (zero-area) triangles are skipped by resampling.
     """
     rng = np.random.default_rng(seed)
-    t64 = tris.astype(np.float64)
     idx = rng.integers(0, tris.shape[0], n)
-    nrm = np.cross(t64[idx, 1] - t64[idx, 0], t64[idx, 2] - t64[idx, 0])
+    v = tris[idx].astype(np.float64)  # [n, 3, 3] picked triangles only
+    nrm = np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0])
     ln = np.linalg.norm(nrm, axis=-1)
     bad = ln == 0
     while bad.any():  # resample degenerate picks
         idx[bad] = rng.integers(0, tris.shape[0], int(bad.sum()))
-        nrm = np.cross(t64[idx, 1] - t64[idx, 0], t64[idx, 2] - t64[idx, 0])
+        v[bad] = tris[idx[bad]].astype(np.float64)
+        nrm = np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0])
         ln = np.linalg.norm(nrm, axis=-1)
         bad = ln == 0
     nrm = nrm / ln[:, None]
@@ -229,7 +230,7 @@ def surface_bounce_rays(tris: np.ndarray, n: int, seed: int, offset: float = 2.0
     r1, r2 = rng.random(n), rng.random(n)
     su = np.sqrt(r1)
     b0, b1, b2 = 1.0 - su, su * (1.0 - r2), su * r2
-    p = b0[:, None] * t64[idx, 0] + b1[:, None] * t64[idx, 1] + b2[:, None] * t64[idx, 2]
+    p = b0[:, None] * v[:, 0] + b1[:, None] * v[:, 1] + b2[:, None] * v[:, 2]
     e1, e2 = _perp_basis(nrm)
     r, phi = rng.random(n), rng.uniform(0.0, 2 * math.pi, n)
     sr = np.sqrt(r)

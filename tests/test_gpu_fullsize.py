@@ -1,0 +1,185 @@
+"""GPU parity at the full workload sizes, in the launch configuration bench.py times.
+
+hair_1m (1,000,002 tris, 4,147,200 rays): BVH, masks (R = 4, 6), codebook and
+indices, and every ray's hit/t/counts in the plain, raw R = 6, raw R = 4 and
+compressed modes, all bit-exact against the oracle.
+
+curly_12m (12,000,000 tris, 8,000,000 rays): BVH bit-exact; masks of a slot
+sample; every 64th ray bit-exact in every mode (oracle with all masks); and on
+all 8M rays the properties that hold at any size: culled hits equal unculled
+hits, per-ray counts none >= compressed >= raw, every stored codebook entry
+contains its slot's exact mask.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_08343_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(request, msg):
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+    with capman.global_and_fixture_disabled():
+        print(f"[gpu-full] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2305_08343_amd import binding
+    c = binding.Context(0)  # default launch shape, as in bench.py
+    yield c
+    c.close()
+
+
+def _compare(dev, ora, sel=None):
+    sel = slice(None) if sel is None else sel
+    for k, o in (("prim", ora.prim), ("box_tests", ora.box_tests), ("tri_tests", ora.tri_tests),
+                 ("mask_tests", ora.mask_tests), ("mask_culls", ora.mask_culls)):
+        d = dev[k][sel]
+        bad = np.flatnonzero(d != o)
+        assert bad.size == 0, f"{k}: {bad.size} rays differ, first {bad[:5]}"
+    assert (dev["t"][sel].view(np.uint32) == ora.t.view(np.uint32)).all()
+
+
+def _superset(big, small):
+    return ((small & ~big) == 0).all(axis=-1)
+
+
+# --------------------------------------------------------------------- hair_1m
+@pytest.fixture(scope="module")
+def hair(request):
+    _say(request, "hair_1m: generating scene and rays")
+    tris = scenes.scene_hair_1m(1)
+    rays = scenes.rays_hair_1m(tris, 1)
+    nt = oracle.cpu_threads()
+    _say(request, f"hair_1m: oracle BVH + masks on {nt} threads")
+    bvh = oracle.bvh_build(tris)
+    ob, delta = oracle.default_bounds(tris)
+    return {"tris": tris, "rays": rays, "bvh": bvh, "ob": ob, "delta": delta, "nt": nt,
+            "masks4": oracle.object_masks(tris, bvh, 4, delta, nthreads=nt),
+            "masks6": oracle.object_masks(tris, bvh, 6, delta, nthreads=nt)}
+
+
+@pytest.mark.timeout(600)
+def test_hair_1m_all_rays_bit_exact(request, ctx, hair):
+    from paper_2305_08343_amd import binding
+    tris, rays, bvh = hair["tris"], hair["rays"], hair["bvh"]
+    for mode, R in (("none", 6), ("raw", 6), ("raw", 4)):
+        _say(request, f"hair_1m mode={mode} R={R}: build, export, trace {rays.shape[0]} rays")
+        s = binding.Scene(ctx, tris, R=R, mode=mode)
+        exp = s.export()
+        assert (exp["cbox"].view(np.uint32) == bvh.cbox.view(np.uint32)).all()
+        assert (exp["cref"] == bvh.cref).all() and (exp["perm"] == bvh.perm).all()
+        kw = dict(origin_bound=hair["ob"], nthreads=hair["nt"])
+        if mode == "raw":
+            assert (exp["masks"] == hair[f"masks{R}"]).all()
+            kw.update(mode="raw", R=R, masks=hair[f"masks{R}"])
+        dev = s.trace(rays).numpy()
+        s.close()
+        _compare(dev, oracle.trace(tris, bvh, rays, **kw))
+
+
+@pytest.mark.timeout(600)
+def test_hair_1m_compressed_bit_exact(request, ctx, hair):
+    from paper_2305_08343_amd import binding
+    tris, rays, bvh = hair["tris"], hair["rays"], hair["bvh"]
+    _say(request, "hair_1m compressed K=4096: codebook, indices, every 2nd ray")
+    s = binding.Scene(ctx, tris, R=6, mode="lut", K=4096)
+    exp = s.export()
+    cb, idx = oracle.compress(hair["masks6"], bvh.slot_boxes(), 6, 4096)
+    assert (exp["codebook"] == cb).all() and (exp["cidx"] == idx).all()
+    sel = rays[::2]
+    dev = s.trace(sel).numpy()
+    s.close()
+    _compare(dev, oracle.trace(tris, bvh, sel, mode="lut", R=6, codebook=cb, cidx=idx,
+                               origin_bound=hair["ob"], nthreads=hair["nt"]))
+
+
+# ------------------------------------------------------------------- curly_12m
+@pytest.fixture(scope="module")
+def curly(request):
+    _say(request, "curly_12m: generating 12M tris, 8M rays")
+    tris = scenes.scene_curly_12m(2)
+    rays = scenes.rays_curly_12m(tris)
+    nt = oracle.cpu_threads()
+    _say(request, f"curly_12m: oracle BVH on {nt} threads")
+    bvh = oracle.bvh_build(tris)
+    ob, delta = oracle.default_bounds(tris)
+    return {"tris": tris, "rays": rays, "bvh": bvh, "ob": ob, "delta": delta, "nt": nt}
+
+
+@pytest.fixture(scope="module")
+def curly_dev(request, ctx, curly):
+    """Device results for all 8M rays in the three modes, plus exports."""
+    from paper_2305_08343_amd import binding
+    out = {}
+    for mode, R in (("none", 6), ("lut", 6), ("raw", 6)):
+        _say(request, f"curly_12m mode={mode}: device build + trace of 8M rays")
+        s = binding.Scene(ctx, curly["tris"], R=R, mode=mode, K=4096)
+        out[mode] = s.trace(curly["rays"]).numpy()
+        if mode != "none":
+            e = s.export()
+            out[f"export_{mode}"] = {k: e[k] for k in ("masks", "codebook", "cidx")}
+        else:
+            out["export_none"] = s.export()
+        s.close()
+    return out
+
+
+@pytest.mark.timeout(900)
+def test_curly_12m_bvh_and_sampled_masks(request, curly, curly_dev):
+    bvh = curly["bvh"]
+    exp = curly_dev["export_none"]
+    _say(request, "curly_12m: BVH export vs oracle")
+    assert exp["cbox"].shape == bvh.cbox.shape
+    assert (exp["cbox"].view(np.uint32) == bvh.cbox.view(np.uint32)).all()
+    assert (exp["cref"] == bvh.cref).all() and (exp["range"] == bvh.range).all()
+    assert (exp["perm"] == bvh.perm).all()
+    rng = np.random.default_rng(0)
+    S = 2 * bvh.n_inner
+    slots = np.unique(np.concatenate([rng.integers(0, S, 3000), np.arange(8)]))
+    _say(request, f"curly_12m: oracle masks of {slots.size} sampled slots")
+    m = oracle.slot_masks(curly["tris"], bvh, slots, 6, curly["delta"], nthreads=curly["nt"])
+    assert (curly_dev["export_raw"]["masks"][slots] == m).all()
+    assert (curly_dev["export_lut"]["masks"][slots] == m).all()
+
+
+@pytest.mark.timeout(900)
+def test_curly_12m_properties_all_rays(request, curly_dev):
+    _say(request, "curly_12m: properties over all 8M rays")
+    n, l, r = curly_dev["none"], curly_dev["lut"], curly_dev["raw"]
+    for d in (l, r):
+        assert (d["prim"] == n["prim"]).all()
+        assert (d["t"].view(np.uint32) == n["t"].view(np.uint32)).all()
+    for f in ("box_tests", "tri_tests"):
+        assert (n[f] >= l[f]).all() and (l[f] >= r[f]).all()
+    assert (r["mask_culls"] <= r["mask_tests"]).all()
+    e = curly_dev["export_lut"]
+    assert _superset(e["codebook"][e["cidx"]], e["masks"]).all()
+    pc = np.unpackbits(e["codebook"].view(np.uint8), axis=1).sum(1)
+    assert (np.diff(pc) >= 0).all()
+
+
+@pytest.mark.timeout(900)
+def test_curly_12m_sampled_rays_bit_exact(request, curly, curly_dev):
+    tris, bvh, rays = curly["tris"], curly["bvh"], curly["rays"]
+    sel = slice(None, None, 64)
+    sample = rays[sel]
+    _say(request, f"curly_12m: oracle traces of {sample.shape[0]} sampled rays, plain")
+    _compare(curly_dev["none"], oracle.trace(tris, bvh, sample, origin_bound=curly["ob"],
+                                             nthreads=curly["nt"]), sel)
+    _say(request, "curly_12m: oracle masks (all slots) for the masked modes")
+    masks = oracle.object_masks(tris, bvh, 6, curly["delta"], nthreads=curly["nt"])
+    assert (curly_dev["export_raw"]["masks"] == masks).all()
+    _compare(curly_dev["raw"], oracle.trace(tris, bvh, sample, mode="raw", R=6, masks=masks,
+                                            origin_bound=curly["ob"], nthreads=curly["nt"]), sel)
+    _say(request, "curly_12m: oracle codebook K=4096 + Alg. 3")
+    cb, idx = oracle.compress(masks, bvh.slot_boxes(), 6, 4096)
+    assert (curly_dev["export_lut"]["codebook"] == cb).all()
+    assert (curly_dev["export_lut"]["cidx"] == idx).all()
+    _compare(curly_dev["lut"], oracle.trace(tris, bvh, sample, mode="lut", R=6, codebook=cb, cidx=idx,
+                                            origin_bound=curly["ob"], nthreads=curly["nt"]), sel)
