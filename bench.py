@@ -29,12 +29,27 @@ METRIC = "rays/sec and node+triangle tests/ray, culled vs unculled, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
 RAY_BYTES, HIT_BYTES, EXTRA_BYTES, TRI_BYTES = 32, 16, 8, 48
 
+# HBM-side bytes per trace launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, each scaled by the
+# same counter's reading for a 1 GiB plain copy (FETCH x2.0, WRITE x1.0). Valid only for the traversal
+# kernel source whose SHA-256 starts with this prefix; otherwise traffic is reported as null.
+MEASURED_TRAFFIC = {"source_sha256_16": "76033640edab544d", "raw6": 20.466e9, "none": 20.773e9}
+TRACE_SOURCE = os.path.join(ROOT, "paper_2305_08343_amd", "csrc", "kernels_trace.hip")
+
 MODES = {
     "raw6": dict(mode="raw", R=6, cull=True, node_bytes=128),
     "none": dict(mode="none", R=6, cull=False, node_bytes=64),
     "raw4": dict(mode="raw", R=4, cull=True, node_bytes=128),
     "lut6": dict(mode="lut", R=6, cull=True, node_bytes=64, K=4096),
 }
+
+
+def measured_traffic(mode):
+    import hashlib
+    with open(TRACE_SOURCE, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    if h != MEASURED_TRAFFIC["source_sha256_16"]:
+        return None
+    return MEASURED_TRAFFIC.get(mode)
 
 
 def log(msg):
@@ -134,6 +149,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tune", default="", help="block,stack,chunk of the traversal launch")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
@@ -183,12 +200,19 @@ def main():
                                f"mode {head}", "n_tris": int(tris.shape[0]), "n_rays": int(rays.shape[0])},
         "tests_per_ray": r["tests_per_ray"],
         "roofline": {"bound": "hbm", "achieved": r["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r["alg_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": r["alg_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(head),
                      "kernel": "trace_kernel", "kernel_ms": r["kernel_ms_mean"],
                      "alg_bytes_per_launch": r["alg_bytes_per_launch"]},
         "modes": results,
         "tune": ctx.get_tune(),
     }
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib * 2 ** 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_probe_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(tris, rays, args.cpu_seconds)
