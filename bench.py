@@ -40,6 +40,8 @@ MODES = {
     "none": dict(mode="none", R=6, cull=False, node_bytes=64),
     "raw4": dict(mode="raw", R=4, cull=True, node_bytes=128),
     "lut6": dict(mode="lut", R=6, cull=True, node_bytes=64, K=4096),
+    "lut6k256": dict(mode="lut", R=6, cull=True, node_bytes=64, K=256),
+    "lut4k256": dict(mode="lut", R=4, cull=True, node_bytes=64, K=256),
 }
 
 
@@ -148,7 +150,7 @@ def main():
     ap.add_argument("--modes", default="raw6,none,raw4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--tune", default="", help="block,stack,chunk of the traversal launch")
+    ap.add_argument("--tune", default="", help="block,stack,chunk,parts of the traversal launch")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -168,8 +170,7 @@ def main():
     log(f"generated {tris.shape[0]} tris, {rays.shape[0]} rays in {time.perf_counter() - t0:.1f}s")
     ctx = binding.Context(0)
     if args.tune:
-        b, s_, c = (int(x) for x in args.tune.split(","))
-        ctx.set_tune(b, s_, c)
+        ctx.set_tune(*(int(x) for x in args.tune.split(",")))
     rays_dev = torch.from_numpy(rays).cuda()
     modes = [m for m in args.modes.split(",") if m]
     results, raw = {}, {}

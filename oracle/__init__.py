@@ -25,7 +25,7 @@ _SRC = os.path.join(_HERE, "sc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-MODES = {"none": 0, "raw": 1, "lut": 2}
+MODES = {"none": 0, "raw": 1, "lut": 2, "sparse": 3}
 FLAG_CULL = 1
 FLAG_SHADOW = 2
 LEAF_BIT = 0x80000000
@@ -142,7 +142,10 @@ class Hits:
 
 
 def trace(tris, bvh: BVH, rays, *, mode="none", R=6, masks=None, codebook=None, cidx=None,
-          lut=None, origin_bound=None, cull=True, shadow=False, nthreads=0) -> Hits:
+          placed=None, lut=None, origin_bound=None, cull=True, shadow=False, nthreads=0) -> Hits:
+    """Traversal with culling. mode "raw": masks per slot; "lut": codebook +
+    cidx; "sparse": masks per slot used only where placed[slot] != 0. A slot
+    whose mask is full is never tested."""
     tris = np.ascontiguousarray(tris, np.float32)
     rays = np.ascontiguousarray(rays, np.float32)
     n = rays.shape[0]
@@ -158,9 +161,10 @@ def trace(tris, bvh: BVH, rays, *, mode="none", R=6, masks=None, codebook=None, 
     masks = None if masks is None else np.ascontiguousarray(masks, np.uint64)
     codebook = None if codebook is None else np.ascontiguousarray(codebook, np.uint64)
     cidx = None if cidx is None else np.ascontiguousarray(cidx, np.uint16)
+    placed = None if placed is None else np.ascontiguousarray(placed, np.uint8)
     rc = lib().orc_trace(_p(tris), _p(bvh.perm), _p(bvh.cbox), _p(bvh.cref), C.c_uint32(bvh.root),
                          C.c_uint32(bvh.depth), C.c_uint32(R), C.c_uint32(mcode), _p(masks),
-                         _p(codebook), _p(cidx), _p(lut), C.c_float(origin_bound),
+                         _p(codebook), _p(cidx), _p(placed), _p(lut), C.c_float(origin_bound),
                          C.c_uint32(flags), _p(rays), C.c_uint32(n), _p(hits), _p(extra), _p(fp),
                          C.c_int(nthreads))
     _check(rc, "trace")

@@ -42,6 +42,7 @@ static inline float min3f(float a, float b, float c) { return min2f(min2f(a, b),
 static inline float max3f(float a, float b, float c) { return max2f(max2f(a, b), c); }
 
 static inline uint32_t words_for(uint32_t R) { return (R * R * R + 63u) / 64u; }
+static uint32_t popc(const uint64_t* m, uint32_t W);
 
 /* ------------------------------------------------------------------------
  * 1. BVH construction: binned SAH (Sect. 4 names a binned SAH builder; the
@@ -417,10 +418,14 @@ int orc_object_masks(const float* tris, const uint32_t* perm, uint32_t n_inner, 
  *          original id is lower).
  *    counts: box_tests = slab tests, tri_tests = triangle tests, mask_tests
  *          = mask ANDs evaluated, mask_culls = ANDs that were zero.
+ *    a child whose stored mask has every bit set is not tested: its AND can
+ *          never be zero, since a ray mask always holds the entry cell. In
+ *          the sparse mode only the placed slots carry masks.
  * ---------------------------------------------------------------------- */
 #define MODE_NONE 0
 #define MODE_RAW 1
 #define MODE_LUT 2
+#define MODE_SPARSE 3
 #define FLAG_CULL 1u
 #define FLAG_SHADOW 2u
 
@@ -446,6 +451,7 @@ typedef struct {
     const float* tris; const uint32_t* perm; const float* cbox; const uint32_t* cref;
     uint32_t root, R, W, mode, flags;
     const uint64_t* masks; const uint64_t* cb; const uint16_t* cidx; const uint64_t* lut;
+    const uint8_t* placed;
     float origin_bound;
     uint32_t* slot_fp;
 } TraceCtx;
@@ -532,7 +538,15 @@ static void trace_one(const TraceCtx* C, const float* ray, uint32_t* hit, uint32
                 }
                 hitc[c] = (t0 <= t1);
                 t0c[c] = t0;
+                uint32_t slot = 2u * ref + (uint32_t)c;
+                const uint64_t* om = NULL;
                 if (hitc[c] && use_mask) {
+                    if (C->mode == MODE_RAW) om = &C->masks[(size_t)slot * C->W];
+                    else if (C->mode == MODE_LUT) om = &C->cb[(size_t)C->cidx[slot] * C->W];
+                    else if (C->placed[slot]) om = &C->masks[(size_t)slot * C->W];
+                    if (om && popc(om, C->W) == C->R * C->R * C->R) om = NULL;
+                }
+                if (om) {
                     ++mask_tests;
                     int cb_[3], ce_[3];
                     raymask_key_cells(lo, hi, o, d, t0, C->R, cb_);
@@ -540,9 +554,6 @@ static void trace_one(const TraceCtx* C, const float* ray, uint32_t* hit, uint32
                     uint32_t R = C->R;
                     size_t key = (((((size_t)cb_[0] * R + cb_[1]) * R + cb_[2]) * R + ce_[0]) * R + ce_[1]) * R + ce_[2];
                     const uint64_t* rm = &C->lut[key * C->W];
-                    uint32_t slot = 2u * ref + (uint32_t)c;
-                    const uint64_t* om = (C->mode == MODE_RAW) ? &C->masks[(size_t)slot * C->W]
-                                                               : &C->cb[(size_t)C->cidx[slot] * C->W];
                     uint64_t any = 0;
                     for (uint32_t w = 0; w < C->W; ++w) any |= rm[w] & om[w];
                     if (any == 0) {
@@ -580,18 +591,19 @@ static void trace_one(const TraceCtx* C, const float* ray, uint32_t* hit, uint32
 
 int orc_trace(const float* tris, const uint32_t* perm, const float* cbox, const uint32_t* cref,
               uint32_t root_ref, uint32_t depth, uint32_t R, uint32_t mode, const uint64_t* masks,
-              const uint64_t* codebook, const uint16_t* cidx, const uint64_t* lut,
+              const uint64_t* codebook, const uint16_t* cidx, const uint8_t* placed, const uint64_t* lut,
               float origin_bound, uint32_t flags, const float* rays, uint32_t nrays,
               uint32_t* out_hits, uint32_t* out_extra, uint32_t* slot_fp, int nthreads) {
     if (depth + 1 > 160) return ORC_ERR_DEPTH;
-    if (mode > MODE_LUT) return ORC_ERR_ARG;
+    if (mode > MODE_SPARSE) return ORC_ERR_ARG;
     if (mode != MODE_NONE && (R < 1 || R > 6 || !lut)) return ORC_ERR_ARG;
-    if (mode == MODE_RAW && !masks) return ORC_ERR_ARG;
+    if ((mode == MODE_RAW || mode == MODE_SPARSE) && !masks) return ORC_ERR_ARG;
+    if (mode == MODE_SPARSE && !placed) return ORC_ERR_ARG;
     if (mode == MODE_LUT && (!codebook || !cidx)) return ORC_ERR_ARG;
     TraceCtx C;
     C.tris = tris; C.perm = perm; C.cbox = cbox; C.cref = cref; C.root = root_ref;
     C.R = R; C.W = words_for(R ? R : 1); C.mode = mode; C.flags = flags;
-    C.masks = masks; C.cb = codebook; C.cidx = cidx; C.lut = lut;
+    C.masks = masks; C.cb = codebook; C.cidx = cidx; C.lut = lut; C.placed = placed;
     C.origin_bound = origin_bound;
     C.slot_fp = (flags & FLAG_SHADOW) ? slot_fp : NULL;
 #ifdef _OPENMP

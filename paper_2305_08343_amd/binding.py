@@ -50,7 +50,8 @@ class sc_scene_info(C.Structure):
 
 
 class sc_tune(C.Structure):
-    _fields_ = [("block", C.c_uint32), ("stack", C.c_uint32), ("chunk", C.c_uint32)]
+    _fields_ = [("block", C.c_uint32), ("stack", C.c_uint32), ("chunk", C.c_uint32),
+                ("parts", C.c_uint32)]
 
 
 class sc_scene_host(C.Structure):
@@ -160,14 +161,14 @@ class Context:
         except Exception:
             pass
 
-    def set_tune(self, block: int = 256, stack: int = 8, chunk: int = 1):
+    def set_tune(self, block: int = 256, stack: int = 8, chunk: int = 1, parts: int = 8):
         """Traversal launch shape for later traces (results never depend on it)."""
-        _check(load().sc_set_tune(self.handle, C.byref(sc_tune(block, stack, chunk))), "sc_set_tune")
+        _check(load().sc_set_tune(self.handle, C.byref(sc_tune(block, stack, chunk, parts))), "sc_set_tune")
 
     def get_tune(self) -> dict:
         t = sc_tune()
         _check(load().sc_get_tune(self.handle, C.byref(t)), "sc_get_tune")
-        return {"block": t.block, "stack": t.stack, "chunk": t.chunk}
+        return {"block": t.block, "stack": t.stack, "chunk": t.chunk, "parts": t.parts}
 
     def raymask_lut(self, R: int, stream=None):
         """Device ray-mask LUT as uint64 numpy array [R^6, W] (copies back)."""

@@ -22,7 +22,7 @@ struct sc_ctx {
     std::mutex lut_mu;
     uint32_t* counters = nullptr;           // kQueueRing ray-queue counters
     std::atomic<uint32_t> next_counter{0};
-    sc_tune tune{256, 8, 1};
+    sc_tune tune{256, 8, 1, kQueueParts};
 };
 
 struct sc_scene {
@@ -34,6 +34,7 @@ struct sc_scene {
     uint64_t* masks = nullptr;            // exact masks [2*n_inner][W]
     uint64_t* codebook = nullptr;         // LUT mode
     uint16_t* cidx = nullptr;             // LUT mode
+    uint32_t full_start = 0;              // LUT mode: first full codebook entry
     uint64_t* side_masks = nullptr;       // SPARSE mode
     std::vector<std::pair<void*, size_t>> owned;
 };
@@ -185,7 +186,7 @@ sc_status sc_create(int device, const sc_allocator* alloc, sc_ctx** out) {
         ctx->alloc = *alloc;
         ctx->has_alloc = true;
     }
-    ctx->counters = static_cast<uint32_t*>(dev_alloc(ctx, kQueueRing * 4, nullptr));
+    ctx->counters = static_cast<uint32_t*>(dev_alloc(ctx, kQueueRing * kQueueParts * 4, nullptr));
     if (!ctx->counters) {
         delete ctx;
         return fail(SC_ERR_OOM, "queue counter allocation failed");
@@ -202,7 +203,7 @@ sc_status sc_destroy(sc_ctx* ctx) {
         if (ctx->lut[R]) dev_free(ctx, ctx->lut[R], lut_bytes(R), nullptr);
         if (ctx->patterns[R]) dev_free(ctx, ctx->patterns[R], pattern_bytes(R), nullptr);
     }
-    dev_free(ctx, ctx->counters, kQueueRing * 4, nullptr);
+    dev_free(ctx, ctx->counters, kQueueRing * kQueueParts * 4, nullptr);
     delete ctx;
     return SC_OK;
 }
@@ -359,6 +360,15 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                 t0 = std::chrono::steady_clock::now();
                 std::vector<uint64_t> cb;
                 select_codebook(hmasks.data(), B.cbox.data(), S, R, K, cb);
+                sc->full_start = K;
+                for (uint32_t k = 0; k < K; ++k) {
+                    uint32_t pc = 0;
+                    for (uint32_t w = 0; w < W; ++w) pc += (uint32_t)__builtin_popcountll(cb[(size_t)k * W + w]);
+                    if (pc == R * R * R) {
+                        sc->full_start = k;
+                        break;
+                    }
+                }
                 I.ms_codebook = ms_since(t0);
                 t0 = std::chrono::steady_clock::now();
                 const uint32_t nch = (R * R * R + 7) / 8;
@@ -378,8 +388,20 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                 dev_free(ctx, d_req, req_bytes, s);
                 if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("compression: ") + hipGetErrorString(e));
                 I.ms_compress = ms_since(t0);
-            } else {  // SPARSE: gather the placed masks
+            } else {  // SPARSE: gather the placed masks (a full mask counts as none)
+                n_masked = 0;
+                for (uint32_t q = 0; q < S; ++q) {
+                    if (side_of_slot[q] == kNoMask) continue;
+                    uint32_t pc = 0;
+                    for (uint32_t w = 0; w < W; ++w) pc += (uint32_t)__builtin_popcountll(hmasks[(size_t)q * W + w]);
+                    side_of_slot[q] = (pc == R * R * R) ? kNoMask : n_masked++;
+                }
+                I.n_masked = n_masked;
                 std::vector<uint64_t> side((size_t)(n_masked ? n_masked : 1) * W, 0);
+                for (uint32_t i = 0; i < B.n_inner; ++i)
+                    std::memcpy(nodes.data() + (size_t)i * stride + 56, &side_of_slot[2 * (size_t)i], 8);
+                e = hipMemcpyAsync(sc->nodes, nodes.data(), nodes.size(), hipMemcpyHostToDevice, s);
+                if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("node upload: ") + hipGetErrorString(e));
                 for (uint32_t q = 0; q < S; ++q)
                     if (side_of_slot[q] != kNoMask)
                         std::memcpy(&side[(size_t)side_of_slot[q] * W], &hmasks[(size_t)q * W], W * 8);
@@ -462,6 +484,7 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
                    uint32_t* d_extra, uint32_t* d_slot_fp, void* stream) {
     if (!scene) return fail(SC_ERR_INVALID_ARG, "scene is NULL");
     if (n > 0 && (!d_rays || !d_hits)) return fail(SC_ERR_INVALID_ARG, "d_rays and d_hits must be non-NULL");
+    if (n > (1u << 31)) return fail(SC_ERR_INVALID_ARG, "at most 2^31 rays per call");
     if (flags & ~(uint32_t)(SC_TRACE_CULL | SC_TRACE_SHADOW | SC_TRACE_SORT))
         return fail(SC_ERR_INVALID_ARG, "unknown trace flag");
     if (flags & SC_TRACE_SORT) return fail(SC_ERR_UNSUPPORTED, "SC_TRACE_SORT is not implemented");
@@ -480,6 +503,8 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     a.lut = (I.mode != SC_MASK_NONE) ? scene->ctx->lut[I.R] : nullptr;
     a.patterns = (I.mode != SC_MASK_NONE) ? scene->ctx->patterns[I.R] : nullptr;
     a.codebook = scene->codebook;
+    a.K = I.codebook_size;
+    a.full_start = scene->full_start;
     a.side_masks = scene->side_masks;
     a.root = I.root_ref;
     a.R = I.R;
@@ -491,7 +516,9 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     a.slot_fp = d_slot_fp;
     if (a.mode == SC_MASK_SPARSE && I.n_masked == 0) a.mode = SC_MASK_NONE;
     sc_ctx* ctx = scene->ctx;
-    a.queue = ctx->counters + (ctx->next_counter.fetch_add(1, std::memory_order_relaxed) % kQueueRing);
+    a.queue = ctx->counters +
+              (size_t)(ctx->next_counter.fetch_add(1, std::memory_order_relaxed) % kQueueRing) * kQueueParts;
+    a.parts = ctx->tune.parts;
     a.chunk = ctx->tune.chunk;
     a.block = ctx->tune.block;
     a.stack = ctx->tune.stack;
@@ -505,6 +532,7 @@ sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune) {
     if (!trace_config_supported(tune->block, tune->stack))
         return fail(SC_ERR_UNSUPPORTED, "no traversal kernel for this (block, stack) pair");
     if (tune->chunk < 1 || tune->chunk > 64) return fail(SC_ERR_INVALID_ARG, "chunk must be 1..64");
+    if (tune->parts < 1 || tune->parts > kQueueParts) return fail(SC_ERR_INVALID_ARG, "parts must be 1..8");
     ctx->tune = *tune;
     return SC_OK;
 }

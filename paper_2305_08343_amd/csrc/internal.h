@@ -25,6 +25,7 @@ constexpr uint32_t kNoMask = 0xFFFFFFFFu;
 //   [48,52) ref 0   [52,56) ref 1     [56,60) aux   [60,64) aux2
 // aux  : LUT mode -> codebook index of child 0 | index of child 1 << 16
 //        SPARSE   -> mask slot of child 0 (kNoMask = none); aux2 -> child 1
+//        RAW      -> bit c set when child c's mask is full
 // RAW nodes are 128 bytes: the raw masks follow at [64, 64 + 2*words*8).
 constexpr uint32_t kNodeBytes = 64;
 constexpr uint32_t kRawNodeBytes = 128;
@@ -61,6 +62,8 @@ struct TraceLaunch {
     const uint64_t* lut;        // full ray-mask LUT [R^6][W]
     const uint64_t* patterns;   // displacement patterns [R(2R-1)^2][W]
     const uint64_t* codebook;   // LUT mode
+    uint32_t K;                 // codebook entries (LUT mode)
+    uint32_t full_start;        // first codebook index holding the full mask (K if none)
     const uint64_t* side_masks; // SPARSE mode
     uint32_t root;
     uint32_t R;
@@ -70,7 +73,8 @@ struct TraceLaunch {
     sc_hit* hits;
     uint32_t* extra;
     uint32_t* slot_fp;
-    uint32_t* queue;            // ray-queue counter for this launch (zeroed on the stream first)
+    uint32_t* queue;            // kQueueParts ray-queue counters for this launch (zeroed on the stream first)
+    uint32_t parts;             // ray partitions in use, 1..kQueueParts
     uint32_t chunk;             // rays per queue fetch = 64 * chunk
     uint32_t block, stack;      // threads per block, LDS stack entries per lane
 };
@@ -78,7 +82,8 @@ struct TraceLaunch {
 // (block, stack) pairs with compiled traversal kernels.
 constexpr uint32_t kTraceConfigs[][2] = {{256, 8}, {128, 8}, {256, 12}, {256, 4}, {128, 16}};
 bool trace_config_supported(uint32_t block, uint32_t stack);
-constexpr uint32_t kQueueRing = 1024;  // launch counters per context
+constexpr uint32_t kQueueRing = 1024;  // launch counter sets per context
+constexpr uint32_t kQueueParts = 8;    // counters per set (one per XCD of an MI355X)
 
 hipError_t launch_trace(const TraceLaunch& a, hipStream_t s);
 hipError_t launch_raymask_patterns(uint32_t R, uint64_t* patterns, hipStream_t s);

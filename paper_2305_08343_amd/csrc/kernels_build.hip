@@ -310,16 +310,26 @@ __global__ __launch_bounds__(256) void compress_kernel(const uint64_t* __restric
 }
 
 // Copy each inner node's two raw masks into bytes [64, 64 + 2*W*8) of its
-// 128-byte node.
+// 128-byte node, and set bit c of the node's aux word when child c's mask is
+// full (such a mask can never cull, so the traversal skips its test).
 template <int R>
 __global__ void pack_raw_kernel(const uint64_t* __restrict__ masks, uint32_t n_inner,
                                 unsigned char* __restrict__ nodes) {
     constexpr int W = (R * R * R + 63) / 64;
-    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (size_t)n_inner * 2 * W) return;
-    const size_t node = gid / (2 * W);
-    const size_t k = gid % (2 * W);
-    reinterpret_cast<uint64_t*>(nodes + node * kRawNodeBytes + 64)[k] = masks[node * 2 * W + k];
+    const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= n_inner) return;
+    uint32_t flags = 0;
+    uint64_t* dst = reinterpret_cast<uint64_t*>(nodes + node * kRawNodeBytes + 64);
+    for (int c = 0; c < 2; ++c) {
+        int pc = 0;
+        for (int w = 0; w < W; ++w) {
+            const uint64_t m = masks[(node * 2 + c) * W + w];
+            dst[c * W + w] = m;
+            pc += __popcll(m);
+        }
+        if (pc == R * R * R) flags |= 1u << c;
+    }
+    reinterpret_cast<uint32_t*>(nodes + node * kRawNodeBytes)[14] = flags;
 }
 
 __global__ void pack_lut_kernel(const uint16_t* __restrict__ idx, uint32_t n_inner,
@@ -389,9 +399,8 @@ hipError_t launch_compress(uint32_t R, const uint64_t* masks, uint32_t n, const 
 hipError_t launch_pack_raw(uint32_t R, const uint64_t* masks, uint32_t n_inner, unsigned char* nodes,
                            hipStream_t s) {
     if (n_inner == 0) return hipSuccess;
-    const size_t n = (size_t)n_inner * 2 * words_for(R);
-    if (R == 4) hipLaunchKernelGGL(pack_raw_kernel<4>, dim3(blocks_for(n, 256)), dim3(256), 0, s, masks, n_inner, nodes);
-    else if (R == 6) hipLaunchKernelGGL(pack_raw_kernel<6>, dim3(blocks_for(n, 256)), dim3(256), 0, s, masks, n_inner, nodes);
+    if (R == 4) hipLaunchKernelGGL(pack_raw_kernel<4>, dim3(blocks_for(n_inner, 256)), dim3(256), 0, s, masks, n_inner, nodes);
+    else if (R == 6) hipLaunchKernelGGL(pack_raw_kernel<6>, dim3(blocks_for(n_inner, 256)), dim3(256), 0, s, masks, n_inner, nodes);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -12,7 +12,8 @@
 //      s = R / (hi - lo) (0 if the extent is not positive or s is infinite),
 //      u = (p - lo) * s clamped to [0, R-1] (NaN -> 0), cell = (int)u
 //  culling: child survives iff (ray mask AND object mask) != 0; skipped for
-//      rays whose max|o| exceeds the scene's origin bound
+//      rays whose max|o| exceeds the scene's origin bound and for children
+//      whose stored mask is full (or, in the sparse layout, absent)
 //  order: both children survive -> the one with the smaller t0 (tie: child
 //      0) is visited next and the other pushed with its t0; a popped entry
 //      with t0 > best_t is dropped
@@ -27,7 +28,12 @@
 // minimum corner, so the 196 patterns (1.5 KiB) sit in LDS and the test is
 // ((object mask >> corner bit) AND pattern) != 0. Both give the table's bits.
 //
-// Scheduling: persistent waves fed by a global ray queue. A wave takes
+// Compressed masks: a codebook of at most 8 KiB (K <= 1024 at R = 4, K <= 256
+// at R = 6) is copied into LDS, so with R = 4 a compressed mask test reads no
+// memory beyond the node itself.
+//
+// Scheduling: persistent waves fed by partitioned ray queues (one range of
+// consecutive rays per XCD by default; see the kernel). A wave takes
 // 64*chunk consecutive rays at a time with one atomic add; whenever lanes
 // finish their ray they take the next unstarted ray (ballot + prefix count),
 // so lanes stay busy while the slowest rays of a wave finish. This changes
@@ -45,8 +51,13 @@ namespace {
 constexpr int kWave = 64;
 constexpr uint32_t kModeNone = SC_MASK_NONE, kModeRaw = SC_MASK_RAW, kModeLut = SC_MASK_LUT,
                    kModeSparse = SC_MASK_SPARSE;
+// Compressed masks with the codebook copied into LDS (chosen when it fits).
+constexpr uint32_t kModeLutLds = 16;
+constexpr uint32_t kCbLdsWords = 1024;  // 8 KiB: K <= 1024 at R = 4, K <= 256 at R = 6
 
-__global__ void reset_counter_kernel(uint32_t* c) { *c = 0u; }
+__global__ void reset_counters_kernel(uint32_t* c, uint32_t n) {
+    if (threadIdx.x < n) c[threadIdx.x] = 0u;
+}
 
 __device__ __forceinline__ float mx(float a, float b) { return (a > b) ? a : b; }
 
@@ -104,15 +115,20 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
     constexpr uint32_t kStride = (MODE == kModeRaw) ? kRawNodeBytes : kNodeBytes;
     constexpr int kWavesPerBlock = BLOCK / kWave;
     constexpr bool kPatLds = (R == 4) && (MODE != kModeNone);
+    constexpr bool kCbLds = (MODE == kModeLutLds);
     __shared__ uint2 lds_stack[STACK * BLOCK];
     __shared__ uint64_t lds_pat[kPatLds ? kPatterns<4> : 1];
+    __shared__ __attribute__((aligned(16))) uint64_t lds_cb[kCbLds ? kCbLdsWords : 2];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     if constexpr (kPatLds) {
         for (int k = tid; k < kPatterns<4>; k += BLOCK) lds_pat[k] = a.patterns[k];
-        __syncthreads();
     }
+    if constexpr (kCbLds) {
+        for (uint32_t k = tid; k < a.K * W; k += BLOCK) lds_cb[k] = a.codebook[k];
+    }
+    if constexpr (kPatLds || kCbLds) __syncthreads();
     const uint64_t lanes_below = (1ull << lane) - 1ull;
     const uint32_t chunk_rays = kWave * a.chunk;
     const bool use_flags = (a.flags & (SC_TRACE_CULL | SC_TRACE_SHADOW)) != 0;
@@ -121,17 +137,33 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
 
     uint2 spill[kMaxDepth - STACK + 1];
 
+    // The rays are split into a.parts contiguous partitions, one queue counter
+    // each. Workgroups are dispatched round-robin over the XCDs, so a wave
+    // starts on partition (block % parts) -- its own XCD's share when parts is
+    // the XCD count -- and moves on to the others once that one is empty.
+    const uint32_t parts = a.parts;
+    const uint32_t home = blockIdx.x % parts;
+    uint32_t exhausted = 0;        // wave-uniform bit per partition
     uint32_t cursor = 0, end = 0;  // wave-uniform range of unstarted rays
     bool more = true;
-    // next range of rays for this wave from the queue; false when none is left
+    // next range of rays for this wave; false when every partition is empty
     auto fetch = [&]() -> bool {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(a.queue, chunk_rays);
-        base = __shfl(base, 0, kWave);
-        if (base >= a.n) return false;
-        cursor = base;
-        end = min(a.n, base + chunk_rays);
-        return true;
+        for (uint32_t t = 0; t < parts; ++t) {
+            const uint32_t p = (home + t) % parts;
+            if (exhausted & (1u << p)) continue;
+            const uint32_t lo = (uint32_t)(((uint64_t)a.n * p) / parts);
+            const uint32_t hi = (uint32_t)(((uint64_t)a.n * (p + 1)) / parts);
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(a.queue + p, chunk_rays);
+            base = __shfl(base, 0, kWave);
+            if (base < hi - lo) {
+                cursor = lo + base;
+                end = min(hi, cursor + chunk_rays);
+                return true;
+            }
+            exhausted |= 1u << p;
+        }
+        return false;
     };
     {
         bool has = false;
@@ -236,12 +268,19 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
                         for (int c = 0; c < 2; ++c) {
                             const bool hit = c ? h1 : h0;
                             if (!hit) continue;
+                            // a full mask cannot cull (the ray mask holds its entry cell): no test
                             const uint64_t* om;
                             if constexpr (MODE == kModeRaw) {
+                                if ((n3.z >> c) & 1u) continue;
                                 om = reinterpret_cast<const uint64_t*>(np + 64) + c * W;
                             } else if constexpr (MODE == kModeLut) {
                                 const uint32_t idx = c ? (n3.z >> 16) : (n3.z & 0xFFFFu);
+                                if (idx >= a.full_start) continue;
                                 om = a.codebook + (size_t)idx * W;
+                            } else if constexpr (MODE == kModeLutLds) {
+                                const uint32_t idx = c ? (n3.z >> 16) : (n3.z & 0xFFFFu);
+                                if (idx >= a.full_start) continue;
+                                om = lds_cb + idx * W;
                             } else {
                                 const uint32_t ms = c ? n3.w : n3.z;
                                 if (ms == kNoMask) continue;
@@ -340,7 +379,7 @@ hipError_t launch_one(const TraceLaunch& a, hipStream_t s) {
     const uint32_t waves = (a.n + kWave - 1) / kWave;
     uint32_t blocks = (waves + BLOCK / kWave - 1) / (BLOCK / kWave);
     blocks = blocks < (uint32_t)resident ? blocks : (uint32_t)resident;
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, a.queue);
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(kQueueParts), 0, s, a.queue, kQueueParts);
     hipLaunchKernelGGL((trace_kernel<MODE, R, BLOCK, STACK>), dim3(blocks), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -352,6 +391,9 @@ hipError_t launch_cfg(const TraceLaunch& a, hipStream_t s) {
         case SC_MASK_RAW:
             return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK>(a, s) : launch_one<kModeRaw, 6, BLOCK, STACK>(a, s);
         case SC_MASK_LUT:
+            if ((size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
+                return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK>(a, s)
+                                : launch_one<kModeLutLds, 6, BLOCK, STACK>(a, s);
             return a.R == 4 ? launch_one<kModeLut, 4, BLOCK, STACK>(a, s) : launch_one<kModeLut, 6, BLOCK, STACK>(a, s);
         case SC_MASK_SPARSE:
             return a.R == 4 ? launch_one<kModeSparse, 4, BLOCK, STACK>(a, s)
@@ -370,7 +412,7 @@ bool trace_config_supported(uint32_t block, uint32_t stack) {
 
 hipError_t launch_trace(const TraceLaunch& a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    if (a.chunk < 1 || !a.queue) return hipErrorInvalidValue;
+    if (a.chunk < 1 || !a.queue || a.parts < 1 || a.parts > kQueueParts) return hipErrorInvalidValue;
     if (a.block == 256 && a.stack == 8) return launch_cfg<256, 8>(a, s);
     if (a.block == 128 && a.stack == 8) return launch_cfg<128, 8>(a, s);
     if (a.block == 256 && a.stack == 12) return launch_cfg<256, 12>(a, s);

@@ -103,6 +103,25 @@ def test_small_scene_trace_bit_exact(ctx, small_scene, small_oracle, mode, R, K)
     s.close()
 
 
+@pytest.mark.parametrize("R", [4, 6])
+def test_sparse_placement_bit_exact(ctx, small_scene, small_oracle, R):
+    from paper_2305_08343_amd import binding
+    tris, rays = small_scene
+    rays = np.concatenate([rays, _aimed(tris, 20000, 11)])
+    bvh = small_oracle["bvh"]
+    S = 2 * bvh.n_inner
+    rng = np.random.default_rng(R)
+    for frac in (0.0, 0.3, 1.0):
+        placed = (rng.random(S) < frac).astype(np.uint8)
+        print(f"[gpu] sparse R={R} placed fraction {frac}", flush=True)
+        s = binding.Scene(ctx, tris, R=R, mode="sparse", placement=placed)
+        dev = s.trace(rays).numpy()
+        s.close()
+        ora = oracle.trace(tris, bvh, rays, mode="sparse", R=R, masks=small_oracle[f"masks{R}"],
+                           placed=placed, origin_bound=small_oracle["origin_bound"])
+        _compare_hits(dev, ora)
+
+
 def test_shadow_counts_bit_exact(ctx, small_scene, small_oracle):
     import torch
     from paper_2305_08343_amd import binding
@@ -245,15 +264,15 @@ def test_every_launch_shape_gives_the_same_results(ctx, small_scene, small_oracl
     s4 = binding.Scene(ctx, tris, R=4, mode="raw")
     try:
         for block, stack in ((256, 8), (128, 8), (256, 12), (256, 4), (128, 16)):
-            for chunk in (1, 3, 64):
-                print(f"[gpu] tune block={block} stack={stack} chunk={chunk}", flush=True)
-                ctx.set_tune(block, stack, chunk)
+            for chunk, parts in ((1, 8), (3, 1), (64, 5)):
+                print(f"[gpu] tune block={block} stack={stack} chunk={chunk} parts={parts}", flush=True)
+                ctx.set_tune(block, stack, chunk, parts)
                 _compare_hits(s6.trace(r).numpy(), ora)
                 _compare_hits(s4.trace(r).numpy(), ora4)
         with pytest.raises(binding.SubcullError):
             ctx.set_tune(64, 8, 1)
     finally:
-        ctx.set_tune(256, 8, 1)
+        ctx.set_tune(256, 8, 1, 8)
         s6.close()
         s4.close()
 

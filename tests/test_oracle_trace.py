@@ -167,18 +167,61 @@ def test_compressed_sits_between_plain_and_raw(small_scene, small_oracle):
 
 
 def test_all_ones_masks_cull_nothing(small_scene, small_oracle):
+    """A full mask can never give a zero AND (the ray mask holds its entry
+    cell), so it is not tested at all and the traversal equals plain."""
     tris, rays = small_scene
     bvh = small_oracle["bvh"]
     full = np.zeros_like(small_oracle["masks6"])
-    bits = np.ones(216, bool)
-    for b in np.flatnonzero(bits):
+    for b in range(216):
         full[:, b >> 6] |= np.uint64(1) << np.uint64(b & 63)
     h0 = oracle.trace(tris, bvh, rays, mode="none")
     h1 = oracle.trace(tris, bvh, rays, mode="raw", R=6, masks=full)
     assert _same_hits(h0, h1)
-    assert (h1.mask_culls == 0).all()
+    assert (h1.mask_culls == 0).all() and (h1.mask_tests == 0).all()
     assert (h1.box_tests == h0.box_tests).all() and (h1.tri_tests == h0.tri_tests).all()
-    assert (h1.mask_tests > 0).any()
+
+
+def test_full_masks_are_not_tested(small_scene, small_oracle):
+    """Replacing some masks by full masks removes exactly their tests and culls."""
+    tris, rays = small_scene
+    rays = np.concatenate([rays, _aimed_rays(tris, 10000, 21)])
+    bvh, ob = small_oracle["bvh"], small_oracle["origin_bound"]
+    m = small_oracle["masks4"].copy()
+    h_raw = oracle.trace(tris, bvh, rays, mode="raw", R=4, masks=m, origin_bound=ob)
+    sel = np.zeros(m.shape[0], bool)
+    sel[::3] = True
+    m2 = m.copy()
+    m2[sel] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    h2 = oracle.trace(tris, bvh, rays, mode="raw", R=4, masks=m2, origin_bound=ob)
+    placed = (~sel).astype(np.uint8)
+    h3 = oracle.trace(tris, bvh, rays, mode="sparse", R=4, masks=m, placed=placed, origin_bound=ob)
+    for f in ("prim", "box_tests", "tri_tests", "mask_tests", "mask_culls"):
+        assert (getattr(h2, f) == getattr(h3, f)).all(), f
+    assert (h2.box_tests >= h_raw.box_tests).all() and h2.mask_tests.sum() < h_raw.mask_tests.sum()
+
+
+@pytest.mark.parametrize("R", [4, 6])
+def test_sparse_placement_bounds(small_scene, small_oracle, R):
+    """All slots placed = raw; none placed = plain; any placement keeps the hits
+    and its counts lie between the two."""
+    tris, rays = small_scene
+    rays = np.concatenate([rays, _aimed_rays(tris, 10000, 22)])
+    bvh, ob = small_oracle["bvh"], small_oracle["origin_bound"]
+    m = small_oracle[f"masks{R}"]
+    S = m.shape[0]
+    h0 = oracle.trace(tris, bvh, rays, mode="none")
+    hr = oracle.trace(tris, bvh, rays, mode="raw", R=R, masks=m, origin_bound=ob)
+    ha = oracle.trace(tris, bvh, rays, mode="sparse", R=R, masks=m, placed=np.ones(S, np.uint8), origin_bound=ob)
+    hn = oracle.trace(tris, bvh, rays, mode="sparse", R=R, masks=m, placed=np.zeros(S, np.uint8), origin_bound=ob)
+    for f in ("prim", "box_tests", "tri_tests", "mask_tests", "mask_culls"):
+        assert (getattr(ha, f) == getattr(hr, f)).all()
+    assert (hn.box_tests == h0.box_tests).all() and (hn.mask_tests == 0).all()
+    rng = np.random.default_rng(R)
+    hp = oracle.trace(tris, bvh, rays, mode="sparse", R=R, masks=m,
+                      placed=(rng.random(S) < 0.4).astype(np.uint8), origin_bound=ob)
+    assert _same_hits(h0, hp)
+    for f in ("box_tests", "tri_tests"):
+        assert (getattr(h0, f) >= getattr(hp, f)).all() and (getattr(hp, f) >= getattr(hr, f)).all()
 
 
 def test_origin_outside_bound_skips_masks(small_scene, small_oracle):
