@@ -142,6 +142,73 @@ def cpu_baseline(tris, rays, target_s):
                       f"{setup:.1f} s not timed"}
 
 
+def run_batch64(args, ctx):
+    """64 scenes of uneven size in one persistent launch replayed from a HIP graph,
+    against the same scenes traced one launch per scene."""
+    import torch
+    from paper_2305_08343_amd import binding, scenes, tune
+    t0 = time.perf_counter()
+    specs = scenes.batch_specs(64)
+    data = [scenes.batch_scene(sp) for sp in specs]
+    n_tris = sum(t.shape[0] for t, _ in data)
+    n_rays = sum(r.shape[0] for _, r in data)
+    log(f"batch64: {n_tris} tris, {n_rays} rays generated in {time.perf_counter() - t0:.1f}s")
+    out = {}
+    for mname in args.modes.split(","):
+        spec = MODES[mname]
+        t0 = time.perf_counter()
+        built = [binding.Scene(ctx, t, R=spec["R"], mode=spec["mode"], K=spec.get("K", 4096)) for t, _ in data]
+        rays = [torch.from_numpy(r).cuda() for _, r in data]
+        build_s = time.perf_counter() - t0
+        direct = binding.Batch(ctx, list(zip(built, rays)), cull=spec["cull"], graph=False)
+        key = f"batch64|{mname}|{n_tris}|{n_rays}"
+        cfg, entry = tune.tuned(ctx, key, direct.launch, log=log)
+        graph = binding.Batch(ctx, list(zip(built, rays)), cull=spec["cull"], graph=True)
+        hits = [torch.empty((max(r.shape[0], 1), 4), dtype=torch.int32, device="cuda") for r in rays]
+
+        def per_scene():
+            for s_, r_, h_ in zip(built, rays, hits):
+                s_.trace(r_, cull=spec["cull"], hits=h_, extra=False)
+
+        res = {}
+        for name, fn in (("graph_batch", graph.launch), ("per_scene_launches", per_scene)):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t1) / args.steps
+            res[name] = {"ms_per_step": dt * 1e3, "rays_per_s": n_rays / dt}
+        graph.launch()
+        per_scene()
+        torch.cuda.synchronize()
+        same = all((graph.hits[k][:r.shape[0]].cpu().numpy() == hits[k][:r.shape[0]].cpu().numpy()).all()
+                   for k, r in enumerate(rays) if r.shape[0])
+        tests = sum(float(graph.hits[k][:r.shape[0], 2:4].sum().item()) for k, r in enumerate(rays))
+        res.update({"tune": list(cfg), "tune_seconds": entry.get("seconds"), "build_s": build_s,
+                    "results_equal_per_scene": bool(same), "tests_per_ray": tests / n_rays})
+        log(f"batch64 {mname}: graph {res['graph_batch']['rays_per_s'] / 1e6:.1f} Mrays/s, per-scene "
+            f"{res['per_scene_launches']['rays_per_s'] / 1e6:.1f} Mrays/s, tune {cfg}")
+        out[mname] = res
+        graph.close()
+        direct.close()
+        for s_ in built:
+            s_.close()
+    head = out[args.modes.split(",")[0]]
+    line = {
+        "metric": METRIC, "value": head["graph_batch"]["rays_per_s"], "unit": "rays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["graph_batch"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64: 64 scenes (10k-500k tris, strands/thin quads/isotropic), 16k-2M rays "
+                               "each (half pinhole, half random), one persistent launch replayed from a HIP graph",
+                   "n_tris": n_tris, "n_rays": n_rays},
+        "modes": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +218,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tune", default="", help="block,stack,chunk,parts of the traversal launch")
+    ap.add_argument("--workload", default="hair_1m", choices=["hair_1m", "batch64"])
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -164,6 +232,13 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     binding.load()
 
+    if args.workload == "batch64":
+        ctx = binding.Context(0)
+        if args.modes == "raw6,none,raw4":
+            args.modes = "raw6,none"
+        run_batch64(args, ctx)
+        ctx.close()
+        return
     t0 = time.perf_counter()
     tris = scenes.scene_hair_1m(1)
     rays = scenes.rays_hair_1m(tris, 1)

@@ -203,6 +203,38 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
 sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune);
 sc_status sc_get_tune(const sc_ctx* ctx, sc_tune* out);
 
+/* One scene's rays in a batched launch. All items of a batch must come from
+ * one context and share the mask mode and R. d_rays/d_hits as in sc_trace;
+ * d_extra and d_slot_fp may be NULL. */
+typedef struct {
+    const sc_scene* scene;
+    const float* d_rays;
+    uint32_t n;
+    sc_hit* d_hits;
+    uint32_t* d_extra;
+    uint32_t* d_slot_fp;
+} sc_batch_item;
+
+typedef struct sc_batch sc_batch;
+
+/* Trace several scenes' rays in one persistent launch: the items form one
+ * ray queue (largest estimated work first), every lane takes its next ray
+ * from any item, so uneven scene sizes keep the GPU busy. Results equal
+ * sc_trace on each item alone. Synchronises `stream` (the descriptor table
+ * uploaded for the call is released afterwards); sc_batch_launch does not. */
+sc_status sc_trace_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_items, uint32_t flags,
+                         void* stream);
+
+/* The same launch recorded once into a HIP graph (counter reset kernel +
+ * traversal kernel, with the context's current launch shape) for cheap
+ * replays: sc_batch_launch replays it on `stream`. The item buffers are
+ * bound at creation; their contents may change between replays. Replays of
+ * one batch share its queue counters: keep them on one stream. */
+sc_status sc_batch_create(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_items, uint32_t flags,
+                          sc_batch** out);
+sc_status sc_batch_launch(sc_batch* batch, void* stream);
+sc_status sc_batch_destroy(sc_batch* batch); /* NULL-safe */
+
 /* The ray-mask LUT of resolution R as built on the device (Sect. 3.1.1):
  * d_out receives R^6 entries of words(R) uint64 (words = 1 for R=4, 4 for
  * R=6); entry key ((((bx*R+by)*R+bz)*R+ex)*R+ey)*R+ez, voxel bit x+R*y+R^2*z. */

@@ -54,6 +54,11 @@ class sc_tune(C.Structure):
                 ("parts", C.c_uint32)]
 
 
+class sc_batch_item(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("d_rays", C.c_void_p), ("n", C.c_uint32), ("d_hits", C.c_void_p),
+                ("d_extra", C.c_void_p), ("d_slot_fp", C.c_void_p)]
+
+
 class sc_scene_host(C.Structure):
     _fields_ = [("cbox", C.c_void_p), ("cref", C.c_void_p), ("range", C.c_void_p),
                 ("perm", C.c_void_p), ("masks", C.c_void_p), ("codebook", C.c_void_p),
@@ -77,6 +82,11 @@ _SIGS = {
     "sc_scene_export": (C.c_int, [C.c_void_p, C.POINTER(sc_scene_host)]),
     "sc_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
+    "sc_trace_batch": (C.c_int, [C.c_void_p, C.POINTER(sc_batch_item), C.c_uint32, C.c_uint32, C.c_void_p]),
+    "sc_batch_create": (C.c_int, [C.c_void_p, C.POINTER(sc_batch_item), C.c_uint32, C.c_uint32,
+                                  C.POINTER(C.c_void_p)]),
+    "sc_batch_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sc_batch_destroy": (C.c_int, [C.c_void_p]),
     "sc_set_tune": (C.c_int, [C.c_void_p, C.POINTER(sc_tune)]),
     "sc_get_tune": (C.c_int, [C.c_void_p, C.POINTER(sc_tune)]),
     "sc_raymask_lut": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
@@ -307,3 +317,64 @@ class Scene:
                                _ptr(extra_out) if extra else None, _ptr(slot_fp),
                                _stream_ptr(stream)), "sc_trace")
         return TraceResult(hits[:n], extra_out[:n] if extra else None)
+
+
+class Batch:
+    """Several scenes' rays traced by one persistent launch.
+
+    ``items`` is a list of (scene, rays) pairs (rays: device float32 [n, 8]).
+    ``graph=True`` records the launch once into a HIP graph; ``launch()``
+    replays it. Output buffers are allocated here and stay bound to the batch.
+    """
+
+    def __init__(self, ctx: Context, items, *, cull: bool = True, shadow: bool = False,
+                 extra: bool = True, graph: bool = True, slot_fp=None):
+        import torch
+        self.ctx = ctx
+        dev = f"cuda:{ctx.device}"
+        self.rays, self.hits, self.extra, self.slot_fp = [], [], [], []
+        arr = (sc_batch_item * len(items))()
+        for k, (scene, rays) in enumerate(items):
+            if not isinstance(rays, torch.Tensor):
+                rays = torch.from_numpy(np.ascontiguousarray(rays, np.float32))
+            rays = rays.to(device=dev, dtype=torch.float32).contiguous()
+            n = rays.shape[0]
+            h = torch.empty((max(n, 1), 4), dtype=torch.int32, device=dev)
+            e = torch.empty((max(n, 1), 2), dtype=torch.int32, device=dev) if extra else None
+            fp = None if slot_fp is None else slot_fp[k]
+            self.rays.append(rays)
+            self.hits.append(h)
+            self.extra.append(e)
+            self.slot_fp.append(fp)
+            arr[k] = sc_batch_item(scene.handle, rays.data_ptr() if n else None, n, h.data_ptr(),
+                                   None if e is None else e.data_ptr(), None if fp is None else fp.data_ptr())
+        self._arr = arr
+        self._n = len(items)
+        self.flags = (SC_TRACE_CULL if cull else 0) | (SC_TRACE_SHADOW if shadow else 0)
+        self.handle = None
+        if graph:
+            h = C.c_void_p()
+            _check(load().sc_batch_create(ctx.handle, arr, self._n, self.flags, C.byref(h)), "sc_batch_create")
+            self.handle = h
+
+    def launch(self, stream=None):
+        if self.handle is not None:
+            _check(load().sc_batch_launch(self.handle, _stream_ptr(stream)), "sc_batch_launch")
+        else:
+            _check(load().sc_trace_batch(self.ctx.handle, self._arr, self._n, self.flags, _stream_ptr(stream)),
+                   "sc_trace_batch")
+
+    def results(self, k) -> TraceResult:
+        n = self.rays[k].shape[0]
+        return TraceResult(self.hits[k][:n], None if self.extra[k] is None else self.extra[k][:n])
+
+    def close(self):
+        if self.handle is not None:
+            load().sc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

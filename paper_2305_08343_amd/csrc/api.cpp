@@ -1,6 +1,7 @@
 // C ABI of libsubcull (include/subcull.h): contexts, scene builds, traces.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -524,6 +525,171 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     a.stack = ctx->tune.stack;
     const hipError_t e = launch_trace(a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "trace launch");
+    return SC_OK;
+}
+
+namespace {
+
+// Checks a batch and fills its launch record and sorted descriptors.
+sc_status prepare_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_items, uint32_t flags,
+                        TraceLaunch& a, std::vector<BatchItem>& desc) {
+    if (!ctx || !items || n_items == 0) return fail(SC_ERR_INVALID_ARG, "ctx and a non-empty item list are required");
+    if (flags & ~(uint32_t)(SC_TRACE_CULL | SC_TRACE_SHADOW)) return fail(SC_ERR_INVALID_ARG, "unsupported batch flag");
+    const sc_scene* first = items[0].scene;
+    if (!first) return fail(SC_ERR_INVALID_ARG, "item scene is NULL");
+    uint64_t total = 0;
+    std::vector<std::pair<double, uint32_t>> order;
+    for (uint32_t k = 0; k < n_items; ++k) {
+        const sc_batch_item& it = items[k];
+        if (!it.scene || it.scene->ctx != ctx) return fail(SC_ERR_INVALID_ARG, "item scene missing or from another context");
+        if (it.scene->info.mode != first->info.mode || it.scene->info.R != first->info.R)
+            return fail(SC_ERR_INVALID_ARG, "all batch items need the same mask mode and R");
+        if (it.n > 0 && (!it.d_rays || !it.d_hits)) return fail(SC_ERR_INVALID_ARG, "item rays/hits are NULL");
+        if (((uintptr_t)it.d_rays & 15) || ((uintptr_t)it.d_hits & 15) || ((uintptr_t)it.d_extra & 7) ||
+            ((uintptr_t)it.d_slot_fp & 3))
+            return fail(SC_ERR_INVALID_ARG, "item rays/hits must be 16-byte aligned, extra 8-byte");
+        total += it.n;
+        // longest estimated work first: rays x log2(triangles)
+        order.emplace_back(-(double)it.n * std::log2(2.0 + it.scene->info.n_tris), k);
+    }
+    if (total > (1ull << 31)) return fail(SC_ERR_INVALID_ARG, "at most 2^31 rays per batch");
+    std::stable_sort(order.begin(), order.end());
+    desc.clear();
+    uint32_t begin = 0;
+    for (const auto& o : order) {
+        const sc_batch_item& it = items[o.second];
+        const sc_scene* sc = it.scene;
+        BatchItem d{};
+        d.nodes = sc->nodes;
+        d.tris = sc->tris;
+        d.codebook = sc->codebook;
+        d.side_masks = sc->side_masks;
+        d.rays = it.d_rays;
+        d.hits = it.d_hits;
+        d.extra = it.d_extra;
+        d.slot_fp = it.d_slot_fp;
+        d.root = sc->info.root_ref;
+        d.full_start = sc->full_start;
+        d.ray_begin = begin;
+        d.n_rays = it.n;
+        d.origin_bound = sc->info.origin_bound;
+        begin += it.n;
+        desc.push_back(d);
+    }
+    const sc_scene_info& I = first->info;
+    std::memset(&a, 0, sizeof(a));
+    a.n = (uint32_t)total;
+    a.R = I.R;
+    a.mode = I.mode;
+    a.flags = flags;
+    a.lut = (I.mode != SC_MASK_NONE) ? ctx->lut[I.R] : nullptr;
+    a.patterns = (I.mode != SC_MASK_NONE) ? ctx->patterns[I.R] : nullptr;
+    a.chunk = ctx->tune.chunk;
+    a.block = ctx->tune.block;
+    a.stack = ctx->tune.stack;
+    a.parts = ctx->tune.parts;
+    a.n_items = n_items;
+    if (I.mode != SC_MASK_NONE && !a.lut) {  // masks exist only if the LUT was built
+        for (uint32_t k = 0; k < n_items; ++k)
+            if (items[k].scene->info.n_inner) return fail(SC_ERR_INVALID_ARG, "scene without its ray-mask LUT");
+    }
+    return SC_OK;
+}
+
+}  // namespace
+
+struct sc_batch {
+    sc_ctx* ctx = nullptr;
+    BatchItem* items = nullptr;
+    size_t items_bytes = 0;
+    uint32_t* counters = nullptr;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+sc_status sc_trace_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_items, uint32_t flags,
+                         void* stream) {
+    TraceLaunch a;
+    std::vector<BatchItem> desc;
+    sc_status st = prepare_batch(ctx, items, n_items, flags, a, desc);
+    if (st != SC_OK) return st;
+    if (a.n == 0) return SC_OK;
+    st = use_device(ctx->device);
+    if (st != SC_OK) return st;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t bytes = desc.size() * sizeof(BatchItem);
+    auto* d = static_cast<BatchItem*>(dev_alloc(ctx, bytes, s));
+    if (!d) return fail(SC_ERR_OOM, "batch descriptor allocation failed");
+    hipError_t e = hipMemcpyAsync(d, desc.data(), bytes, hipMemcpyHostToDevice, s);
+    a.items = d;
+    a.queue = ctx->counters +
+              (size_t)(ctx->next_counter.fetch_add(1, std::memory_order_relaxed) % kQueueRing) * kQueueParts;
+    if (e == hipSuccess) e = launch_trace(a, s);
+    // the descriptors must outlive the launch: wait before releasing them
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(ctx, d, bytes, s);
+    return e == hipSuccess ? SC_OK : hip_fail(e, "batched trace");
+}
+
+sc_status sc_batch_create(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_items, uint32_t flags,
+                          sc_batch** out) {
+    if (!out) return fail(SC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    TraceLaunch a;
+    std::vector<BatchItem> desc;
+    sc_status st = prepare_batch(ctx, items, n_items, flags, a, desc);
+    if (st != SC_OK) return st;
+    st = use_device(ctx->device);
+    if (st != SC_OK) return st;
+    auto* b = new (std::nothrow) sc_batch();
+    if (!b) return fail(SC_ERR_OOM, "batch allocation failed");
+    b->ctx = ctx;
+    b->items_bytes = desc.size() * sizeof(BatchItem);
+    b->items = static_cast<BatchItem*>(dev_alloc(ctx, b->items_bytes, nullptr));
+    b->counters = static_cast<uint32_t*>(dev_alloc(ctx, kQueueParts * 4, nullptr));
+    auto cleanup = [&](sc_status code, const std::string& msg) {
+        sc_batch_destroy(b);
+        return fail(code, msg);
+    };
+    if (!b->items || !b->counters) return cleanup(SC_ERR_OOM, "batch buffers");
+    hipError_t e = hipMemcpy(b->items, desc.data(), b->items_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(SC_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+    a.items = b->items;
+    a.queue = b->counters;
+    e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) return cleanup(SC_ERR_HIP, std::string("stream: ") + hipGetErrorString(e));
+    e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const hipError_t le = (a.n > 0) ? launch_trace(a, b->capture) : hipSuccess;
+        e = hipStreamEndCapture(b->capture, &b->graph);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return cleanup(SC_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    *out = b;
+    return SC_OK;
+}
+
+sc_status sc_batch_launch(sc_batch* batch, void* stream) {
+    if (!batch || !batch->exec) return fail(SC_ERR_INVALID_ARG, "batch is NULL");
+    sc_status st = use_device(batch->ctx->device);
+    if (st != SC_OK) return st;
+    const hipError_t e = hipGraphLaunch(batch->exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SC_OK : hip_fail(e, "graph launch");
+}
+
+sc_status sc_batch_destroy(sc_batch* batch) {
+    if (!batch) return SC_OK;
+    (void)use_device(batch->ctx->device);
+    if (batch->capture) (void)hipStreamSynchronize(batch->capture);
+    (void)hipDeviceSynchronize();
+    if (batch->exec) (void)hipGraphExecDestroy(batch->exec);
+    if (batch->graph) (void)hipGraphDestroy(batch->graph);
+    if (batch->capture) (void)hipStreamDestroy(batch->capture);
+    dev_free(batch->ctx, batch->items, batch->items_bytes, nullptr);
+    dev_free(batch->ctx, batch->counters, kQueueParts * 4, nullptr);
+    delete batch;
     return SC_OK;
 }
 

@@ -54,6 +54,21 @@ void select_codebook(const uint64_t* masks, const float* slot_boxes, size_t S, u
                      uint32_t K, std::vector<uint64_t>& cb);
 
 // ------------------------------------------------------ kernel launchers
+// One scene's share of a batched launch (device-resident descriptor).
+struct BatchItem {
+    const unsigned char* nodes;
+    const float* tris;
+    const uint64_t* codebook;
+    const uint64_t* side_masks;
+    const float* rays;
+    sc_hit* hits;
+    uint32_t* extra;
+    uint32_t* slot_fp;
+    uint32_t root, full_start, ray_begin, n_rays;
+    float origin_bound;
+    uint32_t pad[3];
+};
+
 struct TraceLaunch {
     const float* rays;
     uint32_t n;
@@ -77,6 +92,8 @@ struct TraceLaunch {
     uint32_t parts;             // ray partitions in use, 1..kQueueParts
     uint32_t chunk;             // rays per queue fetch = 64 * chunk
     uint32_t block, stack;      // threads per block, LDS stack entries per lane
+    const BatchItem* items;     // batched launch: per-scene descriptors sorted by ray_begin, else null
+    uint32_t n_items;
 };
 
 // (block, stack) pairs with compiled traversal kernels.

@@ -109,7 +109,7 @@ __device__ __forceinline__ void slab(const float* lo, const float* hi, const Ray
     }
 }
 
-template <uint32_t MODE, int R, int BLOCK, int STACK>
+template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
     constexpr int W = (R * R * R + 63) / 64;
     constexpr uint32_t kStride = (MODE == kModeRaw) ? kRawNodeBytes : kNodeBytes;
@@ -133,9 +133,22 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
     const uint32_t chunk_rays = kWave * a.chunk;
     const bool use_flags = (a.flags & (SC_TRACE_CULL | SC_TRACE_SHADOW)) != 0;
     const bool cull = (a.flags & SC_TRACE_CULL) != 0;
-    const bool shadow = (a.flags & SC_TRACE_SHADOW) != 0 && a.slot_fp != nullptr;
+    const bool shadow_flag = (a.flags & SC_TRACE_SHADOW) != 0;
 
     uint2 spill[kMaxDepth - STACK + 1];
+
+    // The scene of the lane's current ray: uniform for a single scene, per
+    // lane in a batch (set when the lane takes a ray).
+    const unsigned char* s_nodes = a.nodes;
+    const float* s_tris = a.tris;
+    const uint64_t* s_codebook = a.codebook;
+    const uint64_t* s_side = a.side_masks;
+    const float* s_rays = a.rays;
+    uint32_t s_full = a.full_start, s_root = a.root;
+    float s_bound = a.origin_bound;
+    sc_hit* s_hits = a.hits;
+    uint32_t* s_extra = a.extra;
+    uint32_t* s_fp = a.slot_fp;
 
     // The rays are split into a.parts contiguous partitions, one queue counter
     // each. Workgroups are dispatched round-robin over the XCDs, so a wave
@@ -181,12 +194,28 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
                 if (cursor >= end && more) more = fetch();
                 if (cursor < end) {
                     if (!has) {
-                        const uint32_t id = cursor + (uint32_t)__popcll(idle & lanes_below);
-                        if (id < end) {
-                            const float4 r0 = reinterpret_cast<const float4*>(a.rays)[2 * (size_t)id];
-                            const float4 r1 = reinterpret_cast<const float4*>(a.rays)[2 * (size_t)id + 1];
+                        const uint32_t gid = cursor + (uint32_t)__popcll(idle & lanes_below);
+                        if (gid < end) {
+                            uint32_t id = gid;
+                            if constexpr (BATCH) {
+                                // item holding this ray: the last one whose first ray is <= gid
+                                uint32_t lo = 0, hi = a.n_items;
+                                while (hi - lo > 1) {
+                                    const uint32_t mid = (lo + hi) >> 1;
+                                    if (a.items[mid].ray_begin <= gid) lo = mid;
+                                    else hi = mid;
+                                }
+                                const BatchItem& it = a.items[lo];
+                                s_nodes = it.nodes; s_tris = it.tris; s_codebook = it.codebook;
+                                s_side = it.side_masks; s_rays = it.rays; s_full = it.full_start;
+                                s_root = it.root; s_bound = it.origin_bound; s_hits = it.hits;
+                                s_extra = it.extra; s_fp = it.slot_fp;
+                                id = gid - it.ray_begin;
+                            }
+                            const float4 r0 = reinterpret_cast<const float4*>(s_rays)[2 * (size_t)id];
+                            const float4 r1 = reinterpret_cast<const float4*>(s_rays)[2 * (size_t)id + 1];
                             ray_id = id;
-                            if (ray_is_valid(r0, r1) && a.root != kEmptyRef) {
+                            if (ray_is_valid(r0, r1) && s_root != kEmptyRef) {
                                 r.ox = r0.x; r.oy = r0.y; r.oz = r0.z; r.tmin = r0.w;
                                 r.dx = r1.x; r.dy = r1.y; r.dz = r1.z;
                                 r.ix = 1.0f / r.dx; r.iy = 1.0f / r.dy; r.iz = 1.0f / r.dz;
@@ -194,14 +223,14 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
                                 best = kNoHit;
                                 box_tests = tri_tests = mask_tests = mask_culls = 0;
                                 use_mask = (MODE != kModeNone) && use_flags &&
-                                           !(mx(mx(fabsf(r.ox), fabsf(r.oy)), fabsf(r.oz)) > a.origin_bound);
+                                           !(mx(mx(fabsf(r.ox), fabsf(r.oy)), fabsf(r.oz)) > s_bound);
                                 sp = 0;
-                                ref = a.root;
+                                ref = s_root;
                                 has = true;
                             } else {
-                                reinterpret_cast<uint4*>(a.hits)[id] =
+                                reinterpret_cast<uint4*>(s_hits)[id] =
                                     make_uint4(kNoHit, __float_as_uint(__builtin_inff()), 0u, 0u);
-                                if (a.extra) reinterpret_cast<uint2*>(a.extra)[id] = make_uint2(0u, 0u);
+                                if (s_extra) reinterpret_cast<uint2*>(s_extra)[id] = make_uint2(0u, 0u);
                             }
                         }
                     }
@@ -222,7 +251,7 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
                 for (uint32_t k = 0; k < count; ++k) {
                     ++tri_tests;
                     const float4* tp = reinterpret_cast<const float4*>(
-                        reinterpret_cast<const unsigned char*>(a.tris) + (size_t)(first + k) * kTriBytes);
+                        reinterpret_cast<const unsigned char*>(s_tris) + (size_t)(first + k) * kTriBytes);
                     const float4 q0 = tp[0], q1 = tp[1], q2 = tp[2];
                     const float v0x = q0.x, v0y = q0.y, v0z = q0.z;
                     const float e1x = q0.w, e1y = q1.x, e1z = q1.y;
@@ -250,7 +279,7 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
                     }
                 }
             } else {
-                const unsigned char* np = a.nodes + (size_t)ref * kStride;
+                const unsigned char* np = s_nodes + (size_t)ref * kStride;
                 const float4 n0 = reinterpret_cast<const float4*>(np)[0];
                 const float4 n1 = reinterpret_cast<const float4*>(np)[1];
                 const float4 n2 = reinterpret_cast<const float4*>(np)[2];
@@ -275,16 +304,16 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
                                 om = reinterpret_cast<const uint64_t*>(np + 64) + c * W;
                             } else if constexpr (MODE == kModeLut) {
                                 const uint32_t idx = c ? (n3.z >> 16) : (n3.z & 0xFFFFu);
-                                if (idx >= a.full_start) continue;
-                                om = a.codebook + (size_t)idx * W;
+                                if (idx >= s_full) continue;
+                                om = s_codebook + (size_t)idx * W;
                             } else if constexpr (MODE == kModeLutLds) {
                                 const uint32_t idx = c ? (n3.z >> 16) : (n3.z & 0xFFFFu);
-                                if (idx >= a.full_start) continue;
+                                if (idx >= s_full) continue;
                                 om = lds_cb + idx * W;
                             } else {
                                 const uint32_t ms = c ? n3.w : n3.z;
                                 if (ms == kNoMask) continue;
-                                om = a.side_masks + (size_t)ms * W;
+                                om = s_side + (size_t)ms * W;
                             }
                             ++mask_tests;
                             const float* lo = c ? lo1 : lo0;
@@ -322,7 +351,7 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
                             }
                             if (!any) {
                                 ++mask_culls;
-                                if (shadow) atomicAdd(&a.slot_fp[2 * (size_t)ref + c], 1u);
+                                if (shadow_flag && s_fp) atomicAdd(&s_fp[2 * (size_t)ref + c], 1u);
                                 if (cull) {
                                     if (c) h1 = false;
                                     else h0 = false;
@@ -356,9 +385,9 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
                 }
                 if (!found) {
                     const float tout = (best == kNoHit) ? __builtin_inff() : best_t;
-                    reinterpret_cast<uint4*>(a.hits)[ray_id] =
+                    reinterpret_cast<uint4*>(s_hits)[ray_id] =
                         make_uint4(best, __float_as_uint(tout), box_tests, tri_tests);
-                    if (a.extra) reinterpret_cast<uint2*>(a.extra)[ray_id] = make_uint2(mask_tests, mask_culls);
+                    if (s_extra) reinterpret_cast<uint2*>(s_extra)[ray_id] = make_uint2(mask_tests, mask_culls);
                     has = false;
                 }
             }
@@ -366,40 +395,52 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
     }
 }
 
-template <uint32_t MODE, int R, int BLOCK, int STACK>
+template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH>
 hipError_t launch_one(const TraceLaunch& a, hipStream_t s) {
     static int resident = 0;  // blocks resident on the whole device, computed once per instance
     if (resident == 0) {
         int dev = 0, cus = 0, per_cu = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_kernel<MODE, R, BLOCK, STACK>, BLOCK, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_kernel<MODE, R, BLOCK, STACK, BATCH>, BLOCK, 0);
         resident = (cus > 0 && per_cu > 0) ? cus * per_cu : 1024;
     }
     const uint32_t waves = (a.n + kWave - 1) / kWave;
     uint32_t blocks = (waves + BLOCK / kWave - 1) / (BLOCK / kWave);
     blocks = blocks < (uint32_t)resident ? blocks : (uint32_t)resident;
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(kQueueParts), 0, s, a.queue, kQueueParts);
-    hipLaunchKernelGGL((trace_kernel<MODE, R, BLOCK, STACK>), dim3(blocks), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((trace_kernel<MODE, R, BLOCK, STACK, BATCH>), dim3(blocks), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
-template <int BLOCK, int STACK>
+template <int BLOCK, int STACK, bool BATCH>
 hipError_t launch_cfg(const TraceLaunch& a, hipStream_t s) {
     switch (a.mode) {
-        case SC_MASK_NONE: return launch_one<kModeNone, 6, BLOCK, STACK>(a, s);
+        case SC_MASK_NONE: return launch_one<kModeNone, 6, BLOCK, STACK, BATCH>(a, s);
         case SC_MASK_RAW:
-            return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK>(a, s) : launch_one<kModeRaw, 6, BLOCK, STACK>(a, s);
+            return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK, BATCH>(a, s)
+                            : launch_one<kModeRaw, 6, BLOCK, STACK, BATCH>(a, s);
         case SC_MASK_LUT:
-            if ((size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
-                return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK>(a, s)
-                                : launch_one<kModeLutLds, 6, BLOCK, STACK>(a, s);
-            return a.R == 4 ? launch_one<kModeLut, 4, BLOCK, STACK>(a, s) : launch_one<kModeLut, 6, BLOCK, STACK>(a, s);
+            if (!BATCH && (size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
+                return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK, false>(a, s)
+                                : launch_one<kModeLutLds, 6, BLOCK, STACK, false>(a, s);
+            return a.R == 4 ? launch_one<kModeLut, 4, BLOCK, STACK, BATCH>(a, s)
+                            : launch_one<kModeLut, 6, BLOCK, STACK, BATCH>(a, s);
         case SC_MASK_SPARSE:
-            return a.R == 4 ? launch_one<kModeSparse, 4, BLOCK, STACK>(a, s)
-                            : launch_one<kModeSparse, 6, BLOCK, STACK>(a, s);
+            return a.R == 4 ? launch_one<kModeSparse, 4, BLOCK, STACK, BATCH>(a, s)
+                            : launch_one<kModeSparse, 6, BLOCK, STACK, BATCH>(a, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <bool BATCH>
+hipError_t launch_any(const TraceLaunch& a, hipStream_t s) {
+    if (a.block == 256 && a.stack == 8) return launch_cfg<256, 8, BATCH>(a, s);
+    if (a.block == 128 && a.stack == 8) return launch_cfg<128, 8, BATCH>(a, s);
+    if (a.block == 256 && a.stack == 12) return launch_cfg<256, 12, BATCH>(a, s);
+    if (a.block == 256 && a.stack == 4) return launch_cfg<256, 4, BATCH>(a, s);
+    if (a.block == 128 && a.stack == 16) return launch_cfg<128, 16, BATCH>(a, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -413,12 +454,7 @@ bool trace_config_supported(uint32_t block, uint32_t stack) {
 hipError_t launch_trace(const TraceLaunch& a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     if (a.chunk < 1 || !a.queue || a.parts < 1 || a.parts > kQueueParts) return hipErrorInvalidValue;
-    if (a.block == 256 && a.stack == 8) return launch_cfg<256, 8>(a, s);
-    if (a.block == 128 && a.stack == 8) return launch_cfg<128, 8>(a, s);
-    if (a.block == 256 && a.stack == 12) return launch_cfg<256, 12>(a, s);
-    if (a.block == 256 && a.stack == 4) return launch_cfg<256, 4>(a, s);
-    if (a.block == 128 && a.stack == 16) return launch_cfg<128, 16>(a, s);
-    return hipErrorInvalidValue;
+    return a.items ? launch_any<true>(a, s) : launch_any<false>(a, s);
 }
 
 }  // namespace sc

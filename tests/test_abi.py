@@ -23,7 +23,8 @@ def test_header_declares_the_api():
     for must in ("sc_create", "sc_destroy", "sc_scene_build", "sc_scene_destroy", "sc_scene_get_info",
                  "sc_scene_export", "sc_trace", "sc_raymask_lut", "sc_compress_masks",
                  "sc_status_string", "sc_last_error", "sc_build_params_default", "sc_set_tune",
-                 "sc_get_tune"):
+                 "sc_get_tune", "sc_trace_batch", "sc_batch_create", "sc_batch_launch",
+                 "sc_batch_destroy", "sc_bvh_build_host"):
         assert must in names
 
 
@@ -62,6 +63,9 @@ def test_null_arguments_rejected_before_hip():
     assert lib.sc_raymask_lut(None, 6, None, None) == 1
     assert lib.sc_compress_masks(None, 6, None, 64, None, 0, None, None) == 1
     assert lib.sc_set_tune(None, None) == 1 and lib.sc_get_tune(None, None) == 1
+    assert lib.sc_trace_batch(None, None, 0, 0, None) == 1
+    assert lib.sc_batch_create(None, None, 0, 0, None) == 1
+    assert lib.sc_batch_launch(None, None) == 1 and lib.sc_batch_destroy(None) == 0
     assert lib.sc_destroy(None) == 0 and lib.sc_scene_destroy(None) == 0
 
 

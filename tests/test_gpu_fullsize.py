@@ -183,3 +183,43 @@ def test_curly_12m_sampled_rays_bit_exact(request, curly, curly_dev):
     assert (curly_dev["export_lut"]["cidx"] == idx).all()
     _compare(curly_dev["lut"], oracle.trace(tris, bvh, sample, mode="lut", R=6, codebook=cb, cidx=idx,
                                             origin_bound=curly["ob"], nthreads=curly["nt"]), sel)
+
+
+# --------------------------------------------------------------------- batch64
+@pytest.fixture(scope="module")
+def batch64(request):
+    _say(request, "batch64: generating 64 scenes")
+    specs = scenes.batch_specs(64)
+    return specs, [scenes.batch_scene(sp) for sp in specs]
+
+
+@pytest.mark.timeout(900)
+def test_batch64_graph_equals_per_scene_and_oracle(request, ctx, batch64):
+    import torch
+    from paper_2305_08343_amd import binding
+    specs, data = batch64
+    _say(request, f"batch64: build 64 scenes (raw R=6), graph launch over {sum(r.shape[0] for _, r in data)} rays")
+    built = [binding.Scene(ctx, t, R=6, mode="raw") for t, _ in data]
+    b = binding.Batch(ctx, [(s, r) for s, (_, r) in zip(built, data)], graph=True)
+    b.launch()
+    b.launch()
+    torch.cuda.synchronize()
+    for k, s in enumerate(built):
+        single = s.trace(b.rays[k]).numpy()
+        batched = b.results(k).numpy()
+        for f in ("prim", "box_tests", "tri_tests", "mask_tests", "mask_culls"):
+            assert (single[f] == batched[f]).all(), (k, f)
+        assert (single["t"].view(np.uint32) == batched["t"].view(np.uint32)).all()
+    nt = oracle.cpu_threads()
+    for k in (0, 1, 2):  # one scene of each kind against the oracle
+        t, r = data[k]
+        _say(request, f"batch64: oracle check of scene {k} ({specs[k].kind}, {t.shape[0]} tris)")
+        bvh = oracle.bvh_build(t)
+        ob, delta = oracle.default_bounds(t)
+        sel = slice(None, None, 8)
+        ora = oracle.trace(t, bvh, r[sel], mode="raw", R=6, masks=oracle.object_masks(t, bvh, 6, delta, nthreads=nt),
+                           origin_bound=ob, nthreads=nt)
+        _compare(b.results(k).numpy(), ora, sel)
+    b.close()
+    for s in built:
+        s.close()
