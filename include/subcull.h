@@ -246,6 +246,45 @@ sc_status sc_raymask_lut(sc_ctx* ctx, uint32_t R, uint64_t* d_out, void* stream)
 sc_status sc_compress_masks(sc_ctx* ctx, uint32_t R, const uint64_t* d_codebook, uint32_t K,
                             const uint64_t* d_masks, uint32_t n, uint16_t* d_idx, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned mask placement. A small MLP predicts, from a child slot's geometry,
+ * how many false-positive box hits its mask would remove; masks go to the
+ * slots with the highest predictions under a memory budget (SC_MASK_SPARSE).
+ * Skipping a mask is always conservative, so any placement keeps the exact
+ * hits of the method with all masks.
+ * ------------------------------------------------------------------------ */
+#define SC_MLP_PARAMS 5057 /* W1[64][12] b1[64] W2[64][64] b2[64] W3[64] b3 */
+
+/* 12 float features per child slot (d_out [2*n_inner][12], device), for a
+ * scene built with masks (RAW, LUT or SPARSE): extents relative to the parent
+ * box (x, y, z), log2(area / root area) / 32, parent depth / tree depth,
+ * log2(1 + triangles) / 24, occupied fraction of its exact mask, and the
+ * means over its triangles of thinness (1 - 4 sqrt(3) area / sum of squared
+ * edges) and of |cos| between the longest edge and the x, y, z axes, then
+ * 1 if the child is a leaf. Synchronises `stream`. */
+sc_status sc_slot_features(const sc_scene* scene, float* d_out, void* stream);
+
+/* y[n] = MLP(x[n][12]); d_act [n][128] receives both pre-activation layers
+ * for the backward pass, or may be NULL. */
+sc_status sc_mlp_forward(sc_ctx* ctx, const float* d_params, const float* d_x, uint32_t n, float* d_y,
+                         float* d_act, void* stream);
+
+/* Gradient of the mean squared error (1/n) sum (y - t)^2 with respect to the
+ * parameters (d_grad [SC_MLP_PARAMS]), from the forward pass's d_y and d_act.
+ * d_work: device scratch of n * 130 floats. d_loss (one float) or NULL.
+ * Batch sums run in a fixed order, so the result is deterministic. */
+sc_status sc_mlp_backward(sc_ctx* ctx, const float* d_params, const float* d_x, const float* d_act,
+                          const float* d_y, const float* d_t, uint32_t n, float* d_grad, float* d_work,
+                          float* d_loss, void* stream);
+
+/* One Adam step (Kingma & Ba 2015) on all parameters; step counts from 1. */
+sc_status sc_mlp_adam(sc_ctx* ctx, float* d_params, const float* d_grad, float* d_m, float* d_v, uint32_t step,
+                      float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Host: mark the n_place slots with the highest scores (ties: lower slot
+ * first) in h_placement [n_slots] (1 = carries a mask). */
+sc_status sc_place_top(const float* h_scores, uint32_t n_slots, uint32_t n_place, uint8_t* h_placement);
+
 const char* sc_status_string(sc_status s);
 const char* sc_last_error(void);  /* thread-local detail of the last failure */
 

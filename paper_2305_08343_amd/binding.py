@@ -92,6 +92,14 @@ _SIGS = {
     "sc_raymask_lut": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "sc_compress_masks": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
                                     C.c_uint32, C.c_void_p, C.c_void_p]),
+    "sc_slot_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sc_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]),
+    "sc_mlp_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sc_mlp_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
+                              C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]),
+    "sc_place_top": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p]),
     "sc_status_string": (C.c_char_p, [C.c_int]),
     "sc_last_error": (C.c_char_p, []),
 }
@@ -179,6 +187,24 @@ class Context:
         t = sc_tune()
         _check(load().sc_get_tune(self.handle, C.byref(t)), "sc_get_tune")
         return {"block": t.block, "stack": t.stack, "chunk": t.chunk, "parts": t.parts}
+
+    # ---- placement MLP (device tensors in, device tensors out)
+    def mlp_forward(self, params, x, act=None, stream=None):
+        import torch
+        n = x.shape[0]
+        y = torch.empty(max(n, 1), dtype=torch.float32, device=x.device)
+        _check(load().sc_mlp_forward(self.handle, _ptr(params), _ptr(x), n, _ptr(y), _ptr(act),
+                                     _stream_ptr(stream)), "sc_mlp_forward")
+        return y[:n]
+
+    def mlp_backward(self, params, x, act, y, t, grad, work, loss=None, stream=None):
+        _check(load().sc_mlp_backward(self.handle, _ptr(params), _ptr(x), _ptr(act), _ptr(y), _ptr(t),
+                                      x.shape[0], _ptr(grad), _ptr(work), _ptr(loss), _stream_ptr(stream)),
+               "sc_mlp_backward")
+
+    def mlp_adam(self, params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(load().sc_mlp_adam(self.handle, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1,
+                                  beta2, eps, _stream_ptr(stream)), "sc_mlp_adam")
 
     def raymask_lut(self, R: int, stream=None):
         """Device ray-mask LUT as uint64 numpy array [R^6, W] (copies back)."""
@@ -299,6 +325,14 @@ class Scene:
         out["codebook"] = out["codebook"][:K]
         return out
 
+    def features(self, stream=None):
+        """Per-slot placement features, device float32 [2*n_inner, 12]."""
+        import torch
+        S = 2 * self.info["n_inner"]
+        out = torch.empty((max(S, 1), 12), dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        _check(load().sc_slot_features(self.handle, _ptr(out), _stream_ptr(stream)), "sc_slot_features")
+        return out[:S]
+
     def trace(self, rays, *, cull: bool = True, shadow: bool = False, extra: bool = True,
               slot_fp=None, hits=None, extra_out=None, stream=None) -> TraceResult:
         """Trace device rays [n, 8] float32; results stay on the device."""
@@ -317,6 +351,15 @@ class Scene:
                                _ptr(extra_out) if extra else None, _ptr(slot_fp),
                                _stream_ptr(stream)), "sc_trace")
         return TraceResult(hits[:n], extra_out[:n] if extra else None)
+
+
+def place_top(scores, n_place: int) -> np.ndarray:
+    """uint8 placement marking the n_place highest scores (ties: lower index)."""
+    scores = np.ascontiguousarray(scores, np.float32)
+    out = np.zeros(max(scores.size, 1), np.uint8)
+    _check(load().sc_place_top(scores.ctypes.data_as(C.c_void_p), scores.size, n_place,
+                               out.ctypes.data_as(C.c_void_p)), "sc_place_top")
+    return out[:scores.size]
 
 
 class Batch:

@@ -709,6 +709,102 @@ sc_status sc_get_tune(const sc_ctx* ctx, sc_tune* out) {
     return SC_OK;
 }
 
+sc_status sc_slot_features(const sc_scene* scene, float* d_out, void* stream) {
+    if (!scene || !d_out) return fail(SC_ERR_INVALID_ARG, "scene and d_out must be non-NULL");
+    const sc_scene_info& I = scene->info;
+    if (I.n_inner == 0) return SC_OK;
+    if (!scene->masks) return fail(SC_ERR_INVALID_ARG, "features need a scene built with masks");
+    sc_status st = use_device(scene->ctx->device);
+    if (st != SC_OK) return st;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    sc_ctx* ctx = scene->ctx;
+    const HostBVH& B = scene->bvh;
+    std::vector<uint8_t> depth(B.n_inner, 0);
+    depth[0] = 1;
+    for (uint32_t i = 0; i < B.n_inner; ++i)  // DFS pre-order: parents come first
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t r = B.cref[2 * (size_t)i + c];
+            if (!(r & kLeafBit)) depth[r] = (uint8_t)(depth[i] + 1);
+        }
+    double lo[3], hi[3];
+    for (int j = 0; j < 3; ++j) {
+        lo[j] = std::min(B.cbox[j], B.cbox[6 + j]);
+        hi[j] = std::max(B.cbox[3 + j], B.cbox[9 + j]);
+    }
+    const double root_area = 2.0 * (((hi[0] - lo[0]) * (hi[1] - lo[1]) + (hi[1] - lo[1]) * (hi[2] - lo[2])) +
+                                     (hi[2] - lo[2]) * (hi[0] - lo[0]));
+    const uint32_t n = I.n_tris;
+    const size_t pre_bytes = (size_t)4 * n * 8, scr_bytes = scan_scratch_doubles(n, 4) * 8;
+    const size_t rng_bytes = B.range.size() * 4;
+    auto* d_pre = static_cast<double*>(dev_alloc(ctx, pre_bytes, s));
+    auto* d_scr = static_cast<double*>(dev_alloc(ctx, scr_bytes, s));
+    auto* d_rng = static_cast<uint32_t*>(dev_alloc(ctx, rng_bytes, s));
+    auto* d_dep = static_cast<uint8_t*>(dev_alloc(ctx, depth.size(), s));
+    hipError_t e = (d_pre && d_scr && d_rng && d_dep) ? hipSuccess : hipErrorOutOfMemory;
+    if (e == hipSuccess) e = hipMemcpyAsync(d_rng, B.range.data(), rng_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_dep, depth.data(), depth.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_tri_shape(scene->tris, n, d_pre, s);
+    if (e == hipSuccess) e = launch_prefix_scan(d_pre, n, 4, d_scr, s);
+    if (e == hipSuccess)
+        e = launch_slot_features(I.R, scene->nodes, I.node_bytes, d_rng, d_dep, I.depth, scene->masks, d_pre, n,
+                                 root_area, I.n_inner, d_out, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(ctx, d_pre, pre_bytes, s);
+    dev_free(ctx, d_scr, scr_bytes, s);
+    dev_free(ctx, d_rng, rng_bytes, s);
+    dev_free(ctx, d_dep, depth.size(), s);
+    if (e == hipErrorOutOfMemory) return fail(SC_ERR_OOM, "feature buffers");
+    return e == hipSuccess ? SC_OK : hip_fail(e, "slot features");
+}
+
+sc_status sc_mlp_forward(sc_ctx* ctx, const float* d_params, const float* d_x, uint32_t n, float* d_y,
+                         float* d_act, void* stream) {
+    if (!ctx || !d_params || (n && (!d_x || !d_y))) return fail(SC_ERR_INVALID_ARG, "NULL argument");
+    sc_status st = use_device(ctx->device);
+    if (st != SC_OK) return st;
+    const hipError_t e = launch_mlp_forward(d_params, d_x, n, d_y, d_act, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SC_OK : hip_fail(e, "mlp forward");
+}
+
+sc_status sc_mlp_backward(sc_ctx* ctx, const float* d_params, const float* d_x, const float* d_act,
+                          const float* d_y, const float* d_t, uint32_t n, float* d_grad, float* d_work,
+                          float* d_loss, void* stream) {
+    if (!ctx || !d_params || !d_x || !d_act || !d_y || !d_t || !d_grad || !d_work || n == 0)
+        return fail(SC_ERR_INVALID_ARG, "NULL argument or empty batch");
+    sc_status st = use_device(ctx->device);
+    if (st != SC_OK) return st;
+    const hipError_t e =
+        launch_mlp_backward(d_params, d_x, d_act, d_y, d_t, n, d_grad, d_work, d_loss, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SC_OK : hip_fail(e, "mlp backward");
+}
+
+sc_status sc_mlp_adam(sc_ctx* ctx, float* d_params, const float* d_grad, float* d_m, float* d_v, uint32_t step,
+                      float lr, float beta1, float beta2, float eps, void* stream) {
+    if (!ctx || !d_params || !d_grad || !d_m || !d_v || step == 0) return fail(SC_ERR_INVALID_ARG, "bad argument");
+    sc_status st = use_device(ctx->device);
+    if (st != SC_OK) return st;
+    const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    const hipError_t e = launch_adam(d_params, d_grad, d_m, d_v, lr, beta1, beta2, eps, bc1, bc2,
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SC_OK : hip_fail(e, "adam");
+}
+
+sc_status sc_place_top(const float* h_scores, uint32_t n_slots, uint32_t n_place, uint8_t* h_placement) {
+    if ((n_slots && (!h_scores || !h_placement)) || n_place > n_slots) return fail(SC_ERR_INVALID_ARG, "bad argument");
+    std::vector<uint32_t> idx(n_slots);
+    for (uint32_t i = 0; i < n_slots; ++i) idx[i] = i;
+    auto better = [&](uint32_t a, uint32_t b) {
+        const float sa = h_scores[a], sb = h_scores[b];
+        if (sa != sb) return sa > sb;
+        return a < b;
+    };
+    if (n_place < n_slots) std::nth_element(idx.begin(), idx.begin() + n_place, idx.end(), better);
+    std::memset(h_placement, 0, n_slots);
+    for (uint32_t i = 0; i < n_place; ++i) h_placement[idx[i]] = 1;
+    return SC_OK;
+}
+
 sc_status sc_raymask_lut(sc_ctx* ctx, uint32_t R, uint64_t* d_out, void* stream) {
     if (!ctx || !d_out) return fail(SC_ERR_INVALID_ARG, "ctx and d_out must be non-NULL");
     if (R != 4 && R != 6) return fail(SC_ERR_INVALID_ARG, "R must be 4 or 6");

@@ -117,4 +117,19 @@ hipError_t launch_pack_raw(uint32_t R, const uint64_t* masks, uint32_t n_inner, 
                            hipStream_t s);
 hipError_t launch_pack_lut(const uint16_t* idx, uint32_t n_inner, unsigned char* nodes, hipStream_t s);
 
+// learned placement
+constexpr int kMlpParams = SC_MLP_PARAMS;
+hipError_t launch_tri_shape(const float* rec, uint32_t n, double* out, hipStream_t s);
+size_t scan_scratch_doubles(uint32_t n, uint32_t rows);
+hipError_t launch_prefix_scan(double* a, uint32_t n, uint32_t rows, double* scratch, hipStream_t s);
+hipError_t launch_slot_features(uint32_t R, const unsigned char* nodes, uint32_t stride, const uint32_t* range,
+                                const uint8_t* depth, uint32_t max_depth, const uint64_t* masks,
+                                const double* prefix, uint32_t n, double root_area, uint32_t n_inner, float* out,
+                                hipStream_t s);
+hipError_t launch_mlp_forward(const float* prm, const float* x, uint32_t n, float* y, float* act, hipStream_t s);
+hipError_t launch_mlp_backward(const float* prm, const float* x, const float* act, const float* y, const float* t,
+                               uint32_t n, float* grad, float* work, float* loss, hipStream_t s);
+hipError_t launch_adam(float* prm, const float* grad, float* m, float* v, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2, hipStream_t s);
+
 }  // namespace sc

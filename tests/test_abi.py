@@ -24,7 +24,8 @@ def test_header_declares_the_api():
                  "sc_scene_export", "sc_trace", "sc_raymask_lut", "sc_compress_masks",
                  "sc_status_string", "sc_last_error", "sc_build_params_default", "sc_set_tune",
                  "sc_get_tune", "sc_trace_batch", "sc_batch_create", "sc_batch_launch",
-                 "sc_batch_destroy", "sc_bvh_build_host"):
+                 "sc_batch_destroy", "sc_bvh_build_host", "sc_slot_features", "sc_mlp_forward",
+                 "sc_mlp_backward", "sc_mlp_adam", "sc_place_top"):
         assert must in names
 
 
@@ -96,3 +97,13 @@ def test_no_device_is_reported(monkeypatch):
         pytest.skip("a GPU is present")
     h = C.c_void_p()
     assert B.load().sc_create(0, None, C.byref(h)) == 2
+
+
+def test_place_top_host():
+    import numpy as np
+    scores = np.array([0.5, 2.0, -1.0, 2.0, 0.5, 3.0], np.float32)
+    assert list(B.place_top(scores, 3)) == [0, 1, 0, 1, 0, 1]
+    assert list(B.place_top(scores, 4)) == [1, 1, 0, 1, 0, 1]  # tie at 0.5: lower slot first
+    assert B.place_top(scores, 0).sum() == 0 and B.place_top(scores, 6).sum() == 6
+    with pytest.raises(B.SubcullError):
+        B.place_top(scores, 7)
