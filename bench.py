@@ -209,6 +209,37 @@ def run_batch64(args, ctx):
     print(json.dumps(line), flush=True)
 
 
+def run_placement(args, ctx):
+    """Learned mask placement: the MLP is trained on the GPU on per-slot
+    false-positive counts of generated strand / curly / thin-quad scenes
+    (100k-2M tris), then places R = 6 masks at 0.5, 1 and 2 bytes per inner
+    node on held-out 5M-tri scenes with 4M rays; compared with all masks, no
+    masks, the SA x emptiness heuristic, random and true-count placement."""
+    from paper_2305_08343_amd import placement, scenes
+    t0 = time.perf_counter()
+    specs = scenes.placement_specs(args.place_scenes)
+    held = [scenes.placement_heldout(k) for k in range(args.place_heldout)]
+    log(f"placement: {len(specs)} training scenes, {len(held)} held-out scenes")
+    params, hist, res = placement.run_experiment(ctx, specs, held, epochs=20, log=log)
+    total_s = time.perf_counter() - t0
+    table = [[{k: v for k, v in e.__dict__.items()} for e in r] for r in res]
+    head = {(e.name, e.beta): e for e in res[0]}[("learned", 1.0)]
+    line = {
+        "metric": METRIC, "value": head.rays_per_s, "unit": "rays/s", "n_gpus": 1,
+        "steps": 5, "warmup": 1, "ms_per_step": head.ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"placement: MLP 12-64-64-1 trained on {len(specs)} generated scenes "
+                               "(100k-2M tris, 262,144 rays each), R=6 masks placed by predicted "
+                               "false positives at 1 byte per inner node on a held-out 5M-tri hair "
+                               "scene with 4M rays (value); all budgets and baselines in 'placement'",
+                   "n_train_scenes": len(specs)},
+        "tests_per_ray": head.tests_per_ray,
+        "train_loss": hist, "seconds_total": total_s,
+        "placement": table,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,7 +249,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tune", default="", help="block,stack,chunk,parts of the traversal launch")
-    ap.add_argument("--workload", default="hair_1m", choices=["hair_1m", "batch64"])
+    ap.add_argument("--workload", default="hair_1m", choices=["hair_1m", "batch64", "placement"])
+    ap.add_argument("--place-scenes", type=int, default=200)
+    ap.add_argument("--place-heldout", type=int, default=2)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -237,6 +270,11 @@ def main():
         if args.modes == "raw6,none,raw4":
             args.modes = "raw6,none"
         run_batch64(args, ctx)
+        ctx.close()
+        return
+    if args.workload == "placement":
+        ctx = binding.Context(0)
+        run_placement(args, ctx)
         ctx.close()
         return
     t0 = time.perf_counter()

@@ -1,0 +1,219 @@
+"""Learned mask placement (growth direction of the culling method).
+
+Masks cost memory (27 bytes per slot at R = 6) and a test per slab hit; most
+of the false-positive removal comes from few slots. A small MLP predicts,
+from 12 geometric features of a child slot, how many false-positive slab hits
+the slot's mask removes; masks are then placed on the highest-scoring slots
+until a budget of `beta` bytes per inner node is spent (SC_MASK_SPARSE). A
+slot without a mask is traversed exactly as in plain BVH traversal, so every
+placement returns the same hits as all masks and as no masks.
+
+Training data: for each training scene, the shadow trace (culling off,
+masks evaluated) counts per slot the slab hits whose mask test fails; the
+target is log2(1 + 1e6 * count / rays). Training runs on the GPU through the
+library's MLP kernels (forward, backward, Adam). This module only
+orchestrates: sampling of batches, the label transform and bookkeeping use
+torch tensors as plumbing.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import binding
+
+MASK_BYTES_R6 = 27  # 216 bits
+
+
+def he_init(seed: int) -> np.ndarray:
+    """He-normal weights, zero biases, in the library's parameter layout."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(5057, np.float32)
+    p[0:768] = rng.normal(0.0, math.sqrt(2.0 / 12), 768)              # W1 [64][12]
+    p[832:4928] = rng.normal(0.0, math.sqrt(2.0 / 64), 4096)          # W2 [64][64]
+    p[4992:5056] = rng.normal(0.0, math.sqrt(2.0 / 64), 64)           # W3 [64]
+    return p
+
+
+def slot_dataset(ctx, tris, rays, R: int = 6, max_slots: int | None = None, seed: int = 0):
+    """Features [S, 12] and targets [S] (device tensors) of one scene."""
+    import torch
+    scene = binding.Scene(ctx, tris, R=R, mode="raw")
+    S = 2 * scene.info["n_inner"]
+    fp = torch.zeros(max(S, 1), dtype=torch.int32, device=f"cuda:{ctx.device}")
+    rays_dev = torch.from_numpy(np.ascontiguousarray(rays, np.float32)).cuda(ctx.device)
+    scene.trace(rays_dev, cull=False, shadow=True, slot_fp=fp, extra=False)
+    X = scene.features()
+    y = torch.log2(1.0 + 1e6 * fp[:S].double() / rays.shape[0]).float()
+    info = dict(scene.info)
+    scene.close()
+    if max_slots is not None and S > max_slots:
+        idx = torch.from_numpy(np.sort(np.random.default_rng(seed).choice(S, max_slots, replace=False))).cuda()
+        X, y = X[idx], y[idx]
+    return X.contiguous(), y.contiguous(), info
+
+
+def train(ctx, X, y, *, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, seed: int = 0, log=None):
+    """Adam on the mean squared error; returns (params device tensor, loss history)."""
+    import torch
+    dev = X.device
+    N = X.shape[0]
+    params = torch.from_numpy(he_init(seed)).to(dev)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    act = torch.empty((batch, 128), dtype=torch.float32, device=dev)
+    grad = torch.empty_like(params)
+    work = torch.empty(batch * 130, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(seed)
+    step, hist = 0, []
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(N)).to(dev)
+        acc, nb = 0.0, 0
+        for b0 in range(0, N - batch + 1, batch):
+            idx = perm[b0:b0 + batch]
+            xb, yb = X[idx].contiguous(), y[idx].contiguous()
+            pred = ctx.mlp_forward(params, xb, act)
+            ctx.mlp_backward(params, xb, act, pred, yb, grad, work, loss)
+            step += 1
+            ctx.mlp_adam(params, grad, m, v, step, lr=lr)
+            if nb % 64 == 0:
+                acc += loss.item()
+            nb += 1
+        hist.append(acc / max(1, (nb + 63) // 64))
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: {nb} steps, sampled mse {hist[-1]:.4f}")
+    return params, hist
+
+
+def predict(ctx, params, X, chunk: int = 1 << 20):
+    import torch
+    out = []
+    for i in range(0, X.shape[0], chunk):
+        out.append(ctx.mlp_forward(params, X[i:i + chunk].contiguous()))
+    return torch.cat(out) if out else torch.empty(0, device=X.device)
+
+
+def budget_masks(beta: float, n_inner: int, mask_bytes: int = MASK_BYTES_R6) -> int:
+    """Masks affordable with beta bytes per inner node."""
+    return int(math.floor(beta * n_inner / mask_bytes))
+
+
+def heuristic_scores(X) -> np.ndarray:
+    """Surface area times emptiness: SA(N) (1 - O_m(N)/R^3), the paper's
+    mask importance (Sect. 3.2.2) turned towards masks that can cull."""
+    f = X.cpu().numpy().astype(np.float64)
+    return (np.exp2(f[:, 3] * 32.0) * (1.0 - f[:, 6])).astype(np.float32)
+
+
+@dataclass
+class Evaluation:
+    name: str
+    beta: float | None
+    n_masks: int
+    tests_per_ray: float
+    box_per_ray: float
+    tri_per_ray: float
+    ms: float
+    rays_per_s: float
+    hits_equal: bool
+
+
+def evaluate(ctx, tris, rays_dev, placement, ref_hits, *, R: int = 6, name: str = "", beta=None,
+             reps: int = 5, mode: str = "sparse") -> Evaluation:
+    """Trace with a placement (or mode "raw"/"none") and report counts and speed."""
+    import torch
+    if mode == "sparse":
+        scene = binding.Scene(ctx, tris, R=R, mode="sparse", placement=placement)
+    else:
+        scene = binding.Scene(ctx, tris, R=R, mode=mode)
+    n = rays_dev.shape[0]
+    hits = torch.empty((n, 4), dtype=torch.int32, device=rays_dev.device)
+    scene.trace(rays_dev, hits=hits, extra=False)
+    h = hits.cpu().numpy()
+    same = bool(ref_hits is None or ((h[:, 0] == ref_hits[:, 0]).all() and (h[:, 1] == ref_hits[:, 1]).all()))
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        scene.trace(rays_dev, hits=hits, extra=False)
+        b.record()
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+    n_masks = scene.info["n_masked"] if mode == "sparse" else (2 * scene.info["n_inner"] if mode == "raw" else 0)
+    scene.close()
+    box = h[:, 2].astype(np.float64).sum() / n
+    tri = h[:, 3].astype(np.float64).sum() / n
+    return Evaluation(name, beta, int(n_masks), box + tri, box, tri, ms, n / (ms * 1e-3), same)
+
+
+def placements(scores_by_name: dict, n_place: int) -> dict:
+    """uint8 placements of the n_place highest scores for each named scoring."""
+    return {k: binding.place_top(v, n_place) for k, v in scores_by_name.items()}
+
+
+def build_training_set(ctx, specs, *, max_slots: int = 32768, log=None):
+    """Concatenated features/targets over training scenes (device tensors)."""
+    import torch
+    from . import scenes
+    Xs, ys = [], []
+    for i, sp in enumerate(specs):
+        tris, rays = scenes.placement_scene(sp)
+        X, y, info = slot_dataset(ctx, tris, rays, max_slots=max_slots, seed=sp.seed)
+        Xs.append(X)
+        ys.append(y)
+        if log and (i % 10 == 0 or i == len(specs) - 1):
+            log(f"train scene {i + 1}/{len(specs)}: {sp.kind} {tris.shape[0]} tris, "
+                f"{info['n_inner']} inner nodes, mean target {y.mean().item():.3f}")
+    return torch.cat(Xs).contiguous(), torch.cat(ys).contiguous()
+
+
+def evaluate_scene(ctx, params, tris, rays, *, betas=(0.5, 1.0, 2.0), seed: int = 0, reps: int = 5,
+                   log=None) -> list:
+    """All placements of one held-out scene: learned, heuristic, random and
+    true-label at each budget, plus all masks (raw) and no masks."""
+    import torch
+    X, y, info = slot_dataset(ctx, tris, rays)
+    S = X.shape[0]
+    pred = predict(ctx, params, X).cpu().numpy()
+    rng = np.random.default_rng(seed)
+    scores = {"learned": pred, "heuristic": heuristic_scores(X),
+              "random": rng.random(S).astype(np.float32), "true_label": y.cpu().numpy()}
+    rays_dev = torch.from_numpy(np.ascontiguousarray(rays, np.float32)).cuda(ctx.device)
+    sc = binding.Scene(ctx, tris, R=6, mode="none")
+    ref = sc.trace(rays_dev, extra=False).hits.cpu().numpy()
+    sc.close()
+    out = [evaluate(ctx, tris, rays_dev, None, ref, mode="none", name="no_masks", reps=reps),
+           evaluate(ctx, tris, rays_dev, None, ref, mode="raw", name="all_masks", reps=reps)]
+    for beta in betas:
+        M = budget_masks(beta, info["n_inner"])
+        for name, pl in placements(scores, M).items():
+            out.append(evaluate(ctx, tris, rays_dev, pl, ref, name=name, beta=beta, reps=reps))
+    if log:
+        for e in out:
+            log(f"  {e.name:>10} beta={e.beta}: masks {e.n_masks}, tests/ray {e.tests_per_ray:.2f}, "
+                f"{e.rays_per_s / 1e6:.1f} Mrays/s, hits equal {e.hits_equal}")
+    return out
+
+
+def run_experiment(ctx, train_specs, heldout, *, betas=(0.5, 1.0, 2.0), epochs: int = 20,
+                   batch: int = 4096, lr: float = 1e-3, max_slots: int = 32768, seed: int = 0, log=None):
+    """Train on the training scenes, evaluate every placement on each held-out
+    (tris, rays) pair. Returns (params, loss history, [[Evaluation]])."""
+    t0 = time.time()
+    X, y = build_training_set(ctx, train_specs, max_slots=max_slots, log=log)
+    if log:
+        log(f"training set: {X.shape[0]} slots from {len(train_specs)} scenes ({time.time() - t0:.1f} s)")
+    t1 = time.time()
+    params, hist = train(ctx, X, y, epochs=epochs, batch=min(batch, X.shape[0]), lr=lr, seed=seed, log=log)
+    if log:
+        log(f"training: {epochs} epochs in {time.time() - t1:.1f} s")
+    results = []
+    for k, (tris, rays) in enumerate(heldout):
+        if log:
+            log(f"held-out scene {k}: {tris.shape[0]} tris, {rays.shape[0]} rays")
+        results.append(evaluate_scene(ctx, params, tris, rays, betas=betas, seed=seed + k, log=log))
+    return params, hist, results

@@ -351,3 +351,61 @@ def batch_scene(spec: BatchSpec):
     prim = pinhole_rays(res_w, res_h)
     rnd = random_rays(spec.n_rays - prim.shape[0], spec.seed + 50_000)
     return t, np.concatenate([prim, rnd], 0)
+
+
+# ----------------------------------------------------------------------------
+# learned placement: training scenes and held-out scenes
+# ----------------------------------------------------------------------------
+@dataclass(frozen=True)
+class PlacementSpec:
+    seed: int
+    kind: str        # "strands" | "curly" | "quads"
+    n_tris: int
+    n_rays: int
+
+
+def placement_specs(n_scenes: int = 200, seed0: int = 5000, tri_lo: int = 100_000,
+                    tri_hi: int = 2_000_000, n_rays: int = 262_144) -> list:
+    """Training scenes: sizes log-uniform in [tri_lo, tri_hi], kinds cycling
+    straight-ish strands / curly diagonal strands / thin quads."""
+    kinds = ("strands", "curly", "quads")
+    out = []
+    for i in range(n_scenes):
+        rng = np.random.default_rng(seed0 + i)
+        nt = int(round(math.exp(rng.uniform(math.log(tri_lo), math.log(tri_hi)))))
+        out.append(PlacementSpec(seed0 + i, kinds[i % 3], nt, n_rays))
+    return out
+
+
+def placement_scene(spec: PlacementSpec):
+    """Triangles and rays (half pinhole primary, half surface bounce) of one scene."""
+    rng = np.random.default_rng(spec.seed + 777)
+    if spec.kind == "strands":
+        segs = 25
+        t = strands_helical(spec.seed, max(1, spec.n_tris // (2 * segs)), segs,
+                            float(rng.uniform(5e-4, 2e-3)), float(rng.uniform(2e-3, 8e-3)),
+                            float(rng.uniform(0.15, 0.35)), (0.05, 0.0, 0.05), (0.95, 0.5, 0.95),
+                            axis=(0, 1, 0), max_tilt_deg=float(rng.uniform(20.0, 75.0)))
+        t = np.concatenate([t[:max(0, spec.n_tris - 2)], ground_plane(0.0)], 0)
+    elif spec.kind == "curly":
+        segs = 50
+        t = strands_helical(spec.seed, max(1, spec.n_tris // (2 * segs)), segs,
+                            float(rng.uniform(3e-4, 1e-3)), float(rng.uniform(2e-3, 5e-3)),
+                            float(rng.uniform(0.2, 0.4)), (0.0, 0.0, 0.0), (0.82, 0.82, 0.82),
+                            axis=(1, 1, 1), max_tilt_deg=float(rng.uniform(5.0, 30.0)))
+    else:
+        t = thin_quads(spec.seed, max(1, spec.n_tris // 2), float(rng.uniform(0.01, 0.04)),
+                       float(rng.uniform(2e-4, 1e-3)))
+    t = np.ascontiguousarray(t[:spec.n_tris])
+    n_prim = spec.n_rays // 2
+    w = max(1, int(math.sqrt(n_prim)))
+    prim = pinhole_rays(w, max(1, n_prim // w))
+    bounce = surface_bounce_rays(t, spec.n_rays - prim.shape[0], spec.seed + 10_000)
+    return t, np.concatenate([prim, bounce], 0)
+
+
+def placement_heldout(k: int = 0, n_tris: int = 5_000_000, n_rays: int = 4_000_000):
+    """Held-out scene k (seeds disjoint from the training range): a hair
+    scene (k even) or a curly diagonal scene (k odd), with n_rays rays."""
+    kind = "strands" if k % 2 == 0 else "curly"
+    return placement_scene(PlacementSpec(90_000 + k, kind, n_tris, n_rays))
