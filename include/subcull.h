@@ -125,14 +125,17 @@ typedef struct {
  * lane (deeper entries spill to private memory), rays per queue fetch
  * (64 * chunk) and the number of contiguous ray partitions with their own
  * queue (waves start on partition block % parts, i.e. per XCD when parts is
- * 8, and steal from the others). Results never depend on it. Supported
- * (block, stack) pairs: (256,8) (128,8) (256,12) (256,4) (128,16); chunk
- * 1..64; parts 1..8. */
+ * 8, and steal from the others), and a cap on the waves resident per SIMD
+ * (the persistent grid is sized to it; 0 = as many as registers and LDS
+ * allow). Results never depend on it. Supported (block, stack) pairs:
+ * (256,8) (128,8) (256,12) (256,4) (128,16); chunk 1..64; parts 1..8;
+ * waves 0..8. */
 typedef struct {
     uint32_t block;
     uint32_t stack;
     uint32_t chunk;
     uint32_t parts;
+    uint32_t waves;
 } sc_tune;
 
 /* Fill `p` with the defaults: R 6, leaf_max 4, 32 bins, depth cap 64, RAW,
@@ -199,7 +202,7 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
                    sc_hit* d_hits, uint32_t* d_extra, uint32_t* d_slot_fp, void* stream);
 
 /* Select the traversal launch shape for later sc_trace calls on this
- * context (default 256, 8, 1, 8). SC_ERR_UNSUPPORTED for an uncompiled pair. */
+ * context (default 256, 8, 1, 8, 0). SC_ERR_UNSUPPORTED for an uncompiled pair. */
 sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune);
 sc_status sc_get_tune(const sc_ctx* ctx, sc_tune* out);
 

@@ -23,7 +23,7 @@ struct sc_ctx {
     std::mutex lut_mu;
     uint32_t* counters = nullptr;           // kQueueRing ray-queue counters
     std::atomic<uint32_t> next_counter{0};
-    sc_tune tune{256, 8, 1, kQueueParts};
+    sc_tune tune{256, 8, 1, kQueueParts, 0};
 };
 
 struct sc_scene {
@@ -523,6 +523,7 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     a.chunk = ctx->tune.chunk;
     a.block = ctx->tune.block;
     a.stack = ctx->tune.stack;
+    a.waves = ctx->tune.waves;
     const hipError_t e = launch_trace(a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "trace launch");
     return SC_OK;
@@ -587,6 +588,7 @@ sc_status prepare_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_item
     a.chunk = ctx->tune.chunk;
     a.block = ctx->tune.block;
     a.stack = ctx->tune.stack;
+    a.waves = ctx->tune.waves;
     a.parts = ctx->tune.parts;
     a.n_items = n_items;
     if (I.mode != SC_MASK_NONE && !a.lut) {  // masks exist only if the LUT was built
@@ -699,6 +701,7 @@ sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune) {
         return fail(SC_ERR_UNSUPPORTED, "no traversal kernel for this (block, stack) pair");
     if (tune->chunk < 1 || tune->chunk > 64) return fail(SC_ERR_INVALID_ARG, "chunk must be 1..64");
     if (tune->parts < 1 || tune->parts > kQueueParts) return fail(SC_ERR_INVALID_ARG, "parts must be 1..8");
+    if (tune->waves > 8) return fail(SC_ERR_INVALID_ARG, "waves must be 0..8");
     ctx->tune = *tune;
     return SC_OK;
 }

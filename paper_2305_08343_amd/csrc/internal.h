@@ -92,6 +92,7 @@ struct TraceLaunch {
     uint32_t parts;             // ray partitions in use, 1..kQueueParts
     uint32_t chunk;             // rays per queue fetch = 64 * chunk
     uint32_t block, stack;      // threads per block, LDS stack entries per lane
+    uint32_t waves;             // cap on resident waves per SIMD, 0 = occupancy limit
     const BatchItem* items;     // batched launch: per-scene descriptors sorted by ray_begin, else null
     uint32_t n_items;
 };

@@ -109,8 +109,17 @@ __device__ __forceinline__ void slab(const float* lo, const float* hi, const Ray
     }
 }
 
+#ifndef SC_TRACE_WAVES_PER_EU
+#define SC_TRACE_WAVES_PER_EU 0
+#endif
+#if SC_TRACE_WAVES_PER_EU > 0
+#define SC_TRACE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SC_TRACE_WAVES_PER_EU)))
+#else
+#define SC_TRACE_OCCUPANCY
+#endif
+
 template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH>
-__global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
+__global__ __launch_bounds__(BLOCK) SC_TRACE_OCCUPANCY void trace_kernel(TraceLaunch a) {
     constexpr int W = (R * R * R + 63) / 64;
     constexpr uint32_t kStride = (MODE == kModeRaw) ? kRawNodeBytes : kNodeBytes;
     constexpr int kWavesPerBlock = BLOCK / kWave;
@@ -397,17 +406,27 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(TraceLaunch a) {
 
 template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH>
 hipError_t launch_one(const TraceLaunch& a, hipStream_t s) {
-    static int resident = 0;  // blocks resident on the whole device, computed once per instance
-    if (resident == 0) {
-        int dev = 0, cus = 0, per_cu = 0;
+    // blocks per CU that fit, and CUs, computed once per instance
+    static int per_cu = 0, cus = 0;
+    if (per_cu == 0) {
+        int dev = 0, c = 0, p = 0;
         (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_kernel<MODE, R, BLOCK, STACK, BATCH>, BLOCK, 0);
-        resident = (cus > 0 && per_cu > 0) ? cus * per_cu : 1024;
+        (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, trace_kernel<MODE, R, BLOCK, STACK, BATCH>, BLOCK, 0);
+        cus = c > 0 ? c : 256;
+        per_cu = p > 0 ? p : 4;
     }
+    uint32_t blocks_per_cu = (uint32_t)per_cu;
+    if (a.waves > 0) {
+        // 4 SIMDs per CU: waves per SIMD * 4 / waves per block, at least one block
+        uint32_t cap = (a.waves * 4u) / (BLOCK / kWave);
+        cap = cap > 0 ? cap : 1u;
+        blocks_per_cu = cap < blocks_per_cu ? cap : blocks_per_cu;
+    }
+    const uint32_t resident = (uint32_t)cus * blocks_per_cu;
     const uint32_t waves = (a.n + kWave - 1) / kWave;
     uint32_t blocks = (waves + BLOCK / kWave - 1) / (BLOCK / kWave);
-    blocks = blocks < (uint32_t)resident ? blocks : (uint32_t)resident;
+    blocks = blocks < resident ? blocks : resident;
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(kQueueParts), 0, s, a.queue, kQueueParts);
     hipLaunchKernelGGL((trace_kernel<MODE, R, BLOCK, STACK, BATCH>), dim3(blocks), dim3(BLOCK), 0, s, a);
     return hipGetLastError();

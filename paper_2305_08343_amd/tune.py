@@ -1,7 +1,8 @@
 """Launch-shape autotuner for the traversal (successive halving, JSON cache).
 
 The traversal's results never depend on its launch shape (threads per block,
-LDS stack depth, rays per queue fetch, XCD ray partitions), so the tuner only
+LDS stack depth, rays per queue fetch, XCD ray partitions, cap on resident
+waves per SIMD), so the tuner only
 measures time: every candidate is timed once, the faster half is kept and
 timed again with twice the repetitions, until one remains. Results are
 cached per (workload signature, GPU) in a JSON file so later runs reuse
@@ -19,10 +20,11 @@ import numpy as np
 PAIRS = [(256, 8), (128, 8), (256, 12), (256, 4), (128, 16)]
 CHUNKS = [1, 2, 4]
 PARTS = [8, 1]
+WAVES = [0, 6]  # occupancy limit, or at most 6 waves per SIMD
 
 
 def candidates():
-    return [(b, s, c, p) for (b, s) in PAIRS for c in CHUNKS for p in PARTS]
+    return [(b, s, c, p, w) for (b, s) in PAIRS for c in CHUNKS for p in PARTS for w in WAVES]
 
 
 def _gpu_name():

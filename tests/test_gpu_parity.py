@@ -264,13 +264,16 @@ def test_every_launch_shape_gives_the_same_results(ctx, small_scene, small_oracl
     s4 = binding.Scene(ctx, tris, R=4, mode="raw")
     try:
         for block, stack in ((256, 8), (128, 8), (256, 12), (256, 4), (128, 16)):
-            for chunk, parts in ((1, 8), (3, 1), (64, 5)):
-                print(f"[gpu] tune block={block} stack={stack} chunk={chunk} parts={parts}", flush=True)
-                ctx.set_tune(block, stack, chunk, parts)
+            for chunk, parts, waves in ((1, 8, 0), (3, 1, 2), (64, 5, 0), (2, 8, 5)):
+                print(f"[gpu] tune block={block} stack={stack} chunk={chunk} parts={parts} waves={waves}",
+                      flush=True)
+                ctx.set_tune(block, stack, chunk, parts, waves)
                 _compare_hits(s6.trace(r).numpy(), ora)
                 _compare_hits(s4.trace(r).numpy(), ora4)
         with pytest.raises(binding.SubcullError):
             ctx.set_tune(64, 8, 1)
+        with pytest.raises(binding.SubcullError):
+            ctx.set_tune(256, 8, 1, 8, 9)
     finally:
         ctx.set_tune(256, 8, 1, 8)
         s6.close()
