@@ -248,7 +248,7 @@ def main():
     ap.add_argument("--modes", default="raw6,none,raw4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--tune", default="", help="block,stack,chunk,parts of the traversal launch")
+    ap.add_argument("--tune", default="", help="block,stack,chunk,parts[,waves[,sort]] of the traversal launch")
     ap.add_argument("--workload", default="hair_1m", choices=["hair_1m", "batch64", "placement"])
     ap.add_argument("--place-scenes", type=int, default=200)
     ap.add_argument("--place-heldout", type=int, default=2)

@@ -58,7 +58,9 @@ enum {
     SC_TRACE_CULL = 1u,    /* apply the mask test (else masks are ignored)        */
     SC_TRACE_SHADOW = 2u,  /* evaluate masks without culling; count would-be culls
                               per child slot into d_slot_fp                      */
-    SC_TRACE_SORT = 4u     /* reserved                                             */
+    SC_TRACE_SORT = 4u     /* take the rays in the Morton order of their origins
+                              (stable radix sort on the device, workspace from
+                              the context allocator); results are unchanged     */
 };
 
 typedef struct sc_ctx sc_ctx;
@@ -127,15 +129,17 @@ typedef struct {
  * queue (waves start on partition block % parts, i.e. per XCD when parts is
  * 8, and steal from the others), and a cap on the waves resident per SIMD
  * (the persistent grid is sized to it; 0 = as many as registers and LDS
- * allow). Results never depend on it. Supported (block, stack) pairs:
- * (256,8) (128,8) (256,12) (256,4) (128,16); chunk 1..64; parts 1..8;
- * waves 0..8. */
+ * allow), and whether single-scene traces sort their rays as with
+ * SC_TRACE_SORT. Results never depend on it. Supported (block, stack)
+ * pairs: (256,8) (128,8) (256,12) (256,4) (128,16); chunk 1..64; parts
+ * 1..8; waves 0..8; sort 0 or 1. */
 typedef struct {
     uint32_t block;
     uint32_t stack;
     uint32_t chunk;
     uint32_t parts;
     uint32_t waves;
+    uint32_t sort;
 } sc_tune;
 
 /* Fill `p` with the defaults: R 6, leaf_max 4, 32 bins, depth cap 64, RAW,
@@ -201,8 +205,18 @@ sc_status sc_scene_export(const sc_scene* scene, sc_scene_host* out);
 sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags,
                    sc_hit* d_hits, uint32_t* d_extra, uint32_t* d_slot_fp, void* stream);
 
+/* The order in which a sorted trace takes the rays: d_order (device uint32
+ * [n], 4-byte aligned, written) lists ray indices by ascending Morton code
+ * of the ray origin, quantised to 256 cells per axis of the scene's vertex
+ * bounds (origins outside are clamped, NaN goes to cell 0); equal codes keep
+ * index order. A scheduling aid for coherent traversal (not in the paper):
+ * it changes no result. Asynchronous on `stream`; the workspace (16 bytes
+ * per ray plus counts) comes from the context allocator. */
+sc_status sc_ray_order(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t* d_order,
+                       void* stream);
+
 /* Select the traversal launch shape for later sc_trace calls on this
- * context (default 256, 8, 1, 8, 0). SC_ERR_UNSUPPORTED for an uncompiled pair. */
+ * context (default 256, 8, 1, 8, 0, 0). SC_ERR_UNSUPPORTED for an uncompiled pair. */
 sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune);
 sc_status sc_get_tune(const sc_ctx* ctx, sc_tune* out);
 

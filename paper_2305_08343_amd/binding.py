@@ -51,7 +51,7 @@ class sc_scene_info(C.Structure):
 
 class sc_tune(C.Structure):
     _fields_ = [("block", C.c_uint32), ("stack", C.c_uint32), ("chunk", C.c_uint32),
-                ("parts", C.c_uint32), ("waves", C.c_uint32)]
+                ("parts", C.c_uint32), ("waves", C.c_uint32), ("sort", C.c_uint32)]
 
 
 class sc_batch_item(C.Structure):
@@ -82,6 +82,7 @@ _SIGS = {
     "sc_scene_export": (C.c_int, [C.c_void_p, C.POINTER(sc_scene_host)]),
     "sc_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
+    "sc_ray_order": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "sc_trace_batch": (C.c_int, [C.c_void_p, C.POINTER(sc_batch_item), C.c_uint32, C.c_uint32, C.c_void_p]),
     "sc_batch_create": (C.c_int, [C.c_void_p, C.POINTER(sc_batch_item), C.c_uint32, C.c_uint32,
                                   C.POINTER(C.c_void_p)]),
@@ -179,15 +180,17 @@ class Context:
         except Exception:
             pass
 
-    def set_tune(self, block: int = 256, stack: int = 8, chunk: int = 1, parts: int = 8, waves: int = 0):
+    def set_tune(self, block: int = 256, stack: int = 8, chunk: int = 1, parts: int = 8, waves: int = 0,
+                 sort: int = 0):
         """Traversal launch shape for later traces (results never depend on it)."""
-        _check(load().sc_set_tune(self.handle, C.byref(sc_tune(block, stack, chunk, parts, waves))),
+        _check(load().sc_set_tune(self.handle, C.byref(sc_tune(block, stack, chunk, parts, waves, sort))),
                "sc_set_tune")
 
     def get_tune(self) -> dict:
         t = sc_tune()
         _check(load().sc_get_tune(self.handle, C.byref(t)), "sc_get_tune")
-        return {"block": t.block, "stack": t.stack, "chunk": t.chunk, "parts": t.parts, "waves": t.waves}
+        return {"block": t.block, "stack": t.stack, "chunk": t.chunk, "parts": t.parts, "waves": t.waves,
+                "sort": t.sort}
 
     # ---- placement MLP (device tensors in, device tensors out)
     def mlp_forward(self, params, x, act=None, stream=None):
@@ -334,7 +337,7 @@ class Scene:
         _check(load().sc_slot_features(self.handle, _ptr(out), _stream_ptr(stream)), "sc_slot_features")
         return out[:S]
 
-    def trace(self, rays, *, cull: bool = True, shadow: bool = False, extra: bool = True,
+    def trace(self, rays, *, cull: bool = True, shadow: bool = False, extra: bool = True, sort: bool = False,
               slot_fp=None, hits=None, extra_out=None, stream=None) -> TraceResult:
         """Trace device rays [n, 8] float32; results stay on the device."""
         import torch
@@ -347,11 +350,24 @@ class Scene:
             hits = torch.empty((max(n, 1), 4), dtype=torch.int32, device=dev)
         if extra and extra_out is None:
             extra_out = torch.empty((max(n, 1), 2), dtype=torch.int32, device=dev)
-        flags = (SC_TRACE_CULL if cull else 0) | (SC_TRACE_SHADOW if shadow else 0)
+        flags = ((SC_TRACE_CULL if cull else 0) | (SC_TRACE_SHADOW if shadow else 0) |
+                 (SC_TRACE_SORT if sort else 0))
         _check(load().sc_trace(self.handle, _ptr(rays), n, flags, _ptr(hits),
                                _ptr(extra_out) if extra else None, _ptr(slot_fp),
                                _stream_ptr(stream)), "sc_trace")
         return TraceResult(hits[:n], extra_out[:n] if extra else None)
+
+    def ray_order(self, rays, stream=None):
+        """Device int32 [n]: the order a sorted trace takes the rays in (sc_ray_order)."""
+        import torch
+        dev = f"cuda:{self.ctx.device}"
+        if not isinstance(rays, torch.Tensor):
+            rays = torch.from_numpy(np.ascontiguousarray(rays, np.float32))
+        rays = rays.to(device=dev, dtype=torch.float32).contiguous()
+        n = rays.shape[0]
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        _check(load().sc_ray_order(self.handle, _ptr(rays), n, _ptr(out), _stream_ptr(stream)), "sc_ray_order")
+        return out[:n]
 
 
 def place_top(scores, n_place: int) -> np.ndarray:

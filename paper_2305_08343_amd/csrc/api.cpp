@@ -23,7 +23,7 @@ struct sc_ctx {
     std::mutex lut_mu;
     uint32_t* counters = nullptr;           // kQueueRing ray-queue counters
     std::atomic<uint32_t> next_counter{0};
-    sc_tune tune{256, 8, 1, kQueueParts, 0};
+    sc_tune tune{256, 8, 1, kQueueParts, 0, 0};
 };
 
 struct sc_scene {
@@ -37,6 +37,7 @@ struct sc_scene {
     uint16_t* cidx = nullptr;             // LUT mode
     uint32_t full_start = 0;              // LUT mode: first full codebook entry
     uint64_t* side_masks = nullptr;       // SPARSE mode
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // vertex bounds (ray ordering keys)
     std::vector<std::pair<void*, size_t>> owned;
 };
 
@@ -235,10 +236,15 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
         if (e != hipSuccess) return hip_fail(e, "triangle download");
     }
     float M = 0.0f;
-    for (float x : host) {
+    float vlo[3] = {0, 0, 0}, vhi[3] = {0, 0, 0};
+    for (size_t k = 0; k < host.size(); ++k) {
+        const float x = host[k];
         if (!std::isfinite(x)) return fail(SC_ERR_INVALID_ARG, "non-finite triangle vertex");
         const float ax = std::fabs(x);
         M = (ax > M) ? ax : M;
+        const int j = (int)(k % 3);
+        if (k < 3 || x < vlo[j]) vlo[j] = x;
+        if (k < 3 || x > vhi[j]) vhi[j] = x;
     }
     const float m1 = (M > 1.0f) ? M : 1.0f;
     const float ob = (P.origin_bound > 0.0f) ? P.origin_bound : 4.0f * m1;
@@ -247,6 +253,10 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
     auto* sc = new (std::nothrow) sc_scene();
     if (!sc) return fail(SC_ERR_OOM, "scene allocation failed");
     sc->ctx = ctx;
+    for (int j = 0; j < 3; ++j) {
+        sc->lo[j] = vlo[j];
+        sc->hi[j] = vhi[j];
+    }
     auto bail = [&](sc_status code, const std::string& msg) {
         (void)hipStreamSynchronize(s);
         scene_free_all(sc, s);
@@ -488,7 +498,6 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     if (n > (1u << 31)) return fail(SC_ERR_INVALID_ARG, "at most 2^31 rays per call");
     if (flags & ~(uint32_t)(SC_TRACE_CULL | SC_TRACE_SHADOW | SC_TRACE_SORT))
         return fail(SC_ERR_INVALID_ARG, "unknown trace flag");
-    if (flags & SC_TRACE_SORT) return fail(SC_ERR_UNSUPPORTED, "SC_TRACE_SORT is not implemented");
     if (((uintptr_t)d_rays & 15) || ((uintptr_t)d_hits & 15) || ((uintptr_t)d_extra & 7) ||
         ((uintptr_t)d_slot_fp & 3))
         return fail(SC_ERR_INVALID_ARG, "d_rays and d_hits must be 16-byte aligned, d_extra 8-byte");
@@ -524,8 +533,46 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     a.block = ctx->tune.block;
     a.stack = ctx->tune.stack;
     a.waves = ctx->tune.waves;
-    const hipError_t e = launch_trace(a, static_cast<hipStream_t>(stream));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool sort = (flags & SC_TRACE_SORT) || ctx->tune.sort;
+    void* ws = nullptr;
+    const size_t ws_bytes = sort ? ray_order_workspace_bytes(n) : 0;
+    if (sort) {
+        ws = dev_alloc(ctx, ws_bytes, s);
+        if (!ws) return fail(SC_ERR_OOM, "ray order workspace");
+        uint32_t* order = nullptr;
+        const hipError_t e = launch_ray_order(d_rays, n, scene->lo, scene->hi, ws, &order, s);
+        if (e != hipSuccess) {
+            dev_free(ctx, ws, ws_bytes, s);
+            return hip_fail(e, "ray order");
+        }
+        a.order = order;
+    }
+    const hipError_t e = launch_trace(a, s);
+    if (ws) dev_free(ctx, ws, ws_bytes, s);  // stream-ordered: the allocator reuses it after the trace
     if (e != hipSuccess) return hip_fail(e, "trace launch");
+    return SC_OK;
+}
+
+sc_status sc_ray_order(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t* d_order, void* stream) {
+    if (!scene) return fail(SC_ERR_INVALID_ARG, "scene is NULL");
+    if (n > 0 && (!d_rays || !d_order)) return fail(SC_ERR_INVALID_ARG, "d_rays and d_order must be non-NULL");
+    if (n > (1u << 31)) return fail(SC_ERR_INVALID_ARG, "at most 2^31 rays per call");
+    if (((uintptr_t)d_rays & 15) || ((uintptr_t)d_order & 3))
+        return fail(SC_ERR_INVALID_ARG, "d_rays must be 16-byte aligned, d_order 4-byte");
+    if (n == 0) return SC_OK;
+    sc_status st = use_device(scene->ctx->device);
+    if (st != SC_OK) return st;
+    sc_ctx* ctx = scene->ctx;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t ws_bytes = ray_order_workspace_bytes(n);
+    void* ws = dev_alloc(ctx, ws_bytes, s);
+    if (!ws) return fail(SC_ERR_OOM, "ray order workspace");
+    uint32_t* order = nullptr;
+    hipError_t e = launch_ray_order(d_rays, n, scene->lo, scene->hi, ws, &order, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_order, order, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+    dev_free(ctx, ws, ws_bytes, s);
+    if (e != hipSuccess) return hip_fail(e, "ray order");
     return SC_OK;
 }
 
@@ -702,6 +749,7 @@ sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune) {
     if (tune->chunk < 1 || tune->chunk > 64) return fail(SC_ERR_INVALID_ARG, "chunk must be 1..64");
     if (tune->parts < 1 || tune->parts > kQueueParts) return fail(SC_ERR_INVALID_ARG, "parts must be 1..8");
     if (tune->waves > 8) return fail(SC_ERR_INVALID_ARG, "waves must be 0..8");
+    if (tune->sort > 1) return fail(SC_ERR_INVALID_ARG, "sort must be 0 or 1");
     ctx->tune = *tune;
     return SC_OK;
 }

@@ -93,6 +93,7 @@ struct TraceLaunch {
     uint32_t chunk;             // rays per queue fetch = 64 * chunk
     uint32_t block, stack;      // threads per block, LDS stack entries per lane
     uint32_t waves;             // cap on resident waves per SIMD, 0 = occupancy limit
+    const uint32_t* order;      // single scene: rays are taken in this order (NULL = index order)
     const BatchItem* items;     // batched launch: per-scene descriptors sorted by ray_begin, else null
     uint32_t n_items;
 };
@@ -104,6 +105,10 @@ constexpr uint32_t kQueueRing = 1024;  // launch counter sets per context
 constexpr uint32_t kQueueParts = 8;    // counters per set (one per XCD of an MI355X)
 
 hipError_t launch_trace(const TraceLaunch& a, hipStream_t s);
+// ray order by Morton code of the origin in [lo, hi] (stable radix sort); *order points into workspace
+size_t ray_order_workspace_bytes(uint32_t n);
+hipError_t launch_ray_order(const float* rays, uint32_t n, const float lo[3], const float hi[3], void* workspace,
+                            uint32_t** order, hipStream_t s);
 hipError_t launch_raymask_patterns(uint32_t R, uint64_t* patterns, hipStream_t s);
 hipError_t launch_raymask_lut(uint32_t R, const uint64_t* patterns, uint64_t* out, hipStream_t s);
 inline size_t pattern_count(uint32_t R) { return (size_t)R * (2 * R - 1) * (2 * R - 1); }

@@ -206,7 +206,9 @@ __global__ __launch_bounds__(BLOCK) SC_TRACE_OCCUPANCY void trace_kernel(TraceLa
                         const uint32_t gid = cursor + (uint32_t)__popcll(idle & lanes_below);
                         if (gid < end) {
                             uint32_t id = gid;
-                            if constexpr (BATCH) {
+                            if constexpr (!BATCH) {
+                                if (a.order) id = a.order[gid];
+                            } else {
                                 // item holding this ray: the last one whose first ray is <= gid
                                 uint32_t lo = 0, hi = a.n_items;
                                 while (hi - lo > 1) {

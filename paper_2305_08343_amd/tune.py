@@ -2,7 +2,7 @@
 
 The traversal's results never depend on its launch shape (threads per block,
 LDS stack depth, rays per queue fetch, XCD ray partitions, cap on resident
-waves per SIMD), so the tuner only
+waves per SIMD, Morton ray sorting), so the tuner only
 measures time: every candidate is timed once, the faster half is kept and
 timed again with twice the repetitions, until one remains. Results are
 cached per (workload signature, GPU) in a JSON file so later runs reuse
@@ -18,13 +18,14 @@ import numpy as np
 
 # (block, stack) pairs with compiled kernels; chunk = rays per fetch / 64; parts = ray partitions
 PAIRS = [(256, 8), (128, 8), (256, 12), (256, 4), (128, 16)]
-CHUNKS = [1, 2, 4]
+CHUNKS = [1, 2]
 PARTS = [8, 1]
 WAVES = [0, 6]  # occupancy limit, or at most 6 waves per SIMD
+SORT = [0, 1]   # rays in input order, or in the Morton order of their origins
 
 
 def candidates():
-    return [(b, s, c, p, w) for (b, s) in PAIRS for c in CHUNKS for p in PARTS for w in WAVES]
+    return [(b, s, c, p, w, o) for (b, s) in PAIRS for c in CHUNKS for p in PARTS for w in WAVES for o in SORT]
 
 
 def _gpu_name():

@@ -25,7 +25,7 @@ def test_header_declares_the_api():
                  "sc_status_string", "sc_last_error", "sc_build_params_default", "sc_set_tune",
                  "sc_get_tune", "sc_trace_batch", "sc_batch_create", "sc_batch_launch",
                  "sc_batch_destroy", "sc_bvh_build_host", "sc_slot_features", "sc_mlp_forward",
-                 "sc_mlp_backward", "sc_mlp_adam", "sc_place_top"):
+                 "sc_mlp_backward", "sc_mlp_adam", "sc_place_top", "sc_ray_order"):
         assert must in names
 
 
@@ -51,6 +51,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(B.sc_scene_info) == 40 + 8 + 8 + 32
     assert C.sizeof(B.sc_build_params) == 48
     assert C.sizeof(B.sc_scene_host) == 7 * 8
+    assert C.sizeof(B.sc_tune) == 6 * 4
 
 
 def test_null_arguments_rejected_before_hip():
@@ -64,6 +65,7 @@ def test_null_arguments_rejected_before_hip():
     assert lib.sc_raymask_lut(None, 6, None, None) == 1
     assert lib.sc_compress_masks(None, 6, None, 64, None, 0, None, None) == 1
     assert lib.sc_set_tune(None, None) == 1 and lib.sc_get_tune(None, None) == 1
+    assert lib.sc_ray_order(None, None, 0, None, None) == 1
     assert lib.sc_trace_batch(None, None, 0, 0, None) == 1
     assert lib.sc_batch_create(None, None, 0, 0, None) == 1
     assert lib.sc_batch_launch(None, None) == 1 and lib.sc_batch_destroy(None) == 0

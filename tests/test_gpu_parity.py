@@ -264,16 +264,18 @@ def test_every_launch_shape_gives_the_same_results(ctx, small_scene, small_oracl
     s4 = binding.Scene(ctx, tris, R=4, mode="raw")
     try:
         for block, stack in ((256, 8), (128, 8), (256, 12), (256, 4), (128, 16)):
-            for chunk, parts, waves in ((1, 8, 0), (3, 1, 2), (64, 5, 0), (2, 8, 5)):
-                print(f"[gpu] tune block={block} stack={stack} chunk={chunk} parts={parts} waves={waves}",
-                      flush=True)
-                ctx.set_tune(block, stack, chunk, parts, waves)
+            for chunk, parts, waves, sort in ((1, 8, 0, 0), (3, 1, 2, 1), (64, 5, 0, 0), (2, 8, 5, 1)):
+                print(f"[gpu] tune block={block} stack={stack} chunk={chunk} parts={parts} waves={waves} "
+                      f"sort={sort}", flush=True)
+                ctx.set_tune(block, stack, chunk, parts, waves, sort)
                 _compare_hits(s6.trace(r).numpy(), ora)
                 _compare_hits(s4.trace(r).numpy(), ora4)
         with pytest.raises(binding.SubcullError):
             ctx.set_tune(64, 8, 1)
         with pytest.raises(binding.SubcullError):
             ctx.set_tune(256, 8, 1, 8, 9)
+        with pytest.raises(binding.SubcullError):
+            ctx.set_tune(256, 8, 1, 8, 0, 2)
     finally:
         ctx.set_tune(256, 8, 1, 8)
         s6.close()
@@ -289,3 +291,71 @@ def test_repeat_trace_is_deterministic(ctx, small_scene):
     b = s.trace(rays).hits.cpu().numpy()
     assert (a == b).all()
     s.close()
+
+
+def _morton_keys_f32(rays, tris):
+    """Morton code of each origin, 256 cells per axis of the vertex bounds,
+    evaluated in float32 in the documented order: u = (p - lo) * (256 / (hi - lo))."""
+    v = tris.reshape(-1, 3)
+    lo, hi = v.min(0).astype(np.float32), v.max(0).astype(np.float32)
+    ext = (hi - lo).astype(np.float32)
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        sc = np.where((ext > 0) & np.isfinite(np.float32(256) / ext), np.float32(256) / ext, np.float32(0))
+        u = (rays[:, 0:3].astype(np.float32) - lo) * sc.astype(np.float32)
+    finite = np.clip(np.nan_to_num(u, nan=0.0, posinf=255.0, neginf=0.0), 0.0, 255.0)
+    cell = np.where(~(u > 0), 0, np.where(u >= 255, 255, finite.astype(np.int64)))
+    key = np.zeros(rays.shape[0], np.int64)
+    for b in range(8):  # bit b of x, y, z -> bits 3b+2, 3b+1, 3b
+        for j, sh in ((0, 2), (1, 1), (2, 0)):
+            key |= ((cell[:, j] >> b) & 1) << (3 * b + sh)
+    return key
+
+
+@pytest.mark.parametrize("n", [1, 4095, 4096, 3 * 4096 + 77, 300_001])
+def test_ray_order_is_the_stable_morton_order(ctx, small_scene, n):
+    from paper_2305_08343_amd import binding
+    tris, _ = small_scene
+    rng = np.random.default_rng(n)
+    rays = scenes.random_rays(n, n + 5, lo=(-0.2, -0.2, -0.2), hi=(1.2, 1.2, 1.2))
+    if n > 10:
+        rays[: n // 7] = rays[0]            # many equal keys: stability decides their order
+        rays[3, 0] = np.nan                 # NaN origin -> cell 0
+        rays[5, :3] = (1e30, -1e30, 0.5)    # clamped
+    rays = rays[rng.permutation(n)]
+    print(f"[gpu] ray order n={n}", flush=True)
+    s = binding.Scene(ctx, tris, R=6, mode="none")
+    order = s.ray_order(rays).cpu().numpy()
+    s.close()
+    expect = np.argsort(_morton_keys_f32(rays, tris), kind="stable")
+    assert (order == expect).all()
+
+
+@pytest.mark.parametrize("mode,R,K", [("none", 6, 0), ("raw", 6, 0), ("raw", 4, 0), ("lut", 6, 4096),
+                                      ("lut", 4, 256), ("sparse", 6, 0)])
+def test_sorted_trace_matches_oracle(ctx, small_scene, small_oracle, mode, R, K):
+    import torch
+    from paper_2305_08343_amd import binding
+    tris, rays = small_scene
+    rays = np.concatenate([rays, _aimed(tris, 30011, 21)])
+    bvh = small_oracle["bvh"]
+    kw = dict(origin_bound=small_oracle["origin_bound"])
+    placed = None
+    if mode == "sparse":
+        placed = (np.random.default_rng(5).random(2 * bvh.n_inner) < 0.4).astype(np.uint8)
+        kw.update(mode="sparse", R=R, masks=small_oracle[f"masks{R}"], placed=placed)
+    elif mode == "raw":
+        kw.update(mode="raw", R=R, masks=small_oracle[f"masks{R}"])
+    elif mode == "lut":
+        cb, idx = oracle.compress(small_oracle[f"masks{R}"], bvh.slot_boxes(), R, K)
+        kw.update(mode="lut", R=R, codebook=cb, cidx=idx)
+    print(f"[gpu] sorted trace {mode} R={R} K={K}", flush=True)
+    s = binding.Scene(ctx, tris, R=R, mode=mode, K=K or 4096, placement=placed)
+    fp = torch.zeros(max(1, 2 * s.info["n_inner"]), dtype=torch.int32, device="cuda:0")
+    dev = s.trace(rays, sort=True).numpy()
+    shadow = s.trace(rays, sort=True, cull=False, shadow=True, slot_fp=fp).numpy()
+    s.close()
+    _compare_hits(dev, oracle.trace(tris, bvh, rays, **kw))
+    ora_sh = oracle.trace(tris, bvh, rays, cull=False, shadow=True, **kw)
+    _compare_hits(shadow, ora_sh)
+    if mode != "none":
+        assert (fp.cpu().numpy()[:2 * bvh.n_inner].view(np.uint32) == ora_sh.slot_fp).all()
