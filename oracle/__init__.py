@@ -174,6 +174,69 @@ def trace(tris, bvh: BVH, rays, *, mode="none", R=6, masks=None, codebook=None, 
                 None if fp is None else fp[:2 * bvh.n_inner])
 
 
+@dataclass
+class BVH4:
+    """4-wide BVH collapsed from a binary one: child c of node m has box
+    box4[m, c] (lo xyz, hi xyz), ref ref4[m, c] (leaf refs as in the binary
+    BVH, inner refs = 4-wide node index, EMPTY for an unused slot) and comes
+    from binary child slot src4[m, c] (EMPTY when unused)."""
+    box4: np.ndarray   # float32 [n4, 4, 6]
+    ref4: np.ndarray   # uint32 [n4, 4]
+    src4: np.ndarray   # uint32 [n4, 4]
+    root: int
+    depth: int         # of the binary BVH it came from (bounds the 4-wide depth)
+
+    @property
+    def n4(self) -> int:
+        return self.ref4.shape[0]
+
+
+def bvh4_collapse(bvh: BVH) -> BVH4:
+    m = max(bvh.n_inner, 1)
+    box4 = np.zeros((m, 4, 6), np.float32)
+    ref4 = np.zeros((m, 4), np.uint32)
+    src4 = np.zeros((m, 4), np.uint32)
+    n4, root4 = C.c_uint32(0), C.c_uint32(0)
+    _check(lib().orc_bvh4_collapse(_p(bvh.cbox), _p(bvh.cref), C.c_uint32(bvh.n_inner), C.c_uint32(bvh.root),
+                                   _p(box4), _p(ref4), _p(src4), C.byref(n4), C.byref(root4)), "bvh4_collapse")
+    k = n4.value
+    return BVH4(box4[:k].copy(), ref4[:k].copy(), src4[:k].copy(), root4.value, bvh.depth)
+
+
+def trace4(tris, bvh: BVH, bvh4: BVH4, rays, *, mode="none", R=6, masks=None, codebook=None, cidx=None,
+           placed=None, lut=None, origin_bound=None, cull=True, shadow=False, nthreads=0) -> Hits:
+    """Alg. 4 on the 4-wide BVH; masks, codebook indices and shadow counts are
+    per binary child slot, as for trace()."""
+    tris = np.ascontiguousarray(tris, np.float32)
+    rays = np.ascontiguousarray(rays, np.float32)
+    n = rays.shape[0]
+    if origin_bound is None:
+        origin_bound = default_bounds(tris)[0]
+    mcode = MODES[mode]
+    if mcode and lut is None:
+        lut = raymask_lut(R)
+    hits = np.zeros((max(n, 1), 4), np.uint32)
+    extra = np.zeros((max(n, 1), 2), np.uint32)
+    fp = np.zeros(max(2 * bvh.n_inner, 1), np.uint32) if shadow else None
+    flags = (FLAG_CULL if cull else 0) | (FLAG_SHADOW if shadow else 0)
+    masks = None if masks is None else np.ascontiguousarray(masks, np.uint64)
+    codebook = None if codebook is None else np.ascontiguousarray(codebook, np.uint64)
+    cidx = None if cidx is None else np.ascontiguousarray(cidx, np.uint16)
+    placed = None if placed is None else np.ascontiguousarray(placed, np.uint8)
+    b4 = np.ascontiguousarray(bvh4.box4) if bvh4.n4 else np.zeros((1, 4, 6), np.float32)
+    r4 = np.ascontiguousarray(bvh4.ref4) if bvh4.n4 else np.zeros((1, 4), np.uint32)
+    s4 = np.ascontiguousarray(bvh4.src4) if bvh4.n4 else np.zeros((1, 4), np.uint32)
+    rc = lib().orc_trace4(_p(tris), _p(bvh.perm), _p(b4), _p(r4), _p(s4), C.c_uint32(bvh4.root),
+                          C.c_uint32(bvh4.depth), C.c_uint32(R), C.c_uint32(mcode), _p(masks), _p(codebook),
+                          _p(cidx), _p(placed), _p(lut), C.c_float(origin_bound), C.c_uint32(flags), _p(rays),
+                          C.c_uint32(n), _p(hits), _p(extra), _p(fp), C.c_int(nthreads))
+    _check(rc, "trace4")
+    hits, extra = hits[:n], extra[:n]
+    return Hits(hits[:, 0].copy(), hits[:, 1].view(np.float32).copy(), hits[:, 2].copy(),
+                hits[:, 3].copy(), extra[:, 0].copy(), extra[:, 1].copy(),
+                None if fp is None else fp[:2 * bvh.n_inner])
+
+
 def brute_closest(tris, rays, nthreads=0):
     tris = np.ascontiguousarray(tris, np.float32)
     rays = np.ascontiguousarray(rays, np.float32)

@@ -470,6 +470,67 @@ static void raymask_key_cells(const float* lo, const float* hi, const float* o, 
     }
 }
 
+/* Leaf of Alg. 4: Moller-Trumbore against each triangle of the leaf, in leaf
+ * order; the closest t in [tmin, best_t] wins, equal t goes to the lower
+ * original triangle id. */
+static void leaf_tests(const TraceCtx* C, uint32_t ref, const float* o, const float* d, float tmin,
+                       float* best_t, uint32_t* best, uint32_t* tri_tests) {
+    uint32_t first = ref & 0x1FFFFFFFu, count = ((ref >> 29) & 3u) + 1u;
+    for (uint32_t j = first; j < first + count; ++j) {
+        ++*tri_tests;
+        uint32_t id = C->perm[j];
+        const float* v = &C->tris[9 * (size_t)id];
+        float e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
+        float e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
+        float P[3], Q[3], S[3];
+        cross3(d, e2, P);
+        float det = dot3(e1, P);
+        if (det == 0.0f) continue;
+        float idet = 1.0f / det;
+        S[0] = o[0] - v[0]; S[1] = o[1] - v[1]; S[2] = o[2] - v[2];
+        float u = dot3(S, P) * idet;
+        if (u < 0.0f || u > 1.0f) continue;
+        cross3(S, e1, Q);
+        float vv = dot3(d, Q) * idet;
+        if (vv < 0.0f || u + vv > 1.0f) continue;
+        float t = dot3(e2, Q) * idet;
+        if (t < tmin || t > *best_t) continue;
+        if (t < *best_t || (t == *best_t && id < *best)) { *best_t = t; *best = id; }
+    }
+}
+
+/* Mask test of Sect. 3.1.2 for the child in binary slot `slot` whose box
+ * [lo, hi] the ray overlaps over [t0, t1]: the ray mask of the entry and exit
+ * cells (Alg. 1) ANDed with the slot's object mask (raw, codebook entry, or
+ * absent when not placed). A full mask is not tested. Returns 1 when the AND
+ * is zero (the child can be culled). */
+static int mask_test(const TraceCtx* C, uint32_t slot, const float* lo, const float* hi, const float* o,
+                     const float* d, float t0, float t1, uint32_t* mask_tests, uint32_t* mask_culls) {
+    const uint64_t* om = NULL;
+    if (C->mode == MODE_RAW) om = &C->masks[(size_t)slot * C->W];
+    else if (C->mode == MODE_LUT) om = &C->cb[(size_t)C->cidx[slot] * C->W];
+    else if (C->placed[slot]) om = &C->masks[(size_t)slot * C->W];
+    if (!om || popc(om, C->W) == C->R * C->R * C->R) return 0;
+    ++*mask_tests;
+    int cb_[3], ce_[3];
+    raymask_key_cells(lo, hi, o, d, t0, C->R, cb_);
+    raymask_key_cells(lo, hi, o, d, t1, C->R, ce_);
+    uint32_t R = C->R;
+    size_t key = (((((size_t)cb_[0] * R + cb_[1]) * R + cb_[2]) * R + ce_[0]) * R + ce_[1]) * R + ce_[2];
+    const uint64_t* rm = &C->lut[key * C->W];
+    uint64_t any = 0;
+    for (uint32_t w = 0; w < C->W; ++w) any |= rm[w] & om[w];
+    if (any != 0) return 0;
+    ++*mask_culls;
+    if (C->slot_fp) {
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+        C->slot_fp[slot] += 1u;
+    }
+    return 1;
+}
+
 static void trace_one(const TraceCtx* C, const float* ray, uint32_t* hit, uint32_t* extra) {
     uint32_t box_tests = 0, tri_tests = 0, mask_tests = 0, mask_culls = 0;
     uint32_t best = NO_HIT;
@@ -496,28 +557,7 @@ static void trace_one(const TraceCtx* C, const float* ray, uint32_t* hit, uint32
             float tn = st_t[sp];
             if (tn > best_t) continue;
             if (ref & LEAF_BIT) {
-                uint32_t first = ref & 0x1FFFFFFFu, count = ((ref >> 29) & 3u) + 1u;
-                for (uint32_t j = first; j < first + count; ++j) {
-                    ++tri_tests;
-                    uint32_t id = C->perm[j];
-                    const float* v = &C->tris[9 * (size_t)id];
-                    float e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
-                    float e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
-                    float P[3], Q[3], S[3];
-                    cross3(d, e2, P);
-                    float det = dot3(e1, P);
-                    if (det == 0.0f) continue;
-                    float idet = 1.0f / det;
-                    S[0] = o[0] - v[0]; S[1] = o[1] - v[1]; S[2] = o[2] - v[2];
-                    float u = dot3(S, P) * idet;
-                    if (u < 0.0f || u > 1.0f) continue;
-                    cross3(S, e1, Q);
-                    float vv = dot3(d, Q) * idet;
-                    if (vv < 0.0f || u + vv > 1.0f) continue;
-                    float t = dot3(e2, Q) * idet;
-                    if (t < tmin || t > best_t) continue;
-                    if (t < best_t || (t == best_t && id < best)) { best_t = t; best = id; }
-                }
+                leaf_tests(C, ref, o, d, tmin, &best_t, &best, &tri_tests);
                 continue;
             }
             const float* nb = &C->cbox[12 * (size_t)ref];
@@ -538,35 +578,9 @@ static void trace_one(const TraceCtx* C, const float* ray, uint32_t* hit, uint32
                 }
                 hitc[c] = (t0 <= t1);
                 t0c[c] = t0;
-                uint32_t slot = 2u * ref + (uint32_t)c;
-                const uint64_t* om = NULL;
-                if (hitc[c] && use_mask) {
-                    if (C->mode == MODE_RAW) om = &C->masks[(size_t)slot * C->W];
-                    else if (C->mode == MODE_LUT) om = &C->cb[(size_t)C->cidx[slot] * C->W];
-                    else if (C->placed[slot]) om = &C->masks[(size_t)slot * C->W];
-                    if (om && popc(om, C->W) == C->R * C->R * C->R) om = NULL;
-                }
-                if (om) {
-                    ++mask_tests;
-                    int cb_[3], ce_[3];
-                    raymask_key_cells(lo, hi, o, d, t0, C->R, cb_);
-                    raymask_key_cells(lo, hi, o, d, t1, C->R, ce_);
-                    uint32_t R = C->R;
-                    size_t key = (((((size_t)cb_[0] * R + cb_[1]) * R + cb_[2]) * R + ce_[0]) * R + ce_[1]) * R + ce_[2];
-                    const uint64_t* rm = &C->lut[key * C->W];
-                    uint64_t any = 0;
-                    for (uint32_t w = 0; w < C->W; ++w) any |= rm[w] & om[w];
-                    if (any == 0) {
-                        ++mask_culls;
-                        if (C->slot_fp) {
-#ifdef _OPENMP
-#pragma omp atomic
-#endif
-                            C->slot_fp[slot] += 1u;
-                        }
-                        if (cull) hitc[c] = 0;
-                    }
-                }
+                if (hitc[c] && use_mask &&
+                    mask_test(C, 2u * ref + (uint32_t)c, lo, hi, o, d, t0, t1, &mask_tests, &mask_culls) && cull)
+                    hitc[c] = 0;
             }
             const uint32_t* ch = &C->cref[2 * (size_t)ref];
             if (hitc[0] && hitc[1]) {
@@ -613,6 +627,194 @@ int orc_trace(const float* tris, const uint32_t* perm, const float* cbox, const 
     for (int64_t i = 0; i < (int64_t)nrays; ++i)
         trace_one(&C, &rays[8 * (size_t)i], &out_hits[4 * (size_t)i],
                   out_extra ? &out_extra[2 * (size_t)i] : NULL);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * 4-wide BVH (Sect. 3.2.4 packs four child boxes with their four masks in one
+ * node). Built by collapsing the binary BVH: a 4-wide node starts from the
+ * two children of a binary inner node; while it has fewer than four children
+ * and one of them is a binary inner node, the inner child with the largest
+ * surface area (float64; the first in child order on ties) is replaced, in
+ * place, by its two children. 4-wide nodes are numbered in DFS pre-order.
+ * Child c of node m: box4[24m + 6c ..] (lo xyz, hi xyz), ref4[4m + c] (leaf
+ * refs unchanged, inner refs = 4-wide node index, EMPTY_REF for an unused
+ * slot), src4[4m + c] = the binary child slot it came from (its mask and
+ * codebook index), EMPTY_REF when unused.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const float* cbox; const uint32_t* cref;
+    float* box4; uint32_t* ref4; uint32_t* src4;
+    uint32_t n4, cap;
+} Collapse;
+
+static double slot_area(const float* cbox, uint32_t slot) {
+    const float* b = &cbox[6 * (size_t)slot];
+    double dx = (double)b[3] - (double)b[0], dy = (double)b[4] - (double)b[1], dz = (double)b[5] - (double)b[2];
+    return 2.0 * ((dx * dy + dy * dz) + dz * dx);
+}
+
+static uint32_t collapse_rec(Collapse* K, uint32_t node2) {
+    uint32_t me = K->n4++;
+    uint32_t slots[4];
+    int k = 2;
+    slots[0] = 2u * node2;
+    slots[1] = 2u * node2 + 1u;
+    while (k < 4) {
+        int pick = -1;
+        double pick_a = 0.0;
+        for (int i = 0; i < k; ++i) {
+            if (K->cref[slots[i]] & LEAF_BIT) continue;
+            double a = slot_area(K->cbox, slots[i]);
+            if (pick < 0 || a > pick_a) { pick = i; pick_a = a; }
+        }
+        if (pick < 0) break;
+        uint32_t inner = K->cref[slots[pick]];
+        for (int i = k; i > pick + 1; --i) slots[i] = slots[i - 1];
+        slots[pick] = 2u * inner;
+        slots[pick + 1] = 2u * inner + 1u;
+        ++k;
+    }
+    for (int c = 0; c < 4; ++c) {
+        float* b = &K->box4[24 * (size_t)me + 6 * (size_t)c];
+        if (c >= k) {
+            for (int j = 0; j < 6; ++j) b[j] = 0.0f;
+            K->ref4[4 * (size_t)me + c] = EMPTY_REF;
+            K->src4[4 * (size_t)me + c] = EMPTY_REF;
+            continue;
+        }
+        memcpy(b, &K->cbox[6 * (size_t)slots[c]], 6 * sizeof(float));
+        K->src4[4 * (size_t)me + c] = slots[c];
+        uint32_t r = K->cref[slots[c]];
+        K->ref4[4 * (size_t)me + c] = (r & LEAF_BIT) ? r : collapse_rec(K, r);
+    }
+    return me;
+}
+
+/* Returns the number of 4-wide nodes in *n4 and the root ref in *root4
+ * (a leaf or empty root stays as it is). Arrays hold at least max(n_inner,1)
+ * nodes. */
+int orc_bvh4_collapse(const float* cbox, const uint32_t* cref, uint32_t n_inner, uint32_t root_ref,
+                      float* box4, uint32_t* ref4, uint32_t* src4, uint32_t* n4, uint32_t* root4) {
+    Collapse K;
+    K.cbox = cbox; K.cref = cref; K.box4 = box4; K.ref4 = ref4; K.src4 = src4; K.n4 = 0; K.cap = n_inner;
+    if (root_ref == EMPTY_REF || (root_ref & LEAF_BIT) || n_inner == 0) {
+        *n4 = 0;
+        *root4 = root_ref;
+        return ORC_OK;
+    }
+    *root4 = collapse_rec(&K, root_ref);
+    *n4 = K.n4;
+    return ORC_OK;
+}
+
+typedef struct {
+    TraceCtx base;
+    const float* box4; const uint32_t* ref4; const uint32_t* src4;
+} Trace4Ctx;
+
+/* Alg. 4 on the 4-wide BVH: every used child slot gets a slab test and, when
+ * it hits, the mask test of its binary slot; surviving children are visited
+ * nearest t0 first (the lower child on equal t0), the others stacked with
+ * their t0 and dropped on pop when t0 > best_t. */
+static void trace4_one(const Trace4Ctx* T, const float* ray, uint32_t* hit, uint32_t* extra) {
+    const TraceCtx* C = &T->base;
+    uint32_t box_tests = 0, tri_tests = 0, mask_tests = 0, mask_culls = 0;
+    uint32_t best = NO_HIT;
+    float best_t = INFINITY;
+    if (ray_valid(ray) && C->root != EMPTY_REF) {
+        const float o[3] = {ray[0], ray[1], ray[2]};
+        const float d[3] = {ray[4], ray[5], ray[6]};
+        const float tmin = ray[3];
+        float inv[3] = {1.0f / d[0], 1.0f / d[1], 1.0f / d[2]};
+        best_t = ray[7];
+        int use_mask = (C->mode != MODE_NONE) && (C->flags & (FLAG_CULL | FLAG_SHADOW));
+        if (use_mask) {
+            float mo = max3f(fabsf(o[0]), fabsf(o[1]), fabsf(o[2]));
+            if (mo > C->origin_bound) use_mask = 0;
+        }
+        int cull = (C->flags & FLAG_CULL) != 0;
+        uint32_t st_ref[256];
+        float st_t[256];
+        int sp = 0;
+        st_ref[sp] = C->root; st_t[sp] = tmin; ++sp;
+        while (sp > 0) {
+            --sp;
+            uint32_t ref = st_ref[sp];
+            float tn = st_t[sp];
+            if (tn > best_t) continue;
+            if (ref & LEAF_BIT) {
+                leaf_tests(C, ref, o, d, tmin, &best_t, &best, &tri_tests);
+                continue;
+            }
+            int order[4], m = 0;
+            float t0c[4];
+            for (int c = 0; c < 4; ++c) {
+                uint32_t r = T->ref4[4 * (size_t)ref + c];
+                if (r == EMPTY_REF) continue;
+                const float* lo = &T->box4[24 * (size_t)ref + 6 * (size_t)c];
+                const float* hi = lo + 3;
+                ++box_tests;
+                float t0 = tmin, t1 = best_t;
+                for (int j = 0; j < 3; ++j) {
+                    float a = (lo[j] - o[j]) * inv[j];
+                    float b = (hi[j] - o[j]) * inv[j];
+                    if (a > b) { float t = a; a = b; b = t; }
+                    b = b * 0x1.000006p0f;
+                    t0 = (a > t0) ? a : t0;
+                    t1 = (b < t1) ? b : t1;
+                }
+                if (!(t0 <= t1)) continue;
+                if (use_mask && mask_test(C, T->src4[4 * (size_t)ref + c], lo, hi, o, d, t0, t1, &mask_tests,
+                                          &mask_culls) && cull)
+                    continue;
+                /* insert c by t0, after children with an equal or smaller t0 */
+                int i = m++;
+                while (i > 0 && t0c[i - 1] > t0) { order[i] = order[i - 1]; t0c[i] = t0c[i - 1]; --i; }
+                order[i] = c;
+                t0c[i] = t0;
+            }
+            for (int i = m - 1; i >= 0; --i) {
+                st_ref[sp] = T->ref4[4 * (size_t)ref + order[i]];
+                st_t[sp] = t0c[i];
+                ++sp;
+            }
+        }
+    }
+    float tout = (best == NO_HIT) ? INFINITY : best_t;
+    hit[0] = best;
+    memcpy(&hit[1], &tout, 4);
+    hit[2] = box_tests;
+    hit[3] = tri_tests;
+    if (extra) { extra[0] = mask_tests; extra[1] = mask_culls; }
+}
+
+int orc_trace4(const float* tris, const uint32_t* perm, const float* box4, const uint32_t* ref4,
+               const uint32_t* src4, uint32_t root4, uint32_t depth, uint32_t R, uint32_t mode,
+               const uint64_t* masks, const uint64_t* codebook, const uint16_t* cidx, const uint8_t* placed,
+               const uint64_t* lut, float origin_bound, uint32_t flags, const float* rays, uint32_t nrays,
+               uint32_t* out_hits, uint32_t* out_extra, uint32_t* slot_fp, int nthreads) {
+    if (3 * depth + 1 > 256) return ORC_ERR_DEPTH;
+    if (mode > MODE_SPARSE) return ORC_ERR_ARG;
+    if (mode != MODE_NONE && (R < 1 || R > 6 || !lut)) return ORC_ERR_ARG;
+    if ((mode == MODE_RAW || mode == MODE_SPARSE) && !masks) return ORC_ERR_ARG;
+    if (mode == MODE_SPARSE && !placed) return ORC_ERR_ARG;
+    if (mode == MODE_LUT && (!codebook || !cidx)) return ORC_ERR_ARG;
+    Trace4Ctx T;
+    TraceCtx* C = &T.base;
+    C->tris = tris; C->perm = perm; C->cbox = NULL; C->cref = NULL; C->root = root4;
+    C->R = R; C->W = words_for(R ? R : 1); C->mode = mode; C->flags = flags;
+    C->masks = masks; C->cb = codebook; C->cidx = cidx; C->lut = lut; C->placed = placed;
+    C->origin_bound = origin_bound;
+    C->slot_fp = (flags & FLAG_SHADOW) ? slot_fp : NULL;
+    T.box4 = box4; T.ref4 = ref4; T.src4 = src4;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
+    for (int64_t i = 0; i < (int64_t)nrays; ++i)
+        trace4_one(&T, &rays[8 * (size_t)i], &out_hits[4 * (size_t)i],
+                   out_extra ? &out_extra[2 * (size_t)i] : NULL);
     return ORC_OK;
 }
 
