@@ -162,7 +162,9 @@ def run_batch64(args, ctx):
         build_s = time.perf_counter() - t0
         direct = binding.Batch(ctx, list(zip(built, rays)), cull=spec["cull"], graph=False)
         key = f"batch64|{mname}|{n_tris}|{n_rays}"
-        cfg, entry = tune.tuned(ctx, key, direct.launch, log=log)
+        # batched launches take rays in descriptor order (no sorting)
+        cfg, entry = tune.tuned(ctx, key, direct.launch, log=log,
+                                cands=[c for c in tune.candidates() if c[5] == 0])
         graph = binding.Batch(ctx, list(zip(built, rays)), cull=spec["cull"], graph=True)
         hits = [torch.empty((max(r.shape[0], 1), 4), dtype=torch.int32, device="cuda") for r in rays]
 

@@ -88,6 +88,9 @@ typedef struct {
     const uint8_t* mask_placement; /* SC_MASK_SPARSE: host [2*n_inner] 0/1 per child
                                slot (slot = 2*node + child); else NULL            */
     uint32_t placement_len; /* length of mask_placement                            */
+    uint32_t width;         /* 2: binary BVH; 4: 4-wide BVH collapsed from it, each
+                               node with four child boxes and four child masks
+                               (Sect. 3.2.4); modes NONE, RAW, LUT (default 2)    */
 } sc_build_params;
 
 typedef struct {
@@ -95,6 +98,9 @@ typedef struct {
     uint32_t R, mode, codebook_size, words;  /* words = 64-bit words per mask  */
     uint32_t node_bytes;                     /* stride of one inner node        */
     uint32_t n_masked;                       /* slots that carry a mask         */
+    uint32_t width;                          /* 2 or 4                          */
+    uint32_t n_nodes;                        /* inner nodes traversed: n_inner,
+                                                or 4-wide nodes when width 4    */
     float delta, origin_bound;
     uint64_t device_bytes;                   /* scene-owned device memory       */
     double ms_bvh, ms_masks, ms_codebook, ms_compress;  /* build phases (host clock) */
@@ -164,9 +170,12 @@ sc_status sc_destroy(sc_ctx* ctx); /* NULL-safe */
  *  4. (LUT) selects the codebook by the importance SA(N) O_m(N) / R^3 of Eq. 2
  *     on the host, builds the requirement LUTs and compresses every mask with
  *     Alg. 3 on the device (Sect. 3.2.2-3.2.3);
- *  5. packs the device node array.
+ *  5. packs the device node array; with width 4 also collapses the BVH into
+ *     4-wide nodes (see sc_scene_export4) whose children take the masks and
+ *     codebook indices of the binary slots they came from.
  * Errors: SC_ERR_INVALID_ARG (null pointers, n >= 2^29, R not 4 or 6, bad
- * K, non-finite vertex), SC_ERR_DEPTH, SC_ERR_OOM, SC_ERR_HIP. n = 0 gives an
+ * K, non-finite vertex, width not 2 or 4, SPARSE with width 4), SC_ERR_DEPTH
+ * (also: a 4-wide traversal stack above 128 entries), SC_ERR_OOM, SC_ERR_HIP. n = 0 gives an
  * empty scene whose traces all miss. Synchronises `stream`.
  */
 sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_build_params* params,
@@ -185,6 +194,17 @@ sc_status sc_scene_get_info(const sc_scene* scene, sc_scene_info* out);
 /* Copy the scene's BVH, masks and codebook into caller host buffers
  * (synchronous). Used to check the build against an independent reference. */
 sc_status sc_scene_export(const sc_scene* scene, sc_scene_host* out);
+
+/* Copy a 4-wide scene's nodes (host, synchronous): box4 float [n_nodes][4][6]
+ * (child lo xyz, hi xyz), ref4 uint32 [n_nodes][4] (leaf refs as in the
+ * binary BVH, inner refs = 4-wide node index, 0xFFFFFFFF = unused child),
+ * src4 uint32 [n_nodes][4] (the binary child slot each child came from; its
+ * mask and codebook index). The collapse: a node starts from the two children
+ * of a binary inner node and, while it has fewer than four children and one
+ * is a binary inner node, replaces the one with the largest surface area
+ * (the earliest on ties) by its two children; DFS pre-order. Any pointer may
+ * be NULL. SC_ERR_INVALID_ARG for a binary scene. */
+sc_status sc_scene_export4(const sc_scene* scene, float* box4, uint32_t* ref4, uint32_t* src4);
 
 /*
  * Trace `n` rays (device float32 [n][8]: ox oy oz tmin dx dy dz tmax) with

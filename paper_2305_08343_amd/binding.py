@@ -37,14 +37,15 @@ class sc_build_params(C.Structure):
     _fields_ = [("R", C.c_uint32), ("leaf_max", C.c_uint32), ("sah_bins", C.c_uint32),
                 ("depth_cap", C.c_uint32), ("mode", C.c_uint32), ("codebook_size", C.c_uint32),
                 ("delta", C.c_float), ("origin_bound", C.c_float),
-                ("mask_placement", C.c_void_p), ("placement_len", C.c_uint32)]
+                ("mask_placement", C.c_void_p), ("placement_len", C.c_uint32), ("width", C.c_uint32)]
 
 
 class sc_scene_info(C.Structure):
     _fields_ = [("n_tris", C.c_uint32), ("n_inner", C.c_uint32), ("depth", C.c_uint32),
                 ("root_ref", C.c_uint32), ("R", C.c_uint32), ("mode", C.c_uint32),
                 ("codebook_size", C.c_uint32), ("words", C.c_uint32), ("node_bytes", C.c_uint32),
-                ("n_masked", C.c_uint32), ("delta", C.c_float), ("origin_bound", C.c_float),
+                ("n_masked", C.c_uint32), ("width", C.c_uint32), ("n_nodes", C.c_uint32),
+                ("delta", C.c_float), ("origin_bound", C.c_float),
                 ("device_bytes", C.c_uint64), ("ms_bvh", C.c_double), ("ms_masks", C.c_double),
                 ("ms_codebook", C.c_double), ("ms_compress", C.c_double)]
 
@@ -82,6 +83,7 @@ _SIGS = {
     "sc_scene_export": (C.c_int, [C.c_void_p, C.POINTER(sc_scene_host)]),
     "sc_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
+    "sc_scene_export4": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sc_ray_order": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "sc_trace_batch": (C.c_int, [C.c_void_p, C.POINTER(sc_batch_item), C.c_uint32, C.c_uint32, C.c_void_p]),
     "sc_batch_create": (C.c_int, [C.c_void_p, C.POINTER(sc_batch_item), C.c_uint32, C.c_uint32,
@@ -274,7 +276,7 @@ class Scene:
 
     def __init__(self, ctx: Context, tris, *, R: int = 6, mode: str = "raw", K: int = 4096,
                  leaf_max: int = 4, bins: int = 32, depth_cap: int = 64, delta: float = 0.0,
-                 origin_bound: float = 0.0, placement=None, stream=None):
+                 origin_bound: float = 0.0, placement=None, width: int = 2, stream=None):
         import torch
         lib = load()
         self.ctx = ctx
@@ -287,6 +289,7 @@ class Scene:
         p.R, p.leaf_max, p.sah_bins, p.depth_cap = R, leaf_max, bins, depth_cap
         p.mode, p.codebook_size = MODES[mode], K
         p.delta, p.origin_bound = delta, origin_bound
+        p.width = width
         self._placement = None
         if placement is not None:
             self._placement = np.ascontiguousarray(placement, np.uint8)
@@ -328,6 +331,15 @@ class Scene:
         out["perm"], out["masks"], out["cidx"] = out["perm"][:n], out["masks"][:2 * ni], out["cidx"][:2 * ni]
         out["codebook"] = out["codebook"][:K]
         return out
+
+    def export4(self) -> dict:
+        """Host copies of a 4-wide scene's nodes: box4 [n4, 4, 6], ref4 and src4 [n4, 4]."""
+        n4 = self.info["n_nodes"]
+        out = {"box4": np.zeros((max(n4, 1), 4, 6), np.float32), "ref4": np.zeros((max(n4, 1), 4), np.uint32),
+               "src4": np.zeros((max(n4, 1), 4), np.uint32)}
+        _check(load().sc_scene_export4(self.handle, *(out[k].ctypes.data_as(C.c_void_p)
+                                                       for k in ("box4", "ref4", "src4"))), "sc_scene_export4")
+        return {k: v[:n4] for k, v in out.items()}
 
     def features(self, stream=None):
         """Per-slot placement features, device float32 [2*n_inner, 12]."""

@@ -20,7 +20,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsubcull.so")
 SOURCES = ["api.cpp", "bvh.cpp", "codebook.cpp", "kernels_build.hip", "kernels_trace.hip", "placement.hip",
-           "raysort.hip"]
+           "raysort.hip", "bvh4.cpp"]
 ARCH = os.environ.get("SUBCULL_ARCH", "gfx950")
 
 COMMON = [

@@ -38,6 +38,11 @@ struct sc_scene {
     uint32_t full_start = 0;              // LUT mode: first full codebook entry
     uint64_t* side_masks = nullptr;       // SPARSE mode
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // vertex bounds (ray ordering keys)
+    uint32_t stride2 = kNodeBytes;        // stride of the binary node array `nodes`
+    HostBVH4 bvh4;                        // 4-wide scenes: host copy for export
+    unsigned char* nodes4 = nullptr;      // 4-wide nodes (kNode4Bytes each)
+    uint64_t* masks4 = nullptr;           // 4-wide RAW: child masks [4*n4][W]
+    uint32_t* src4 = nullptr;             // 4-wide: binary slot of each child [4*n4]
     std::vector<std::pair<void*, size_t>> owned;
 };
 
@@ -136,6 +141,8 @@ bool check_params(const sc_build_params& p, std::string& why) {
         return false;
     }
     if (p.mode == SC_MASK_SPARSE && !p.mask_placement) { why = "SPARSE needs mask_placement"; return false; }
+    if (p.width != 2 && p.width != 4) { why = "width must be 2 or 4"; return false; }
+    if (p.width == 4 && p.mode == SC_MASK_SPARSE) { why = "SPARSE needs width 2"; return false; }
     if (!std::isfinite(p.delta) || !std::isfinite(p.origin_bound)) { why = "non-finite delta/origin_bound"; return false; }
     return true;
 }
@@ -155,6 +162,7 @@ void sc_build_params_default(sc_build_params* p) {
     p->codebook_size = 4096;
     p->delta = 0.0f;
     p->origin_bound = 0.0f;
+    p->width = 2;
 }
 
 const char* sc_status_string(sc_status s) {
@@ -284,6 +292,8 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
     I.node_bytes = (P.mode == SC_MASK_RAW) ? kRawNodeBytes : kNodeBytes;
     I.delta = delta;
     I.origin_bound = ob;
+    I.width = P.width;
+    I.n_nodes = B.n_inner;
     const uint32_t S = 2 * B.n_inner;
     if (P.mode == SC_MASK_SPARSE && P.placement_len != S)
         return bail(SC_ERR_INVALID_ARG, "mask_placement length must be 2*n_inner = " + std::to_string(S));
@@ -301,6 +311,7 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
     }
     // nodes
     const uint32_t stride = I.node_bytes;
+    sc->stride2 = stride;
     std::vector<unsigned char> nodes((size_t)stride * (B.n_inner ? B.n_inner : 1), 0);
     std::vector<uint32_t> side_of_slot;
     uint32_t n_masked = (P.mode == SC_MASK_NONE) ? 0 : S;
@@ -423,6 +434,37 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
             }
         }
     }
+    if (P.width == 4) {
+        collapse_bvh4(B, sc->bvh4);
+        const HostBVH4& B4 = sc->bvh4;
+        if (B4.max_stack > kMaxStack4) return bail(SC_ERR_DEPTH, "4-wide traversal stack deeper than 128 entries");
+        I.n_nodes = B4.n4;
+        I.node_bytes = kNode4Bytes;
+        if (B4.n4 > 0) {
+            std::vector<unsigned char> n4((size_t)B4.n4 * kNode4Bytes, 0);
+            for (uint32_t m = 0; m < B4.n4; ++m) {
+                float* f = reinterpret_cast<float*>(&n4[(size_t)m * kNode4Bytes]);
+                for (int c = 0; c < 4; ++c)
+                    for (int j = 0; j < 6; ++j) f[4 * j + c] = B4.box[24 * (size_t)m + 6 * c + j];
+                std::memcpy(&n4[(size_t)m * kNode4Bytes + 96], &B4.ref[4 * (size_t)m], 16);
+            }
+            sc->nodes4 = scene_alloc<unsigned char>(sc, n4.size(), s);
+            sc->src4 = scene_alloc<uint32_t>(sc, B4.src.size() * 4, s);
+            if (!sc->nodes4 || !sc->src4) return bail(SC_ERR_OOM, "4-wide node allocation failed");
+            e = hipMemcpyAsync(sc->nodes4, n4.data(), n4.size(), hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(sc->src4, B4.src.data(), B4.src.size() * 4, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);  // n4 is a host temporary
+            if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("4-wide upload: ") + hipGetErrorString(e));
+            if (P.mode == SC_MASK_RAW) {
+                sc->masks4 = scene_alloc<uint64_t>(sc, (size_t)B4.n4 * 4 * W * 8, s);
+                if (!sc->masks4) return bail(SC_ERR_OOM, "4-wide mask allocation failed");
+            }
+            if (P.mode == SC_MASK_RAW || P.mode == SC_MASK_LUT) {
+                e = launch_pack4(P.mode, R, sc->src4, B4.n4, sc->masks, sc->cidx, sc->nodes4, sc->masks4, s);
+                if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("4-wide pack: ") + hipGetErrorString(e));
+            }
+        }
+    }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("scene build: ") + hipGetErrorString(e));
     *out = sc;
@@ -491,6 +533,16 @@ sc_status sc_scene_export(const sc_scene* scene, sc_scene_host* out) {
     return SC_OK;
 }
 
+sc_status sc_scene_export4(const sc_scene* scene, float* box4, uint32_t* ref4, uint32_t* src4) {
+    if (!scene) return fail(SC_ERR_INVALID_ARG, "scene is NULL");
+    if (scene->info.width != 4) return fail(SC_ERR_INVALID_ARG, "not a 4-wide scene");
+    const HostBVH4& B4 = scene->bvh4;
+    if (box4 && !B4.box.empty()) std::memcpy(box4, B4.box.data(), B4.box.size() * 4);
+    if (ref4 && !B4.ref.empty()) std::memcpy(ref4, B4.ref.data(), B4.ref.size() * 4);
+    if (src4 && !B4.src.empty()) std::memcpy(src4, B4.src.data(), B4.src.size() * 4);
+    return SC_OK;
+}
+
 sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags, sc_hit* d_hits,
                    uint32_t* d_extra, uint32_t* d_slot_fp, void* stream) {
     if (!scene) return fail(SC_ERR_INVALID_ARG, "scene is NULL");
@@ -519,6 +571,13 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     a.root = I.root_ref;
     a.R = I.R;
     a.mode = (I.n_inner == 0) ? (uint32_t)SC_MASK_NONE : I.mode;
+    a.width = I.width;
+    if (I.width == 4) {
+        // the 4-wide root is node 0 exactly when the binary root is node 0 (else the same leaf or empty ref)
+        a.nodes = scene->nodes4;
+        a.side_masks = scene->masks4;
+        a.src4 = scene->src4;
+    }
     a.flags = flags;
     a.origin_bound = I.origin_bound;
     a.hits = d_hits;
@@ -592,6 +651,7 @@ sc_status prepare_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_item
         if (!it.scene || it.scene->ctx != ctx) return fail(SC_ERR_INVALID_ARG, "item scene missing or from another context");
         if (it.scene->info.mode != first->info.mode || it.scene->info.R != first->info.R)
             return fail(SC_ERR_INVALID_ARG, "all batch items need the same mask mode and R");
+        if (it.scene->info.width != 2) return fail(SC_ERR_UNSUPPORTED, "batches take binary-BVH scenes only");
         if (it.n > 0 && (!it.d_rays || !it.d_hits)) return fail(SC_ERR_INVALID_ARG, "item rays/hits are NULL");
         if (((uintptr_t)it.d_rays & 15) || ((uintptr_t)it.d_hits & 15) || ((uintptr_t)it.d_extra & 7) ||
             ((uintptr_t)it.d_slot_fp & 3))
@@ -637,6 +697,7 @@ sc_status prepare_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_item
     a.stack = ctx->tune.stack;
     a.waves = ctx->tune.waves;
     a.parts = ctx->tune.parts;
+    a.width = 2;
     a.n_items = n_items;
     if (I.mode != SC_MASK_NONE && !a.lut) {  // masks exist only if the LUT was built
         for (uint32_t k = 0; k < n_items; ++k)
@@ -797,7 +858,7 @@ sc_status sc_slot_features(const sc_scene* scene, float* d_out, void* stream) {
     if (e == hipSuccess) e = launch_tri_shape(scene->tris, n, d_pre, s);
     if (e == hipSuccess) e = launch_prefix_scan(d_pre, n, 4, d_scr, s);
     if (e == hipSuccess)
-        e = launch_slot_features(I.R, scene->nodes, I.node_bytes, d_rng, d_dep, I.depth, scene->masks, d_pre, n,
+        e = launch_slot_features(I.R, scene->nodes, scene->stride2, d_rng, d_dep, I.depth, scene->masks, d_pre, n,
                                  root_area, I.n_inner, d_out, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     dev_free(ctx, d_pre, pre_bytes, s);

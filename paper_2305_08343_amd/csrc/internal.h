@@ -44,6 +44,23 @@ struct HostBVH {
     std::vector<uint32_t> perm;   // [n] original id per leaf-order position
 };
 
+// 4-wide BVH collapsed from the binary one (the node of Sect. 3.2.4 holds four
+// child boxes and four child masks). Child c of node m: box[24m + 6c ..] (lo
+// xyz, hi xyz), ref[4m + c] (leaf refs as in the binary BVH, inner refs =
+// 4-wide node index, kEmptyRef when unused), src[4m + c] = the binary child
+// slot it came from (kEmptyRef when unused). max_stack bounds the traversal
+// stack (entries on a root-to-leaf path: one per pushed sibling, plus one).
+struct HostBVH4 {
+    uint32_t n4 = 0;
+    uint32_t root = kEmptyRef;
+    uint32_t max_stack = 1;
+    std::vector<float> box;
+    std::vector<uint32_t> ref, src;
+};
+void collapse_bvh4(const HostBVH& B, HostBVH4& out);
+constexpr uint32_t kNode4Bytes = 128;  // SoA boxes (96 B), refs (16 B), aux (16 B)
+constexpr uint32_t kMaxStack4 = 128;   // traversal stack entries per ray for the 4-wide BVH
+
 // Binned SAH build; returns SC_OK, SC_ERR_DEPTH or SC_ERR_OOM.
 sc_status build_bvh(const float* tris, uint32_t n, uint32_t leaf_max, uint32_t bins,
                     uint32_t depth_cap, HostBVH& out);
@@ -94,6 +111,8 @@ struct TraceLaunch {
     uint32_t block, stack;      // threads per block, LDS stack entries per lane
     uint32_t waves;             // cap on resident waves per SIMD, 0 = occupancy limit
     const uint32_t* order;      // single scene: rays are taken in this order (NULL = index order)
+    uint32_t width;             // 2 (binary nodes) or 4 (4-wide nodes; side_masks = raw masks [4*node+c])
+    const uint32_t* src4;       // 4-wide: binary slot of child [4*node+c] (shadow counts)
     const BatchItem* items;     // batched launch: per-scene descriptors sorted by ray_begin, else null
     uint32_t n_items;
 };
@@ -122,6 +141,9 @@ hipError_t launch_compress(uint32_t R, const uint64_t* masks, uint32_t n, const 
 hipError_t launch_pack_raw(uint32_t R, const uint64_t* masks, uint32_t n_inner, unsigned char* nodes,
                            hipStream_t s);
 hipError_t launch_pack_lut(const uint16_t* idx, uint32_t n_inner, unsigned char* nodes, hipStream_t s);
+// 4-wide nodes: gather each child's raw mask (and full flag) or codebook index from its binary slot
+hipError_t launch_pack4(uint32_t mode, uint32_t R, const uint32_t* src4, uint32_t n4, const uint64_t* masks,
+                        const uint16_t* cidx, unsigned char* nodes4, uint64_t* masks4, hipStream_t s);
 
 // learned placement
 constexpr int kMlpParams = SC_MLP_PARAMS;

@@ -340,6 +340,39 @@ __global__ void pack_lut_kernel(const uint16_t* __restrict__ idx, uint32_t n_inn
     reinterpret_cast<uint32_t*>(nodes + node * kNodeBytes)[14] = v;
 }
 
+// 4-wide node m, child c from binary slot src4[4m + c]: the raw mask goes to
+// masks4[4m + c] and bit c of aux word 0 (byte 112) marks a full mask; a
+// codebook index goes to the 16-bit aux entry c.
+template <int R>
+__global__ void pack4_kernel(uint32_t mode, const uint32_t* __restrict__ src4, uint32_t n4,
+                             const uint64_t* __restrict__ masks, const uint16_t* __restrict__ cidx,
+                             unsigned char* __restrict__ nodes4, uint64_t* __restrict__ masks4) {
+    constexpr int W = (R * R * R + 63) / 64;
+    const size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n4) return;
+    uint32_t* aux = reinterpret_cast<uint32_t*>(nodes4 + m * kNode4Bytes + 112);
+    uint32_t full = 0, idx01 = 0, idx23 = 0;
+    for (int c = 0; c < 4; ++c) {
+        const uint32_t s = src4[4 * m + c];
+        if (s == kEmptyRef) continue;
+        if (mode == SC_MASK_RAW) {
+            int pc = 0;
+            for (int w = 0; w < W; ++w) {
+                const uint64_t v = masks[(size_t)s * W + w];
+                masks4[(4 * m + c) * W + w] = v;
+                pc += __popcll(v);
+            }
+            if (pc == R * R * R) full |= 1u << c;
+        } else {
+            const uint32_t v = cidx[s];
+            if (c < 2) idx01 |= v << (16 * c);
+            else idx23 |= v << (16 * (c - 2));
+        }
+    }
+    aux[0] = (mode == SC_MASK_RAW) ? full : idx01;
+    aux[1] = (mode == SC_MASK_RAW) ? 0u : idx23;
+}
+
 inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -402,6 +435,21 @@ hipError_t launch_pack_raw(uint32_t R, const uint64_t* masks, uint32_t n_inner, 
     if (R == 4) hipLaunchKernelGGL(pack_raw_kernel<4>, dim3(blocks_for(n_inner, 256)), dim3(256), 0, s, masks, n_inner, nodes);
     else if (R == 6) hipLaunchKernelGGL(pack_raw_kernel<6>, dim3(blocks_for(n_inner, 256)), dim3(256), 0, s, masks, n_inner, nodes);
     else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_pack4(uint32_t mode, uint32_t R, const uint32_t* src4, uint32_t n4, const uint64_t* masks,
+                        const uint16_t* cidx, unsigned char* nodes4, uint64_t* masks4, hipStream_t s) {
+    if (n4 == 0) return hipSuccess;
+    if (mode != SC_MASK_RAW && mode != SC_MASK_LUT) return hipErrorInvalidValue;
+    if (R == 4)
+        hipLaunchKernelGGL(pack4_kernel<4>, dim3(blocks_for(n4, 256)), dim3(256), 0, s, mode, src4, n4, masks, cidx,
+                           nodes4, masks4);
+    else if (R == 6)
+        hipLaunchKernelGGL(pack4_kernel<6>, dim3(blocks_for(n4, 256)), dim3(256), 0, s, mode, src4, n4, masks, cidx,
+                           nodes4, masks4);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -109,6 +109,56 @@ __device__ __forceinline__ void slab(const float* lo, const float* hi, const Ray
     }
 }
 
+// (ray mask of the cells holding o + t0 d and o + t1 d) AND (object mask om) != 0
+template <int R>
+__device__ __forceinline__ bool mask_overlap(const float* lo, const float* hi, const Ray& r, float t0, float t1,
+                                             const uint64_t* om, const uint64_t* lut, const uint64_t* lds_pat) {
+    constexpr int W = (R * R * R + 63) / 64;
+    const float sx = grid_scale<R>(lo[0], hi[0]);
+    const float sy = grid_scale<R>(lo[1], hi[1]);
+    const float sz = grid_scale<R>(lo[2], hi[2]);
+    const int bx = cell_of<R>(lo[0], sx, r.ox, r.dx, t0);
+    const int by = cell_of<R>(lo[1], sy, r.oy, r.dy, t0);
+    const int bz = cell_of<R>(lo[2], sz, r.oz, r.dz, t0);
+    const int ex = cell_of<R>(lo[0], sx, r.ox, r.dx, t1);
+    const int ey = cell_of<R>(lo[1], sy, r.oy, r.dy, t1);
+    const int ez = cell_of<R>(lo[2], sz, r.oz, r.dz, t1);
+    uint64_t ob[W];
+    load_mask<W>(om, ob);
+    if constexpr (R == 4) {
+        // displacement pattern (LDS) against the mask moved to its corner
+        int qx = bx, qy = by, qz = bz, fx = ex, fy = ey, fz = ez;
+        if (fx < qx) {
+            qx = ex; qy = ey; qz = ez; fx = bx; fy = by; fz = bz;
+        }
+        const int pidx = ((fx - qx) * 7 + (fy - qy + 3)) * 7 + (fz - qz + 3);
+        const int my = qy < fy ? qy : fy, mz = qz < fz ? qz : fz;
+        return ((ob[0] >> (uint32_t)(qx + 4 * my + 16 * mz)) & lds_pat[pidx]) != 0;
+    } else {
+        const uint32_t key = (uint32_t)(((((bx * R + by) * R + bz) * R + ex) * R + ey) * R + ez);
+        uint64_t rm[W];
+        load_mask<W>(lut + (size_t)key * W, rm);
+        uint64_t acc = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) acc |= rm[w] & ob[w];
+        return acc != 0;
+    }
+}
+
+// order by (key, id): swap when b comes first
+__device__ __forceinline__ void order2(float& ka, uint32_t& ia, uint32_t& ra, float& kb, uint32_t& ib,
+                                       uint32_t& rb) {
+    const bool sw = (kb < ka) || (kb == ka && ib < ia);
+    const float k = sw ? kb : ka;
+    const uint32_t i = sw ? ib : ia, q = sw ? rb : ra;
+    kb = sw ? ka : kb;
+    ib = sw ? ia : ib;
+    rb = sw ? ra : rb;
+    ka = k;
+    ia = i;
+    ra = q;
+}
+
 #ifndef SC_TRACE_WAVES_PER_EU
 #define SC_TRACE_WAVES_PER_EU 0
 #endif
@@ -118,8 +168,9 @@ __device__ __forceinline__ void slab(const float* lo, const float* hi, const Ray
 #define SC_TRACE_OCCUPANCY
 #endif
 
-template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH>
+template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH, int WIDTH>
 __global__ __launch_bounds__(BLOCK) SC_TRACE_OCCUPANCY void trace_kernel(TraceLaunch a) {
+    static_assert(WIDTH == 2 || (WIDTH == 4 && !BATCH && MODE != kModeSparse), "4-wide: single scene, no sparse masks");
     constexpr int W = (R * R * R + 63) / 64;
     constexpr uint32_t kStride = (MODE == kModeRaw) ? kRawNodeBytes : kNodeBytes;
     constexpr int kWavesPerBlock = BLOCK / kWave;
@@ -144,7 +195,10 @@ __global__ __launch_bounds__(BLOCK) SC_TRACE_OCCUPANCY void trace_kernel(TraceLa
     const bool cull = (a.flags & SC_TRACE_CULL) != 0;
     const bool shadow_flag = (a.flags & SC_TRACE_SHADOW) != 0;
 
-    uint2 spill[kMaxDepth - STACK + 1];
+    // deeper stack entries: a binary traversal holds at most depth + 1 <= 65,
+    // a 4-wide one at most kMaxStack4 (checked when the scene is built)
+    constexpr int kSpill = (WIDTH == 2) ? (int)kMaxDepth - STACK + 1 : (int)kMaxStack4 - STACK;
+    uint2 spill[kSpill];
 
     // The scene of the lane's current ray: uniform for a single scene, per
     // lane in a batch (set when the lane takes a ray).
@@ -289,6 +343,84 @@ __global__ __launch_bounds__(BLOCK) SC_TRACE_OCCUPANCY void trace_kernel(TraceLa
                         best = id;
                     }
                 }
+            } else if constexpr (WIDTH == 4) {
+                // 4-wide node: SoA boxes lo.x[4] lo.y[4] lo.z[4] hi.x[4] hi.y[4] hi.z[4], refs[4], aux
+                const float4* np4 = reinterpret_cast<const float4*>(s_nodes + (size_t)ref * kNode4Bytes);
+                const float4 lx = np4[0], ly = np4[1], lz = np4[2], hx = np4[3], hy = np4[4], hz = np4[5];
+                const uint4 cr = reinterpret_cast<const uint4*>(np4)[6];
+                const uint4 ax = reinterpret_cast<const uint4*>(np4)[7];
+                const float clx[4] = {lx.x, lx.y, lx.z, lx.w}, cly[4] = {ly.x, ly.y, ly.z, ly.w};
+                const float clz[4] = {lz.x, lz.y, lz.z, lz.w}, chx[4] = {hx.x, hx.y, hx.z, hx.w};
+                const float chy[4] = {hy.x, hy.y, hy.z, hy.w}, chz[4] = {hz.x, hz.y, hz.z, hz.w};
+                const uint32_t crf[4] = {cr.x, cr.y, cr.z, cr.w};
+                // surviving children as (t0, child index, ref); dead ones sort last. The
+                // loop keeps a flag instead of leaving an iteration early: a form with
+                // `continue` in the mask branch was compiled into code that dropped every
+                // child whose mask was tested.
+                float key[4];
+                uint32_t kid[4], kref[4];
+                uint32_t alive = 0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    key[c] = __builtin_inff();
+                    kid[c] = 4u + (uint32_t)c;
+                    kref[c] = crf[c];
+                    bool keep = false;
+                    float t0 = 0.0f, t1 = 0.0f;
+                    const float lo[3] = {clx[c], cly[c], clz[c]}, hi[3] = {chx[c], chy[c], chz[c]};
+                    if (crf[c] != kEmptyRef) {
+                        ++box_tests;
+                        slab(lo, hi, r, best_t, t0, t1);
+                        keep = t0 <= t1;
+                    }
+                    if constexpr (MODE != kModeNone) {
+                        if (keep && use_mask) {
+                            const uint64_t* om = nullptr;
+                            if constexpr (MODE == kModeRaw) {
+                                if (!((ax.x >> c) & 1u)) om = s_side + ((size_t)ref * 4 + c) * W;
+                            } else {
+                                const uint32_t idx = ((c < 2 ? ax.x : ax.y) >> (16 * (c & 1))) & 0xFFFFu;
+                                if (idx < s_full) {
+                                    if constexpr (MODE == kModeLutLds) om = lds_cb + idx * W;
+                                    else om = s_codebook + (size_t)idx * W;
+                                }
+                            }
+                            if (om) {
+                                ++mask_tests;
+                                if (!mask_overlap<R>(lo, hi, r, t0, t1, om, a.lut, lds_pat)) {
+                                    ++mask_culls;
+                                    if (shadow_flag && s_fp) atomicAdd(&s_fp[a.src4[(size_t)ref * 4 + c]], 1u);
+                                    keep = !cull;
+                                }
+                            }
+                        }
+                    }
+                    if (keep) {
+                        key[c] = t0;
+                        kid[c] = (uint32_t)c;
+                        ++alive;
+                    }
+                }
+                // sorting network for four (t0, child) pairs
+                order2(key[0], kid[0], kref[0], key[1], kid[1], kref[1]);
+                order2(key[2], kid[2], kref[2], key[3], kid[3], kref[3]);
+                order2(key[0], kid[0], kref[0], key[2], kid[2], kref[2]);
+                order2(key[1], kid[1], kref[1], key[3], kid[3], kref[3]);
+                order2(key[1], kid[1], kref[1], key[2], kid[2], kref[2]);
+                if (alive > 0) {
+                    // farther survivors go on the stack, the second nearest on top
+#pragma unroll
+                    for (int j = 3; j >= 1; --j) {
+                        if ((uint32_t)j < alive) {
+                            const uint2 e = make_uint2(kref[j], __float_as_uint(key[j]));
+                            if (sp < STACK) lds_stack[sp * BLOCK + tid] = e;
+                            else spill[sp - STACK] = e;
+                            ++sp;
+                        }
+                    }
+                    ref = kref[0];
+                    pop = false;
+                }
             } else {
                 const unsigned char* np = s_nodes + (size_t)ref * kStride;
                 const float4 n0 = reinterpret_cast<const float4*>(np)[0];
@@ -330,37 +462,7 @@ __global__ __launch_bounds__(BLOCK) SC_TRACE_OCCUPANCY void trace_kernel(TraceLa
                             const float* lo = c ? lo1 : lo0;
                             const float* hi = c ? hi1 : hi0;
                             const float t0 = c ? t01 : t00, t1 = c ? t11 : t10;
-                            const float sx = grid_scale<R>(lo[0], hi[0]);
-                            const float sy = grid_scale<R>(lo[1], hi[1]);
-                            const float sz = grid_scale<R>(lo[2], hi[2]);
-                            const int bx = cell_of<R>(lo[0], sx, r.ox, r.dx, t0);
-                            const int by = cell_of<R>(lo[1], sy, r.oy, r.dy, t0);
-                            const int bz = cell_of<R>(lo[2], sz, r.oz, r.dz, t0);
-                            const int ex = cell_of<R>(lo[0], sx, r.ox, r.dx, t1);
-                            const int ey = cell_of<R>(lo[1], sy, r.oy, r.dy, t1);
-                            const int ez = cell_of<R>(lo[2], sz, r.oz, r.dz, t1);
-                            uint64_t ob[W];
-                            load_mask<W>(om, ob);
-                            bool any;
-                            if constexpr (R == 4) {
-                                // displacement pattern (LDS) against the mask moved to its corner
-                                int qx = bx, qy = by, qz = bz, fx = ex, fy = ey, fz = ez;
-                                if (fx < qx) {
-                                    qx = ex; qy = ey; qz = ez; fx = bx; fy = by; fz = bz;
-                                }
-                                const int pidx = ((fx - qx) * 7 + (fy - qy + 3)) * 7 + (fz - qz + 3);
-                                const int my = qy < fy ? qy : fy, mz = qz < fz ? qz : fz;
-                                any = ((ob[0] >> (uint32_t)(qx + 4 * my + 16 * mz)) & lds_pat[pidx]) != 0;
-                            } else {
-                                const uint32_t key = (uint32_t)(((((bx * R + by) * R + bz) * R + ex) * R + ey) * R + ez);
-                                uint64_t rm[W];
-                                load_mask<W>(a.lut + (size_t)key * W, rm);
-                                uint64_t acc = 0;
-#pragma unroll
-                                for (int w = 0; w < W; ++w) acc |= rm[w] & ob[w];
-                                any = acc != 0;
-                            }
-                            if (!any) {
+                            if (!mask_overlap<R>(lo, hi, r, t0, t1, om, a.lut, lds_pat)) {
                                 ++mask_culls;
                                 if (shadow_flag && s_fp) atomicAdd(&s_fp[2 * (size_t)ref + c], 1u);
                                 if (cull) {
@@ -406,7 +508,7 @@ __global__ __launch_bounds__(BLOCK) SC_TRACE_OCCUPANCY void trace_kernel(TraceLa
     }
 }
 
-template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH>
+template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH, int WIDTH>
 hipError_t launch_one(const TraceLaunch& a, hipStream_t s) {
     // blocks per CU that fit, and CUs, computed once per instance
     static int per_cu = 0, cus = 0;
@@ -414,7 +516,8 @@ hipError_t launch_one(const TraceLaunch& a, hipStream_t s) {
         int dev = 0, c = 0, p = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, trace_kernel<MODE, R, BLOCK, STACK, BATCH>, BLOCK, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, trace_kernel<MODE, R, BLOCK, STACK, BATCH, WIDTH>,
+                                                           BLOCK, 0);
         cus = c > 0 ? c : 256;
         per_cu = p > 0 ? p : 4;
     }
@@ -430,32 +533,58 @@ hipError_t launch_one(const TraceLaunch& a, hipStream_t s) {
     uint32_t blocks = (waves + BLOCK / kWave - 1) / (BLOCK / kWave);
     blocks = blocks < resident ? blocks : resident;
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(kQueueParts), 0, s, a.queue, kQueueParts);
-    hipLaunchKernelGGL((trace_kernel<MODE, R, BLOCK, STACK, BATCH>), dim3(blocks), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((trace_kernel<MODE, R, BLOCK, STACK, BATCH, WIDTH>), dim3(blocks), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
 template <int BLOCK, int STACK, bool BATCH>
 hipError_t launch_cfg(const TraceLaunch& a, hipStream_t s) {
     switch (a.mode) {
-        case SC_MASK_NONE: return launch_one<kModeNone, 6, BLOCK, STACK, BATCH>(a, s);
+        case SC_MASK_NONE: return launch_one<kModeNone, 6, BLOCK, STACK, BATCH, 2>(a, s);
         case SC_MASK_RAW:
-            return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK, BATCH>(a, s)
-                            : launch_one<kModeRaw, 6, BLOCK, STACK, BATCH>(a, s);
+            return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK, BATCH, 2>(a, s)
+                            : launch_one<kModeRaw, 6, BLOCK, STACK, BATCH, 2>(a, s);
         case SC_MASK_LUT:
             if (!BATCH && (size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
-                return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK, false>(a, s)
-                                : launch_one<kModeLutLds, 6, BLOCK, STACK, false>(a, s);
-            return a.R == 4 ? launch_one<kModeLut, 4, BLOCK, STACK, BATCH>(a, s)
-                            : launch_one<kModeLut, 6, BLOCK, STACK, BATCH>(a, s);
+                return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK, false, 2>(a, s)
+                                : launch_one<kModeLutLds, 6, BLOCK, STACK, false, 2>(a, s);
+            return a.R == 4 ? launch_one<kModeLut, 4, BLOCK, STACK, BATCH, 2>(a, s)
+                            : launch_one<kModeLut, 6, BLOCK, STACK, BATCH, 2>(a, s);
         case SC_MASK_SPARSE:
-            return a.R == 4 ? launch_one<kModeSparse, 4, BLOCK, STACK, BATCH>(a, s)
-                            : launch_one<kModeSparse, 6, BLOCK, STACK, BATCH>(a, s);
+            return a.R == 4 ? launch_one<kModeSparse, 4, BLOCK, STACK, BATCH, 2>(a, s)
+                            : launch_one<kModeSparse, 6, BLOCK, STACK, BATCH, 2>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int BLOCK, int STACK>
+hipError_t launch_cfg4(const TraceLaunch& a, hipStream_t s) {
+    switch (a.mode) {
+        case SC_MASK_NONE: return launch_one<kModeNone, 6, BLOCK, STACK, false, 4>(a, s);
+        case SC_MASK_RAW:
+            return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK, false, 4>(a, s)
+                            : launch_one<kModeRaw, 6, BLOCK, STACK, false, 4>(a, s);
+        case SC_MASK_LUT:
+            if ((size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
+                return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK, false, 4>(a, s)
+                                : launch_one<kModeLutLds, 6, BLOCK, STACK, false, 4>(a, s);
+            return a.R == 4 ? launch_one<kModeLut, 4, BLOCK, STACK, false, 4>(a, s)
+                            : launch_one<kModeLut, 6, BLOCK, STACK, false, 4>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <bool BATCH>
 hipError_t launch_any(const TraceLaunch& a, hipStream_t s) {
+    if (!BATCH && a.width == 4) {
+        if (a.block == 256 && a.stack == 8) return launch_cfg4<256, 8>(a, s);
+        if (a.block == 128 && a.stack == 8) return launch_cfg4<128, 8>(a, s);
+        if (a.block == 256 && a.stack == 12) return launch_cfg4<256, 12>(a, s);
+        if (a.block == 256 && a.stack == 4) return launch_cfg4<256, 4>(a, s);
+        if (a.block == 128 && a.stack == 16) return launch_cfg4<128, 16>(a, s);
+        return hipErrorInvalidValue;
+    }
+    if (a.width != 2) return hipErrorInvalidValue;
     if (a.block == 256 && a.stack == 8) return launch_cfg<256, 8, BATCH>(a, s);
     if (a.block == 128 && a.stack == 8) return launch_cfg<128, 8, BATCH>(a, s);
     if (a.block == 256 && a.stack == 12) return launch_cfg<256, 12, BATCH>(a, s);

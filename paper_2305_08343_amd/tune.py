@@ -66,8 +66,9 @@ def successive_halving(ctx, run, cands=None, reps0: int = 1, log=None):
     return best, last
 
 
-def tuned(ctx, key: str, run, cache_path: str | None = None, log=None):
-    """Look up (or measure and store) the best launch shape for `key`."""
+def tuned(ctx, key: str, run, cache_path: str | None = None, log=None, cands=None):
+    """Look up (or measure and store) the best launch shape for `key` among `cands`
+    (default: every candidate)."""
     cache_path = cache_path or os.path.join(os.path.expanduser("~"), ".cache", "subcull_tune.json")
     full_key = f"{key}|{_gpu_name()}"
     cache = {}
@@ -82,7 +83,7 @@ def tuned(ctx, key: str, run, cache_path: str | None = None, log=None):
         ctx.set_tune(*cfg)
         return cfg, cache[full_key]
     t0 = time.perf_counter()
-    best, times = successive_halving(ctx, run, log=log)
+    best, times = successive_halving(ctx, run, cands=cands, log=log)
     entry = {"config": list(best), "ms": times[best], "seconds": time.perf_counter() - t0,
              "tried": {",".join(map(str, k)): v for k, v in times.items()}}
     cache[full_key] = entry

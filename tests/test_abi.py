@@ -15,7 +15,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sc_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(sc_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_api():
@@ -25,7 +25,8 @@ def test_header_declares_the_api():
                  "sc_status_string", "sc_last_error", "sc_build_params_default", "sc_set_tune",
                  "sc_get_tune", "sc_trace_batch", "sc_batch_create", "sc_batch_launch",
                  "sc_batch_destroy", "sc_bvh_build_host", "sc_slot_features", "sc_mlp_forward",
-                 "sc_mlp_backward", "sc_mlp_adam", "sc_place_top", "sc_ray_order"):
+                 "sc_mlp_backward", "sc_mlp_adam", "sc_place_top", "sc_ray_order",
+                 "sc_scene_export4"):
         assert must in names
 
 
@@ -41,14 +42,14 @@ def test_params_default_and_status_strings():
     p = B.sc_build_params()
     lib.sc_build_params_default(C.byref(p))
     assert (p.R, p.leaf_max, p.sah_bins, p.depth_cap, p.mode, p.codebook_size) == (6, 4, 32, 64, 1, 4096)
-    assert p.delta == 0.0 and p.origin_bound == 0.0 and not p.mask_placement
+    assert p.delta == 0.0 and p.origin_bound == 0.0 and not p.mask_placement and p.width == 2
     for s, txt in [(0, b"ok"), (1, b"invalid argument"), (4, b"BVH depth cap exceeded")]:
         assert lib.sc_status_string(s) == txt
 
 
 def test_struct_sizes_match_header_layout():
-    # 10 uint32, 2 float, uint64, 4 double
-    assert C.sizeof(B.sc_scene_info) == 40 + 8 + 8 + 32
+    # 12 uint32, 2 float, uint64, 4 double
+    assert C.sizeof(B.sc_scene_info) == 48 + 8 + 8 + 32
     assert C.sizeof(B.sc_build_params) == 48
     assert C.sizeof(B.sc_scene_host) == 7 * 8
     assert C.sizeof(B.sc_tune) == 6 * 4
@@ -66,6 +67,7 @@ def test_null_arguments_rejected_before_hip():
     assert lib.sc_compress_masks(None, 6, None, 64, None, 0, None, None) == 1
     assert lib.sc_set_tune(None, None) == 1 and lib.sc_get_tune(None, None) == 1
     assert lib.sc_ray_order(None, None, 0, None, None) == 1
+    assert lib.sc_scene_export4(None, None, None, None) == 1
     assert lib.sc_trace_batch(None, None, 0, 0, None) == 1
     assert lib.sc_batch_create(None, None, 0, 0, None) == 1
     assert lib.sc_batch_launch(None, None) == 1 and lib.sc_batch_destroy(None) == 0
@@ -79,7 +81,7 @@ def test_bad_build_params_rejected_before_hip():
     fake_ctx = C.c_void_p(1)  # never dereferenced: parameter checks come first
     out = C.c_void_p()
     for field, value in [("R", 5), ("leaf_max", 0), ("leaf_max", 5), ("sah_bins", 1), ("depth_cap", 65),
-                         ("mode", 9)]:
+                         ("mode", 9), ("width", 3), ("width", 0)]:
         q = B.sc_build_params.from_buffer_copy(p)
         setattr(q, field, value)
         assert lib.sc_scene_build(fake_ctx, None, 0, C.byref(q), None, C.byref(out)) == 1, field
@@ -90,6 +92,10 @@ def test_bad_build_params_rejected_before_hip():
     q.mode = 3
     assert lib.sc_scene_build(fake_ctx, None, 0, C.byref(q), None, C.byref(out)) == 1
     assert b"mask_placement" in lib.sc_last_error()
+    q.width = 4
+    q.mask_placement = C.c_void_p(1)
+    assert lib.sc_scene_build(fake_ctx, None, 0, C.byref(q), None, C.byref(out)) == 1
+    assert b"width 2" in lib.sc_last_error()
     assert lib.sc_scene_build(fake_ctx, None, 1 << 29, C.byref(p), None, C.byref(out)) == 1
 
 
