@@ -6,10 +6,15 @@ radius 5e-3, tilt up to 60 degrees, plus a 2-triangle ground plane) and
 4,147,200 rays (1920x1080 pinhole primaries followed by one cosine-diffuse
 surface ray per pixel). One step = one trace of the whole ray batch, rays
 and scene resident in HBM. The headline value is the 216-bit (R = 6) raw-mask
-culled trace; the plain BVH and 64-bit (R = 4) masks are timed beside it.
+culled trace on the 4-wide BVH (Sect. 3.2.4 node: four child boxes and
+masks); the plain traversal (4-wide and binary), the binary culled trace and
+64-bit (R = 4) masks are timed beside it. Each mode's launch shape is picked
+is the one the autotuner picked for it on this workload (stored in MODES;
+--autotune re-runs the tuner); results never depend on it.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes raw6,none,raw4]
-                    [--no-cpu-baseline] [--cpu-seconds S]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes raw6w4,nonew4,none,raw6,raw4w4]
+                    [--no-cpu-baseline] [--cpu-seconds S] [--autotune | --tune b,s,c,p,w,o]
+                    [--workload hair_1m|batch64|placement]
 """
 from __future__ import annotations
 
@@ -32,17 +37,26 @@ RAY_BYTES, HIT_BYTES, EXTRA_BYTES, TRI_BYTES = 32, 16, 8, 48
 # HBM-side bytes per trace launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, each scaled by the
 # same counter's reading for a 1 GiB plain copy (FETCH x2.0, WRITE x1.0). Valid only for the traversal
 # kernel source whose SHA-256 starts with this prefix; otherwise traffic is reported as null.
-MEASURED_TRAFFIC = {"source_sha256_16": "e446efb3fbebc7ba", "raw6": 18.569e9, "none": 19.427e9}
+MEASURED_TRAFFIC = {"source_sha256_16": "16c8c195c7ce2346", "raw6w4": 16.853e9, "none": 19.430e9}
 TRACE_SOURCE = os.path.join(ROOT, "paper_2305_08343_amd", "csrc", "kernels_trace.hip")
 
+# width 2: binary nodes (node_bytes per visit); width 4: 4-wide nodes of Sect. 3.2.4 (child records of
+# 32 bytes, raw masks in their own array, mask_bytes per mask test). tune = (block, stack, chunk, parts,
+# waves, sort) picked by the autotuner (bench.py --autotune) on this workload on one MI355X.
 MODES = {
-    "raw6": dict(mode="raw", R=6, cull=True, node_bytes=128),
-    "none": dict(mode="none", R=6, cull=False, node_bytes=64),
-    "raw4": dict(mode="raw", R=4, cull=True, node_bytes=128),
-    "lut6": dict(mode="lut", R=6, cull=True, node_bytes=64, K=4096),
-    "lut6k256": dict(mode="lut", R=6, cull=True, node_bytes=64, K=256),
-    "lut4k256": dict(mode="lut", R=4, cull=True, node_bytes=64, K=256),
+    "raw6w4": dict(mode="raw", R=6, cull=True, width=4, mask_bytes=32, tune=(256, 12, 1, 8, 6, 0)),
+    "raw4w4": dict(mode="raw", R=4, cull=True, width=4, mask_bytes=8, tune=(256, 12, 1, 8, 6, 0)),
+    "nonew4": dict(mode="none", R=6, cull=False, width=4, mask_bytes=0, tune=(256, 12, 1, 8, 0, 0)),
+    "lut6w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, tune=(256, 12, 1, 8, 6, 0)),
+    "lut4k256w4": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 0, 0)),
+    "raw6": dict(mode="raw", R=6, cull=True, width=2, node_bytes=128, tune=(256, 12, 1, 8, 6, 1)),
+    "none": dict(mode="none", R=6, cull=False, width=2, node_bytes=64, tune=(256, 8, 1, 8, 0, 0)),
+    "raw4": dict(mode="raw", R=4, cull=True, width=2, node_bytes=128, tune=(256, 8, 1, 8, 0, 0)),
+    "lut6": dict(mode="lut", R=6, cull=True, width=2, node_bytes=64, K=4096),
+    "lut6k256": dict(mode="lut", R=6, cull=True, width=2, node_bytes=64, K=256),
+    "lut4k256": dict(mode="lut", R=4, cull=True, width=2, node_bytes=64, K=256),
 }
+CHILD_BYTES_W4 = 32  # 24-byte box + 4-byte ref + 4 bytes of the node's aux word, per tested child
 
 
 def measured_traffic(mode):
@@ -58,25 +72,37 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(box_tests, tri_tests, n_rays, node_bytes):
+def algorithmic_bytes(box_tests, tri_tests, mask_tests, n_rays, spec):
     """Bytes one trace launch must move: rays in, hits and mask counters out,
-    one node line per inner-node visit (two slab tests each) and one
-    triangle record per triangle test. The ray-mask LUT and the codebook
-    are cache-resident by design and not counted."""
-    visits = box_tests.sum(dtype=np.float64) / 2.0
-    return (n_rays * (RAY_BYTES + HIT_BYTES + EXTRA_BYTES) + visits * node_bytes
+    one triangle record per triangle test, and the nodes: for binary nodes
+    one node line per inner-node visit (two slab tests each); for 4-wide
+    nodes one 32-byte child record per slab test plus one raw mask per mask
+    test. The ray-mask LUT and the codebook are cache-resident by design and
+    not counted."""
+    tests = box_tests.sum(dtype=np.float64)
+    if spec["width"] == 2:
+        nodes = tests / 2.0 * spec["node_bytes"]
+    else:
+        nodes = tests * CHILD_BYTES_W4 + mask_tests.sum(dtype=np.float64) * spec["mask_bytes"]
+    return (n_rays * (RAY_BYTES + HIT_BYTES + EXTRA_BYTES) + nodes
             + tri_tests.sum(dtype=np.float64) * TRI_BYTES)
 
 
-def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup):
+def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup, autotune=False):
     import torch
-    from paper_2305_08343_amd import binding
+    from paper_2305_08343_amd import binding, tune
     t0 = time.perf_counter()
-    scene = binding.Scene(ctx, tris, R=spec["R"], mode=spec["mode"], K=spec.get("K", 4096))
+    scene = binding.Scene(ctx, tris, R=spec["R"], mode=spec["mode"], K=spec.get("K", 4096), width=spec["width"])
     build_s = time.perf_counter() - t0
     n = rays_dev.shape[0]
     hits = torch.empty((n, 4), dtype=torch.int32, device=rays_dev.device)
     extra = torch.empty((n, 2), dtype=torch.int32, device=rays_dev.device)
+    tuned = None
+    if autotune:
+        key = f"hair_1m|{name}|{tris.shape[0]}|{n}"
+        cfg, entry = tune.tuned(ctx, key, lambda: scene.trace(rays_dev, cull=spec["cull"], hits=hits,
+                                                              extra_out=extra), log=log)
+        tuned = {"config": list(cfg), "seconds": entry.get("seconds")}
     res = scene.trace(rays_dev, cull=spec["cull"], hits=hits, extra_out=extra).numpy()
     for _ in range(warmup):
         scene.trace(rays_dev, cull=spec["cull"], hits=hits, extra_out=extra)
@@ -92,7 +118,7 @@ def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup):
     wall = time.perf_counter() - t_start
     kernel_ms = np.array([a.elapsed_time(b) for a, b in ev])
     box, tri = res["box_tests"], res["tri_tests"]
-    alg = algorithmic_bytes(box, tri, n, spec["node_bytes"])
+    alg = algorithmic_bytes(box, tri, res["mask_tests"], n, spec)
     info = scene.info
     out = {
         "rays_per_s": n * steps / wall,
@@ -109,37 +135,48 @@ def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup):
         "alg_gbs": alg / (kernel_ms.mean() * 1e-3) / 1e9,
         "build_s": build_s,
         "build_ms": {k: info[k] for k in ("ms_bvh", "ms_masks", "ms_codebook", "ms_compress")},
-        "n_inner": info["n_inner"], "depth": info["depth"],
+        "n_inner": info["n_inner"], "n_nodes": info["n_nodes"], "width": info["width"], "depth": info["depth"],
+        "tune": ctx.get_tune(), "autotune": tuned,
         "scene_mbytes": info["device_bytes"] / 2 ** 20,
     }
     scene.close()
     return out, res
 
 
-def cpu_baseline(tris, rays, target_s):
-    """The oracle as it stands, on this host's cores, on an every-k-th ray sample."""
+def cpu_baseline(tris, rays, target_s, width=2):
+    """The oracle as it stands, on this host's cores, on an every-k-th ray sample
+    (R = 6 raw masks, culled, on the binary or the 4-wide BVH)."""
     import oracle
     cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
     bvh = oracle.bvh_build(tris)
     ob, delta = oracle.default_bounds(tris)
     masks = oracle.object_masks(tris, bvh, 6, delta, nthreads=cores)
+    b4 = oracle.bvh4_collapse(bvh) if width == 4 else None
     setup = time.perf_counter() - t0
     lut = oracle.raymask_lut(6)
+
+    def run(sample):
+        kw = dict(mode="raw", R=6, masks=masks, lut=lut, origin_bound=ob, nthreads=cores)
+        if b4 is not None:
+            oracle.trace4(tris, bvh, b4, sample, **kw)
+        else:
+            oracle.trace(tris, bvh, sample, **kw)
+
     probe = rays[::4096]
     t0 = time.perf_counter()
-    oracle.trace(tris, bvh, probe, mode="raw", R=6, masks=masks, lut=lut, origin_bound=ob, nthreads=cores)
+    run(probe)
     dt = max(time.perf_counter() - t0, 1e-4)
     want = int(min(rays.shape[0], max(probe.shape[0], probe.shape[0] * target_s / dt)))
     step = max(1, rays.shape[0] // want)
     sample = rays[::step]
     t0 = time.perf_counter()
-    oracle.trace(tris, bvh, sample, mode="raw", R=6, masks=masks, lut=lut, origin_bound=ob, nthreads=cores)
+    run(sample)
     dt = time.perf_counter() - t0
     return {"value": sample.shape[0] / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
-            "sample": f"every {step}th ray of the 4,147,200 ({sample.shape[0]} rays), R=6 raw masks, "
-                      f"culled; {dt:.1f} s of trace on {cores} threads; oracle BVH+mask setup "
-                      f"{setup:.1f} s not timed"}
+            "sample": f"every {step}th ray of the {rays.shape[0]:,} ({sample.shape[0]} rays), R=6 raw masks, "
+                      f"culled, {'4-wide' if width == 4 else 'binary'} BVH; {dt:.1f} s of trace on {cores} "
+                      f"threads; oracle BVH+mask setup {setup:.1f} s not timed"}
 
 
 def run_batch64(args, ctx):
@@ -247,7 +284,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="raw6,none,raw4")
+    ap.add_argument("--modes", default="raw6w4,nonew4,none,raw6,raw4w4")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick each mode's launch shape live with the autotuner instead of the stored one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tune", default="", help="block,stack,chunk,parts[,waves[,sort]] of the traversal launch")
@@ -269,7 +308,7 @@ def main():
 
     if args.workload == "batch64":
         ctx = binding.Context(0)
-        if args.modes == "raw6,none,raw4":
+        if args.modes == ap.get_default("modes"):
             args.modes = "raw6,none"
         run_batch64(args, ctx)
         ctx.close()
@@ -284,26 +323,30 @@ def main():
     rays = scenes.rays_hair_1m(tris, 1)
     log(f"generated {tris.shape[0]} tris, {rays.shape[0]} rays in {time.perf_counter() - t0:.1f}s")
     ctx = binding.Context(0)
-    if args.tune:
-        ctx.set_tune(*(int(x) for x in args.tune.split(",")))
+    autotune = args.autotune and not args.tune
     rays_dev = torch.from_numpy(rays).cuda()
     modes = [m for m in args.modes.split(",") if m]
     results, raw = {}, {}
     for m in modes:
-        log(f"mode {m}: build + {args.warmup} warmup + {args.steps} timed traces")
-        results[m], raw[m] = time_mode(ctx, tris, rays_dev, m, MODES[m], args.steps, args.warmup)
+        if args.tune:
+            ctx.set_tune(*(int(x) for x in args.tune.split(",")))
+        else:
+            ctx.set_tune(*MODES[m].get("tune", ()))
+        log(f"mode {m}: build{' + autotune' if autotune else ''} + {args.warmup} warmup + {args.steps} timed traces")
+        results[m], raw[m] = time_mode(ctx, tris, rays_dev, m, MODES[m], args.steps, args.warmup, autotune)
         log(f"mode {m}: {results[m]['rays_per_s'] / 1e6:.1f} Mrays/s, "
             f"{results[m]['tests_per_ray']:.2f} tests/ray, kernel {results[m]['kernel_ms_mean']:.3f} ms")
     head = modes[0]
-    if "none" in raw:
-        for m in modes:
-            if m == "none":
+    for m in modes:
+        # unculled reference: the plain traversal of the same node width, and the plain binary BVH
+        for key, ref in (("unculled", "nonew4" if MODES[m]["width"] == 4 else "none"), ("plain_binary", "none")):
+            if ref not in raw or ref == m:
                 continue
-            same = bool((raw[m]["prim"] == raw["none"]["prim"]).all() and
-                        (raw[m]["t"].view(np.uint32) == raw["none"]["t"].view(np.uint32)).all())
-            results[m]["hits_equal_unculled"] = same
-            results[m]["tests_ratio_vs_unculled"] = results[m]["tests_per_ray"] / results["none"]["tests_per_ray"]
-            results[m]["speedup_vs_unculled"] = results[m]["rays_per_s"] / results["none"]["rays_per_s"]
+            same = bool((raw[m]["prim"] == raw[ref]["prim"]).all() and
+                        (raw[m]["t"].view(np.uint32) == raw[ref]["t"].view(np.uint32)).all())
+            results[m][f"hits_equal_{key}"] = same
+            results[m][f"tests_ratio_vs_{key}"] = results[m]["tests_per_ray"] / results[ref]["tests_per_ray"]
+            results[m][f"speedup_vs_{key}"] = results[m]["rays_per_s"] / results[ref]["rays_per_s"]
     r = results[head]
     line = {
         "metric": METRIC, "value": r["rays_per_s"], "unit": "rays/s", "n_gpus": 1,
@@ -312,15 +355,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "hair_1m: 1,000,002 tris (20k helical strands x 25 segments x 2 tris, "
                                "width 1e-3, + ground plane), 4,147,200 rays (1920x1080 primary + 1 "
-                               "diffuse surface ray per pixel), binary SAH BVH, "
+                               "diffuse surface ray per pixel), SAH BVH (binary; 4-wide in the w4 modes), "
                                f"mode {head}", "n_tris": int(tris.shape[0]), "n_rays": int(rays.shape[0])},
         "tests_per_ray": r["tests_per_ray"],
         "roofline": {"bound": "hbm", "achieved": r["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["alg_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(head),
-                     "kernel": "trace_kernel", "kernel_ms": r["kernel_ms_mean"],
+                     "kernel": "trace_kernel", "kernel_ms": r["kernel_ms_mean"], "launch_shape": r["tune"],
                      "alg_bytes_per_launch": r["alg_bytes_per_launch"]},
         "modes": results,
-        "tune": ctx.get_tune(),
+        "tune": r["tune"],
     }
     if args.copy_probe_mib:
         src = torch.ones(args.copy_probe_mib * 2 ** 18, dtype=torch.float32, device="cuda")
@@ -331,7 +374,7 @@ def main():
         line["copy_probe_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(tris, rays, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(tris, rays, args.cpu_seconds, MODES[head]["width"])
     print(json.dumps(line), flush=True)
     ctx.close()
 
