@@ -130,6 +130,36 @@ def object_masks(tris: np.ndarray, bvh: BVH, R: int, delta: float, nthreads: int
     return out[:2 * bvh.n_inner]
 
 
+def fill_table(R: int) -> np.ndarray:
+    """Filling-pattern table of Alg. 2: [R^6, W], key ((((x0*R+y0)*R+z0)*R+x1)*R+y1)*R+z1."""
+    out = np.zeros((R ** 6, words_for(R)), np.uint64)
+    _check(lib().orc_fill_table(C.c_uint32(R), _p(out)), "fill_table")
+    return out
+
+
+def fill_one(parent_box, child_mask, child_box, R: int, delta: float, table=None) -> np.ndarray:
+    """Alg. 2 for one child mask: the parent voxels its set voxels fill."""
+    table = fill_table(R) if table is None else table
+    pb = np.ascontiguousarray(parent_box, np.float32)
+    cb = np.ascontiguousarray(child_box, np.float32)
+    cm = np.ascontiguousarray(child_mask, np.uint64)
+    out = np.zeros(words_for(R), np.uint64)
+    _check(lib().orc_fill_one(_p(pb[:3].copy()), _p(pb[3:].copy()), _p(cm), _p(cb[:3].copy()), _p(cb[3:].copy()),
+                              C.c_uint32(R), C.c_float(delta), _p(table), _p(out)), "fill_one")
+    return out
+
+
+def approx_masks(tris: np.ndarray, bvh: BVH, R: int, delta: float, L: int, table=None) -> np.ndarray:
+    """Child-slot masks with the approximation of Sect. 3.2.1 / Alg. 2 at level L."""
+    tris = np.ascontiguousarray(tris, np.float32)
+    table = fill_table(R) if table is None else np.ascontiguousarray(table, np.uint64)
+    out = np.zeros((max(2 * bvh.n_inner, 1), words_for(R)), np.uint64)
+    _check(lib().orc_approx_masks(_p(tris), _p(bvh.perm), C.c_uint32(bvh.n_inner), _p(bvh.cbox), _p(bvh.cref),
+                                  _p(bvh.range), C.c_uint32(R), C.c_float(delta), C.c_uint32(L), _p(table),
+                                  _p(out)), "approx_masks")
+    return out[:2 * bvh.n_inner]
+
+
 @dataclass
 class Hits:
     prim: np.ndarray        # uint32, NO_HIT on a miss

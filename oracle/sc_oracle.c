@@ -403,6 +403,148 @@ int orc_object_masks(const float* tris, const uint32_t* perm, uint32_t n_inner, 
 }
 
 /* ------------------------------------------------------------------------
+ * 3b. Approximate object masks (Sect. 3.2.1, Alg. 2). The mask of child
+ *     slot s (node N, box P) takes the occupancy from N's subtree down to L
+ *     levels: the triangles of every leaf within L levels are voxelized
+ *     exactly into P's grid (as in 3.), and every inner node exactly L
+ *     levels down contributes its own approximate mask through Alg. 2: each
+ *     set voxel of that child box C fills the box-shaped block of P's
+ *     voxels its extent projects to, read from the filling-pattern table.
+ *     Leaf slots are always exact; L >= the subtree height gives the exact
+ *     mask.
+ *     Projection (float64): for child grid border i = 0..R,
+ *       b_i = cLo + (i * cExt) / R,
+ *       lo index = floor((R * ((b_i - 2 delta) - pLo)) / pExt),
+ *       hi index = floor((R * ((b_i + 2 delta) - pLo)) / pExt),
+ *     clamped to [0, R-1]; child voxel x fills parent indices
+ *     [lo index of border x, hi index of border x+1]. A parent axis of zero
+ *     extent is filled whole (as the exact mask sets every voxel of it).
+ *     The 2 delta margin keeps the result a superset of the exact mask under
+ *     rounding.
+ *     Filling-pattern table key ((((x0*R+y0)*R+z0)*R+x1)*R+y1)*R+z1: the
+ *     voxels with x0<=x<=x1, y0<=y<=y1, z0<=z<=z1.
+ * ---------------------------------------------------------------------- */
+int orc_fill_table(uint32_t R, uint64_t* out) {
+    if (R < 1 || R > 6) return ORC_ERR_ARG;
+    uint32_t W = words_for(R);
+    size_t keys = (size_t)R * R * R * R * R * R;
+    for (size_t k = 0; k < keys; ++k) {
+        size_t q = k;
+        uint32_t z1 = q % R; q /= R;
+        uint32_t y1 = q % R; q /= R;
+        uint32_t x1 = q % R; q /= R;
+        uint32_t z0 = q % R; q /= R;
+        uint32_t y0 = q % R; q /= R;
+        uint32_t x0 = (uint32_t)q;
+        uint64_t* m = &out[k * W];
+        for (uint32_t w = 0; w < W; ++w) m[w] = 0;
+        for (uint32_t z = z0; z <= z1; ++z)
+            for (uint32_t y = y0; y <= y1; ++y)
+                for (uint32_t x = x0; x <= x1; ++x) {
+                    uint32_t bit = x + R * y + R * R * z;
+                    m[bit >> 6] |= 1ull << (bit & 63);
+                }
+    }
+    return ORC_OK;
+}
+
+static int clamp_index(double u, uint32_t R) {
+    double f = floor(u);
+    if (!(f > 0.0)) return 0;
+    if (f > (double)(R - 1)) return (int)(R - 1);
+    return (int)f;
+}
+
+/* Alg. 2: OR into m (box P = plo..phi) the filling patterns of the set
+ * voxels of child mask cm (box C = clo..chi). */
+static void fill_from_child(uint64_t* m, const float* plo, const float* phi, const uint64_t* cm, const float* clo,
+                           const float* chi, uint32_t R, float delta, const uint64_t* table) {
+    uint32_t W = words_for(R);
+    int lo_idx[3][7], hi_idx[3][7];
+    for (int j = 0; j < 3; ++j) {
+        double pl = (double)plo[j], pe = (double)phi[j] - (double)plo[j];
+        double cl = (double)clo[j], ce = (double)chi[j] - (double)clo[j];
+        for (uint32_t i = 0; i <= R; ++i) {
+            if (!(pe > 0.0)) {
+                lo_idx[j][i] = 0;
+                hi_idx[j][i] = (int)R - 1;
+                continue;
+            }
+            double b = cl + ((double)i * ce) / (double)R;
+            lo_idx[j][i] = clamp_index(((double)R * ((b - 2.0 * (double)delta) - pl)) / pe, R);
+            hi_idx[j][i] = clamp_index(((double)R * ((b + 2.0 * (double)delta) - pl)) / pe, R);
+        }
+    }
+    for (uint32_t z = 0; z < R; ++z)
+        for (uint32_t y = 0; y < R; ++y)
+            for (uint32_t x = 0; x < R; ++x) {
+                uint32_t bit = x + R * y + R * R * z;
+                if (!((cm[bit >> 6] >> (bit & 63)) & 1u)) continue;
+                size_t key = (((((size_t)lo_idx[0][x] * R + lo_idx[1][y]) * R + lo_idx[2][z]) * R +
+                               hi_idx[0][x + 1]) * R + hi_idx[1][y + 1]) * R + hi_idx[2][z + 1];
+                const uint64_t* pat = &table[key * W];
+                for (uint32_t w = 0; w < W; ++w) m[w] |= pat[w];
+            }
+}
+
+/* Alg. 2 for one child mask alone (for tests): out = fill of cm into P. */
+int orc_fill_one(const float* plo, const float* phi, const uint64_t* cm, const float* clo, const float* chi,
+                 uint32_t R, float delta, const uint64_t* table, uint64_t* out) {
+    if (R < 1 || R > 6) return ORC_ERR_ARG;
+    for (uint32_t w = 0; w < words_for(R); ++w) out[w] = 0;
+    fill_from_child(out, plo, phi, cm, clo, chi, R, delta, table);
+    return ORC_OK;
+}
+
+/* Masks of every child slot with approximation level L (>= 1), computed
+ * from the deepest nodes up (nodes are in DFS pre-order, so every
+ * descendant has a larger index than its ancestors). */
+int orc_approx_masks(const float* tris, const uint32_t* perm, uint32_t n_inner, const float* cbox,
+                     const uint32_t* cref, const uint32_t* range, uint32_t R, float delta, uint32_t L,
+                     const uint64_t* table, uint64_t* out) {
+    if (R < 1 || R > 6 || L < 1 || L > 64) return ORC_ERR_ARG;
+    uint32_t W = words_for(R);
+    uint32_t st_slot[256], st_lev[256];
+    for (int64_t node = (int64_t)n_inner - 1; node >= 0; --node) {
+        for (uint32_t c = 0; c < 2; ++c) {
+            uint32_t s = 2u * (uint32_t)node + c;
+            uint64_t* m = &out[(size_t)s * W];
+            for (uint32_t w = 0; w < W; ++w) m[w] = 0;
+            const float* P = &cbox[6 * (size_t)s];
+            uint32_t r = cref[s];
+            if (r & LEAF_BIT) {
+                uint32_t first, count;
+                slot_range(cref, range, s, &first, &count);
+                for (uint32_t j = first; j < first + count; ++j)
+                    voxelize_tri(&tris[9 * (size_t)perm[j]], P, P + 3, R, delta, m);
+                continue;
+            }
+            int sp = 0;
+            st_slot[sp] = 2u * r + 1u; st_lev[sp] = 1; ++sp;
+            st_slot[sp] = 2u * r; st_lev[sp] = 1; ++sp;
+            while (sp > 0) {
+                --sp;
+                uint32_t d = st_slot[sp], k = st_lev[sp];
+                uint32_t rd = cref[d];
+                if (rd & LEAF_BIT) {
+                    uint32_t first, count;
+                    slot_range(cref, range, d, &first, &count);
+                    for (uint32_t j = first; j < first + count; ++j)
+                        voxelize_tri(&tris[9 * (size_t)perm[j]], P, P + 3, R, delta, m);
+                } else if (k == L) {
+                    const float* Cb = &cbox[6 * (size_t)d];
+                    fill_from_child(m, P, P + 3, &out[(size_t)d * W], Cb, Cb + 3, R, delta, table);
+                } else {
+                    st_slot[sp] = 2u * rd + 1u; st_lev[sp] = k + 1; ++sp;
+                    st_slot[sp] = 2u * rd; st_lev[sp] = k + 1; ++sp;
+                }
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
  * 4. Traversal with culling (Alg. 4 with Alg. 1 inside).
  *    slab: per axis x,y,z a = (lo-o)*inv, b = (hi-o)*inv, swap if a > b,
  *          b *= 1 + 3*2^-23 (robust far value), t0 = max2(a, t0),
