@@ -14,7 +14,7 @@ is the one the autotuner picked for it on this workload (stored in MODES;
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes raw6w4,nonew4,none,raw6,raw4w4]
                     [--no-cpu-baseline] [--cpu-seconds S] [--autotune | --tune b,s,c,p,w,o]
-                    [--workload hair_1m|batch64|placement]
+                    [--workload hair_1m|batch64|placement|approx]
 """
 from __future__ import annotations
 
@@ -279,6 +279,58 @@ def run_placement(args, ctx):
     print(json.dumps(line), flush=True)
 
 
+def run_approx(args, ctx):
+    """Approximate object masks (Sect. 3.2.1, Alg. 2) on the 1M-triangle hair workload: mask build time and
+    culling (tests/ray, rays/s) for L = 1..5 and exact masks, R = 4 and 6, on the 4-wide BVH."""
+    import torch
+    from paper_2305_08343_amd import binding, scenes
+    tris = scenes.scene_hair_1m(1)
+    rays = scenes.rays_hair_1m(tris, 1)
+    rays_dev = torch.from_numpy(rays).cuda()
+    n = rays.shape[0]
+    hits = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    table = {}
+    for R in (4, 6):
+        for L in (1, 2, 3, 4, 5, 0):
+            ctx.set_tune(*MODES[f"raw{R}w4"]["tune"])
+            sc = binding.Scene(ctx, tris, R=R, mode="raw", width=4, approx_levels=L)
+            ms_masks = sc.info["ms_masks"]
+            sc.trace(rays_dev, hits=hits, extra=False)
+            torch.cuda.synchronize()
+            h = hits.cpu().numpy()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.steps)]
+            for a, b in evs:
+                a.record()
+                sc.trace(rays_dev, hits=hits, extra=False)
+                b.record()
+            torch.cuda.synchronize()
+            ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+            sc.close()
+            tests = (h[:, 2].astype(np.float64).sum() + h[:, 3].astype(np.float64).sum()) / n
+            key = f"R{R}_L{L if L else 'exact'}"
+            table[key] = {"mask_build_ms": ms_masks, "tests_per_ray": tests, "trace_ms": ms,
+                          "rays_per_s": n / (ms * 1e-3)}
+            log(f"approx {key}: masks {ms_masks:.2f} ms, {tests:.2f} tests/ray, {n / ms / 1e3:.1f} Mrays/s")
+    for R in (4, 6):
+        base = table[f"R{R}_L1"]
+        for k, v in table.items():
+            if k.startswith(f"R{R}_"):
+                v["tests_ratio_vs_L1"] = v["tests_per_ray"] / base["tests_per_ray"]
+                v["build_time_ratio_vs_L1"] = v["mask_build_ms"] / base["mask_build_ms"]
+    head = table["R6_L3"]
+    line = {
+        "metric": METRIC, "value": head["rays_per_s"], "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": head["trace_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "approx: hair_1m (1,000,002 tris, 4,147,200 rays), 4-wide BVH, raw masks built by "
+                               "Alg. 2 at L = 1..5 or exactly; value = R=6, L=3", "n_tris": int(tris.shape[0]),
+                   "n_rays": n},
+        "approx": table,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,7 +342,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tune", default="", help="block,stack,chunk,parts[,waves[,sort]] of the traversal launch")
-    ap.add_argument("--workload", default="hair_1m", choices=["hair_1m", "batch64", "placement"])
+    ap.add_argument("--workload", default="hair_1m", choices=["hair_1m", "batch64", "placement", "approx"])
     ap.add_argument("--place-scenes", type=int, default=200)
     ap.add_argument("--place-heldout", type=int, default=2)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -311,6 +363,11 @@ def main():
         if args.modes == ap.get_default("modes"):
             args.modes = "raw6,none"
         run_batch64(args, ctx)
+        ctx.close()
+        return
+    if args.workload == "approx":
+        ctx = binding.Context(0)
+        run_approx(args, ctx)
         ctx.close()
         return
     if args.workload == "placement":

@@ -91,6 +91,14 @@ typedef struct {
     uint32_t width;         /* 2: binary BVH; 4: 4-wide BVH collapsed from it, each
                                node with four child boxes and four child masks
                                (Sect. 3.2.4); modes NONE, RAW, LUT (default 2)    */
+    uint32_t approx_levels; /* 0: exact masks from every triangle below (L = inf);
+                               L in 1..64: approximate masks of Sect. 3.2.1 /
+                               Alg. 2 -- triangles of leaves at most L levels
+                               below, plus the masks of inner nodes exactly L
+                               levels below projected onto the box (each set
+                               voxel fills the parent voxels its extent plus
+                               2 delta covers); always a superset of the exact
+                               mask                                              */
 } sc_build_params;
 
 typedef struct {

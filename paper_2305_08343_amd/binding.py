@@ -37,7 +37,8 @@ class sc_build_params(C.Structure):
     _fields_ = [("R", C.c_uint32), ("leaf_max", C.c_uint32), ("sah_bins", C.c_uint32),
                 ("depth_cap", C.c_uint32), ("mode", C.c_uint32), ("codebook_size", C.c_uint32),
                 ("delta", C.c_float), ("origin_bound", C.c_float),
-                ("mask_placement", C.c_void_p), ("placement_len", C.c_uint32), ("width", C.c_uint32)]
+                ("mask_placement", C.c_void_p), ("placement_len", C.c_uint32), ("width", C.c_uint32),
+                ("approx_levels", C.c_uint32)]
 
 
 class sc_scene_info(C.Structure):
@@ -276,7 +277,8 @@ class Scene:
 
     def __init__(self, ctx: Context, tris, *, R: int = 6, mode: str = "raw", K: int = 4096,
                  leaf_max: int = 4, bins: int = 32, depth_cap: int = 64, delta: float = 0.0,
-                 origin_bound: float = 0.0, placement=None, width: int = 2, stream=None):
+                 origin_bound: float = 0.0, placement=None, width: int = 2, approx_levels: int = 0,
+                 stream=None):
         import torch
         lib = load()
         self.ctx = ctx
@@ -290,6 +292,7 @@ class Scene:
         p.mode, p.codebook_size = MODES[mode], K
         p.delta, p.origin_bound = delta, origin_bound
         p.width = width
+        p.approx_levels = approx_levels
         self._placement = None
         if placement is not None:
             self._placement = np.ascontiguousarray(placement, np.uint8)

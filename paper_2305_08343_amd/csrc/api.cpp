@@ -142,6 +142,7 @@ bool check_params(const sc_build_params& p, std::string& why) {
     }
     if (p.mode == SC_MASK_SPARSE && !p.mask_placement) { why = "SPARSE needs mask_placement"; return false; }
     if (p.width != 2 && p.width != 4) { why = "width must be 2 or 4"; return false; }
+    if (p.approx_levels > 64) { why = "approx_levels must be 0..64"; return false; }
     if (p.width == 4 && p.mode == SC_MASK_SPARSE) { why = "SPARSE needs width 2"; return false; }
     if (!std::isfinite(p.delta) || !std::isfinite(p.origin_bound)) { why = "non-finite delta/origin_bound"; return false; }
     return true;
@@ -362,7 +363,46 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
             e = hipMemcpyAsync(d_range, B.range.data(), B.range.size() * 4, hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
             e = launch_object_masks(R, d_tris, d_perm, n, sc->nodes, stride, d_range, B.root, delta,
-                                    sc->masks, s);
+                                    P.approx_levels, sc->masks, s);
+        if (e == hipSuccess && P.approx_levels > 0) {
+            // fill part of the approximation, one launch per depth, deepest first
+            std::vector<uint32_t> depth(B.n_inner, 0);
+            uint32_t max_depth = 0;
+            for (uint32_t i = 0; i < B.n_inner; ++i)
+                for (int c = 0; c < 2; ++c) {
+                    const uint32_t r = B.cref[2 * (size_t)i + c];
+                    if (!(r & kLeafBit)) {
+                        depth[r] = depth[i] + 1;
+                        max_depth = std::max(max_depth, depth[r]);
+                    }
+                }
+            std::vector<uint32_t> order, start(max_depth + 2, 0);
+            for (uint32_t i = 0; i < B.n_inner; ++i) ++start[depth[i] + 1];
+            for (uint32_t k = 1; k < start.size(); ++k) start[k] += start[k - 1];
+            order.resize(2 * (size_t)B.n_inner);
+            std::vector<uint32_t> fillp(start.begin(), start.end() - 1);
+            for (uint32_t i = 0; i < B.n_inner; ++i) {
+                const uint32_t at = fillp[depth[i]]++;
+                order[2 * (size_t)at] = 2 * i;
+                order[2 * (size_t)at + 1] = 2 * i + 1;
+            }
+            auto* d_order = static_cast<uint32_t*>(dev_alloc(ctx, order.size() * 4, s));
+            auto* d_cbox = static_cast<float*>(dev_alloc(ctx, B.cbox.size() * 4, s));
+            auto* d_cref = static_cast<uint32_t*>(dev_alloc(ctx, B.cref.size() * 4, s));
+            if (!d_order || !d_cbox || !d_cref) e = hipErrorOutOfMemory;
+            if (e == hipSuccess) e = hipMemcpyAsync(d_order, order.data(), order.size() * 4, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(d_cbox, B.cbox.data(), B.cbox.size() * 4, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(d_cref, B.cref.data(), B.cref.size() * 4, hipMemcpyHostToDevice, s);
+            for (int64_t k = (int64_t)max_depth; k >= 0 && e == hipSuccess; --k) {
+                // slots of the nodes at node depth k
+                const uint32_t a = 2 * start[k], b = 2 * start[k + 1];
+                e = launch_approx_fill(R, d_order + a, b - a, d_cbox, d_cref, P.approx_levels, delta, sc->masks, s);
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            dev_free(ctx, d_order, order.size() * 4, s);
+            dev_free(ctx, d_cbox, B.cbox.size() * 4, s);
+            dev_free(ctx, d_cref, B.cref.size() * 4, s);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         dev_free(ctx, d_perm, (size_t)n * 4, s);
         dev_free(ctx, d_range, B.range.size() * 4, s);

@@ -131,10 +131,14 @@ hipError_t launch_ray_order(const float* rays, uint32_t n, const float lo[3], co
 hipError_t launch_raymask_patterns(uint32_t R, uint64_t* patterns, hipStream_t s);
 hipError_t launch_raymask_lut(uint32_t R, const uint64_t* patterns, uint64_t* out, hipStream_t s);
 inline size_t pattern_count(uint32_t R) { return (size_t)R * (2 * R - 1) * (2 * R - 1); }
+// levels = 0: exact masks; L > 0: the triangle part of the approximation (slots at most L above the leaf)
 hipError_t launch_object_masks(uint32_t R, const float* tris_orig, const uint32_t* perm, uint32_t n,
                                const unsigned char* nodes, uint32_t node_stride,
-                               const uint32_t* range, uint32_t root, float delta, uint64_t* masks,
-                               hipStream_t s);
+                               const uint32_t* range, uint32_t root, float delta, uint32_t levels,
+                               uint64_t* masks, hipStream_t s);
+// approximation, fill part (Alg. 2) for the given slots of one depth; deeper depths first
+hipError_t launch_approx_fill(uint32_t R, const uint32_t* slots, uint32_t count, const float* cbox,
+                              const uint32_t* cref, uint32_t levels, float delta, uint64_t* masks, hipStream_t s);
 hipError_t launch_req_luts(uint32_t R, const uint64_t* cb, uint32_t K, uint64_t* req, hipStream_t s);
 hipError_t launch_compress(uint32_t R, const uint64_t* masks, uint32_t n, const uint64_t* req,
                            uint32_t K, uint16_t* idx, hipStream_t s);

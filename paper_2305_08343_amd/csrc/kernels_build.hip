@@ -184,18 +184,21 @@ __device__ __forceinline__ uint64_t shfl_down64(uint64_t x, int off) {
 }
 
 // ---------------------------------------------------------------------------
-// Exact object masks (L = infinity, Sect. 3.2.1): one thread per triangle
-// in leaf order. The thread walks from the root to its leaf; at every level
-// it voxelizes its triangle into the child box that contains it. Threads of
-// a wave hold consecutive triangles, so the lanes sharing a child slot are
+// Object masks from triangles (Sect. 3.2.1): one thread per triangle in leaf
+// order. The thread walks from the root to its leaf; at every level it
+// voxelizes its triangle into the child box that contains it. Threads of a
+// wave hold consecutive triangles, so the lanes sharing a child slot are
 // contiguous: a segmented OR across the wave leaves one value per slot, and
-// the first lane of each segment ORs it into global memory.
+// the first lane of each segment ORs it into global memory. With levels = 0
+// every slot on the path gets the triangle (the exact mask, L = infinity);
+// with levels = L only the slots at most L levels above the triangle's leaf
+// do (the triangle part of the approximation; the rest comes from fills).
 // ---------------------------------------------------------------------------
 template <int R>
 __global__ __launch_bounds__(256) void object_mask_kernel(
     const float* __restrict__ tris, const uint32_t* __restrict__ perm, uint32_t n,
     const unsigned char* __restrict__ nodes, uint32_t stride, const uint32_t* __restrict__ range,
-    uint32_t root, float delta, unsigned long long* __restrict__ masks) {
+    uint32_t root, float delta, uint32_t levels, unsigned long long* __restrict__ masks) {
     constexpr int W = (R * R * R + 63) / 64;
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
@@ -206,8 +209,25 @@ __global__ __launch_bounds__(256) void object_mask_kernel(
 #pragma unroll
         for (int k = 0; k < 9; ++k) v[k] = src[k];
     }
+    // depth of the triangle's leaf slot (root children at depth 1)
+    uint32_t leaf_depth = 0;
+    if (active && levels > 0) {
+        uint32_t nd = root;
+        while (true) {
+            const uint32_t* nu = reinterpret_cast<const uint32_t*>(nodes + (size_t)nd * stride);
+            const uint32_t ref0 = nu[12];
+            const uint32_t lcount = (ref0 & kLeafBit) ? ((ref0 >> 29) & 3u) + 1u : range[2 * (size_t)ref0 + 1];
+            const int c = (j < range[2 * (size_t)nd] + lcount) ? 0 : 1;
+            ++leaf_depth;
+            const uint32_t ref = nu[12 + c];
+            if (ref & kLeafBit) break;
+            nd = ref;
+        }
+    }
+    uint32_t depth = 0;
     uint32_t node = root;
     while (__ballot(active) != 0) {
+        ++depth;
         uint32_t slot = 0xFFFFFFFFu;
         uint64_t bits[W];
 #pragma unroll
@@ -221,7 +241,7 @@ __global__ __launch_bounds__(256) void object_mask_kernel(
             const uint32_t lcount = (ref0 & kLeafBit) ? ((ref0 >> 29) & 3u) + 1u : range[2 * (size_t)ref0 + 1];
             const int c = (j < range[2 * (size_t)node] + lcount) ? 0 : 1;
             slot = 2u * node + (uint32_t)c;
-            voxelize<R>(v, nf + 6 * c, nf + 6 * c + 3, delta, bits);
+            if (levels == 0 || depth + levels >= leaf_depth) voxelize<R>(v, nf + 6 * c, nf + 6 * c + 3, delta, bits);
             const uint32_t ref = nu[12 + c];
             leaf = (ref & kLeafBit) != 0;
             next = ref;
@@ -244,6 +264,94 @@ __global__ __launch_bounds__(256) void object_mask_kernel(
         active = active && !leaf;
         node = next;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Approximate masks, fill part (Alg. 2): for each slot s of one depth whose
+// node is inner, every inner node exactly L levels below contributes its own
+// (already final) mask: a set child voxel fills the parent voxels its extent
+// plus a 2 delta margin projects to (float64, floor, clamped to [0, R-1]; a
+// parent axis of zero extent is filled whole). The box of voxels is built
+// from bit runs instead of read from the filling-pattern table; both give
+// the same bits. One thread per slot; slots of deeper levels are done first.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int clamp_floor(double u, int R) {
+    const double f = floor(u);
+    if (!(f > 0.0)) return 0;
+    if (f > (double)(R - 1)) return R - 1;
+    return (int)f;
+}
+
+template <int R>
+__device__ void or_box(uint64_t* m, int x0, int y0, int z0, int x1, int y1, int z1) {
+    const uint64_t row = ((1ull << (x1 + 1)) - 1ull) & ~((1ull << x0) - 1ull);
+    for (int z = z0; z <= z1; ++z)
+        for (int y = y0; y <= y1; ++y) {
+            const int bit = R * y + R * R * z;
+            const int w = bit >> 6, sh = bit & 63;
+            m[w] |= row << sh;
+            if (sh + R > 64) m[w + 1] |= row >> (64 - sh);
+        }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void approx_fill_kernel(const uint32_t* __restrict__ slots, uint32_t count,
+                                                          const float* __restrict__ cbox,
+                                                          const uint32_t* __restrict__ cref, uint32_t levels,
+                                                          float delta, uint64_t* __restrict__ masks) {
+    constexpr int W = (R * R * R + 63) / 64;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const uint32_t s = slots[t];
+    const uint32_t r = cref[s];
+    if (r & kLeafBit) return;
+    const float* P = cbox + 6 * (size_t)s;
+    uint64_t m[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) m[w] = 0;
+    uint32_t st[65];
+    uint32_t lev[65];
+    int sp = 0;
+    st[sp] = 2u * r + 1u; lev[sp] = 1; ++sp;
+    st[sp] = 2u * r; lev[sp] = 1; ++sp;
+    while (sp > 0) {
+        --sp;
+        const uint32_t d = st[sp], k = lev[sp];
+        const uint32_t rd = cref[d];
+        if (rd & kLeafBit) continue;  // its triangles came in the triangle part
+        if (k < levels) {
+            st[sp] = 2u * rd + 1u; lev[sp] = k + 1; ++sp;
+            st[sp] = 2u * rd; lev[sp] = k + 1; ++sp;
+            continue;
+        }
+        const float* Cb = cbox + 6 * (size_t)d;
+        int lo_idx[3][R + 1], hi_idx[3][R + 1];
+        for (int j = 0; j < 3; ++j) {
+            const double pl = (double)P[j], pe = (double)P[3 + j] - (double)P[j];
+            const double cl = (double)Cb[j], ce = (double)Cb[3 + j] - (double)Cb[j];
+            for (int i = 0; i <= R; ++i) {
+                if (!(pe > 0.0)) {
+                    lo_idx[j][i] = 0;
+                    hi_idx[j][i] = R - 1;
+                    continue;
+                }
+                const double b = cl + ((double)i * ce) / (double)R;
+                lo_idx[j][i] = clamp_floor(((double)R * ((b - 2.0 * (double)delta) - pl)) / pe, R);
+                hi_idx[j][i] = clamp_floor(((double)R * ((b + 2.0 * (double)delta) - pl)) / pe, R);
+            }
+        }
+        const uint64_t* cm = masks + (size_t)d * W;
+        for (int w = 0; w < W; ++w) {
+            for (uint64_t bits = cm[w]; bits; bits &= bits - 1) {
+                const int bit = 64 * w + __builtin_ctzll(bits);
+                const int x = bit % R, y = (bit / R) % R, z = bit / (R * R);
+                or_box<R>(m, lo_idx[0][x], lo_idx[1][y], lo_idx[2][z], hi_idx[0][x + 1], hi_idx[1][y + 1],
+                          hi_idx[2][z + 1]);
+            }
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) masks[(size_t)s * W + w] |= m[w];
 }
 
 // ---------------------------------------------------------------------------
@@ -394,16 +502,30 @@ hipError_t launch_raymask_lut(uint32_t R, const uint64_t* patterns, uint64_t* ou
 
 hipError_t launch_object_masks(uint32_t R, const float* tris_orig, const uint32_t* perm, uint32_t n,
                                const unsigned char* nodes, uint32_t node_stride,
-                               const uint32_t* range, uint32_t root, float delta, uint64_t* masks,
-                               hipStream_t s) {
+                               const uint32_t* range, uint32_t root, float delta, uint32_t levels,
+                               uint64_t* masks, hipStream_t s) {
     if (n == 0) return hipSuccess;
     auto* m = reinterpret_cast<unsigned long long*>(masks);
     if (R == 4)
         hipLaunchKernelGGL(object_mask_kernel<4>, dim3(blocks_for(n, 256)), dim3(256), 0, s, tris_orig,
-                           perm, n, nodes, node_stride, range, root, delta, m);
+                           perm, n, nodes, node_stride, range, root, delta, levels, m);
     else if (R == 6)
         hipLaunchKernelGGL(object_mask_kernel<6>, dim3(blocks_for(n, 256)), dim3(256), 0, s, tris_orig,
-                           perm, n, nodes, node_stride, range, root, delta, m);
+                           perm, n, nodes, node_stride, range, root, delta, levels, m);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_approx_fill(uint32_t R, const uint32_t* slots, uint32_t count, const float* cbox,
+                              const uint32_t* cref, uint32_t levels, float delta, uint64_t* masks, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    if (levels < 1 || levels > 64) return hipErrorInvalidValue;
+    if (R == 4)
+        hipLaunchKernelGGL(approx_fill_kernel<4>, dim3(blocks_for(count, 256)), dim3(256), 0, s, slots, count, cbox,
+                           cref, levels, delta, masks);
+    else if (R == 6)
+        hipLaunchKernelGGL(approx_fill_kernel<6>, dim3(blocks_for(count, 256)), dim3(256), 0, s, slots, count, cbox,
+                           cref, levels, delta, masks);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

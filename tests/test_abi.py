@@ -50,7 +50,7 @@ def test_params_default_and_status_strings():
 def test_struct_sizes_match_header_layout():
     # 12 uint32, 2 float, uint64, 4 double
     assert C.sizeof(B.sc_scene_info) == 48 + 8 + 8 + 32
-    assert C.sizeof(B.sc_build_params) == 48
+    assert C.sizeof(B.sc_build_params) == 56
     assert C.sizeof(B.sc_scene_host) == 7 * 8
     assert C.sizeof(B.sc_tune) == 6 * 4
 
@@ -81,7 +81,7 @@ def test_bad_build_params_rejected_before_hip():
     fake_ctx = C.c_void_p(1)  # never dereferenced: parameter checks come first
     out = C.c_void_p()
     for field, value in [("R", 5), ("leaf_max", 0), ("leaf_max", 5), ("sah_bins", 1), ("depth_cap", 65),
-                         ("mode", 9), ("width", 3), ("width", 0)]:
+                         ("mode", 9), ("width", 3), ("width", 0), ("approx_levels", 65)]:
         q = B.sc_build_params.from_buffer_copy(p)
         setattr(q, field, value)
         assert lib.sc_scene_build(fake_ctx, None, 0, C.byref(q), None, C.byref(out)) == 1, field
