@@ -267,6 +267,16 @@ def trace4(tris, bvh: BVH, bvh4: BVH4, rays, *, mode="none", R=6, masks=None, co
                 None if fp is None else fp[:2 * bvh.n_inner])
 
 
+def bit_table(R: int, cb, lut=None) -> np.ndarray:
+    """2-D bit table: uint32 [R^6, K/32], bit k of row key = (LUT[key] AND cb[k]) != 0."""
+    cb = np.ascontiguousarray(cb, np.uint64)
+    K = cb.shape[0]
+    lut = raymask_lut(R) if lut is None else np.ascontiguousarray(lut, np.uint64)
+    out = np.zeros((R ** 6, K // 32), np.uint32)
+    _check(lib().orc_bit_table(_p(lut), C.c_uint32(R), _p(cb), C.c_uint32(K), _p(out)), "bit_table")
+    return out
+
+
 def brute_closest(tris, rays, nthreads=0):
     tris = np.ascontiguousarray(tris, np.float32)
     rays = np.ascontiguousarray(rays, np.float32)

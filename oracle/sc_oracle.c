@@ -960,6 +960,28 @@ int orc_trace4(const float* tris, const uint32_t* perm, const float* box4, const
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------
+ * 2-D bit table (Sect. 3.2.2, note on the two LUTs): bit (key, k) is 1 iff
+ * the ray mask LUT[key] and codebook entry k share a set bit, so a
+ * compressed mask test becomes one bit fetch. Row key holds K bits in K/32
+ * 32-bit words, entry k at bit k % 32 of word k / 32.
+ * ---------------------------------------------------------------------- */
+int orc_bit_table(const uint64_t* lut, uint32_t R, const uint64_t* cb, uint32_t K, uint32_t* out) {
+    if (R < 1 || R > 6 || K == 0 || K % 32) return ORC_ERR_ARG;
+    uint32_t W = words_for(R);
+    size_t keys = (size_t)R * R * R * R * R * R;
+    for (size_t key = 0; key < keys; ++key) {
+        uint32_t* row = &out[key * (K / 32)];
+        for (uint32_t w = 0; w < K / 32; ++w) row[w] = 0;
+        for (uint32_t k = 0; k < K; ++k) {
+            uint64_t any = 0;
+            for (uint32_t w = 0; w < W; ++w) any |= lut[key * W + w] & cb[(size_t)k * W + w];
+            if (any) row[k / 32] |= 1u << (k % 32);
+        }
+    }
+    return ORC_OK;
+}
+
 /* Closest hit by scanning every triangle with the same triangle test and
  * tie rule; no hierarchy. out[i] = (id, t bits). */
 int orc_brute_closest(const float* tris, uint32_t n, const float* rays, uint32_t nrays,
