@@ -49,6 +49,10 @@ MODES = {
     "nonew4": dict(mode="none", R=6, cull=False, width=4, mask_bytes=0, tune=(256, 12, 1, 8, 0, 0)),
     "lut6w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, tune=(256, 12, 1, 8, 6, 0)),
     "lut4k256w4": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 0, 0)),
+    "lut6k256w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 6, 0)),
+    "lut6w4b": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, bit_table=True, tune=(256, 12, 1, 8, 0, 0)),
+    "lut6k256w4b": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=256, bit_table=True, tune=(256, 12, 1, 8, 6, 0)),
+    "lut4k256w4b": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, bit_table=True, tune=(256, 12, 1, 8, 0, 0)),
     "raw6": dict(mode="raw", R=6, cull=True, width=2, node_bytes=128, tune=(256, 12, 1, 8, 6, 1)),
     "none": dict(mode="none", R=6, cull=False, width=2, node_bytes=64, tune=(256, 8, 1, 8, 0, 0)),
     "raw4": dict(mode="raw", R=4, cull=True, width=2, node_bytes=128, tune=(256, 8, 1, 8, 0, 0)),
@@ -92,7 +96,8 @@ def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup, autotune=False):
     import torch
     from paper_2305_08343_amd import binding, tune
     t0 = time.perf_counter()
-    scene = binding.Scene(ctx, tris, R=spec["R"], mode=spec["mode"], K=spec.get("K", 4096), width=spec["width"])
+    scene = binding.Scene(ctx, tris, R=spec["R"], mode=spec["mode"], K=spec.get("K", 4096), width=spec["width"],
+                          bit_table=spec.get("bit_table", False))
     build_s = time.perf_counter() - t0
     n = rays_dev.shape[0]
     hits = torch.empty((n, 4), dtype=torch.int32, device=rays_dev.device)

@@ -99,6 +99,11 @@ typedef struct {
                                voxel fills the parent voxels its extent plus
                                2 delta covers); always a superset of the exact
                                mask                                              */
+    uint32_t bit_table;     /* LUT mode: 1 builds the 2-D bit table of Sect. 3.2.2
+                               (bit (key, k) = ray mask LUT[key] AND codebook
+                               entry k is nonzero; R^6 * K / 8 bytes) and single
+                               scene traces test a compressed mask with one bit
+                               of it; results are unchanged (default 0)           */
 } sc_build_params;
 
 typedef struct {
@@ -109,6 +114,8 @@ typedef struct {
     uint32_t width;                          /* 2 or 4                          */
     uint32_t n_nodes;                        /* inner nodes traversed: n_inner,
                                                 or 4-wide nodes when width 4    */
+    uint32_t approx_levels;                  /* as built (0 = exact masks)      */
+    uint32_t bit_table;                      /* 1 if the scene has a bit table  */
     float delta, origin_bound;
     uint64_t device_bytes;                   /* scene-owned device memory       */
     double ms_bvh, ms_masks, ms_codebook, ms_compress;  /* build phases (host clock) */
@@ -213,6 +220,11 @@ sc_status sc_scene_export(const sc_scene* scene, sc_scene_host* out);
  * (the earliest on ties) by its two children; DFS pre-order. Any pointer may
  * be NULL. SC_ERR_INVALID_ARG for a binary scene. */
 sc_status sc_scene_export4(const sc_scene* scene, float* box4, uint32_t* ref4, uint32_t* src4);
+
+/* Copy a LUT scene's 2-D bit table to host `out` (uint32 [R^6][K/32]; bit k
+ * % 32 of word k / 32 of row key), synchronous. SC_ERR_INVALID_ARG if the
+ * scene was built without one. */
+sc_status sc_scene_export_bit_table(const sc_scene* scene, uint32_t* out);
 
 /*
  * Trace `n` rays (device float32 [n][8]: ox oy oz tmin dx dy dz tmax) with

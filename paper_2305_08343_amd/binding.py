@@ -38,7 +38,7 @@ class sc_build_params(C.Structure):
                 ("depth_cap", C.c_uint32), ("mode", C.c_uint32), ("codebook_size", C.c_uint32),
                 ("delta", C.c_float), ("origin_bound", C.c_float),
                 ("mask_placement", C.c_void_p), ("placement_len", C.c_uint32), ("width", C.c_uint32),
-                ("approx_levels", C.c_uint32)]
+                ("approx_levels", C.c_uint32), ("bit_table", C.c_uint32)]
 
 
 class sc_scene_info(C.Structure):
@@ -46,6 +46,7 @@ class sc_scene_info(C.Structure):
                 ("root_ref", C.c_uint32), ("R", C.c_uint32), ("mode", C.c_uint32),
                 ("codebook_size", C.c_uint32), ("words", C.c_uint32), ("node_bytes", C.c_uint32),
                 ("n_masked", C.c_uint32), ("width", C.c_uint32), ("n_nodes", C.c_uint32),
+                ("approx_levels", C.c_uint32), ("bit_table", C.c_uint32),
                 ("delta", C.c_float), ("origin_bound", C.c_float),
                 ("device_bytes", C.c_uint64), ("ms_bvh", C.c_double), ("ms_masks", C.c_double),
                 ("ms_codebook", C.c_double), ("ms_compress", C.c_double)]
@@ -85,6 +86,7 @@ _SIGS = {
     "sc_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
     "sc_scene_export4": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sc_scene_export_bit_table": (C.c_int, [C.c_void_p, C.c_void_p]),
     "sc_ray_order": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "sc_trace_batch": (C.c_int, [C.c_void_p, C.POINTER(sc_batch_item), C.c_uint32, C.c_uint32, C.c_void_p]),
     "sc_batch_create": (C.c_int, [C.c_void_p, C.POINTER(sc_batch_item), C.c_uint32, C.c_uint32,
@@ -278,7 +280,7 @@ class Scene:
     def __init__(self, ctx: Context, tris, *, R: int = 6, mode: str = "raw", K: int = 4096,
                  leaf_max: int = 4, bins: int = 32, depth_cap: int = 64, delta: float = 0.0,
                  origin_bound: float = 0.0, placement=None, width: int = 2, approx_levels: int = 0,
-                 stream=None):
+                 bit_table: bool = False, stream=None):
         import torch
         lib = load()
         self.ctx = ctx
@@ -293,6 +295,7 @@ class Scene:
         p.delta, p.origin_bound = delta, origin_bound
         p.width = width
         p.approx_levels = approx_levels
+        p.bit_table = int(bit_table)
         self._placement = None
         if placement is not None:
             self._placement = np.ascontiguousarray(placement, np.uint8)
@@ -343,6 +346,14 @@ class Scene:
         _check(load().sc_scene_export4(self.handle, *(out[k].ctypes.data_as(C.c_void_p)
                                                        for k in ("box4", "ref4", "src4"))), "sc_scene_export4")
         return {k: v[:n4] for k, v in out.items()}
+
+    def export_bit_table(self) -> np.ndarray:
+        """Host copy of the 2-D bit table: uint32 [R^6, K/32]."""
+        R, K = self.info["R"], self.info["codebook_size"]
+        out = np.zeros((R ** 6, K // 32), np.uint32)
+        _check(load().sc_scene_export_bit_table(self.handle, out.ctypes.data_as(C.c_void_p)),
+               "sc_scene_export_bit_table")
+        return out
 
     def features(self, stream=None):
         """Per-slot placement features, device float32 [2*n_inner, 12]."""

@@ -43,6 +43,7 @@ struct sc_scene {
     unsigned char* nodes4 = nullptr;      // 4-wide nodes (kNode4Bytes each)
     uint64_t* masks4 = nullptr;           // 4-wide RAW: child masks [4*n4][W]
     uint32_t* src4 = nullptr;             // 4-wide: binary slot of each child [4*n4]
+    uint32_t* bit_table = nullptr;        // LUT mode: 2-D bit table [R^6][K/32]
     std::vector<std::pair<void*, size_t>> owned;
 };
 
@@ -143,6 +144,7 @@ bool check_params(const sc_build_params& p, std::string& why) {
     if (p.mode == SC_MASK_SPARSE && !p.mask_placement) { why = "SPARSE needs mask_placement"; return false; }
     if (p.width != 2 && p.width != 4) { why = "width must be 2 or 4"; return false; }
     if (p.approx_levels > 64) { why = "approx_levels must be 0..64"; return false; }
+    if (p.bit_table > 1 || (p.bit_table && p.mode != SC_MASK_LUT)) { why = "bit_table needs LUT mode"; return false; }
     if (p.width == 4 && p.mode == SC_MASK_SPARSE) { why = "SPARSE needs width 2"; return false; }
     if (!std::isfinite(p.delta) || !std::isfinite(p.origin_bound)) { why = "non-finite delta/origin_bound"; return false; }
     return true;
@@ -295,6 +297,8 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
     I.origin_bound = ob;
     I.width = P.width;
     I.n_nodes = B.n_inner;
+    I.approx_levels = P.approx_levels;
+    I.bit_table = P.bit_table;
     const uint32_t S = 2 * B.n_inner;
     if (P.mode == SC_MASK_SPARSE && P.placement_len != S)
         return bail(SC_ERR_INVALID_ARG, "mask_placement length must be 2*n_inner = " + std::to_string(S));
@@ -446,6 +450,15 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                 if (e == hipSuccess) e = launch_req_luts(R, sc->codebook, K, d_req, s);
                 if (e == hipSuccess) e = launch_compress(R, sc->masks, S, d_req, K, sc->cidx, s);
                 if (e == hipSuccess) e = launch_pack_lut(sc->cidx, B.n_inner, sc->nodes, s);
+                if (e == hipSuccess && P.bit_table) {
+                    const size_t tb = (size_t)R * R * R * R * R * R * (K / 32) * 4;
+                    sc->bit_table = scene_alloc<uint32_t>(sc, tb, s);
+                    if (!sc->bit_table) {
+                        dev_free(ctx, d_req, req_bytes, s);
+                        return bail(SC_ERR_OOM, "bit table allocation failed");
+                    }
+                    e = launch_bit_table(R, ctx->lut[R], sc->codebook, K, sc->bit_table, s);
+                }
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
                 dev_free(ctx, d_req, req_bytes, s);
                 if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("compression: ") + hipGetErrorString(e));
@@ -573,6 +586,18 @@ sc_status sc_scene_export(const sc_scene* scene, sc_scene_host* out) {
     return SC_OK;
 }
 
+sc_status sc_scene_export_bit_table(const sc_scene* scene, uint32_t* out) {
+    if (!scene || !out) return fail(SC_ERR_INVALID_ARG, "scene and out must be non-NULL");
+    if (!scene->bit_table) return fail(SC_ERR_INVALID_ARG, "the scene has no bit table");
+    sc_status st = use_device(scene->ctx->device);
+    if (st != SC_OK) return st;
+    const uint32_t R = scene->info.R;
+    const size_t bytes = (size_t)R * R * R * R * R * R * (scene->info.codebook_size / 32) * 4;
+    const hipError_t e = hipMemcpy(out, scene->bit_table, bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "bit table export");
+    return SC_OK;
+}
+
 sc_status sc_scene_export4(const sc_scene* scene, float* box4, uint32_t* ref4, uint32_t* src4) {
     if (!scene) return fail(SC_ERR_INVALID_ARG, "scene is NULL");
     if (scene->info.width != 4) return fail(SC_ERR_INVALID_ARG, "not a 4-wide scene");
@@ -612,6 +637,7 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     a.R = I.R;
     a.mode = (I.n_inner == 0) ? (uint32_t)SC_MASK_NONE : I.mode;
     a.width = I.width;
+    a.bit_table = scene->bit_table;
     if (I.width == 4) {
         // the 4-wide root is node 0 exactly when the binary root is node 0 (else the same leaf or empty ref)
         a.nodes = scene->nodes4;

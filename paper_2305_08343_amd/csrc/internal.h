@@ -113,6 +113,7 @@ struct TraceLaunch {
     const uint32_t* order;      // single scene: rays are taken in this order (NULL = index order)
     uint32_t width;             // 2 (binary nodes) or 4 (4-wide nodes; side_masks = raw masks [4*node+c])
     const uint32_t* src4;       // 4-wide: binary slot of child [4*node+c] (shadow counts)
+    const uint32_t* bit_table;  // LUT mode: [R^6][K/32] ray-mask key x codebook entry bits, or NULL
     const BatchItem* items;     // batched launch: per-scene descriptors sorted by ray_begin, else null
     uint32_t n_items;
 };
@@ -145,6 +146,9 @@ hipError_t launch_compress(uint32_t R, const uint64_t* masks, uint32_t n, const 
 hipError_t launch_pack_raw(uint32_t R, const uint64_t* masks, uint32_t n_inner, unsigned char* nodes,
                            hipStream_t s);
 hipError_t launch_pack_lut(const uint16_t* idx, uint32_t n_inner, unsigned char* nodes, hipStream_t s);
+// 2-D bit table: bit k of row key = (LUT[key] AND codebook[k]) != 0; [R^6][K/32] words
+hipError_t launch_bit_table(uint32_t R, const uint64_t* lut, const uint64_t* cb, uint32_t K, uint32_t* out,
+                            hipStream_t s);
 // 4-wide nodes: gather each child's raw mask (and full flag) or codebook index from its binary slot
 hipError_t launch_pack4(uint32_t mode, uint32_t R, const uint32_t* src4, uint32_t n4, const uint64_t* masks,
                         const uint16_t* cidx, unsigned char* nodes4, uint64_t* masks4, hipStream_t s);

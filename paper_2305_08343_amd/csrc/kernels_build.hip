@@ -481,6 +481,32 @@ __global__ void pack4_kernel(uint32_t mode, const uint32_t* __restrict__ src4, u
     aux[1] = (mode == SC_MASK_RAW) ? 0u : idx23;
 }
 
+// 2-D bit table (Sect. 3.2.2): one thread per (ray-mask key, 32 codebook entries).
+template <int R>
+__global__ __launch_bounds__(256) void bit_table_kernel(const uint64_t* __restrict__ lut,
+                                                        const uint64_t* __restrict__ cb, uint32_t K,
+                                                        uint32_t* __restrict__ out) {
+    constexpr int W = (R * R * R + 63) / 64;
+    constexpr size_t kKeys = (size_t)R * R * R * R * R * R;
+    const uint32_t kw = K / 32;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= kKeys * kw) return;
+    const size_t key = gid / kw;
+    const uint32_t w = (uint32_t)(gid % kw);
+    uint64_t rm[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) rm[q] = lut[key * W + q];
+    uint32_t word = 0;
+    for (uint32_t b = 0; b < 32; ++b) {
+        const uint64_t* e = cb + (size_t)(32 * w + b) * W;
+        uint64_t any = 0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) any |= rm[q] & e[q];
+        if (any) word |= 1u << b;
+    }
+    out[gid] = word;
+}
+
 inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -572,6 +598,16 @@ hipError_t launch_pack4(uint32_t mode, uint32_t R, const uint32_t* src4, uint32_
                            nodes4, masks4);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_bit_table(uint32_t R, const uint64_t* lut, const uint64_t* cb, uint32_t K, uint32_t* out,
+                            hipStream_t s) {
+    if (K == 0 || K % 32) return hipErrorInvalidValue;
+    const size_t n = (size_t)R * R * R * R * R * R * (K / 32);
+    if (R == 4) hipLaunchKernelGGL(bit_table_kernel<4>, dim3(blocks_for(n, 256)), dim3(256), 0, s, lut, cb, K, out);
+    else if (R == 6) hipLaunchKernelGGL(bit_table_kernel<6>, dim3(blocks_for(n, 256)), dim3(256), 0, s, lut, cb, K, out);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -53,6 +53,8 @@ constexpr uint32_t kModeNone = SC_MASK_NONE, kModeRaw = SC_MASK_RAW, kModeLut = 
                    kModeSparse = SC_MASK_SPARSE;
 // Compressed masks with the codebook copied into LDS (chosen when it fits).
 constexpr uint32_t kModeLutLds = 16;
+// Compressed masks tested through the scene's 2-D bit table (one bit per test).
+constexpr uint32_t kModeLutBits = 17;
 constexpr uint32_t kCbLdsWords = 1024;  // 8 KiB: K <= 1024 at R = 4, K <= 256 at R = 6
 
 __global__ void reset_counters_kernel(uint32_t* c, uint32_t n) {
@@ -109,20 +111,38 @@ __device__ __forceinline__ void slab(const float* lo, const float* hi, const Ray
     }
 }
 
+// cells of box [lo, hi] holding o + t0 d (b) and o + t1 d (e)
+template <int R>
+__device__ __forceinline__ void ray_cells(const float* lo, const float* hi, const Ray& r, float t0, float t1,
+                                          int& bx, int& by, int& bz, int& ex, int& ey, int& ez) {
+    const float sx = grid_scale<R>(lo[0], hi[0]);
+    const float sy = grid_scale<R>(lo[1], hi[1]);
+    const float sz = grid_scale<R>(lo[2], hi[2]);
+    bx = cell_of<R>(lo[0], sx, r.ox, r.dx, t0);
+    by = cell_of<R>(lo[1], sy, r.oy, r.dy, t0);
+    bz = cell_of<R>(lo[2], sz, r.oz, r.dz, t0);
+    ex = cell_of<R>(lo[0], sx, r.ox, r.dx, t1);
+    ey = cell_of<R>(lo[1], sy, r.oy, r.dy, t1);
+    ez = cell_of<R>(lo[2], sz, r.oz, r.dz, t1);
+}
+
+// the 2-D bit table answers (ray mask of key) AND (codebook entry idx) != 0 with one bit
+template <int R>
+__device__ __forceinline__ bool bit_overlap(const float* lo, const float* hi, const Ray& r, float t0, float t1,
+                                            const uint32_t* table, uint32_t K, uint32_t idx) {
+    int bx, by, bz, ex, ey, ez;
+    ray_cells<R>(lo, hi, r, t0, t1, bx, by, bz, ex, ey, ez);
+    const uint32_t key = (uint32_t)(((((bx * R + by) * R + bz) * R + ex) * R + ey) * R + ez);
+    return (table[(size_t)key * (K >> 5) + (idx >> 5)] >> (idx & 31u)) & 1u;
+}
+
 // (ray mask of the cells holding o + t0 d and o + t1 d) AND (object mask om) != 0
 template <int R>
 __device__ __forceinline__ bool mask_overlap(const float* lo, const float* hi, const Ray& r, float t0, float t1,
                                              const uint64_t* om, const uint64_t* lut, const uint64_t* lds_pat) {
     constexpr int W = (R * R * R + 63) / 64;
-    const float sx = grid_scale<R>(lo[0], hi[0]);
-    const float sy = grid_scale<R>(lo[1], hi[1]);
-    const float sz = grid_scale<R>(lo[2], hi[2]);
-    const int bx = cell_of<R>(lo[0], sx, r.ox, r.dx, t0);
-    const int by = cell_of<R>(lo[1], sy, r.oy, r.dy, t0);
-    const int bz = cell_of<R>(lo[2], sz, r.oz, r.dz, t0);
-    const int ex = cell_of<R>(lo[0], sx, r.ox, r.dx, t1);
-    const int ey = cell_of<R>(lo[1], sy, r.oy, r.dy, t1);
-    const int ez = cell_of<R>(lo[2], sz, r.oz, r.dz, t1);
+    int bx, by, bz, ex, ey, ez;
+    ray_cells<R>(lo, hi, r, t0, t1, bx, by, bz, ex, ey, ez);
     uint64_t ob[W];
     load_mask<W>(om, ob);
     if constexpr (R == 4) {
@@ -174,7 +194,7 @@ __global__ __launch_bounds__(BLOCK) SC_TRACE_OCCUPANCY void trace_kernel(TraceLa
     constexpr int W = (R * R * R + 63) / 64;
     constexpr uint32_t kStride = (MODE == kModeRaw) ? kRawNodeBytes : kNodeBytes;
     constexpr int kWavesPerBlock = BLOCK / kWave;
-    constexpr bool kPatLds = (R == 4) && (MODE != kModeNone);
+    constexpr bool kPatLds = (R == 4) && (MODE != kModeNone) && (MODE != kModeLutBits);
     constexpr bool kCbLds = (MODE == kModeLutLds);
     __shared__ uint2 lds_stack[STACK * BLOCK];
     __shared__ uint64_t lds_pat[kPatLds ? kPatterns<4> : 1];
@@ -376,18 +396,23 @@ __global__ __launch_bounds__(BLOCK) SC_TRACE_OCCUPANCY void trace_kernel(TraceLa
                     if constexpr (MODE != kModeNone) {
                         if (keep && use_mask) {
                             const uint64_t* om = nullptr;
+                            bool test;
+                            uint32_t idx = 0;
                             if constexpr (MODE == kModeRaw) {
-                                if (!((ax.x >> c) & 1u)) om = s_side + ((size_t)ref * 4 + c) * W;
+                                test = !((ax.x >> c) & 1u);
+                                om = s_side + ((size_t)ref * 4 + c) * W;
                             } else {
-                                const uint32_t idx = ((c < 2 ? ax.x : ax.y) >> (16 * (c & 1))) & 0xFFFFu;
-                                if (idx < s_full) {
-                                    if constexpr (MODE == kModeLutLds) om = lds_cb + idx * W;
-                                    else om = s_codebook + (size_t)idx * W;
-                                }
+                                idx = ((c < 2 ? ax.x : ax.y) >> (16 * (c & 1))) & 0xFFFFu;
+                                test = idx < s_full;
+                                if constexpr (MODE == kModeLutLds) om = lds_cb + (test ? idx : 0u) * W;
+                                if constexpr (MODE == kModeLut) om = s_codebook + (size_t)idx * W;
                             }
-                            if (om) {
+                            if (test) {
                                 ++mask_tests;
-                                if (!mask_overlap<R>(lo, hi, r, t0, t1, om, a.lut, lds_pat)) {
+                                bool any;
+                                if constexpr (MODE == kModeLutBits) any = bit_overlap<R>(lo, hi, r, t0, t1, a.bit_table, a.K, idx);
+                                else any = mask_overlap<R>(lo, hi, r, t0, t1, om, a.lut, lds_pat);
+                                if (!any) {
                                     ++mask_culls;
                                     if (shadow_flag && s_fp) atomicAdd(&s_fp[a.src4[(size_t)ref * 4 + c]], 1u);
                                     keep = !cull;
@@ -438,36 +463,38 @@ __global__ __launch_bounds__(BLOCK) SC_TRACE_OCCUPANCY void trace_kernel(TraceLa
                     if (use_mask) {
 #pragma unroll
                         for (int c = 0; c < 2; ++c) {
-                            const bool hit = c ? h1 : h0;
-                            if (!hit) continue;
                             // a full mask cannot cull (the ray mask holds its entry cell): no test
-                            const uint64_t* om;
+                            bool test;
+                            const uint64_t* om = nullptr;
+                            uint32_t idx = 0;
                             if constexpr (MODE == kModeRaw) {
-                                if ((n3.z >> c) & 1u) continue;
+                                test = !((n3.z >> c) & 1u);
                                 om = reinterpret_cast<const uint64_t*>(np + 64) + c * W;
-                            } else if constexpr (MODE == kModeLut) {
-                                const uint32_t idx = c ? (n3.z >> 16) : (n3.z & 0xFFFFu);
-                                if (idx >= s_full) continue;
-                                om = s_codebook + (size_t)idx * W;
-                            } else if constexpr (MODE == kModeLutLds) {
-                                const uint32_t idx = c ? (n3.z >> 16) : (n3.z & 0xFFFFu);
-                                if (idx >= s_full) continue;
-                                om = lds_cb + idx * W;
+                            } else if constexpr (MODE == kModeLut || MODE == kModeLutLds || MODE == kModeLutBits) {
+                                idx = c ? (n3.z >> 16) : (n3.z & 0xFFFFu);
+                                test = idx < s_full;
+                                if constexpr (MODE == kModeLut) om = s_codebook + (size_t)idx * W;
+                                if constexpr (MODE == kModeLutLds) om = lds_cb + (test ? idx : 0u) * W;
                             } else {
                                 const uint32_t ms = c ? n3.w : n3.z;
-                                if (ms == kNoMask) continue;
-                                om = s_side + (size_t)ms * W;
+                                test = ms != kNoMask;
+                                om = s_side + (size_t)(test ? ms : 0u) * W;
                             }
-                            ++mask_tests;
-                            const float* lo = c ? lo1 : lo0;
-                            const float* hi = c ? hi1 : hi0;
-                            const float t0 = c ? t01 : t00, t1 = c ? t11 : t10;
-                            if (!mask_overlap<R>(lo, hi, r, t0, t1, om, a.lut, lds_pat)) {
-                                ++mask_culls;
-                                if (shadow_flag && s_fp) atomicAdd(&s_fp[2 * (size_t)ref + c], 1u);
-                                if (cull) {
-                                    if (c) h1 = false;
-                                    else h0 = false;
+                            if ((c ? h1 : h0) && test) {
+                                ++mask_tests;
+                                const float* lo = c ? lo1 : lo0;
+                                const float* hi = c ? hi1 : hi0;
+                                const float t0 = c ? t01 : t00, t1 = c ? t11 : t10;
+                                bool any;
+                                if constexpr (MODE == kModeLutBits) any = bit_overlap<R>(lo, hi, r, t0, t1, a.bit_table, a.K, idx);
+                                else any = mask_overlap<R>(lo, hi, r, t0, t1, om, a.lut, lds_pat);
+                                if (!any) {
+                                    ++mask_culls;
+                                    if (shadow_flag && s_fp) atomicAdd(&s_fp[2 * (size_t)ref + c], 1u);
+                                    if (cull) {
+                                        if (c) h1 = false;
+                                        else h0 = false;
+                                    }
                                 }
                             }
                         }
@@ -545,6 +572,9 @@ hipError_t launch_cfg(const TraceLaunch& a, hipStream_t s) {
             return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK, BATCH, 2>(a, s)
                             : launch_one<kModeRaw, 6, BLOCK, STACK, BATCH, 2>(a, s);
         case SC_MASK_LUT:
+            if (!BATCH && a.bit_table)
+                return a.R == 4 ? launch_one<kModeLutBits, 4, BLOCK, STACK, false, 2>(a, s)
+                                : launch_one<kModeLutBits, 6, BLOCK, STACK, false, 2>(a, s);
             if (!BATCH && (size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
                 return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK, false, 2>(a, s)
                                 : launch_one<kModeLutLds, 6, BLOCK, STACK, false, 2>(a, s);
@@ -565,6 +595,9 @@ hipError_t launch_cfg4(const TraceLaunch& a, hipStream_t s) {
             return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK, false, 4>(a, s)
                             : launch_one<kModeRaw, 6, BLOCK, STACK, false, 4>(a, s);
         case SC_MASK_LUT:
+            if (a.bit_table)
+                return a.R == 4 ? launch_one<kModeLutBits, 4, BLOCK, STACK, false, 4>(a, s)
+                                : launch_one<kModeLutBits, 6, BLOCK, STACK, false, 4>(a, s);
             if ((size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
                 return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK, false, 4>(a, s)
                                 : launch_one<kModeLutLds, 6, BLOCK, STACK, false, 4>(a, s);

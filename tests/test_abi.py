@@ -26,7 +26,7 @@ def test_header_declares_the_api():
                  "sc_get_tune", "sc_trace_batch", "sc_batch_create", "sc_batch_launch",
                  "sc_batch_destroy", "sc_bvh_build_host", "sc_slot_features", "sc_mlp_forward",
                  "sc_mlp_backward", "sc_mlp_adam", "sc_place_top", "sc_ray_order",
-                 "sc_scene_export4"):
+                 "sc_scene_export4", "sc_scene_export_bit_table"):
         assert must in names
 
 
@@ -48,8 +48,8 @@ def test_params_default_and_status_strings():
 
 
 def test_struct_sizes_match_header_layout():
-    # 12 uint32, 2 float, uint64, 4 double
-    assert C.sizeof(B.sc_scene_info) == 48 + 8 + 8 + 32
+    # 14 uint32, 2 float, uint64, 4 double
+    assert C.sizeof(B.sc_scene_info) == 56 + 8 + 8 + 32
     assert C.sizeof(B.sc_build_params) == 56
     assert C.sizeof(B.sc_scene_host) == 7 * 8
     assert C.sizeof(B.sc_tune) == 6 * 4
@@ -68,6 +68,7 @@ def test_null_arguments_rejected_before_hip():
     assert lib.sc_set_tune(None, None) == 1 and lib.sc_get_tune(None, None) == 1
     assert lib.sc_ray_order(None, None, 0, None, None) == 1
     assert lib.sc_scene_export4(None, None, None, None) == 1
+    assert lib.sc_scene_export_bit_table(None, None) == 1
     assert lib.sc_trace_batch(None, None, 0, 0, None) == 1
     assert lib.sc_batch_create(None, None, 0, 0, None) == 1
     assert lib.sc_batch_launch(None, None) == 1 and lib.sc_batch_destroy(None) == 0
@@ -81,7 +82,7 @@ def test_bad_build_params_rejected_before_hip():
     fake_ctx = C.c_void_p(1)  # never dereferenced: parameter checks come first
     out = C.c_void_p()
     for field, value in [("R", 5), ("leaf_max", 0), ("leaf_max", 5), ("sah_bins", 1), ("depth_cap", 65),
-                         ("mode", 9), ("width", 3), ("width", 0), ("approx_levels", 65)]:
+                         ("mode", 9), ("width", 3), ("width", 0), ("approx_levels", 65), ("bit_table", 1)]:
         q = B.sc_build_params.from_buffer_copy(p)
         setattr(q, field, value)
         assert lib.sc_scene_build(fake_ctx, None, 0, C.byref(q), None, C.byref(out)) == 1, field
