@@ -171,11 +171,35 @@ class Hits:
     slot_fp: np.ndarray | None = None
 
 
+RAY_MASKS = {"lut": 0, "lut2r": 1, "ideal": 2}
+
+
+def raymask_lut2(R: int) -> np.ndarray:
+    """Ray-mask table at ray resolution 2R: [(2R)^6, W] R-grid masks."""
+    F = 2 * R
+    out = np.zeros((F ** 6, words_for(R)), np.uint64)
+    _check(lib().orc_raymask_lut2(C.c_uint32(R), _p(out)), "raymask_lut2")
+    return out
+
+
+def ideal_mask(box, o, d, t0, t1, R):
+    """Ideal ray mask of segment o + t d, t in [t0, t1], in box (lo xyz, hi xyz)."""
+    b = np.ascontiguousarray(box, np.float32)
+    out = np.zeros(words_for(R), np.uint64)
+    _check(lib().orc_ideal_mask(_p(b[:3].copy()), _p(b[3:].copy()), _p(np.asarray(o, np.float32)),
+                                _p(np.asarray(d, np.float32)), C.c_float(t0), C.c_float(t1), C.c_uint32(R),
+                                _p(out)), "ideal_mask")
+    return out
+
+
 def trace(tris, bvh: BVH, rays, *, mode="none", R=6, masks=None, codebook=None, cidx=None,
-          placed=None, lut=None, origin_bound=None, cull=True, shadow=False, nthreads=0) -> Hits:
+          placed=None, lut=None, origin_bound=None, cull=True, shadow=False, nthreads=0,
+          ray_masks="lut", lut2=None) -> Hits:
     """Traversal with culling. mode "raw": masks per slot; "lut": codebook +
     cidx; "sparse": masks per slot used only where placed[slot] != 0. A slot
-    whose mask is full is never tested."""
+    whose mask is full is never tested. ray_masks: "lut" (the table at R, the
+    method), "lut2r" (the table at 2R) or "ideal" (every voxel the segment
+    crosses), the last two as tightness references."""
     tris = np.ascontiguousarray(tris, np.float32)
     rays = np.ascontiguousarray(rays, np.float32)
     n = rays.shape[0]
@@ -192,11 +216,14 @@ def trace(tris, bvh: BVH, rays, *, mode="none", R=6, masks=None, codebook=None, 
     codebook = None if codebook is None else np.ascontiguousarray(codebook, np.uint64)
     cidx = None if cidx is None else np.ascontiguousarray(cidx, np.uint16)
     placed = None if placed is None else np.ascontiguousarray(placed, np.uint8)
-    rc = lib().orc_trace(_p(tris), _p(bvh.perm), _p(bvh.cbox), _p(bvh.cref), C.c_uint32(bvh.root),
-                         C.c_uint32(bvh.depth), C.c_uint32(R), C.c_uint32(mcode), _p(masks),
-                         _p(codebook), _p(cidx), _p(placed), _p(lut), C.c_float(origin_bound),
-                         C.c_uint32(flags), _p(rays), C.c_uint32(n), _p(hits), _p(extra), _p(fp),
-                         C.c_int(nthreads))
+    kind = RAY_MASKS[ray_masks]
+    if kind == 1 and lut2 is None:
+        lut2 = raymask_lut2(R)
+    rc = lib().orc_trace_ex(_p(tris), _p(bvh.perm), _p(bvh.cbox), _p(bvh.cref), C.c_uint32(bvh.root),
+                            C.c_uint32(bvh.depth), C.c_uint32(R), C.c_uint32(mcode), _p(masks),
+                            _p(codebook), _p(cidx), _p(placed), _p(lut), C.c_float(origin_bound),
+                            C.c_uint32(flags), _p(rays), C.c_uint32(n), _p(hits), _p(extra), _p(fp),
+                            C.c_int(nthreads), C.c_uint32(kind), _p(lut2))
     _check(rc, "trace")
     hits, extra = hits[:n], extra[:n]
     return Hits(hits[:, 0].copy(), hits[:, 1].view(np.float32).copy(), hits[:, 2].copy(),

@@ -285,6 +285,62 @@ int orc_raymask_lut(uint32_t R, uint64_t* out) {
     return ORC_OK;
 }
 
+/* Ray-mask table at ray resolution 2R (Sect. 4.2 compares R_ray = R and
+ * R_ray = 2R): the key holds the entry and exit cells on the twice finer grid
+ * F = 2R, ((((bx*F+by)*F+bz)*F+ex)*F+ey)*F+ez; the value is the R-grid mask
+ * of the coarse voxels that contain a fine voxel of the strict sweep between
+ * the two fine cells (the definition of the R table applied at F, each fine
+ * voxel v then mapped to coarse voxel v / 2). Exact integer arithmetic with
+ * the sweep parameter scaled by 27720 (divisible by every |e - b| <= 11). */
+int orc_raymask_lut2(uint32_t R, uint64_t* out) {
+    if (R < 1 || R > 6) return ORC_ERR_ARG;
+    const int64_t T = 27720;
+    const int F = 2 * (int)R;
+    uint32_t W = words_for(R);
+    size_t keys = (size_t)F * F * F * F * F * F;
+    for (size_t key = 0; key < keys; ++key) {
+        size_t q = key;
+        int e[3], b[3];
+        e[2] = (int)(q % F); q /= F;
+        e[1] = (int)(q % F); q /= F;
+        e[0] = (int)(q % F); q /= F;
+        b[2] = (int)(q % F); q /= F;
+        b[1] = (int)(q % F); q /= F;
+        b[0] = (int)q;
+        uint64_t* m = &out[key * W];
+        for (uint32_t w = 0; w < W; ++w) m[w] = 0;
+        int vlo[3], vhi[3];
+        for (int i = 0; i < 3; ++i) {
+            vlo[i] = b[i] < e[i] ? b[i] : e[i];
+            vhi[i] = b[i] < e[i] ? e[i] : b[i];
+        }
+        for (int z = vlo[2]; z <= vhi[2]; ++z)
+            for (int y = vlo[1]; y <= vhi[1]; ++y)
+                for (int x = vlo[0]; x <= vhi[0]; ++x) {
+                    int v[3] = {x, y, z};
+                    int64_t lo = -(int64_t)1 << 40, hi = (int64_t)1 << 40;
+                    int ok = 1;
+                    for (int i = 0; i < 3; ++i) {
+                        int64_t d = e[i] - b[i];
+                        if (d == 0) {
+                            if (v[i] != b[i]) ok = 0;
+                            continue;
+                        }
+                        int64_t a = T * (v[i] - 1 - b[i]) / d;
+                        int64_t c = T * (v[i] + 1 - b[i]) / d;
+                        if (a > c) { int64_t t = a; a = c; c = t; }
+                        if (a > lo) lo = a;
+                        if (c < hi) hi = c;
+                    }
+                    if (ok && lo < hi && lo < T && hi > 0) {
+                        uint32_t bit = (uint32_t)(x / 2) + R * (uint32_t)(y / 2) + R * R * (uint32_t)(z / 2);
+                        m[bit >> 6] |= 1ull << (bit & 63);
+                    }
+                }
+    }
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------
  * 3. Object masks with L = infinity (Sect. 3.1.1, 3.2.1): bit v of a node is
  *    set iff some triangle of the node's subtree overlaps voxel v of the
@@ -596,6 +652,8 @@ typedef struct {
     const uint8_t* placed;
     float origin_bound;
     uint32_t* slot_fp;
+    uint32_t rm_kind;          /* ray mask: 0 table at R, 1 table at 2R (lut2), 2 ideal */
+    const uint64_t* lut2;
 } TraceCtx;
 
 static void raymask_key_cells(const float* lo, const float* hi, const float* o, const float* d,
@@ -610,6 +668,53 @@ static void raymask_key_cells(const float* lo, const float* hi, const float* o, 
         u = (u < (float)(R - 1)) ? u : (float)(R - 1);
         cell[j] = (int)u;
     }
+}
+
+/* "Ideal" ray mask (Sect. 4.1, the grid traversal reference): every voxel of
+ * box [lo, hi] whose closed box the segment o + t d, t in [t0, t1], meets,
+ * by a float64 slab test per voxel; voxel k on axis j spans
+ * [lo + (k ext) / R, lo + ((k + 1) ext) / R]. The triangle side keeps its
+ * delta dilation, so the test stays conservative. */
+static void ideal_ray_mask(const float* lo, const float* hi, const float* o, const float* d, float t0, float t1,
+                           uint32_t R, uint64_t* m) {
+    double bl[3][7];
+    for (int j = 0; j < 3; ++j) {
+        double e = (double)hi[j] - (double)lo[j];
+        for (uint32_t k = 0; k <= R; ++k) bl[j][k] = (double)lo[j] + ((double)k * e) / (double)R;
+    }
+    for (uint32_t z = 0; z < R; ++z)
+        for (uint32_t y = 0; y < R; ++y)
+            for (uint32_t x = 0; x < R; ++x) {
+                uint32_t v[3] = {x, y, z};
+                double s0 = (double)t0, s1 = (double)t1;
+                int ok = 1;
+                for (int j = 0; j < 3 && ok; ++j) {
+                    double a = bl[j][v[j]], b = bl[j][v[j] + 1];
+                    double oj = (double)o[j], dj = (double)d[j];
+                    if (dj == 0.0) {
+                        if (oj < a || oj > b) ok = 0;
+                        continue;
+                    }
+                    double ta = (a - oj) / dj, tb = (b - oj) / dj;
+                    if (ta > tb) { double t = ta; ta = tb; tb = t; }
+                    if (ta > s0) s0 = ta;
+                    if (tb < s1) s1 = tb;
+                    if (s0 > s1) ok = 0;
+                }
+                if (ok) {
+                    uint32_t bit = x + R * y + R * R * z;
+                    m[bit >> 6] |= 1ull << (bit & 63);
+                }
+            }
+}
+
+/* The ideal ray mask alone (for tests). */
+int orc_ideal_mask(const float* lo, const float* hi, const float* o, const float* d, float t0, float t1, uint32_t R,
+                   uint64_t* out) {
+    if (R < 1 || R > 6) return ORC_ERR_ARG;
+    for (uint32_t w = 0; w < words_for(R); ++w) out[w] = 0;
+    ideal_ray_mask(lo, hi, o, d, t0, t1, R, out);
+    return ORC_OK;
 }
 
 /* Leaf of Alg. 4: Moller-Trumbore against each triangle of the leaf, in leaf
@@ -654,12 +759,20 @@ static int mask_test(const TraceCtx* C, uint32_t slot, const float* lo, const fl
     else if (C->placed[slot]) om = &C->masks[(size_t)slot * C->W];
     if (!om || popc(om, C->W) == C->R * C->R * C->R) return 0;
     ++*mask_tests;
-    int cb_[3], ce_[3];
-    raymask_key_cells(lo, hi, o, d, t0, C->R, cb_);
-    raymask_key_cells(lo, hi, o, d, t1, C->R, ce_);
     uint32_t R = C->R;
-    size_t key = (((((size_t)cb_[0] * R + cb_[1]) * R + cb_[2]) * R + ce_[0]) * R + ce_[1]) * R + ce_[2];
-    const uint64_t* rm = &C->lut[key * C->W];
+    uint64_t ideal[4] = {0, 0, 0, 0};
+    const uint64_t* rm;
+    if (C->rm_kind == 2) {
+        ideal_ray_mask(lo, hi, o, d, t0, t1, R, ideal);
+        rm = ideal;
+    } else {
+        uint32_t Q = (C->rm_kind == 1) ? 2 * R : R;
+        int cb_[3], ce_[3];
+        raymask_key_cells(lo, hi, o, d, t0, Q, cb_);
+        raymask_key_cells(lo, hi, o, d, t1, Q, ce_);
+        size_t key = (((((size_t)cb_[0] * Q + cb_[1]) * Q + cb_[2]) * Q + ce_[0]) * Q + ce_[1]) * Q + ce_[2];
+        rm = (C->rm_kind == 1) ? &C->lut2[key * C->W] : &C->lut[key * C->W];
+    }
     uint64_t any = 0;
     for (uint32_t w = 0; w < C->W; ++w) any |= rm[w] & om[w];
     if (any != 0) return 0;
@@ -745,11 +858,31 @@ static void trace_one(const TraceCtx* C, const float* ray, uint32_t* hit, uint32
     if (extra) { extra[0] = mask_tests; extra[1] = mask_culls; }
 }
 
+int orc_trace_ex(const float* tris, const uint32_t* perm, const float* cbox, const uint32_t* cref,
+                 uint32_t root_ref, uint32_t depth, uint32_t R, uint32_t mode, const uint64_t* masks,
+                 const uint64_t* codebook, const uint16_t* cidx, const uint8_t* placed, const uint64_t* lut,
+                 float origin_bound, uint32_t flags, const float* rays, uint32_t nrays,
+                 uint32_t* out_hits, uint32_t* out_extra, uint32_t* slot_fp, int nthreads,
+                 uint32_t rm_kind, const uint64_t* lut2);
+
 int orc_trace(const float* tris, const uint32_t* perm, const float* cbox, const uint32_t* cref,
               uint32_t root_ref, uint32_t depth, uint32_t R, uint32_t mode, const uint64_t* masks,
               const uint64_t* codebook, const uint16_t* cidx, const uint8_t* placed, const uint64_t* lut,
               float origin_bound, uint32_t flags, const float* rays, uint32_t nrays,
               uint32_t* out_hits, uint32_t* out_extra, uint32_t* slot_fp, int nthreads) {
+    return orc_trace_ex(tris, perm, cbox, cref, root_ref, depth, R, mode, masks, codebook, cidx, placed, lut,
+                        origin_bound, flags, rays, nrays, out_hits, out_extra, slot_fp, nthreads, 0, NULL);
+}
+
+/* As orc_trace, with the ray mask taken from the table at R (rm_kind 0), the
+ * table at 2R (1, lut2 from orc_raymask_lut2) or the ideal mask (2). */
+int orc_trace_ex(const float* tris, const uint32_t* perm, const float* cbox, const uint32_t* cref,
+                 uint32_t root_ref, uint32_t depth, uint32_t R, uint32_t mode, const uint64_t* masks,
+                 const uint64_t* codebook, const uint16_t* cidx, const uint8_t* placed, const uint64_t* lut,
+                 float origin_bound, uint32_t flags, const float* rays, uint32_t nrays,
+                 uint32_t* out_hits, uint32_t* out_extra, uint32_t* slot_fp, int nthreads,
+                 uint32_t rm_kind, const uint64_t* lut2) {
+    if (rm_kind > 2 || (rm_kind == 1 && !lut2)) return ORC_ERR_ARG;
     if (depth + 1 > 160) return ORC_ERR_DEPTH;
     if (mode > MODE_SPARSE) return ORC_ERR_ARG;
     if (mode != MODE_NONE && (R < 1 || R > 6 || !lut)) return ORC_ERR_ARG;
@@ -762,6 +895,8 @@ int orc_trace(const float* tris, const uint32_t* perm, const float* cbox, const 
     C.masks = masks; C.cb = codebook; C.cidx = cidx; C.lut = lut; C.placed = placed;
     C.origin_bound = origin_bound;
     C.slot_fp = (flags & FLAG_SHADOW) ? slot_fp : NULL;
+    C.rm_kind = rm_kind;
+    C.lut2 = lut2;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 256)
@@ -949,6 +1084,8 @@ int orc_trace4(const float* tris, const uint32_t* perm, const float* box4, const
     C->masks = masks; C->cb = codebook; C->cidx = cidx; C->lut = lut; C->placed = placed;
     C->origin_bound = origin_bound;
     C->slot_fp = (flags & FLAG_SHADOW) ? slot_fp : NULL;
+    C->rm_kind = 0;
+    C->lut2 = NULL;
     T.box4 = box4; T.ref4 = ref4; T.src4 = src4;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
