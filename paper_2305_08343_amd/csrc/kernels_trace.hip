@@ -106,8 +106,11 @@ __device__ __forceinline__ void slab(const float* lo, const float* hi, const Ray
             b = t;
         }
         b = b * 0x1.000006p0f;
-        t0 = (a > t0) ? a : t0;
-        t1 = (b < t1) ? b : t1;
+        // hardware max/min: with a NaN first operand they keep t0 / t1 as the
+        // compare-and-select form does; they may differ from it only in the
+        // sign of a zero result, which no comparison, cell index or order sees
+        t0 = fmaxf(a, t0);
+        t1 = fminf(b, t1);
     }
 }
 
@@ -179,17 +182,21 @@ __device__ __forceinline__ void order2(float& ka, uint32_t& ia, uint32_t& ra, fl
     ra = q;
 }
 
-#ifndef SC_TRACE_WAVES_PER_EU
-#define SC_TRACE_WAVES_PER_EU 0
-#endif
-#if SC_TRACE_WAVES_PER_EU > 0
-#define SC_TRACE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SC_TRACE_WAVES_PER_EU)))
-#else
-#define SC_TRACE_OCCUPANCY
-#endif
+// Minimum waves per SIMD the register allocation must allow (1 = no constraint).
+// The 4-wide kernels for R = 4 raw masks and for the bit table run faster held
+// to 80 VGPRs (6 waves); the other 4-wide mask kernels spill on their hot path
+// there and are held to 96 VGPRs (5 waves), which they fit without spilling.
+template <uint32_t MODE, int R, int WIDTH>
+struct MinWaves {
+    static constexpr int value =
+        (WIDTH == 4 && ((MODE == kModeRaw && R == 4) || MODE == kModeLutBits)) ? 6
+        : (WIDTH == 4 && MODE != kModeNone)                                   ? 5
+                                                                               : 1;
+};
 
 template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH, int WIDTH>
-__global__ __launch_bounds__(BLOCK) SC_TRACE_OCCUPANCY void trace_kernel(TraceLaunch a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MinWaves<MODE, R, WIDTH>::value)))
+void trace_kernel(TraceLaunch a) {
     static_assert(WIDTH == 2 || (WIDTH == 4 && !BATCH && MODE != kModeSparse), "4-wide: single scene, no sparse masks");
     constexpr int W = (R * R * R + 63) / 64;
     constexpr uint32_t kStride = (MODE == kModeRaw) ? kRawNodeBytes : kNodeBytes;
