@@ -602,7 +602,9 @@ int orc_approx_masks(const float* tris, const uint32_t* perm, uint32_t n_inner, 
 
 /* ------------------------------------------------------------------------
  * 4. Traversal with culling (Alg. 4 with Alg. 1 inside).
- *    slab: per axis x,y,z a = (lo-o)*inv, b = (hi-o)*inv, swap if a > b,
+ *    slab: per axis x,y,z the near bound n = lo and far bound f = hi when
+ *          inv >= 0 (sign bit clear), swapped when inv is negative (PBRT's
+ *          form), a = (n-o)*inv, b = (f-o)*inv,
  *          b *= 1 + 3*2^-23 (robust far value), t0 = max2(a, t0),
  *          t1 = min2(b, t1) from t0 = tmin, t1 = best_t; hit iff t0 <= t1.
  *    ray mask (Alg. 1): p = o + t*d at t0 and t1; scale s = R/ext (0 when
@@ -824,9 +826,10 @@ static void trace_one(const TraceCtx* C, const float* ray, uint32_t* hit, uint32
                 ++box_tests;
                 float t0 = tmin, t1 = best_t;
                 for (int j = 0; j < 3; ++j) {
-                    float a = (lo[j] - o[j]) * inv[j];
-                    float b = (hi[j] - o[j]) * inv[j];
-                    if (a > b) { float t = a; a = b; b = t; }
+                    /* near bound first: lo for a positive direction, hi for a negative one */
+                    int neg = signbit(inv[j]) != 0;
+                    float a = ((neg ? hi[j] : lo[j]) - o[j]) * inv[j];
+                    float b = ((neg ? lo[j] : hi[j]) - o[j]) * inv[j];
                     b = b * 0x1.000006p0f;
                     t0 = (a > t0) ? a : t0;
                     t1 = (b < t1) ? b : t1;
@@ -1034,9 +1037,10 @@ static void trace4_one(const Trace4Ctx* T, const float* ray, uint32_t* hit, uint
                 ++box_tests;
                 float t0 = tmin, t1 = best_t;
                 for (int j = 0; j < 3; ++j) {
-                    float a = (lo[j] - o[j]) * inv[j];
-                    float b = (hi[j] - o[j]) * inv[j];
-                    if (a > b) { float t = a; a = b; b = t; }
+                    /* near bound first: lo for a positive direction, hi for a negative one */
+                    int neg = signbit(inv[j]) != 0;
+                    float a = ((neg ? hi[j] : lo[j]) - o[j]) * inv[j];
+                    float b = ((neg ? lo[j] : hi[j]) - o[j]) * inv[j];
                     b = b * 0x1.000006p0f;
                     t0 = (a > t0) ? a : t0;
                     t1 = (b < t1) ? b : t1;

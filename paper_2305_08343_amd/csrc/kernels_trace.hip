@@ -4,10 +4,11 @@
 // Every ray runs the same canonical sequence as the plain reference
 // traversal, so hits and the per-ray test counts are reproducible bit for
 // bit:
-//  slab test of child box [lo, hi]: per axis x, y, z
-//      a = (lo - o) * inv, b = (hi - o) * inv, swap if a > b,
-//      b = b * (1 + 3*2^-23) (robust far value), t0 = (a > t0) ? a : t0,
-//      t1 = (b < t1) ? b : t1, from t0 = tmin, t1 = best_t; hit iff t0 <= t1
+//  slab test of child box [lo, hi]: per axis x, y, z the near bound n and far
+//      bound f are lo and hi, swapped when the reciprocal direction inv is
+//      negative; a = (n - o) * inv, b = (f - o) * inv,
+//      b = b * (1 + 3*2^-23) (robust far value), t0 = max(a, t0),
+//      t1 = min(b, t1), from t0 = tmin, t1 = best_t; hit iff t0 <= t1
 //  ray mask (Alg. 1): for p = o + t*d at t0 and at t1, per axis
 //      s = R / (hi - lo) (0 if the extent is not positive or s is infinite),
 //      u = (p - lo) * s clamped to [0, R-1] (NaN -> 0), cell = (int)u
@@ -88,23 +89,21 @@ __device__ __forceinline__ int cell_of(float lo, float s, float o, float d, floa
 
 struct Ray {
     float ox, oy, oz, dx, dy, dz, ix, iy, iz, tmin;
+    uint32_t neg;  // bit j: the direction's axis-j reciprocal is negative (sign bit set)
 };
 
-__device__ __forceinline__ void slab(const float* lo, const float* hi, const Ray& r, float tmax,
-                                     float& t0, float& t1) {
+// Slab interval of a box given by its near and far bound per axis (the lower
+// bound is near where the reciprocal direction is non-negative).
+__device__ __forceinline__ void slab_nf(const float* nr, const float* fr, const Ray& r, float tmax, float& t0,
+                                        float& t1) {
     t0 = r.tmin;
     t1 = tmax;
     const float o[3] = {r.ox, r.oy, r.oz};
     const float inv[3] = {r.ix, r.iy, r.iz};
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        float a = (lo[j] - o[j]) * inv[j];
-        float b = (hi[j] - o[j]) * inv[j];
-        if (a > b) {
-            const float t = a;
-            a = b;
-            b = t;
-        }
+        const float a = (nr[j] - o[j]) * inv[j];
+        float b = (fr[j] - o[j]) * inv[j];
         b = b * 0x1.000006p0f;
         // hardware max/min: with a NaN first operand they keep t0 / t1 as the
         // compare-and-select form does; they may differ from it only in the
@@ -112,6 +111,13 @@ __device__ __forceinline__ void slab(const float* lo, const float* hi, const Ray
         t0 = fmaxf(a, t0);
         t1 = fminf(b, t1);
     }
+}
+
+__device__ __forceinline__ void slab(const float* lo, const float* hi, const Ray& r, float tmax,
+                                     float& t0, float& t1) {
+    const float nr[3] = {(r.neg & 1u) ? hi[0] : lo[0], (r.neg & 2u) ? hi[1] : lo[1], (r.neg & 4u) ? hi[2] : lo[2]};
+    const float fr[3] = {(r.neg & 1u) ? lo[0] : hi[0], (r.neg & 2u) ? lo[1] : hi[1], (r.neg & 4u) ? lo[2] : hi[2]};
+    slab_nf(nr, fr, r, tmax, t0, t1);
 }
 
 // cells of box [lo, hi] holding o + t0 d (b) and o + t1 d (e)
@@ -183,15 +189,16 @@ __device__ __forceinline__ void order2(float& ka, uint32_t& ia, uint32_t& ra, fl
 }
 
 // Minimum waves per SIMD the register allocation must allow (1 = no constraint).
-// The 4-wide kernels for R = 4 raw masks and for the bit table run faster held
-// to 80 VGPRs (6 waves); the other 4-wide mask kernels spill on their hot path
-// there and are held to 96 VGPRs (5 waves), which they fit without spilling.
+// The plain 4-wide kernel and the 4-wide kernels for R = 4 raw masks and for
+// the bit table run faster held to 80 VGPRs (6 waves); the other 4-wide mask
+// kernels spill on their hot path there and are held to 96 VGPRs (5 waves),
+// which they fit without spilling.
 template <uint32_t MODE, int R, int WIDTH>
 struct MinWaves {
     static constexpr int value =
-        (WIDTH == 4 && ((MODE == kModeRaw && R == 4) || MODE == kModeLutBits)) ? 6
-        : (WIDTH == 4 && MODE != kModeNone)                                   ? 5
-                                                                               : 1;
+        (WIDTH == 4 && (MODE == kModeNone || (MODE == kModeRaw && R == 4) || MODE == kModeLutBits)) ? 6
+        : (WIDTH == 4)                                                                              ? 5
+                                                                                                    : 1;
 };
 
 template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH, int WIDTH>
@@ -311,6 +318,8 @@ void trace_kernel(TraceLaunch a) {
                                 r.ox = r0.x; r.oy = r0.y; r.oz = r0.z; r.tmin = r0.w;
                                 r.dx = r1.x; r.dy = r1.y; r.dz = r1.z;
                                 r.ix = 1.0f / r.dx; r.iy = 1.0f / r.dy; r.iz = 1.0f / r.dz;
+                                r.neg = (signbit(r.ix) ? 1u : 0u) | (signbit(r.iy) ? 2u : 0u) |
+                                        (signbit(r.iz) ? 4u : 0u);
                                 best_t = r1.w;
                                 best = kNoHit;
                                 box_tests = tri_tests = mask_tests = mask_culls = 0;
@@ -373,12 +382,16 @@ void trace_kernel(TraceLaunch a) {
             } else if constexpr (WIDTH == 4) {
                 // 4-wide node: SoA boxes lo.x[4] lo.y[4] lo.z[4] hi.x[4] hi.y[4] hi.z[4], refs[4], aux
                 const float4* np4 = reinterpret_cast<const float4*>(s_nodes + (size_t)ref * kNode4Bytes);
-                const float4 lx = np4[0], ly = np4[1], lz = np4[2], hx = np4[3], hy = np4[4], hz = np4[5];
+                // near and far bounds of the four children, picked by address from the
+                // lo / hi rows (row j holds lo, row j + 3 hi, of axis j)
+                const uint32_t sx = r.neg & 1u, sy = (r.neg >> 1) & 1u, sz = (r.neg >> 2) & 1u;
+                const float4 nx = np4[3 * sx], ny = np4[1 + 3 * sy], nz = np4[2 + 3 * sz];
+                const float4 fx = np4[3 - 3 * sx], fy = np4[4 - 3 * sy], fz = np4[5 - 3 * sz];
                 const uint4 cr = reinterpret_cast<const uint4*>(np4)[6];
                 const uint4 ax = reinterpret_cast<const uint4*>(np4)[7];
-                const float clx[4] = {lx.x, lx.y, lx.z, lx.w}, cly[4] = {ly.x, ly.y, ly.z, ly.w};
-                const float clz[4] = {lz.x, lz.y, lz.z, lz.w}, chx[4] = {hx.x, hx.y, hx.z, hx.w};
-                const float chy[4] = {hy.x, hy.y, hy.z, hy.w}, chz[4] = {hz.x, hz.y, hz.z, hz.w};
+                const float cnx[4] = {nx.x, nx.y, nx.z, nx.w}, cny[4] = {ny.x, ny.y, ny.z, ny.w};
+                const float cnz[4] = {nz.x, nz.y, nz.z, nz.w}, cfx[4] = {fx.x, fx.y, fx.z, fx.w};
+                const float cfy[4] = {fy.x, fy.y, fy.z, fy.w}, cfz[4] = {fz.x, fz.y, fz.z, fz.w};
                 const uint32_t crf[4] = {cr.x, cr.y, cr.z, cr.w};
                 // surviving children as (t0, child index, ref); dead ones sort last. The
                 // loop keeps a flag instead of leaving an iteration early: a form with
@@ -394,10 +407,10 @@ void trace_kernel(TraceLaunch a) {
                     kref[c] = crf[c];
                     bool keep = false;
                     float t0 = 0.0f, t1 = 0.0f;
-                    const float lo[3] = {clx[c], cly[c], clz[c]}, hi[3] = {chx[c], chy[c], chz[c]};
+                    const float nr[3] = {cnx[c], cny[c], cnz[c]}, fr[3] = {cfx[c], cfy[c], cfz[c]};
                     if (crf[c] != kEmptyRef) {
                         ++box_tests;
-                        slab(lo, hi, r, best_t, t0, t1);
+                        slab_nf(nr, fr, r, best_t, t0, t1);
                         keep = t0 <= t1;
                     }
                     if constexpr (MODE != kModeNone) {
@@ -416,6 +429,8 @@ void trace_kernel(TraceLaunch a) {
                             }
                             if (test) {
                                 ++mask_tests;
+                                const float lo[3] = {sx ? fr[0] : nr[0], sy ? fr[1] : nr[1], sz ? fr[2] : nr[2]};
+                                const float hi[3] = {sx ? nr[0] : fr[0], sy ? nr[1] : fr[1], sz ? nr[2] : fr[2]};
                                 bool any;
                                 if constexpr (MODE == kModeLutBits) any = bit_overlap<R>(lo, hi, r, t0, t1, a.bit_table, a.K, idx);
                                 else any = mask_overlap<R>(lo, hi, r, t0, t1, om, a.lut, lds_pat);

@@ -181,3 +181,25 @@ def test_features_of_4_wide_scene_are_the_binary_slot_features(ctx, small_scene)
         s2.close()
         s4.close()
         assert (f2.view(np.uint32) == f4.view(np.uint32)).all()
+
+
+def test_negative_zero_direction_on_a_box_plane_keeps_the_hit(ctx):
+    """Both node widths keep a box hit for a ray with a -0 direction component
+    that starts on the box's plane (near/far bounds chosen by the direction's
+    sign), as the oracle and brute force do."""
+    from paper_2305_08343_amd import binding
+    tri = np.array([[[0.5, 0.4, 0.5], [0.5, 0.6, 0.5], [0.7, 0.5, 0.5]]], np.float32)
+    far = np.array([[[5.0 + k, 5.0, 5.0], [5.2 + k, 5.0, 5.0], [5.0 + k, 5.2, 5.1]] for k in range(8)], np.float32)
+    tris = np.concatenate([tri, far])
+    rays = np.array([[0.5, 0.5, 0.0, 0.0, -0.0, 0.0, 1.0, np.inf],
+                     [0.5, 0.5, 0.0, 0.0, 0.0, 0.0, 1.0, np.inf]], np.float32)
+    bvh = oracle.bvh_build(tris)
+    for width in (2, 4):
+        print(f"[gpu-bvh4] -0 direction on a box plane, width {width}", flush=True)
+        s = binding.Scene(ctx, tris, R=6, mode="raw", width=width)
+        dev = s.trace(rays).numpy()
+        s.close()
+        assert (dev["prim"] == 0).all()
+        ora = oracle.trace(tris, bvh, rays) if width == 2 else oracle.trace4(tris, bvh, oracle.bvh4_collapse(bvh), rays)
+        assert (dev["t"].view(np.uint32) == ora.t.view(np.uint32)).all()
+        assert (dev["box_tests"] == ora.box_tests).all()

@@ -236,10 +236,9 @@ def _recursive_trace4(tris, bvh, b4, ray, masks=None, lut=None, R=6, ob=np.inf):
             t0, t1 = tmin, st["t"]
             with np.errstate(all="ignore"):
                 for j in range(3):
-                    a = f32(f32(lo[j] - o[j]) * inv[j])
-                    b = f32(f32(hi[j] - o[j]) * inv[j])
-                    if a > b:
-                        a, b = b, a
+                    near, far = (hi[j], lo[j]) if np.signbit(inv[j]) else (lo[j], hi[j])
+                    a = f32(f32(near - o[j]) * inv[j])
+                    b = f32(f32(far - o[j]) * inv[j])
                     b = f32(b * f32(1.0000003576278687))
                     t0 = a if a > t0 else t0
                     t1 = b if b < t1 else t1

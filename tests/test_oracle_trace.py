@@ -327,10 +327,9 @@ def _recursive_trace(tris, bvh, ray, masks=None, lut=None, R=6, ob=np.inf):
             t0, t1 = tmin, st["t"]
             with np.errstate(all="ignore"):
                 for j in range(3):
-                    a = f32(f32(lo[j] - o[j]) * inv[j])
-                    b = f32(f32(hi[j] - o[j]) * inv[j])
-                    if a > b:
-                        a, b = b, a
+                    near, far = (hi[j], lo[j]) if np.signbit(inv[j]) else (lo[j], hi[j])
+                    a = f32(f32(near - o[j]) * inv[j])
+                    b = f32(f32(far - o[j]) * inv[j])
                     b = f32(b * f32(1.0000003576278687))
                     t0 = a if a > t0 else t0
                     t1 = b if b < t1 else t1
@@ -422,3 +421,20 @@ def test_ray_mask_covers_exact_segment():
                 xs, ys, zs = (np.flatnonzero(near[p, :, j]) for j in range(3))
                 covered = any(m[x + R * y + R * R * z] for x in xs for y in ys for z in zs)
                 assert covered
+
+
+def test_negative_zero_direction_on_a_box_plane_keeps_the_hit():
+    """A ray whose x direction is -0 and whose origin lies on the plane x = lo of
+    a child box: with the near/far bounds chosen by the direction's sign, the
+    box stays hit (0 * -inf is NaN on one bound only, and NaN never narrows the
+    interval), so the triangle edge on that plane is found as by brute force."""
+    tri = np.array([[[0.5, 0.4, 0.5], [0.5, 0.6, 0.5], [0.7, 0.5, 0.5]]], np.float32)
+    far = np.array([[[5.0 + k, 5.0, 5.0], [5.2 + k, 5.0, 5.0], [5.0 + k, 5.2, 5.1]] for k in range(8)], np.float32)
+    tris = np.concatenate([tri, far])
+    ray = np.array([[0.5, 0.5, 0.0, 0.0, -0.0, 0.0, 1.0, np.inf]], np.float32)
+    bp, bt = oracle.brute_closest(tris, ray)
+    assert bp[0] == 0
+    bvh = oracle.bvh_build(tris)
+    assert not (bvh.root & LEAF)
+    for h in (oracle.trace(tris, bvh, ray), oracle.trace4(tris, bvh, oracle.bvh4_collapse(bvh), ray)):
+        assert h.prim[0] == 0 and h.t.view(np.uint32)[0] == bt.view(np.uint32)[0]
