@@ -264,7 +264,7 @@ def run_placement(args, ctx):
     specs = scenes.placement_specs(args.place_scenes)
     held = [scenes.placement_heldout(k) for k in range(args.place_heldout)]
     log(f"placement: {len(specs)} training scenes, {len(held)} held-out scenes")
-    params, hist, res = placement.run_experiment(ctx, specs, held, epochs=20, log=log)
+    params, hist, res = placement.run_experiment(ctx, specs, held, log=log)
     total_s = time.perf_counter() - t0
     table = [[{k: v for k, v in e.__dict__.items()} for e in r] for r in res]
     head = {(e.name, e.beta): e for e in res[0]}[("learned", 1.0)]

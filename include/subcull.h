@@ -339,7 +339,8 @@ sc_status sc_mlp_adam(sc_ctx* ctx, float* d_params, const float* d_grad, float* 
                       float lr, float beta1, float beta2, float eps, void* stream);
 
 /* Host: mark the n_place slots with the highest scores (ties: lower slot
- * first) in h_placement [n_slots] (1 = carries a mask). */
+ * first; a NaN score counts as -infinity) in h_placement [n_slots]
+ * (1 = carries a mask). */
 sc_status sc_place_top(const float* h_scores, uint32_t n_slots, uint32_t n_place, uint8_t* h_placement);
 
 const char* sc_status_string(sc_status s);

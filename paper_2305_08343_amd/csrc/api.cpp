@@ -5,6 +5,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -972,8 +973,10 @@ sc_status sc_place_top(const float* h_scores, uint32_t n_slots, uint32_t n_place
     if ((n_slots && (!h_scores || !h_placement)) || n_place > n_slots) return fail(SC_ERR_INVALID_ARG, "bad argument");
     std::vector<uint32_t> idx(n_slots);
     for (uint32_t i = 0; i < n_slots; ++i) idx[i] = i;
+    // NaN counts as -infinity, so the order stays a strict weak order
+    auto key = [&](uint32_t i) { return std::isnan(h_scores[i]) ? -std::numeric_limits<float>::infinity() : h_scores[i]; };
     auto better = [&](uint32_t a, uint32_t b) {
-        const float sa = h_scores[a], sb = h_scores[b];
+        const float sa = key(a), sb = key(b);
         if (sa != sb) return sa > sb;
         return a < b;
     };

@@ -10,7 +10,14 @@ placement returns the same hits as all masks and as no masks.
 
 Training data: for each training scene, the shadow trace (culling off,
 masks evaluated) counts per slot the slab hits whose mask test fails; the
-target is log2(1 + 1e6 * count / rays). Training runs on the GPU through the
+label is log2(1 + 1e6 * count / rays). Placement only ranks the slots of one
+scene against each other, so the regression target is the label
+standardised within its scene (minus the scene's mean, over its standard
+deviation): the scene-wide level of false positives, which the geometric
+features cannot see, no longer has to be fitted. Each scene contributes its
+highest-label slots (a quarter of its sample) plus a uniform draw of the
+rest, since the budget places masks on the top few percent only. Training
+runs on the GPU through the
 library's MLP kernels (forward, backward, Adam). This module only
 orchestrates: sampling of batches, the label transform and bookkeeping use
 torch tensors as plumbing.
@@ -38,8 +45,8 @@ def he_init(seed: int) -> np.ndarray:
     return p
 
 
-def slot_dataset(ctx, tris, rays, R: int = 6, max_slots: int | None = None, seed: int = 0):
-    """Features [S, 12] and targets [S] (device tensors) of one scene."""
+def slot_dataset(ctx, tris, rays, R: int = 6):
+    """Features [S, 12] and labels [S] (device tensors) of one scene's slots."""
     import torch
     scene = binding.Scene(ctx, tris, R=R, mode="raw")
     S = 2 * scene.info["n_inner"]
@@ -50,9 +57,6 @@ def slot_dataset(ctx, tris, rays, R: int = 6, max_slots: int | None = None, seed
     y = torch.log2(1.0 + 1e6 * fp[:S].double() / rays.shape[0]).float()
     info = dict(scene.info)
     scene.close()
-    if max_slots is not None and S > max_slots:
-        idx = torch.from_numpy(np.sort(np.random.default_rng(seed).choice(S, max_slots, replace=False))).cuda()
-        X, y = X[idx], y[idx]
     return X.contiguous(), y.contiguous(), info
 
 
@@ -150,24 +154,55 @@ def evaluate(ctx, tris, rays_dev, placement, ref_hits, *, R: int = 6, name: str 
     return Evaluation(name, beta, int(n_masks), box + tri, box, tri, ms, n / (ms * 1e-3), same)
 
 
-def placements(scores_by_name: dict, n_place: int) -> dict:
-    """uint8 placements of the n_place highest scores for each named scoring."""
-    return {k: binding.place_top(v, n_place) for k, v in scores_by_name.items()}
+def placeable(scores, X) -> np.ndarray:
+    """Scores with every slot whose exact mask is full (occupied fraction 1)
+    moved last: a full mask always overlaps the ray mask, is never tested and
+    would only use up the budget."""
+    s = np.asarray(scores, np.float32).copy()
+    s[X[:, 6].detach().cpu().numpy() >= 1.0] = -np.inf
+    return s
 
 
-def build_training_set(ctx, specs, *, max_slots: int = 32768, log=None):
-    """Concatenated features/targets over training scenes (device tensors)."""
+def placements(scores_by_name: dict, n_place: int, X=None) -> dict:
+    """uint8 placements of the n_place highest scores for each named scoring
+    (full-mask slots last when the features X are given)."""
+    return {k: binding.place_top(placeable(v, X) if X is not None else v, n_place)
+            for k, v in scores_by_name.items()}
+
+
+def scene_targets(y, max_slots: int, seed: int, top_share: float = 0.25):
+    """Sample of one scene's slots and their standardised targets: the
+    top_share * max_slots highest labels (ties: lower slot) plus a uniform
+    draw from the other slots, (label - mean) / std over all of the scene's
+    slots (0 where the std is 0). Returns (slot indices ascending, targets)."""
+    yy = y.detach().cpu().numpy().astype(np.float64)
+    S = yy.size
+    mu, sd = float(yy.mean()) if S else 0.0, float(yy.std()) if S else 0.0
+    t = (yy - mu) / sd if sd > 0.0 else np.zeros_like(yy)
+    if S <= max_slots:
+        idx = np.arange(S)
+    else:
+        n_top = int(max_slots * top_share)
+        order = np.argsort(-yy, kind="stable")
+        rest = np.random.default_rng(seed).choice(order[n_top:], max_slots - n_top, replace=False)
+        idx = np.sort(np.concatenate([order[:n_top], rest]))
+    return idx, t[idx].astype(np.float32)
+
+
+def build_training_set(ctx, specs, *, max_slots: int = 65536, log=None):
+    """Concatenated features / standardised targets over training scenes (device tensors)."""
     import torch
     from . import scenes
     Xs, ys = [], []
     for i, sp in enumerate(specs):
         tris, rays = scenes.placement_scene(sp)
-        X, y, info = slot_dataset(ctx, tris, rays, max_slots=max_slots, seed=sp.seed)
-        Xs.append(X)
-        ys.append(y)
+        X, y, info = slot_dataset(ctx, tris, rays)
+        idx, t = scene_targets(y, max_slots, sp.seed)
+        Xs.append(X[torch.from_numpy(idx).to(X.device)])
+        ys.append(torch.from_numpy(t).to(X.device))
         if log and (i % 10 == 0 or i == len(specs) - 1):
             log(f"train scene {i + 1}/{len(specs)}: {sp.kind} {tris.shape[0]} tris, "
-                f"{info['n_inner']} inner nodes, mean target {y.mean().item():.3f}")
+                f"{info['n_inner']} inner nodes, mean label {y.mean().item():.3f}")
     return torch.cat(Xs).contiguous(), torch.cat(ys).contiguous()
 
 
@@ -190,7 +225,7 @@ def evaluate_scene(ctx, params, tris, rays, *, betas=(0.5, 1.0, 2.0), seed: int 
            evaluate(ctx, tris, rays_dev, None, ref, mode="raw", name="all_masks", reps=reps)]
     for beta in betas:
         M = budget_masks(beta, info["n_inner"])
-        for name, pl in placements(scores, M).items():
+        for name, pl in placements(scores, M, X).items():
             out.append(evaluate(ctx, tris, rays_dev, pl, ref, name=name, beta=beta, reps=reps))
     if log:
         for e in out:
@@ -199,8 +234,8 @@ def evaluate_scene(ctx, params, tris, rays, *, betas=(0.5, 1.0, 2.0), seed: int 
     return out
 
 
-def run_experiment(ctx, train_specs, heldout, *, betas=(0.5, 1.0, 2.0), epochs: int = 20,
-                   batch: int = 4096, lr: float = 1e-3, max_slots: int = 32768, seed: int = 0, log=None):
+def run_experiment(ctx, train_specs, heldout, *, betas=(0.5, 1.0, 2.0), epochs: int = 30,
+                   batch: int = 4096, lr: float = 1e-3, max_slots: int = 65536, seed: int = 0, log=None):
     """Train on the training scenes, evaluate every placement on each held-out
     (tris, rays) pair. Returns (params, loss history, [[Evaluation]])."""
     t0 = time.time()

@@ -116,3 +116,22 @@ def test_place_top_host():
     assert B.place_top(scores, 0).sum() == 0 and B.place_top(scores, 6).sum() == 6
     with pytest.raises(B.SubcullError):
         B.place_top(scores, 7)
+
+
+def test_place_top_orders_nan_and_minus_infinity_last():
+    import numpy as np
+    scores = np.array([np.nan, 1.0, -np.inf, 0.0, np.nan], np.float32)
+    assert list(B.place_top(scores, 2)) == [0, 1, 0, 1, 0]
+    # NaN and -inf tie at the bottom: lower slot first
+    assert list(B.place_top(scores, 3)) == [1, 1, 0, 1, 0]
+    assert list(B.place_top(scores, 4)) == [1, 1, 1, 1, 0]
+
+
+def test_placeable_moves_full_mask_slots_last():
+    import numpy as np
+    import torch
+    from paper_2305_08343_amd import placement
+    X = torch.zeros((4, 12))
+    X[:, 6] = torch.tensor([0.5, 1.0, 0.1, 1.0])
+    s = placement.placeable(np.array([1.0, 9.0, 2.0, 8.0], np.float32), X)
+    assert list(B.place_top(s, 2)) == [1, 0, 1, 0]

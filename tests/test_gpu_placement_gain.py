@@ -7,8 +7,10 @@ per inner node on a held-out 1M-tri hair scene with 1M rays. Checked:
   * hits are identical under every placement, all masks and no masks;
   * all masks <= any placement <= no masks in tests per ray;
   * the learned placement removes tests at every budget, more at larger
-    budgets, at least twice what random placement removes, and at least 70%
-    of what placement by the true (measured) counts removes.
+    budgets, at least twice what random placement removes, at least 70% of
+    what placement by the true (measured) counts removes and at least 90% of
+    what the surface-area x emptiness heuristic removes (trained on 16 small
+    scenes the two are within a few percent of each other).
 Times (rays/s) are printed, not asserted: they depend on the launch.
 """
 import numpy as np
@@ -47,4 +49,5 @@ def test_learned_placement_gain(request):
         assert gain > prev
         assert gain >= 2.0 * (none.tests_per_ray - Rn.tests_per_ray)
         assert gain >= 0.7 * (none.tests_per_ray - T.tests_per_ray)
+        assert gain >= 0.9 * (none.tests_per_ray - ev[("heuristic", beta)].tests_per_ray)
         prev = gain
