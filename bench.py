@@ -8,13 +8,15 @@ surface ray per pixel). One step = one trace of the whole ray batch, rays
 and scene resident in HBM. The headline value is the 216-bit (R = 6) raw-mask
 culled trace on the 4-wide BVH (Sect. 3.2.4 node: four child boxes and
 masks); the plain traversal (4-wide and binary), the binary culled trace and
-64-bit (R = 4) masks are timed beside it. Each mode's launch shape is picked
-is the one the autotuner picked for it on this workload (stored in MODES;
---autotune re-runs the tuner); results never depend on it.
+64-bit (R = 4) masks are timed beside it. Each mode's launch shape is the one
+the autotuner picked for it on this workload (stored in MODES; --autotune
+re-runs the tuner, --sort switches Morton ray ordering); results never depend
+on it. Other workloads: curly_12m (12M curly diagonal strands, 8M incoherent
+bounce rays, LUT-compressed masks), batch64, placement, approx.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes raw6w4,nonew4,none,raw6,raw4w4]
                     [--no-cpu-baseline] [--cpu-seconds S] [--autotune | --tune b,s,c,p,w,o]
-                    [--workload hair_1m|batch64|placement|approx]
+                    [--workload hair_1m|curly_12m|batch64|placement|approx] [--sort stored|0|1]
 """
 from __future__ import annotations
 
@@ -63,8 +65,10 @@ MODES = {
 CHILD_BYTES_W4 = 32  # 24-byte box + 4-byte ref + 4 bytes of the node's aux word, per tested child
 
 
-def measured_traffic(mode):
+def measured_traffic(mode, workload="hair_1m"):
     import hashlib
+    if workload != "hair_1m":
+        return None
     with open(TRACE_SOURCE, "rb") as f:
         h = hashlib.sha256(f.read()).hexdigest()[:16]
     if h != MEASURED_TRAFFIC["source_sha256_16"]:
@@ -92,7 +96,7 @@ def algorithmic_bytes(box_tests, tri_tests, mask_tests, n_rays, spec):
             + tri_tests.sum(dtype=np.float64) * TRI_BYTES)
 
 
-def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup, autotune=False):
+def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup, autotune=False, workload="hair_1m"):
     import torch
     from paper_2305_08343_amd import binding, tune
     t0 = time.perf_counter()
@@ -104,7 +108,7 @@ def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup, autotune=False):
     extra = torch.empty((n, 2), dtype=torch.int32, device=rays_dev.device)
     tuned = None
     if autotune:
-        key = f"hair_1m|{name}|{tris.shape[0]}|{n}"
+        key = f"{workload}|{name}|{tris.shape[0]}|{n}"
         cfg, entry = tune.tuned(ctx, key, lambda: scene.trace(rays_dev, cull=spec["cull"], hits=hits,
                                                               extra_out=extra), log=log)
         tuned = {"config": list(cfg), "seconds": entry.get("seconds")}
@@ -347,7 +351,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tune", default="", help="block,stack,chunk,parts[,waves[,sort]] of the traversal launch")
-    ap.add_argument("--workload", default="hair_1m", choices=["hair_1m", "batch64", "placement", "approx"])
+    ap.add_argument("--workload", default="hair_1m",
+                    choices=["hair_1m", "curly_12m", "batch64", "placement", "approx"])
+    ap.add_argument("--sort", choices=["stored", "0", "1"], default="stored",
+                    help="Morton ray ordering: as stored in each mode's launch shape, off, or on")
     ap.add_argument("--place-scenes", type=int, default=200)
     ap.add_argument("--place-heldout", type=int, default=2)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -381,8 +388,22 @@ def main():
         ctx.close()
         return
     t0 = time.perf_counter()
-    tris = scenes.scene_hair_1m(1)
-    rays = scenes.rays_hair_1m(tris, 1)
+    if args.workload == "curly_12m":
+        tris = scenes.scene_curly_12m(2)
+        rays = scenes.rays_curly_12m(tris)
+        if args.modes == ap.get_default("modes"):
+            args.modes = "lut6w4,lut6,nonew4,none,raw4w4,lut4k256w4"
+        # the oracle's mask build alone takes minutes at 12M triangles: no CPU leg here
+        args.no_cpu_baseline = True
+        desc = ("curly_12m: 12,000,000 tris (120k curly strands x 50 segments x 2 tris, diagonal to the axes), "
+                "8,000,000 incoherent surface bounce rays, SAH BVH (binary; 4-wide in the w4 modes), "
+                "216-bit masks LUT-compressed to a 4,096-entry codebook in the lut6 modes")
+    else:
+        tris = scenes.scene_hair_1m(1)
+        rays = scenes.rays_hair_1m(tris, 1)
+        desc = ("hair_1m: 1,000,002 tris (20k helical strands x 25 segments x 2 tris, "
+                "width 1e-3, + ground plane), 4,147,200 rays (1920x1080 primary + 1 "
+                "diffuse surface ray per pixel), SAH BVH (binary; 4-wide in the w4 modes)")
     log(f"generated {tris.shape[0]} tris, {rays.shape[0]} rays in {time.perf_counter() - t0:.1f}s")
     ctx = binding.Context(0)
     autotune = args.autotune and not args.tune
@@ -394,8 +415,12 @@ def main():
             ctx.set_tune(*(int(x) for x in args.tune.split(",")))
         else:
             ctx.set_tune(*MODES[m].get("tune", ()))
+        if args.sort != "stored":
+            t = ctx.get_tune()
+            ctx.set_tune(t["block"], t["stack"], t["chunk"], t["parts"], t["waves"], int(args.sort))
         log(f"mode {m}: build{' + autotune' if autotune else ''} + {args.warmup} warmup + {args.steps} timed traces")
-        results[m], raw[m] = time_mode(ctx, tris, rays_dev, m, MODES[m], args.steps, args.warmup, autotune)
+        results[m], raw[m] = time_mode(ctx, tris, rays_dev, m, MODES[m], args.steps, args.warmup, autotune,
+                                       args.workload)
         log(f"mode {m}: {results[m]['rays_per_s'] / 1e6:.1f} Mrays/s, "
             f"{results[m]['tests_per_ray']:.2f} tests/ray, kernel {results[m]['kernel_ms_mean']:.3f} ms")
     head = modes[0]
@@ -415,13 +440,11 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "hair_1m: 1,000,002 tris (20k helical strands x 25 segments x 2 tris, "
-                               "width 1e-3, + ground plane), 4,147,200 rays (1920x1080 primary + 1 "
-                               "diffuse surface ray per pixel), SAH BVH (binary; 4-wide in the w4 modes), "
-                               f"mode {head}", "n_tris": int(tris.shape[0]), "n_rays": int(rays.shape[0])},
+        "config": {"workload": f"{desc}, mode {head}", "n_tris": int(tris.shape[0]),
+                   "n_rays": int(rays.shape[0])},
         "tests_per_ray": r["tests_per_ray"],
         "roofline": {"bound": "hbm", "achieved": r["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r["alg_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(head),
+                     "frac": r["alg_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(head, args.workload),
                      "kernel": "trace_kernel", "kernel_ms": r["kernel_ms_mean"], "launch_shape": r["tune"],
                      "alg_bytes_per_launch": r["alg_bytes_per_launch"]},
         "modes": results,
