@@ -15,7 +15,7 @@ on it. Other workloads: curly_12m (12M curly diagonal strands, 8M incoherent
 bounce rays, LUT-compressed masks), batch64, placement, approx.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes raw6w4,nonew4,none,raw6,raw4w4]
-                    [--no-cpu-baseline] [--cpu-seconds S] [--autotune | --tune b,s,c,p,w,o]
+                    [--no-cpu-baseline] [--cpu-seconds S] [--autotune | --tune b,s,c,p,w,o,q]
                     [--workload hair_1m|curly_12m|batch64|placement|approx] [--sort stored|0|1]
 """
 from __future__ import annotations
@@ -109,8 +109,10 @@ def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup, autotune=False, wo
     tuned = None
     if autotune:
         key = f"{workload}|{name}|{tris.shape[0]}|{n}"
+        lut = spec["mode"] == "lut" and not spec.get("bit_table", False)
         cfg, entry = tune.tuned(ctx, key, lambda: scene.trace(rays_dev, cull=spec["cull"], hits=hits,
-                                                              extra_out=extra), log=log)
+                                                              extra_out=extra), log=log,
+                                cands=tune.candidates(lut=lut))
         tuned = {"config": list(cfg), "seconds": entry.get("seconds")}
     res = scene.trace(rays_dev, cull=spec["cull"], hits=hits, extra_out=extra).numpy()
     for _ in range(warmup):
@@ -350,7 +352,7 @@ def main():
                     help="pick each mode's launch shape live with the autotuner instead of the stored one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--tune", default="", help="block,stack,chunk,parts[,waves[,sort]] of the traversal launch")
+    ap.add_argument("--tune", default="", help="block,stack,chunk,parts[,waves[,sort[,codebook]]] of the traversal launch")
     ap.add_argument("--workload", default="hair_1m",
                     choices=["hair_1m", "curly_12m", "batch64", "placement", "approx"])
     ap.add_argument("--sort", choices=["stored", "0", "1"], default="stored",
@@ -417,7 +419,7 @@ def main():
             ctx.set_tune(*MODES[m].get("tune", ()))
         if args.sort != "stored":
             t = ctx.get_tune()
-            ctx.set_tune(t["block"], t["stack"], t["chunk"], t["parts"], t["waves"], int(args.sort))
+            ctx.set_tune(t["block"], t["stack"], t["chunk"], t["parts"], t["waves"], int(args.sort), t["codebook"])
         log(f"mode {m}: build{' + autotune' if autotune else ''} + {args.warmup} warmup + {args.steps} timed traces")
         results[m], raw[m] = time_mode(ctx, tris, rays_dev, m, MODES[m], args.steps, args.warmup, autotune,
                                        args.workload)

@@ -597,7 +597,7 @@ hipError_t launch_cfg(const TraceLaunch& a, hipStream_t s) {
             if (!BATCH && a.bit_table)
                 return a.R == 4 ? launch_one<kModeLutBits, 4, BLOCK, STACK, false, 2>(a, s)
                                 : launch_one<kModeLutBits, 6, BLOCK, STACK, false, 2>(a, s);
-            if (!BATCH && (size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
+            if (!BATCH && !a.cb_global && (size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
                 return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK, false, 2>(a, s)
                                 : launch_one<kModeLutLds, 6, BLOCK, STACK, false, 2>(a, s);
             return a.R == 4 ? launch_one<kModeLut, 4, BLOCK, STACK, BATCH, 2>(a, s)
@@ -620,7 +620,7 @@ hipError_t launch_cfg4(const TraceLaunch& a, hipStream_t s) {
             if (a.bit_table)
                 return a.R == 4 ? launch_one<kModeLutBits, 4, BLOCK, STACK, false, 4>(a, s)
                                 : launch_one<kModeLutBits, 6, BLOCK, STACK, false, 4>(a, s);
-            if ((size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
+            if (!a.cb_global && (size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
                 return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK, false, 4>(a, s)
                                 : launch_one<kModeLutLds, 6, BLOCK, STACK, false, 4>(a, s);
             return a.R == 4 ? launch_one<kModeLut, 4, BLOCK, STACK, false, 4>(a, s)

@@ -2,7 +2,8 @@
 
 The traversal's results never depend on its launch shape (threads per block,
 LDS stack depth, rays per queue fetch, XCD ray partitions, cap on resident
-waves per SIMD, Morton ray sorting), so the tuner only
+waves per SIMD, Morton ray sorting, and for LUT-compressed masks whether the
+codebook is copied to LDS or read through the caches), so the tuner only
 measures time: every candidate is timed once, the faster half is kept and
 timed again with twice the repetitions, until one remains. Results are
 cached per (workload signature, GPU) in a JSON file so later runs reuse
@@ -22,10 +23,15 @@ CHUNKS = [1, 2]
 PARTS = [8, 1]
 WAVES = [0, 6]  # occupancy limit, or at most 6 waves per SIMD
 SORT = [0, 1]   # rays in input order, or in the Morton order of their origins
+CODEBOOK = [0, 1]  # LUT mode: codebook in LDS when it fits, or read from global memory
 
 
-def candidates():
-    return [(b, s, c, p, w, o) for (b, s) in PAIRS for c in CHUNKS for p in PARTS for w in WAVES for o in SORT]
+def candidates(lut: bool = False):
+    """Every launch shape (block, stack, chunk, parts, waves, sort, codebook); the
+    codebook choice only for LUT-mode scenes (it changes nothing elsewhere)."""
+    cbs = CODEBOOK if lut else [0]
+    return [(b, s, c, p, w, o, q) for (b, s) in PAIRS for c in CHUNKS for p in PARTS for w in WAVES
+            for o in SORT for q in cbs]
 
 
 def _gpu_name():

@@ -81,8 +81,14 @@ def test_trace_bit_exact(ctx, small_scene, small_oracle, mode, R, K):
     kw = _kw(small_oracle, mode, R, K)
     print(f"[gpu-bvh4] trace {mode} R={R} K={K}", flush=True)
     s = binding.Scene(ctx, tris, R=R, mode=mode, K=K or 4096, width=4)
-    for cull in (True, False):
-        _compare(s.trace(rays, cull=cull).numpy(), oracle.trace4(tris, bvh, b4, rays, cull=cull, **kw))
+    try:
+        # LUT mode: codebook from LDS (when it fits) and from global memory
+        for cbg in ((0, 1) if mode == "lut" else (0,)):
+            ctx.set_tune(codebook=cbg)
+            for cull in (True, False):
+                _compare(s.trace(rays, cull=cull).numpy(), oracle.trace4(tris, bvh, b4, rays, cull=cull, **kw))
+    finally:
+        ctx.set_tune()
     if mode != "none":
         fp = torch.zeros(2 * bvh.n_inner, dtype=torch.int32, device="cuda:0")
         dev = s.trace(rays, cull=False, shadow=True, slot_fp=fp).numpy()

@@ -96,11 +96,17 @@ def test_small_scene_trace_bit_exact(ctx, small_scene, small_oracle, mode, R, K)
         assert (exp["codebook"] == cb).all()
         assert (exp["cidx"] == idx).all()
         kw.update(mode="lut", R=R, codebook=cb, cidx=idx)
-    for cull in (True, False):
-        ora = oracle.trace(tris, bvh, rays, cull=cull, **kw)
-        dev = s.trace(rays, cull=cull).numpy()
-        _compare_hits(dev, ora)
-    s.close()
+    try:
+        # LUT mode: codebook from LDS (when it fits) and from global memory
+        for cbg in ((0, 1) if mode == "lut" else (0,)):
+            ctx.set_tune(codebook=cbg)
+            for cull in (True, False):
+                ora = oracle.trace(tris, bvh, rays, cull=cull, **kw)
+                dev = s.trace(rays, cull=cull).numpy()
+                _compare_hits(dev, ora)
+    finally:
+        ctx.set_tune()
+        s.close()
 
 
 @pytest.mark.parametrize("R", [4, 6])
@@ -276,6 +282,8 @@ def test_every_launch_shape_gives_the_same_results(ctx, small_scene, small_oracl
             ctx.set_tune(256, 8, 1, 8, 9)
         with pytest.raises(binding.SubcullError):
             ctx.set_tune(256, 8, 1, 8, 0, 2)
+        with pytest.raises(binding.SubcullError):
+            ctx.set_tune(256, 8, 1, 8, 0, 0, 2)
     finally:
         ctx.set_tune(256, 8, 1, 8)
         s6.close()
