@@ -284,6 +284,7 @@ void trace_kernel(TraceLaunch a) {
         bool use_mask = false;
         int sp = 0;
         uint32_t ref = 0;
+        uint32_t waited = 0;  // steps the leaf lanes have waited in a row
         while (true) {
             // refill idle lanes with unstarted rays
             const uint64_t idle = __ballot(!has);
@@ -341,6 +342,21 @@ void trace_kernel(TraceLaunch a) {
             if (__ballot(has) == 0) {
                 if (!more && cursor >= end) break;  // no ray left for this wave
                 continue;                           // every refilled ray finished at once (invalid rays)
+            }
+            {
+                // Leaf gathering: a wave runs the triangle tests as soon as one lane needs
+                // them, for the price of all. A lane whose ray stands at a leaf therefore
+                // waits (its ray does not advance) while fewer than a.gather lanes do and
+                // some lane still stands at an inner node, at most a.gather / 2 steps in a
+                // row. Every ray keeps its own sequence of visits, so no result or count
+                // changes; the wait ends at the latest when the inner lanes run out, which
+                // they do once the ray queue is empty.
+                const bool at_leaf = has && (ref & kLeafBit) != 0;
+                const uint64_t leaves = __ballot(at_leaf);
+                const uint64_t inner = __ballot(has && (ref & kLeafBit) == 0);
+                const bool gather = inner != 0 && (uint32_t)__popcll(leaves) < a.gather && waited < a.gather / 2;
+                waited = gather ? waited + 1u : 0u;  // the same in every lane
+                if (gather && at_leaf) continue;
             }
             if (!has) continue;
 

@@ -2,8 +2,9 @@
 
 The traversal's results never depend on its launch shape (threads per block,
 LDS stack depth, rays per queue fetch, XCD ray partitions, cap on resident
-waves per SIMD, Morton ray sorting, and for LUT-compressed masks whether the
-codebook is copied to LDS or read through the caches), so the tuner only
+waves per SIMD, Morton ray sorting, leaf gathering, and for LUT-compressed
+masks whether the codebook is copied to LDS or read through the caches), so
+the tuner only
 measures time: every candidate is timed once, the faster half is kept and
 timed again with twice the repetitions, until one remains. Results are
 cached per (workload signature, GPU) in a JSON file so later runs reuse
@@ -24,14 +25,15 @@ PARTS = [8, 1]
 WAVES = [0, 6]  # occupancy limit, or at most 6 waves per SIMD
 SORT = [0, 1]   # rays in input order, or in the Morton order of their origins
 CODEBOOK = [0, 1]  # LUT mode: codebook in LDS when it fits, or read from global memory
+GATHER = [0, 8, 16]  # leaf lanes wait for this many of their wave (0 = never)
 
 
 def candidates(lut: bool = False):
-    """Every launch shape (block, stack, chunk, parts, waves, sort, codebook); the
-    codebook choice only for LUT-mode scenes (it changes nothing elsewhere)."""
+    """Every launch shape (block, stack, chunk, parts, waves, sort, codebook, gather);
+    the codebook choice only for LUT-mode scenes (it changes nothing elsewhere)."""
     cbs = CODEBOOK if lut else [0]
-    return [(b, s, c, p, w, o, q) for (b, s) in PAIRS for c in CHUNKS for p in PARTS for w in WAVES
-            for o in SORT for q in cbs]
+    return [(b, s, c, p, w, o, q, g) for (b, s) in PAIRS for c in CHUNKS for p in PARTS for w in WAVES
+            for o in SORT for q in cbs for g in GATHER]
 
 
 def _gpu_name():

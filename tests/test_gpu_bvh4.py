@@ -152,9 +152,9 @@ def test_sorted_and_every_launch_shape(ctx, small_scene, small_oracle):
     s = binding.Scene(ctx, tris, R=6, mode="raw", width=4)
     try:
         for block, stack in ((256, 8), (128, 8), (256, 12), (256, 4), (128, 16)):
-            for chunk, parts, waves, sort in ((1, 8, 0, 0), (3, 1, 2, 1), (2, 8, 5, 1)):
-                print(f"[gpu-bvh4] tune {block} {stack} {chunk} {parts} {waves} {sort}", flush=True)
-                ctx.set_tune(block, stack, chunk, parts, waves, sort)
+            for chunk, parts, waves, sort, gather in ((1, 8, 0, 0, 0), (3, 1, 2, 1, 64), (2, 8, 5, 1, 8)):
+                print(f"[gpu-bvh4] tune {block} {stack} {chunk} {parts} {waves} {sort} {gather}", flush=True)
+                ctx.set_tune(block, stack, chunk, parts, waves, sort, 0, gather)
                 _compare(s.trace(rays).numpy(), ora)
     finally:
         ctx.set_tune()

@@ -270,10 +270,11 @@ def test_every_launch_shape_gives_the_same_results(ctx, small_scene, small_oracl
     s4 = binding.Scene(ctx, tris, R=4, mode="raw")
     try:
         for block, stack in ((256, 8), (128, 8), (256, 12), (256, 4), (128, 16)):
-            for chunk, parts, waves, sort in ((1, 8, 0, 0), (3, 1, 2, 1), (64, 5, 0, 0), (2, 8, 5, 1)):
+            for chunk, parts, waves, sort, gather in ((1, 8, 0, 0, 16), (3, 1, 2, 1, 0), (64, 5, 0, 0, 64),
+                                                      (2, 8, 5, 1, 8)):
                 print(f"[gpu] tune block={block} stack={stack} chunk={chunk} parts={parts} waves={waves} "
-                      f"sort={sort}", flush=True)
-                ctx.set_tune(block, stack, chunk, parts, waves, sort)
+                      f"sort={sort} gather={gather}", flush=True)
+                ctx.set_tune(block, stack, chunk, parts, waves, sort, 0, gather)
                 _compare_hits(s6.trace(r).numpy(), ora)
                 _compare_hits(s4.trace(r).numpy(), ora4)
         with pytest.raises(binding.SubcullError):
@@ -284,6 +285,8 @@ def test_every_launch_shape_gives_the_same_results(ctx, small_scene, small_oracl
             ctx.set_tune(256, 8, 1, 8, 0, 2)
         with pytest.raises(binding.SubcullError):
             ctx.set_tune(256, 8, 1, 8, 0, 0, 2)
+        with pytest.raises(binding.SubcullError):
+            ctx.set_tune(256, 8, 1, 8, 0, 0, 0, 65)
     finally:
         ctx.set_tune(256, 8, 1, 8)
         s6.close()
