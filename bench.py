@@ -15,7 +15,7 @@ on it. Other workloads: curly_12m (12M curly diagonal strands, 8M incoherent
 bounce rays, LUT-compressed masks), batch64, placement, approx.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes raw6w4,nonew4,none,raw6,raw4w4]
-                    [--no-cpu-baseline] [--cpu-seconds S] [--autotune | --tune b,s,c,p,w,o,q,g]
+                    [--no-cpu-baseline] [--cpu-seconds S] [--autotune | --tune b,s,c,p,w,o,q,g,f]
                     [--workload hair_1m|curly_12m|batch64|placement|approx] [--sort stored|0|1]
 """
 from __future__ import annotations
@@ -46,17 +46,17 @@ TRACE_SOURCE = os.path.join(ROOT, "paper_2305_08343_amd", "csrc", "kernels_trace
 # 32 bytes, raw masks in their own array, mask_bytes per mask test). tune = (block, stack, chunk, parts,
 # waves, sort) picked by the autotuner (bench.py --autotune) on this workload on one MI355X.
 MODES = {
-    "raw6w4": dict(mode="raw", R=6, cull=True, width=4, mask_bytes=32, tune=(256, 12, 1, 8, 6, 0, 0, 16)),
-    "raw4w4": dict(mode="raw", R=4, cull=True, width=4, mask_bytes=8, tune=(256, 12, 1, 8, 6, 0, 0, 16)),
-    "nonew4": dict(mode="none", R=6, cull=False, width=4, mask_bytes=0, tune=(256, 12, 1, 8, 0, 0, 0, 8)),
+    "raw6w4": dict(mode="raw", R=6, cull=True, width=4, mask_bytes=32, tune=(256, 12, 1, 8, 6, 0, 0, 16, 16)),
+    "raw4w4": dict(mode="raw", R=4, cull=True, width=4, mask_bytes=8, tune=(256, 12, 1, 8, 6, 0, 0, 16, 16)),
+    "nonew4": dict(mode="none", R=6, cull=False, width=4, mask_bytes=0, tune=(256, 12, 1, 8, 0, 0, 0, 8, 24)),
     "lut6w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, tune=(256, 12, 1, 8, 6, 0)),
     "lut4k256w4": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 0, 0)),
     "lut6k256w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 6, 0)),
-    "lut6w4b": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, bit_table=True, tune=(256, 12, 1, 8, 0, 0, 0, 8)),
+    "lut6w4b": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, bit_table=True, tune=(256, 12, 1, 8, 0, 0, 0, 8, 16)),
     "lut6k256w4b": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=256, bit_table=True, tune=(256, 12, 1, 8, 6, 0)),
     "lut4k256w4b": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, bit_table=True, tune=(256, 12, 1, 8, 0, 0)),
-    "raw6": dict(mode="raw", R=6, cull=True, width=2, node_bytes=128, tune=(256, 12, 1, 8, 6, 1, 0, 8)),
-    "none": dict(mode="none", R=6, cull=False, width=2, node_bytes=64, tune=(256, 8, 1, 8, 0, 0, 0, 16)),
+    "raw6": dict(mode="raw", R=6, cull=True, width=2, node_bytes=128, tune=(256, 12, 1, 8, 6, 1, 0, 8, 24)),
+    "none": dict(mode="none", R=6, cull=False, width=2, node_bytes=64, tune=(256, 8, 1, 8, 0, 0, 0, 16, 24)),
     "raw4": dict(mode="raw", R=4, cull=True, width=2, node_bytes=128, tune=(256, 8, 1, 8, 0, 0)),
     "lut6": dict(mode="lut", R=6, cull=True, width=2, node_bytes=64, K=4096),
     "lut6k256": dict(mode="lut", R=6, cull=True, width=2, node_bytes=64, K=256),
@@ -352,7 +352,7 @@ def main():
                     help="pick each mode's launch shape live with the autotuner instead of the stored one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--tune", default="", help="block,stack,chunk,parts[,waves[,sort[,codebook[,gather]]]] of the traversal launch")
+    ap.add_argument("--tune", default="", help="block,stack,chunk,parts[,waves[,sort[,codebook[,gather[,refill]]]]] of the traversal launch")
     ap.add_argument("--workload", default="hair_1m",
                     choices=["hair_1m", "curly_12m", "batch64", "placement", "approx"])
     ap.add_argument("--sort", choices=["stored", "0", "1"], default="stored",
@@ -420,7 +420,7 @@ def main():
         if args.sort != "stored":
             t = ctx.get_tune()
             ctx.set_tune(t["block"], t["stack"], t["chunk"], t["parts"], t["waves"], int(args.sort), t["codebook"],
-                         t["gather"])
+                         t["gather"], t["refill"])
         log(f"mode {m}: build{' + autotune' if autotune else ''} + {args.warmup} warmup + {args.steps} timed traces")
         results[m], raw[m] = time_mode(ctx, tris, rays_dev, m, MODES[m], args.steps, args.warmup, autotune,
                                        args.workload)

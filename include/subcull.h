@@ -157,10 +157,12 @@ typedef struct {
  * a lane whose ray stands at a leaf waits (its ray does not advance) while
  * fewer than `gather` lanes of its wave do and another lane stands at an
  * inner node, at most gather / 2 steps in a row, so that the wave runs the
- * triangle tests for many lanes at once (0 = never wait). Results never
- * depend on it. Supported (block, stack) pairs: (256,8) (128,8) (256,12)
- * (256,4) (128,16); chunk 1..64; parts 1..8; waves 0..8; sort 0 or 1;
- * codebook 0 or 1; gather 0..64. */
+ * triangle tests for many lanes at once (0 = never wait), and refill
+ * gathering: idle lanes take new rays only when at least `refill` lanes of
+ * the wave are idle or none is busy (0 or 1 = as soon as one is idle).
+ * Results never depend on it. Supported (block, stack) pairs: (256,8)
+ * (128,8) (256,12) (256,4) (128,16); chunk 1..64; parts 1..8; waves 0..8;
+ * sort 0 or 1; codebook 0 or 1; gather 0..64; refill 0..64. */
 typedef struct {
     uint32_t block;
     uint32_t stack;
@@ -170,6 +172,7 @@ typedef struct {
     uint32_t sort;
     uint32_t codebook;
     uint32_t gather;
+    uint32_t refill;
 } sc_tune;
 
 /* Fill `p` with the defaults: R 6, leaf_max 4, 32 bins, depth cap 64, RAW,
@@ -265,7 +268,7 @@ sc_status sc_ray_order(const sc_scene* scene, const float* d_rays, uint32_t n, u
                        void* stream);
 
 /* Select the traversal launch shape for later sc_trace calls on this
- * context (default 256, 8, 1, 8, 0, 0, 0, 16). SC_ERR_UNSUPPORTED for an uncompiled pair. */
+ * context (default 256, 8, 1, 8, 0, 0, 0, 16, 16). SC_ERR_UNSUPPORTED for an uncompiled pair. */
 sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune);
 sc_status sc_get_tune(const sc_ctx* ctx, sc_tune* out);
 

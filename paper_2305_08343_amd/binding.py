@@ -55,7 +55,7 @@ class sc_scene_info(C.Structure):
 class sc_tune(C.Structure):
     _fields_ = [("block", C.c_uint32), ("stack", C.c_uint32), ("chunk", C.c_uint32),
                 ("parts", C.c_uint32), ("waves", C.c_uint32), ("sort", C.c_uint32), ("codebook", C.c_uint32),
-                ("gather", C.c_uint32)]
+                ("gather", C.c_uint32), ("refill", C.c_uint32)]
 
 
 class sc_batch_item(C.Structure):
@@ -187,16 +187,16 @@ class Context:
             pass
 
     def set_tune(self, block: int = 256, stack: int = 8, chunk: int = 1, parts: int = 8, waves: int = 0,
-                 sort: int = 0, codebook: int = 0, gather: int = 16):
+                 sort: int = 0, codebook: int = 0, gather: int = 16, refill: int = 16):
         """Traversal launch shape for later traces (results never depend on it)."""
         _check(load().sc_set_tune(self.handle, C.byref(sc_tune(block, stack, chunk, parts, waves, sort,
-                                                               codebook, gather))), "sc_set_tune")
+                                                               codebook, gather, refill))), "sc_set_tune")
 
     def get_tune(self) -> dict:
         t = sc_tune()
         _check(load().sc_get_tune(self.handle, C.byref(t)), "sc_get_tune")
         return {"block": t.block, "stack": t.stack, "chunk": t.chunk, "parts": t.parts, "waves": t.waves,
-                "sort": t.sort, "codebook": t.codebook, "gather": t.gather}
+                "sort": t.sort, "codebook": t.codebook, "gather": t.gather, "refill": t.refill}
 
     # ---- placement MLP (device tensors in, device tensors out)
     def mlp_forward(self, params, x, act=None, stream=None):

@@ -24,7 +24,7 @@ struct sc_ctx {
     std::mutex lut_mu;
     uint32_t* counters = nullptr;           // kQueueRing ray-queue counters
     std::atomic<uint32_t> next_counter{0};
-    sc_tune tune{256, 8, 1, kQueueParts, 0, 0, 0, 16};
+    sc_tune tune{256, 8, 1, kQueueParts, 0, 0, 0, 16, 16};
 };
 
 struct sc_scene {
@@ -661,6 +661,7 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     a.waves = ctx->tune.waves;
     a.cb_global = ctx->tune.codebook;
     a.gather = ctx->tune.gather;
+    a.refill = ctx->tune.refill;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const bool sort = (flags & SC_TRACE_SORT) || ctx->tune.sort;
     void* ws = nullptr;
@@ -767,6 +768,7 @@ sc_status prepare_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_item
     a.waves = ctx->tune.waves;
     a.parts = ctx->tune.parts;
     a.gather = ctx->tune.gather;
+    a.refill = ctx->tune.refill;
     a.width = 2;
     a.n_items = n_items;
     if (I.mode != SC_MASK_NONE && !a.lut) {  // masks exist only if the LUT was built
@@ -883,6 +885,7 @@ sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune) {
     if (tune->sort > 1) return fail(SC_ERR_INVALID_ARG, "sort must be 0 or 1");
     if (tune->codebook > 1) return fail(SC_ERR_INVALID_ARG, "codebook must be 0 or 1");
     if (tune->gather > 64) return fail(SC_ERR_INVALID_ARG, "gather must be 0..64");
+    if (tune->refill > 64) return fail(SC_ERR_INVALID_ARG, "refill must be 0..64");
     ctx->tune = *tune;
     return SC_OK;
 }

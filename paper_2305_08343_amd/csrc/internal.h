@@ -112,6 +112,7 @@ struct TraceLaunch {
     uint32_t waves;             // cap on resident waves per SIMD, 0 = occupancy limit
     uint32_t cb_global;         // LUT mode: 1 = read the codebook from global memory even when it fits LDS
     uint32_t gather;            // leaf gathering: lanes at leaves wait while fewer than this many are (0 = off)
+    uint32_t refill;            // idle lanes take rays once this many are idle or none is busy (0, 1 = at once)
     const uint32_t* order;      // single scene: rays are taken in this order (NULL = index order)
     uint32_t width;             // 2 (binary nodes) or 4 (4-wide nodes; side_masks = raw masks [4*node+c])
     const uint32_t* src4;       // 4-wide: binary slot of child [4*node+c] (shadow counts)

@@ -286,9 +286,12 @@ void trace_kernel(TraceLaunch a) {
         uint32_t ref = 0;
         uint32_t waited = 0;  // steps the leaf lanes have waited in a row
         while (true) {
-            // refill idle lanes with unstarted rays
+            // refill idle lanes with unstarted rays, once a.refill of them are idle or
+            // none is busy: the refill (ray load, validity test, set-up) costs the
+            // wave the same for one lane as for many; a ray that starts a few steps
+            // later traverses exactly as before
             const uint64_t idle = __ballot(!has);
-            if (idle != 0) {
+            if (idle != 0 && ((uint32_t)__popcll(idle) >= a.refill || idle == __ballot(true))) {
                 if (cursor >= end && more) more = fetch();
                 if (cursor < end) {
                     if (!has) {

@@ -2,7 +2,7 @@
 
 The traversal's results never depend on its launch shape (threads per block,
 LDS stack depth, rays per queue fetch, XCD ray partitions, cap on resident
-waves per SIMD, Morton ray sorting, leaf gathering, and for LUT-compressed
+waves per SIMD, Morton ray sorting, leaf and refill gathering, and for LUT-compressed
 masks whether the codebook is copied to LDS or read through the caches), so
 the tuner only
 measures time: every candidate is timed once, the faster half is kept and
@@ -26,14 +26,15 @@ WAVES = [0, 6]  # occupancy limit, or at most 6 waves per SIMD
 SORT = [0, 1]   # rays in input order, or in the Morton order of their origins
 CODEBOOK = [0, 1]  # LUT mode: codebook in LDS when it fits, or read from global memory
 GATHER = [0, 8, 16]  # leaf lanes wait for this many of their wave (0 = never)
+REFILL = [1, 16, 24]  # idle lanes take new rays once this many are idle (1 = at once)
 
 
 def candidates(lut: bool = False):
-    """Every launch shape (block, stack, chunk, parts, waves, sort, codebook, gather);
-    the codebook choice only for LUT-mode scenes (it changes nothing elsewhere)."""
+    """Every launch shape (block, stack, chunk, parts, waves, sort, codebook, gather,
+    refill); the codebook choice only for LUT-mode scenes (it changes nothing elsewhere)."""
     cbs = CODEBOOK if lut else [0]
-    return [(b, s, c, p, w, o, q, g) for (b, s) in PAIRS for c in CHUNKS for p in PARTS for w in WAVES
-            for o in SORT for q in cbs for g in GATHER]
+    return [(b, s, c, p, w, o, q, g, f) for (b, s) in PAIRS for c in CHUNKS for p in PARTS for w in WAVES
+            for o in SORT for q in cbs for g in GATHER for f in REFILL]
 
 
 def _gpu_name():

@@ -52,7 +52,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(B.sc_scene_info) == 56 + 8 + 8 + 32
     assert C.sizeof(B.sc_build_params) == 56
     assert C.sizeof(B.sc_scene_host) == 7 * 8
-    assert C.sizeof(B.sc_tune) == 8 * 4
+    assert C.sizeof(B.sc_tune) == 9 * 4
 
 
 def test_null_arguments_rejected_before_hip():

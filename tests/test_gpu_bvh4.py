@@ -152,9 +152,11 @@ def test_sorted_and_every_launch_shape(ctx, small_scene, small_oracle):
     s = binding.Scene(ctx, tris, R=6, mode="raw", width=4)
     try:
         for block, stack in ((256, 8), (128, 8), (256, 12), (256, 4), (128, 16)):
-            for chunk, parts, waves, sort, gather in ((1, 8, 0, 0, 0), (3, 1, 2, 1, 64), (2, 8, 5, 1, 8)):
-                print(f"[gpu-bvh4] tune {block} {stack} {chunk} {parts} {waves} {sort} {gather}", flush=True)
-                ctx.set_tune(block, stack, chunk, parts, waves, sort, 0, gather)
+            for chunk, parts, waves, sort, gather, refill in ((1, 8, 0, 0, 0, 1), (3, 1, 2, 1, 64, 64),
+                                                              (2, 8, 5, 1, 8, 24)):
+                print(f"[gpu-bvh4] tune {block} {stack} {chunk} {parts} {waves} {sort} {gather} {refill}",
+                      flush=True)
+                ctx.set_tune(block, stack, chunk, parts, waves, sort, 0, gather, refill)
                 _compare(s.trace(rays).numpy(), ora)
     finally:
         ctx.set_tune()

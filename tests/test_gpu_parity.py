@@ -270,11 +270,11 @@ def test_every_launch_shape_gives_the_same_results(ctx, small_scene, small_oracl
     s4 = binding.Scene(ctx, tris, R=4, mode="raw")
     try:
         for block, stack in ((256, 8), (128, 8), (256, 12), (256, 4), (128, 16)):
-            for chunk, parts, waves, sort, gather in ((1, 8, 0, 0, 16), (3, 1, 2, 1, 0), (64, 5, 0, 0, 64),
-                                                      (2, 8, 5, 1, 8)):
+            for chunk, parts, waves, sort, gather, refill in ((1, 8, 0, 0, 16, 16), (3, 1, 2, 1, 0, 64),
+                                                              (64, 5, 0, 0, 64, 1), (2, 8, 5, 1, 8, 0)):
                 print(f"[gpu] tune block={block} stack={stack} chunk={chunk} parts={parts} waves={waves} "
-                      f"sort={sort} gather={gather}", flush=True)
-                ctx.set_tune(block, stack, chunk, parts, waves, sort, 0, gather)
+                      f"sort={sort} gather={gather} refill={refill}", flush=True)
+                ctx.set_tune(block, stack, chunk, parts, waves, sort, 0, gather, refill)
                 _compare_hits(s6.trace(r).numpy(), ora)
                 _compare_hits(s4.trace(r).numpy(), ora4)
         with pytest.raises(binding.SubcullError):
@@ -287,6 +287,8 @@ def test_every_launch_shape_gives_the_same_results(ctx, small_scene, small_oracl
             ctx.set_tune(256, 8, 1, 8, 0, 0, 2)
         with pytest.raises(binding.SubcullError):
             ctx.set_tune(256, 8, 1, 8, 0, 0, 0, 65)
+        with pytest.raises(binding.SubcullError):
+            ctx.set_tune(256, 8, 1, 8, 0, 0, 0, 16, 65)
     finally:
         ctx.set_tune(256, 8, 1, 8)
         s6.close()
