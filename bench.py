@@ -39,7 +39,7 @@ RAY_BYTES, HIT_BYTES, EXTRA_BYTES, TRI_BYTES = 32, 16, 8, 48
 # HBM-side bytes per trace launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, each scaled by the
 # same counter's reading for a 1 GiB plain copy (FETCH x2.0, WRITE x1.0). Valid only for the traversal
 # kernel source whose SHA-256 starts with this prefix; otherwise traffic is reported as null.
-MEASURED_TRAFFIC = {"source_sha256_16": "f5c32bf0e707d4cc", "raw6w4": 16.861e9, "none": 19.433e9}
+MEASURED_TRAFFIC = {"source_sha256_16": "19f1ef43eb46dee9", "raw6w4": 16.847e9, "none": 18.558e9}
 TRACE_SOURCE = os.path.join(ROOT, "paper_2305_08343_amd", "csrc", "kernels_trace.hip")
 
 # width 2: binary nodes (node_bytes per visit); width 4: 4-wide nodes of Sect. 3.2.4 (child records of
@@ -185,7 +185,8 @@ def cpu_baseline(tris, rays, target_s, width=2):
     run(sample)
     dt = time.perf_counter() - t0
     return {"value": sample.shape[0] / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
-            "sample": f"every {step}th ray of the {rays.shape[0]:,} ({sample.shape[0]} rays), R=6 raw masks, "
+            "sample": (f"all {rays.shape[0]:,} rays" if step == 1 else
+                       f"every {step}th ray of the {rays.shape[0]:,} ({sample.shape[0]} rays)") + ", R=6 raw masks, "
                       f"culled, {'4-wide' if width == 4 else 'binary'} BVH; {dt:.1f} s of trace on {cores} "
                       f"threads; oracle BVH+mask setup {setup:.1f} s not timed"}
 
