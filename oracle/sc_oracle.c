@@ -318,7 +318,7 @@ int orc_raymask_lut2(uint32_t R, uint64_t* out) {
             for (int y = vlo[1]; y <= vhi[1]; ++y)
                 for (int x = vlo[0]; x <= vhi[0]; ++x) {
                     int v[3] = {x, y, z};
-                    int64_t lo = -(int64_t)1 << 40, hi = (int64_t)1 << 40;
+                    int64_t lo = -((int64_t)1 << 40), hi = (int64_t)1 << 40;
                     int ok = 1;
                     for (int i = 0; i < 3; ++i) {
                         int64_t d = e[i] - b[i];

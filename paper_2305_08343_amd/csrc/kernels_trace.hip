@@ -188,26 +188,39 @@ __device__ __forceinline__ void order2(float& ka, uint32_t& ia, uint32_t& ra, fl
     ra = q;
 }
 
+// LDS of one block of the traversal kernel: its stack, the R = 4 ray-mask
+// patterns and the codebook copy where the mode keeps them in LDS.
+template <uint32_t MODE, int R, int BLOCK, int STACK>
+constexpr uint32_t trace_lds_bytes() {
+    const bool pat = (R == 4) && (MODE != kModeNone) && (MODE != kModeLutBits);
+    return (uint32_t)(STACK * BLOCK) * 8u + (pat ? (uint32_t)kPatterns<4> * 8u : 8u) +
+           (MODE == kModeLutLds ? kCbLdsWords * 8u : 16u);
+}
+constexpr uint32_t kLdsPerCu = 160u * 1024u;  // gfx950
+
 // Minimum waves per SIMD the register allocation must allow (1 = no constraint).
 // The plain 4-wide kernel and the 4-wide kernels for R = 4 raw masks and for
 // the bit table run faster held to 80 VGPRs (6 waves); the other 4-wide mask
 // kernels spill on their hot path there and are held to 96 VGPRs (5 waves),
-// which they fit without spilling.
-template <uint32_t MODE, int R, int WIDTH>
+// which they fit without spilling. Where LDS already allows fewer waves than
+// that, the target is what LDS allows: registers beyond it would buy nothing.
+template <uint32_t MODE, int R, int WIDTH, int BLOCK, int STACK>
 struct MinWaves {
-    static constexpr int value =
+    static constexpr int target =
         (WIDTH == 4 && (MODE == kModeNone || (MODE == kModeRaw && R == 4) || MODE == kModeLutBits)) ? 6
         : (WIDTH == 4)                                                                              ? 5
                                                                                                     : 1;
+    static constexpr int lds_waves =
+        (int)((kLdsPerCu / trace_lds_bytes<MODE, R, BLOCK, STACK>()) * (uint32_t)(BLOCK / kWave) / 4u);
+    static constexpr int value = (lds_waves < target) ? (lds_waves > 1 ? lds_waves : 1) : target;
 };
 
 template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH, int WIDTH>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MinWaves<MODE, R, WIDTH>::value)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MinWaves<MODE, R, WIDTH, BLOCK, STACK>::value)))
 void trace_kernel(TraceLaunch a) {
     static_assert(WIDTH == 2 || (WIDTH == 4 && !BATCH && MODE != kModeSparse), "4-wide: single scene, no sparse masks");
     constexpr int W = (R * R * R + 63) / 64;
     constexpr uint32_t kStride = (MODE == kModeRaw) ? kRawNodeBytes : kNodeBytes;
-    constexpr int kWavesPerBlock = BLOCK / kWave;
     constexpr bool kPatLds = (R == 4) && (MODE != kModeNone) && (MODE != kModeLutBits);
     constexpr bool kCbLds = (MODE == kModeLutLds);
     __shared__ uint2 lds_stack[STACK * BLOCK];
