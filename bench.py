@@ -46,17 +46,17 @@ TRACE_SOURCE = os.path.join(ROOT, "paper_2305_08343_amd", "csrc", "kernels_trace
 # 32 bytes, raw masks in their own array, mask_bytes per mask test). tune = (block, stack, chunk, parts,
 # waves, sort) picked by the autotuner (bench.py --autotune) on this workload on one MI355X.
 MODES = {
-    "raw6w4": dict(mode="raw", R=6, cull=True, width=4, mask_bytes=32, tune=(256, 12, 1, 8, 6, 0, 0, 16, 16)),
-    "raw4w4": dict(mode="raw", R=4, cull=True, width=4, mask_bytes=8, tune=(256, 12, 1, 8, 6, 0, 0, 16, 16)),
-    "nonew4": dict(mode="none", R=6, cull=False, width=4, mask_bytes=0, tune=(128, 16, 1, 8, 6, 1, 0, 16, 24)),
+    "raw6w4": dict(mode="raw", R=6, cull=True, width=4, mask_bytes=32, tune=(256, 12, 1, 8, 6, 0, 0, 12, 12)),
+    "raw4w4": dict(mode="raw", R=4, cull=True, width=4, mask_bytes=8, tune=(256, 12, 1, 8, 6, 0, 0, 12, 8)),
+    "nonew4": dict(mode="none", R=6, cull=False, width=4, mask_bytes=0, tune=(128, 16, 1, 8, 6, 1, 0, 20, 20)),
     "lut6w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, tune=(256, 12, 1, 8, 6, 0)),
     "lut4k256w4": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 0, 0)),
     "lut6k256w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 6, 0)),
     "lut6w4b": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, bit_table=True, tune=(256, 12, 1, 8, 0, 0, 0, 8, 16)),
     "lut6k256w4b": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=256, bit_table=True, tune=(256, 12, 1, 8, 6, 0)),
     "lut4k256w4b": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, bit_table=True, tune=(256, 12, 1, 8, 0, 0)),
-    "raw6": dict(mode="raw", R=6, cull=True, width=2, node_bytes=128, tune=(256, 12, 1, 8, 6, 1, 0, 8, 24)),
-    "none": dict(mode="none", R=6, cull=False, width=2, node_bytes=64, tune=(256, 12, 1, 8, 0, 1, 0, 16, 16)),
+    "raw6": dict(mode="raw", R=6, cull=True, width=2, node_bytes=128, tune=(256, 12, 1, 8, 6, 1, 0, 12, 32)),
+    "none": dict(mode="none", R=6, cull=False, width=2, node_bytes=64, tune=(256, 12, 1, 8, 0, 1, 0, 24, 20)),
     "raw4": dict(mode="raw", R=4, cull=True, width=2, node_bytes=128, tune=(256, 8, 1, 8, 0, 0)),
     "lut6": dict(mode="lut", R=6, cull=True, width=2, node_bytes=64, K=4096),
     "lut6k256": dict(mode="lut", R=6, cull=True, width=2, node_bytes=64, K=256),

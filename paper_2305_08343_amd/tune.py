@@ -25,8 +25,8 @@ PARTS = [8, 1]
 WAVES = [0, 6]  # occupancy limit, or at most 6 waves per SIMD
 SORT = [0, 1]   # rays in input order, or in the Morton order of their origins
 CODEBOOK = [0, 1]  # LUT mode: codebook in LDS when it fits, or read from global memory
-GATHER = [0, 8, 16]  # leaf lanes wait for this many of their wave (0 = never)
-REFILL = [1, 16, 24]  # idle lanes take new rays once this many are idle (1 = at once)
+GATHER = [0, 12, 20]  # leaf lanes wait for this many of their wave (0 = never)
+REFILL = [1, 12, 24]  # idle lanes take new rays once this many are idle (1 = at once)
 
 
 def candidates(lut: bool = False):
