@@ -96,6 +96,26 @@ def algorithmic_bytes(box_tests, tri_tests, mask_tests, n_rays, spec):
             + tri_tests.sum(dtype=np.float64) * TRI_BYTES)
 
 
+def hbm_probe(gib=2, reps=5):
+    """Achievable HBM bandwidth: a plain device copy of `gib` GiB (read + write), best of `reps`."""
+    import torch
+    src = torch.ones(gib * 2 ** 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    bytes_moved = 2 * src.numel() * 4
+    del src, dst
+    return bytes_moved / (best * 1e-3) / 1e9
+
+
 def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup, autotune=False, workload="hair_1m"):
     import torch
     from paper_2305_08343_amd import binding, tune
@@ -174,6 +194,23 @@ def cpu_baseline(tris, rays, target_s, width=2):
         else:
             oracle.trace(tris, bvh, sample, **kw)
 
+    # one thread on 65,536 rays spread evenly over the batch (rays/s per core; the first rays
+    # of the image are mostly sky and would flatter it)
+    first = rays[::max(1, rays.shape[0] // 65536)][:65536]
+    t0 = time.perf_counter()
+    kw1 = dict(mode="raw", R=6, masks=masks, lut=lut, origin_bound=ob, nthreads=1)
+    if b4 is not None:
+        oracle.trace4(tris, bvh, b4, first, **kw1)
+    else:
+        oracle.trace(tris, bvh, first, **kw1)
+    one = first.shape[0] / (time.perf_counter() - t0)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+
     probe = rays[::4096]
     t0 = time.perf_counter()
     run(probe)
@@ -184,7 +221,9 @@ def cpu_baseline(tris, rays, target_s, width=2):
     t0 = time.perf_counter()
     run(sample)
     dt = time.perf_counter() - t0
-    return {"value": sample.shape[0] / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
+    return {"value": sample.shape[0] / dt, "unit": "rays/s", "cores": cores, "kind": "oracle", "cpu_model": model,
+            "one_thread": {"value": one, "unit": "rays/s",
+                           "sample": f"every {max(1, rays.shape[0] // 65536)}th ray ({first.shape[0]:,} rays), 1 thread"},
             "sample": (f"all {rays.shape[0]:,} rays" if step == 1 else
                        f"every {step}th ray of the {rays.shape[0]:,} ({sample.shape[0]} rays)") + ", R=6 raw masks, "
                       f"culled, {'4-wide' if width == 4 else 'binary'} BVH; {dt:.1f} s of trace on {cores} "
@@ -439,6 +478,10 @@ def main():
             results[m][f"tests_ratio_vs_{key}"] = results[m]["tests_per_ray"] / results[ref]["tests_per_ray"]
             results[m][f"speedup_vs_{key}"] = results[m]["rays_per_s"] / results[ref]["rays_per_s"]
     r = results[head]
+    n_rays = int(rays.shape[0])
+    traffic = measured_traffic(head, args.workload)
+    probe_gbs = hbm_probe()
+    log(f"HBM copy probe: {probe_gbs:.0f} GB/s")
     line = {
         "metric": METRIC, "value": r["rays_per_s"], "unit": "rays/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
@@ -448,9 +491,14 @@ def main():
                    "n_rays": int(rays.shape[0])},
         "tests_per_ray": r["tests_per_ray"],
         "roofline": {"bound": "hbm", "achieved": r["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r["alg_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(head, args.workload),
+                     "frac": r["alg_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "trace_kernel", "kernel_ms": r["kernel_ms_mean"], "launch_shape": r["tune"],
-                     "alg_bytes_per_launch": r["alg_bytes_per_launch"]},
+                     "alg_bytes_per_launch": r["alg_bytes_per_launch"],
+                     "alg_bytes_per_ray": r["alg_bytes_per_launch"] / n_rays,
+                     "roofline_rays_per_s": HBM_PEAK_GBS * 1e9 / (r["alg_bytes_per_launch"] / n_rays),
+                     "traffic_gbs": (traffic / (r["kernel_ms_mean"] * 1e-3) / 1e9) if traffic else None,
+                     "traffic_bytes_per_ray": (traffic / n_rays) if traffic else None,
+                     "hbm_probe_gbs": probe_gbs},
         "modes": results,
         "tune": r["tune"],
     }
