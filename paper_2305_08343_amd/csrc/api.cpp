@@ -121,6 +121,8 @@ sc_status ensure_lut(sc_ctx* ctx, uint32_t R, hipStream_t s) {
     }
     hipError_t e = launch_raymask_patterns(R, pat, s);
     if (e == hipSuccess) e = launch_raymask_lut(R, pat, lut, s);
+    // finished before the tables are published: a trace on another stream may use them next
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipStreamSynchronize(s);
         dev_free(ctx, pat, pattern_bytes(R), s);

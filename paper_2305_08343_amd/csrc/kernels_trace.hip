@@ -591,17 +591,20 @@ void trace_kernel(TraceLaunch a) {
 
 template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH, int WIDTH>
 hipError_t launch_one(const TraceLaunch& a, hipStream_t s) {
-    // blocks per CU that fit, and CUs, computed once per instance
-    static int per_cu = 0, cus = 0;
-    if (per_cu == 0) {
+    // blocks per CU that fit, and CUs: queried once per instance (on the device current at
+    // the first launch; every GPU of an MI355X node is the same part), thread-safe
+    struct Occupancy {
+        int per_cu, cus;
+    };
+    static const Occupancy occ = [] {
         int dev = 0, c = 0, p = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, trace_kernel<MODE, R, BLOCK, STACK, BATCH, WIDTH>,
                                                            BLOCK, 0);
-        cus = c > 0 ? c : 256;
-        per_cu = p > 0 ? p : 4;
-    }
+        return Occupancy{p > 0 ? p : 4, c > 0 ? c : 256};
+    }();
+    const int per_cu = occ.per_cu, cus = occ.cus;
     uint32_t blocks_per_cu = (uint32_t)per_cu;
     if (a.waves > 0) {
         // 4 SIMDs per CU: waves per SIMD * 4 / waves per block, at least one block
