@@ -1,0 +1,60 @@
+"""Two host threads on one fresh context: each builds a scene (the first use
+builds the context's ray-mask tables) and traces it three times on its own
+stream, one the binary BVH and one the 4-wide BVH, at the same time. Every
+result must equal the oracle's: the shared tables are complete before any
+stream uses them, and the launcher's per-kernel occupancy cache is filled
+once for both threads."""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _same(d, o):
+    return bool((d["prim"] == o.prim).all() and (d["t"].view(np.uint32) == o.t.view(np.uint32)).all()
+                and (d["box_tests"] == o.box_tests).all() and (d["tri_tests"] == o.tri_tests).all()
+                and (d["mask_tests"] == o.mask_tests).all() and (d["mask_culls"] == o.mask_culls).all())
+
+
+@pytest.mark.timeout(300)
+def test_two_threads_two_streams_one_fresh_context():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2305_08343_amd import binding, scenes
+    tris = scenes.scene_small(0)
+    rays = scenes.rays_small(128)
+    ctx = binding.Context(0)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    results, errors = [None, None], []
+
+    def work(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                sc = binding.Scene(ctx, tris, R=6, mode="raw", width=2 if i == 0 else 4, stream=streams[i])
+                rd = torch.from_numpy(rays).cuda()
+                outs = [sc.trace(rd, stream=streams[i]) for _ in range(3)]
+                streams[i].synchronize()
+                results[i] = [o.numpy() for o in outs]
+                sc.close()
+        except Exception as e:  # reported below, on the main thread
+            errors.append(repr(e))
+
+    print("[gpu-conc] two threads, two streams, one context", flush=True)
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    ctx.close()
+    assert not errors, errors
+    bvh = oracle.bvh_build(tris)
+    ob, delta = oracle.default_bounds(tris)
+    masks = oracle.object_masks(tris, bvh, 6, delta)
+    ora2 = oracle.trace(tris, bvh, rays, mode="raw", R=6, masks=masks, origin_bound=ob)
+    ora4 = oracle.trace4(tris, bvh, oracle.bvh4_collapse(bvh), rays, mode="raw", R=6, masks=masks, origin_bound=ob)
+    assert all(_same(d, ora2) for d in results[0])
+    assert all(_same(d, ora4) for d in results[1])
