@@ -420,7 +420,17 @@ void trace_kernel(TraceLaunch a) {
                 const float4 nx = np4[3 * sx], ny = np4[1 + 3 * sy], nz = np4[2 + 3 * sz];
                 const float4 fx = np4[3 - 3 * sx], fy = np4[4 - 3 * sy], fz = np4[5 - 3 * sz];
                 const uint4 cr = reinterpret_cast<const uint4*>(np4)[6];
-                const uint4 ax = reinterpret_cast<const uint4*>(np4)[7];
+                // aux words at byte 112: only as many as the mode reads (raw: the full-mask
+                // flags; LUT: four 16-bit codebook indices). Every lane's load touches its own
+                // node line, so the address path pays for each byte: load no more than needed.
+                uint32_t ax0 = 0u, ax1 = 0u;
+                if constexpr (MODE == kModeRaw) {
+                    ax0 = reinterpret_cast<const uint32_t*>(np4)[28];
+                } else if constexpr (MODE != kModeNone) {
+                    const uint2 a2 = reinterpret_cast<const uint2*>(np4)[14];
+                    ax0 = a2.x;
+                    ax1 = a2.y;
+                }
                 const float cnx[4] = {nx.x, nx.y, nx.z, nx.w}, cny[4] = {ny.x, ny.y, ny.z, ny.w};
                 const float cnz[4] = {nz.x, nz.y, nz.z, nz.w}, cfx[4] = {fx.x, fx.y, fx.z, fx.w};
                 const float cfy[4] = {fy.x, fy.y, fy.z, fy.w}, cfz[4] = {fz.x, fz.y, fz.z, fz.w};
@@ -451,10 +461,10 @@ void trace_kernel(TraceLaunch a) {
                             bool test;
                             uint32_t idx = 0;
                             if constexpr (MODE == kModeRaw) {
-                                test = !((ax.x >> c) & 1u);
+                                test = !((ax0 >> c) & 1u);
                                 om = s_side + ((size_t)ref * 4 + c) * W;
                             } else {
-                                idx = ((c < 2 ? ax.x : ax.y) >> (16 * (c & 1))) & 0xFFFFu;
+                                idx = ((c < 2 ? ax0 : ax1) >> (16 * (c & 1))) & 0xFFFFu;
                                 test = idx < s_full;
                                 if constexpr (MODE == kModeLutLds) om = lds_cb + (test ? idx : 0u) * W;
                                 if constexpr (MODE == kModeLut) om = s_codebook + (size_t)idx * W;
