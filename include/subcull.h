@@ -90,7 +90,8 @@ typedef struct {
     uint32_t placement_len; /* length of mask_placement                            */
     uint32_t width;         /* 2: binary BVH; 4: 4-wide BVH collapsed from it, each
                                node with four child boxes and four child masks
-                               (Sect. 3.2.4); modes NONE, RAW, LUT (default 2)    */
+                               (Sect. 3.2.4); modes NONE, RAW, LUT; at most
+                               2^28-1 triangles (default 2)                       */
     uint32_t approx_levels; /* 0: exact masks from every triangle below (L = inf);
                                L in 1..64: approximate masks of Sect. 3.2.1 /
                                Alg. 2 -- triangles of leaves at most L levels

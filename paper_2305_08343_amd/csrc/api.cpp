@@ -232,6 +232,8 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
     if (n >= (1u << 29)) return fail(SC_ERR_INVALID_ARG, "at most 2^29-1 triangles");
     std::string why;
     if (!check_params(*params, why)) return fail(SC_ERR_INVALID_ARG, why);
+    if (params->width == 4 && n >= kRef4Full)
+        return fail(SC_ERR_INVALID_ARG, "4-wide scenes hold at most 2^28-1 triangles");
     sc_status st = use_device(ctx->device);
     if (st != SC_OK) return st;
     const hipStream_t s = static_cast<hipStream_t>(stream);

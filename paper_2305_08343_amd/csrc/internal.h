@@ -59,6 +59,11 @@ struct HostBVH4 {
 };
 void collapse_bvh4(const HostBVH& B, HostBVH4& out);
 constexpr uint32_t kNode4Bytes = 128;  // SoA boxes (96 B), refs (16 B), aux (16 B)
+// 4-wide RAW nodes: bit 28 of a child's ref marks a full mask, so the traversal reads
+// the flags with the refs and needs no aux load. Leaf first-triangle and node indices
+// of 4-wide scenes stay below 2^28 (checked at build); the traversal clears the bit
+// before it uses a ref.
+constexpr uint32_t kRef4Full = 1u << 28;
 constexpr uint32_t kMaxStack4 = 128;   // traversal stack entries per ray for the 4-wide BVH
 
 // Binned SAH build; returns SC_OK, SC_ERR_DEPTH or SC_ERR_OOM.

@@ -449,7 +449,8 @@ __global__ void pack_lut_kernel(const uint16_t* __restrict__ idx, uint32_t n_inn
 }
 
 // 4-wide node m, child c from binary slot src4[4m + c]: the raw mask goes to
-// masks4[4m + c] and bit c of aux word 0 (byte 112) marks a full mask; a
+// masks4[4m + c] and bit c of aux word 0 (byte 112) and bit 28 of the child's ref
+// mark a full mask; a
 // codebook index goes to the 16-bit aux entry c.
 template <int R>
 __global__ void pack4_kernel(uint32_t mode, const uint32_t* __restrict__ src4, uint32_t n4,
@@ -479,6 +480,12 @@ __global__ void pack4_kernel(uint32_t mode, const uint32_t* __restrict__ src4, u
     }
     aux[0] = (mode == SC_MASK_RAW) ? full : idx01;
     aux[1] = (mode == SC_MASK_RAW) ? 0u : idx23;
+    if (mode == SC_MASK_RAW) {
+        // the full flags again in the refs (bit 28), where the traversal reads them
+        uint32_t* refs = reinterpret_cast<uint32_t*>(nodes4 + m * kNode4Bytes + 96);
+        for (int c = 0; c < 4; ++c)
+            if (((full >> c) & 1u) && refs[c] != kEmptyRef) refs[c] |= kRef4Full;
+    }
 }
 
 // 2-D bit table (Sect. 3.2.2): one thread per (ray-mask key, 32 codebook entries).

@@ -420,13 +420,11 @@ void trace_kernel(TraceLaunch a) {
                 const float4 nx = np4[3 * sx], ny = np4[1 + 3 * sy], nz = np4[2 + 3 * sz];
                 const float4 fx = np4[3 - 3 * sx], fy = np4[4 - 3 * sy], fz = np4[5 - 3 * sz];
                 const uint4 cr = reinterpret_cast<const uint4*>(np4)[6];
-                // aux words at byte 112: only as many as the mode reads (raw: the full-mask
-                // flags; LUT: four 16-bit codebook indices). Every lane's load touches its own
-                // node line, so the address path pays for each byte: load no more than needed.
+                // aux words at byte 112, for the LUT modes' four 16-bit codebook indices; raw
+                // nodes keep their full-mask flags in bit 28 of the refs, so they load one line
+                // piece less per visit (each lane's load costs the address path a line access)
                 uint32_t ax0 = 0u, ax1 = 0u;
-                if constexpr (MODE == kModeRaw) {
-                    ax0 = reinterpret_cast<const uint32_t*>(np4)[28];
-                } else if constexpr (MODE != kModeNone) {
+                if constexpr (MODE != kModeNone && MODE != kModeRaw) {  // raw: flags in the refs
                     const uint2 a2 = reinterpret_cast<const uint2*>(np4)[14];
                     ax0 = a2.x;
                     ax1 = a2.y;
@@ -446,7 +444,7 @@ void trace_kernel(TraceLaunch a) {
                 for (int c = 0; c < 4; ++c) {
                     key[c] = __builtin_inff();
                     kid[c] = 4u + (uint32_t)c;
-                    kref[c] = crf[c];
+                    kref[c] = (crf[c] == kEmptyRef) ? kEmptyRef : (crf[c] & ~kRef4Full);
                     bool keep = false;
                     float t0 = 0.0f, t1 = 0.0f;
                     const float nr[3] = {cnx[c], cny[c], cnz[c]}, fr[3] = {cfx[c], cfy[c], cfz[c]};
@@ -461,7 +459,7 @@ void trace_kernel(TraceLaunch a) {
                             bool test;
                             uint32_t idx = 0;
                             if constexpr (MODE == kModeRaw) {
-                                test = !((ax0 >> c) & 1u);
+                                test = !(crf[c] & kRef4Full);
                                 om = s_side + ((size_t)ref * 4 + c) * W;
                             } else {
                                 idx = ((c < 2 ? ax0 : ax1) >> (16 * (c & 1))) & 0xFFFFu;

@@ -116,6 +116,22 @@ def test_micro_scenes(ctx, seed):
         s.close()
 
 
+def test_too_many_triangles_for_4_wide_rejected_before_any_read(ctx):
+    import ctypes as C
+    import torch
+    from paper_2305_08343_amd import binding
+    print("[gpu-bvh4] 2^28 triangles rejected", flush=True)
+    lib = binding.load()
+    p = binding.sc_build_params()
+    lib.sc_build_params_default(C.byref(p))
+    p.width = 4
+    dummy = torch.zeros(9, dtype=torch.float32, device="cuda:0")  # never read: the count is checked first
+    h = C.c_void_p()
+    assert lib.sc_scene_build(ctx.handle, C.c_void_p(dummy.data_ptr()), 1 << 28, C.byref(p), None,
+                              C.byref(h)) == 1
+    assert b"2^28" in lib.sc_last_error() and not h.value
+
+
 def test_degenerate_inputs(ctx, small_scene):
     from paper_2305_08343_amd import binding
     print("[gpu-bvh4] empty scene, single leaf, invalid rays", flush=True)
