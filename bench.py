@@ -8,13 +8,14 @@ surface ray per pixel). One step = one trace of the whole ray batch, rays
 and scene resident in HBM. The headline value is the 216-bit (R = 6) raw-mask
 culled trace on the 4-wide BVH (Sect. 3.2.4 node: four child boxes and
 masks); the plain traversal (4-wide and binary), the binary culled trace and
-64-bit (R = 4) masks are timed beside it. Each mode's launch shape is the one
+64-bit (R = 4) masks are timed beside it, and raw6w4l: the same masks kept only
+on leaf children's slots (inner children carry the untested full mask). Each mode's launch shape is the one
 the autotuner picked for it on this workload (stored in MODES; --autotune
 re-runs the tuner, --sort switches Morton ray ordering); results never depend
 on it. Other workloads: curly_12m (12M curly diagonal strands, 8M incoherent
 bounce rays, LUT-compressed masks), batch64, placement, approx.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes raw6w4,nonew4,none,raw6,raw4w4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes raw6w4,raw6w4l,nonew4,none,raw6,raw4w4]
                     [--no-cpu-baseline] [--cpu-seconds S] [--autotune | --tune b,s,c,p,w,o,q,g,f]
                     [--workload hair_1m|curly_12m|batch64|placement|approx] [--sort stored|0|1]
 """
@@ -48,6 +49,8 @@ TRACE_SOURCE = os.path.join(ROOT, "paper_2305_08343_amd", "csrc", "kernels_trace
 MODES = {
     "raw6w4": dict(mode="raw", R=6, cull=True, width=4, mask_bytes=32, tune=(256, 12, 1, 8, 6, 0, 0, 12, 12)),
     "raw4w4": dict(mode="raw", R=4, cull=True, width=4, mask_bytes=8, tune=(256, 12, 1, 8, 6, 0, 0, 12, 8)),
+    "raw6w4l": dict(mode="raw", R=6, cull=True, width=4, mask_bytes=32, mask_slots="leaves", tune=(256, 12, 1, 8, 6, 0, 0, 12, 12)),
+    "raw4w4l": dict(mode="raw", R=4, cull=True, width=4, mask_bytes=8, mask_slots="leaves", tune=(256, 12, 1, 8, 6, 0, 0, 12, 8)),
     "nonew4": dict(mode="none", R=6, cull=False, width=4, mask_bytes=0, tune=(128, 16, 1, 8, 6, 1, 0, 20, 20)),
     "lut6w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, tune=(256, 12, 1, 8, 6, 0)),
     "lut4k256w4": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 0, 0)),
@@ -121,7 +124,7 @@ def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup, autotune=False, wo
     from paper_2305_08343_amd import binding, tune
     t0 = time.perf_counter()
     scene = binding.Scene(ctx, tris, R=spec["R"], mode=spec["mode"], K=spec.get("K", 4096), width=spec["width"],
-                          bit_table=spec.get("bit_table", False))
+                          bit_table=spec.get("bit_table", False), mask_slots=spec.get("mask_slots", "all"))
     build_s = time.perf_counter() - t0
     n = rays_dev.shape[0]
     hits = torch.empty((n, 4), dtype=torch.int32, device=rays_dev.device)
@@ -387,7 +390,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="raw6w4,nonew4,none,raw6,raw4w4")
+    ap.add_argument("--modes", default="raw6w4,raw6w4l,nonew4,none,raw6,raw4w4")
     ap.add_argument("--autotune", action="store_true",
                     help="pick each mode's launch shape live with the autotuner instead of the stored one")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -105,6 +105,12 @@ typedef struct {
                                entry k is nonzero; R^6 * K / 8 bytes) and single
                                scene traces test a compressed mask with one bit
                                of it; results are unchanged (default 0)           */
+    uint32_t mask_slots;    /* which child slots keep a testable mask: 0 = every
+                               slot (default, as in the paper), 1 = only slots
+                               whose child is a leaf -- slots of inner children
+                               get the full mask, which is never tested, so the
+                               traversal tests masks where a cull saves
+                               triangle tests (results unchanged)                */
 } sc_build_params;
 
 typedef struct {

@@ -81,6 +81,22 @@ class BVH:
         return self.cbox.reshape(-1, 6)
 
 
+def leaf_slot_masks(masks: np.ndarray, bvh: "BVH", R: int) -> np.ndarray:
+    """Masks kept only on the child slots whose child is a leaf: the slot of an
+    inner child gets the full mask (all R^3 bits), which traversal never tests
+    (a full mask always meets the ray mask). The same result as tracing with
+    masks on leaf slots only."""
+    W = words_for(R)
+    out = np.array(masks, dtype=np.uint64, copy=True).reshape(-1, W)
+    full = np.zeros(W, np.uint64)
+    for w in range(W):
+        bits = R ** 3 - 64 * w
+        full[w] = np.uint64(0xFFFFFFFFFFFFFFFF) if bits >= 64 else np.uint64((1 << bits) - 1)
+    inner = (bvh.cref.reshape(-1) & np.uint32(0x80000000)) == 0
+    out[inner] = full
+    return out.reshape(np.shape(masks))
+
+
 def bvh_build(tris: np.ndarray, leaf_max: int = 4, bins: int = 32, depth_cap: int = 64) -> BVH:
     tris = np.ascontiguousarray(tris, np.float32)
     n = tris.shape[0]

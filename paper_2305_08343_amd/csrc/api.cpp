@@ -147,6 +147,7 @@ bool check_params(const sc_build_params& p, std::string& why) {
     if (p.mode == SC_MASK_SPARSE && !p.mask_placement) { why = "SPARSE needs mask_placement"; return false; }
     if (p.width != 2 && p.width != 4) { why = "width must be 2 or 4"; return false; }
     if (p.approx_levels > 64) { why = "approx_levels must be 0..64"; return false; }
+    if (p.mask_slots > 1) { why = "mask_slots must be 0 or 1"; return false; }
     if (p.bit_table > 1 || (p.bit_table && p.mode != SC_MASK_LUT)) { why = "bit_table needs LUT mode"; return false; }
     if (p.width == 4 && p.mode == SC_MASK_SPARSE) { why = "SPARSE needs width 2"; return false; }
     if (!std::isfinite(p.delta) || !std::isfinite(p.origin_bound)) { why = "non-finite delta/origin_bound"; return false; }
@@ -412,6 +413,8 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
             dev_free(ctx, d_cbox, B.cbox.size() * 4, s);
             dev_free(ctx, d_cref, B.cref.size() * 4, s);
         }
+        if (e == hipSuccess && P.mask_slots == 1)  // masks only where the child is a leaf
+            e = launch_full_inner_slots(R, sc->nodes, stride, B.n_inner, sc->masks, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         dev_free(ctx, d_perm, (size_t)n * 4, s);
         dev_free(ctx, d_range, B.range.size() * 4, s);

@@ -145,6 +145,9 @@ hipError_t launch_object_masks(uint32_t R, const float* tris_orig, const uint32_
                                const unsigned char* nodes, uint32_t node_stride,
                                const uint32_t* range, uint32_t root, float delta, uint32_t levels,
                                uint64_t* masks, hipStream_t s);
+// every slot whose child (ref at node bytes 48 + 4c) is an inner node gets the full mask
+hipError_t launch_full_inner_slots(uint32_t R, const unsigned char* nodes, uint32_t stride, uint32_t n_inner,
+                                   uint64_t* masks, hipStream_t s);
 // approximation, fill part (Alg. 2) for the given slots of one depth; deeper depths first
 hipError_t launch_approx_fill(uint32_t R, const uint32_t* slots, uint32_t count, const float* cbox,
                               const uint32_t* cref, uint32_t levels, float delta, uint64_t* masks, hipStream_t s);

@@ -514,6 +514,22 @@ __global__ __launch_bounds__(256) void bit_table_kernel(const uint64_t* __restri
     out[gid] = word;
 }
 
+// Slot s = 2*node + c keeps its mask only when child c is a leaf; an inner child's
+// slot gets the full mask (all R^3 bits), which no traversal tests.
+template <int R>
+__global__ void full_inner_slots_kernel(const unsigned char* __restrict__ nodes, uint32_t stride, uint32_t n_inner,
+                                        uint64_t* __restrict__ masks) {
+    constexpr int W = (R * R * R + 63) / 64;
+    const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= 2 * (size_t)n_inner) return;
+    const uint32_t ref = reinterpret_cast<const uint32_t*>(nodes + (s >> 1) * stride + 48)[s & 1];
+    if ((ref & kLeafBit) || ref == kEmptyRef) return;
+    for (int w = 0; w < W; ++w) {
+        const int bits = R * R * R - 64 * w;
+        masks[s * W + w] = bits >= 64 ? ~0ull : ((1ull << bits) - 1ull);
+    }
+}
+
 inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -590,6 +606,21 @@ hipError_t launch_pack_raw(uint32_t R, const uint64_t* masks, uint32_t n_inner, 
     if (R == 4) hipLaunchKernelGGL(pack_raw_kernel<4>, dim3(blocks_for(n_inner, 256)), dim3(256), 0, s, masks, n_inner, nodes);
     else if (R == 6) hipLaunchKernelGGL(pack_raw_kernel<6>, dim3(blocks_for(n_inner, 256)), dim3(256), 0, s, masks, n_inner, nodes);
     else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_full_inner_slots(uint32_t R, const unsigned char* nodes, uint32_t stride, uint32_t n_inner,
+                                   uint64_t* masks, hipStream_t s) {
+    if (n_inner == 0) return hipSuccess;
+    const size_t S = 2 * (size_t)n_inner;
+    if (R == 4)
+        hipLaunchKernelGGL(full_inner_slots_kernel<4>, dim3(blocks_for(S, 256)), dim3(256), 0, s, nodes, stride,
+                           n_inner, masks);
+    else if (R == 6)
+        hipLaunchKernelGGL(full_inner_slots_kernel<6>, dim3(blocks_for(S, 256)), dim3(256), 0, s, nodes, stride,
+                           n_inner, masks);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
