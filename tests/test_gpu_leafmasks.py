@@ -53,3 +53,23 @@ def test_bad_mask_slots_rejected(ctx, small_scene):
     from paper_2305_08343_amd import binding
     with pytest.raises(ValueError):
         binding.Scene(ctx, small_scene[0], mask_slots="inner")
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_leaf_slot_masks_micro_scenes(ctx, seed):
+    from paper_2305_08343_amd import binding, scenes
+    n = 1 + (seed * 13) % 64
+    tris = scenes.micro_scene(seed, n)
+    rays = np.concatenate([_aimed(tris, 300, seed), scenes.random_rays(100, seed)])
+    bvh = oracle.bvh_build(tris)
+    b4 = oracle.bvh4_collapse(bvh)
+    ob, delta = oracle.default_bounds(tris)
+    print(f"[gpu-leaf] micro scene {seed} ({n} tris)", flush=True)
+    for R in (4, 6):
+        lm = oracle.leaf_slot_masks(oracle.object_masks(tris, bvh, R, delta), bvh, R)
+        for width in (2, 4):
+            s = binding.Scene(ctx, tris, R=R, mode="raw", width=width, mask_slots="leaves")
+            ora = (oracle.trace(tris, bvh, rays, mode="raw", R=R, masks=lm, origin_bound=ob) if width == 2 else
+                   oracle.trace4(tris, bvh, b4, rays, mode="raw", R=R, masks=lm, origin_bound=ob))
+            _compare(s.trace(rays).numpy(), ora)
+            s.close()
