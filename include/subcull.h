@@ -278,8 +278,8 @@ sc_status sc_ray_order(const sc_scene* scene, const float* d_rays, uint32_t n, u
  * sc_batch_create calls on this context (default 256, 8, 1, 8, 0, 0, 0, 16,
  * 16). Errors: SC_ERR_INVALID_ARG (NULL pointer, a field out of its range),
  * SC_ERR_UNSUPPORTED (an uncompiled (block, stack) pair); the context keeps
- * its previous shape on error. sc_get_tune copies the current shape. Not
- * synchronised with traces already queued: set it between calls. */
+ * its previous shape on error. sc_get_tune copies the current shape. The
+ * shape is read when a trace is issued: traces already queued keep theirs. */
 sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune);
 sc_status sc_get_tune(const sc_ctx* ctx, sc_tune* out);
 
