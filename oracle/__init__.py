@@ -276,6 +276,53 @@ def bvh4_collapse(bvh: BVH) -> BVH4:
     return BVH4(box4[:k].copy(), ref4[:k].copy(), src4[:k].copy(), root4.value, bvh.depth)
 
 
+@dataclass
+class Quant4:
+    """Quantised child boxes of a 4-wide BVH (orc_quantise4): per node the
+    minimum corner lo [n4, 3] of its used children, the biased exponents
+    ebias [n4, 3] (scale 2^(ebias - 127) per axis), the 8-bit planes
+    q [n4, 4, 6] (qlo xyz, qhi xyz per child) and the decoded boxes
+    dec [n4, 4, 6], laid out as BVH4.box4."""
+    lo: np.ndarray
+    ebias: np.ndarray
+    q: np.ndarray
+    dec: np.ndarray
+
+
+def quantise4(bvh4: BVH4) -> Quant4:
+    """Child boxes of every 4-wide node as 8-bit offsets from the node's minimum
+    corner in steps of a power of two per axis, rounded outward (the child-box
+    compression of compressed wide BVHs; not part of the paper)."""
+    m = max(bvh4.n4, 1)
+    lo = np.zeros((m, 3), np.float32)
+    eb = np.zeros((m, 3), np.uint8)
+    q = np.zeros((m, 4, 6), np.uint8)
+    dec = np.zeros((m, 4, 6), np.float32)
+    if bvh4.n4:
+        _check(lib().orc_quantise4(_p(np.ascontiguousarray(bvh4.box4, np.float32)),
+                                   _p(np.ascontiguousarray(bvh4.ref4, np.uint32)), C.c_uint32(bvh4.n4),
+                                   _p(lo), _p(eb), _p(q), _p(dec)), "quantise4")
+    k = bvh4.n4
+    return Quant4(lo[:k].copy(), eb[:k].copy(), q[:k].copy(), dec[:k].copy())
+
+
+def decoded_bvh4(bvh4: BVH4, qt: Quant4) -> BVH4:
+    """The 4-wide BVH with every child box replaced by its decoded box."""
+    return BVH4(qt.dec.copy(), bvh4.ref4.copy(), bvh4.src4.copy(), bvh4.root, bvh4.depth)
+
+
+def with_slot_boxes(bvh: BVH, bvh4: BVH4) -> BVH:
+    """A copy of the binary BVH whose child slots that a 4-wide node uses carry
+    that node's box for the child (the decoded box, for a decoded BVH4); masks,
+    approximate masks and codebook importances built on it then belong to the
+    boxes the 4-wide traversal tests. Slots no 4-wide node uses keep theirs."""
+    cbox = bvh.cbox.copy().reshape(-1, 6)
+    used = bvh4.ref4 != EMPTY_REF
+    cbox[bvh4.src4[used]] = bvh4.box4[used]
+    return BVH(bvh.n_inner, bvh.root, bvh.depth, cbox.reshape(bvh.cbox.shape), bvh.cref.copy(),
+               bvh.range.copy(), bvh.perm.copy())
+
+
 def trace4(tris, bvh: BVH, bvh4: BVH4, rays, *, mode="none", R=6, masks=None, codebook=None, cidx=None,
            placed=None, lut=None, origin_bound=None, cull=True, shadow=False, nthreads=0) -> Hits:
     """Alg. 4 on the 4-wide BVH; masks, codebook indices and shadow counts are

@@ -988,6 +988,70 @@ int orc_bvh4_collapse(const float* cbox, const uint32_t* cref, uint32_t n_inner,
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------
+ * Quantised 4-wide child boxes (not in the paper: the child-box compression of
+ * compressed wide BVHs, applied to the 4-wide nodes above). Per node m and
+ * axis a, over the used children only:
+ *   lo_a  = min of the children's minima, hi_a = max of their maxima;
+ *   e_a   = the smallest integer in [-126, 127] with 255 * 2^e_a >= hi_a - lo_a
+ *           (the difference taken exactly, in double);
+ *   qlo   = floor((child min - lo_a) / 2^e_a), qhi = ceil((child max - lo_a) / 2^e_a),
+ *           both in [0, 255];
+ *   decoded plane = float32(lo_a + float32(q * 2^e_a)).
+ * q * 2^e_a is exact in float32 (8 significant bits, a normal power of two),
+ * and rounding the sum to nearest is monotone with the exact child plane a
+ * float on the right side of it, so every decoded box contains its child's
+ * box. Unused slots get q = 0 and a zero decoded box. Outputs: lo[3m + a],
+ * ebias[3m + a] = e_a + 127, q[24m + 6c + j] (qlo xyz, qhi xyz), dec in the
+ * layout of box4.
+ * ---------------------------------------------------------------------- */
+static int quant_exponent(double ext) {
+    int e = -126;
+    while (e < 127 && 255.0 * ldexp(1.0, e) < ext) ++e;
+    return e;
+}
+
+int orc_quantise4(const float* box4, const uint32_t* ref4, uint32_t n4, float* lo, uint8_t* ebias,
+                  uint8_t* q, float* dec) {
+    for (uint32_t m = 0; m < n4; ++m) {
+        for (int a = 0; a < 3; ++a) {
+            float l = INFINITY, h = -INFINITY;
+            for (int c = 0; c < 4; ++c) {
+                if (ref4[4 * (size_t)m + c] == EMPTY_REF) continue;
+                const float* b = &box4[24 * (size_t)m + 6 * (size_t)c];
+                if (b[a] < l) l = b[a];
+                if (b[3 + a] > h) h = b[3 + a];
+            }
+            if (l > h) { l = 0.0f; h = 0.0f; }  /* no used child */
+            const int e = quant_exponent((double)h - (double)l);
+            const double step = ldexp(1.0, e);
+            const float stepf = (float)step;
+            lo[3 * (size_t)m + a] = l;
+            ebias[3 * (size_t)m + a] = (uint8_t)(e + 127);
+            for (int c = 0; c < 4; ++c) {
+                const size_t k = 24 * (size_t)m + 6 * (size_t)c;
+                if (ref4[4 * (size_t)m + c] == EMPTY_REF) {
+                    q[k + a] = 0; q[k + 3 + a] = 0;
+                    dec[k + a] = 0.0f; dec[k + 3 + a] = 0.0f;
+                    continue;
+                }
+                double ql = floor(((double)box4[k + a] - (double)l) / step);
+                double qh = ceil(((double)box4[k + 3 + a] - (double)l) / step);
+                if (ql < 0.0) ql = 0.0;
+                if (ql > 255.0) ql = 255.0;
+                if (qh < 0.0) qh = 0.0;
+                if (qh > 255.0) qh = 255.0;
+                q[k + a] = (uint8_t)ql;
+                q[k + 3 + a] = (uint8_t)qh;
+                const float pl = (float)q[k + a] * stepf, ph = (float)q[k + 3 + a] * stepf;
+                dec[k + a] = l + pl;
+                dec[k + 3 + a] = l + ph;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
 typedef struct {
     TraceCtx base;
     const float* box4; const uint32_t* ref4; const uint32_t* src4;

@@ -1,0 +1,149 @@
+"""Pins of the oracle's quantised 4-wide child boxes.
+
+The quantisation is a layout choice, not part of the paper: each 4-wide node
+(the node of Sect. 3.2.4 with four child boxes) stores the minimum corner of
+its children, one power-of-two step per axis and every child plane as an 8-bit
+count of steps, rounded outward. What fixes it independently of the oracle's
+own code:
+  * a hand-worked node whose exponents, counts and decoded planes follow from
+    the definition by arithmetic done on paper (below);
+  * for every node of real collapses: each decoded box contains the exact
+    child box (the property the traversal relies on), each decoded plane lies
+    within one step (and the final rounding) of the exact one, the exponent is
+    the smallest whose 255 steps cover the extent, and the corner is an exact
+    child plane;
+  * Alg. 4 over the decoded boxes, plain and with masks built on the decoded
+    boxes, returns the brute-force closest hit (closest hit and ties as in the
+    binary traversal).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_08343_amd import scenes
+from tests.test_oracle_trace import _aimed_rays
+
+EMPTY = oracle.EMPTY_REF
+LEAF = oracle.LEAF_BIT
+
+
+def _hand_node():
+    box4 = np.zeros((1, 4, 6), np.float32)
+    box4[0, 0] = [0.1, -2.0, 5.0, 0.7, -1.0, 5.0]
+    box4[0, 1] = [0.0, -1.5, 5.0, 1.0, 3.0, 5.0]
+    ref4 = np.array([[LEAF | 0, LEAF | 1, EMPTY, EMPTY]], np.uint32)
+    src4 = np.array([[0, 1, EMPTY, EMPTY]], np.uint32)
+    return oracle.BVH4(box4, ref4, src4, 0, 1)
+
+
+def test_hand_worked_node():
+    # x: corner 0, extent 1: 255 * 2^-8 < 1 <= 255 * 2^-7, so the step is 2^-7 (bias 120).
+    #    float32(0.1) / 2^-7 = 12.8000002 -> 12 -> 0.09375; float32(0.7) / 2^-7 = 89.5999985 -> 90
+    #    -> 0.703125; child 1: 0 and 1 / 2^-7 = 128 exactly.
+    # y: corner -2, extent 5: 255 * 2^-6 < 5 <= 255 * 2^-5, step 2^-5 (bias 122); offsets 0, 1, 0.5
+    #    and 5 are whole steps (0, 32, 16, 160), so the planes decode exactly.
+    # z: extent 0: the smallest exponent, -126 (bias 1), every count 0.
+    qt = oracle.quantise4(_hand_node())
+    assert qt.lo.tolist() == [[0.0, -2.0, 5.0]]
+    assert qt.ebias.tolist() == [[120, 122, 1]]
+    assert qt.q[0, 0].tolist() == [12, 0, 0, 90, 32, 0]
+    assert qt.q[0, 1].tolist() == [0, 16, 0, 128, 160, 0]
+    assert (qt.q[0, 2:] == 0).all() and (qt.dec[0, 2:] == 0).all()
+    assert qt.dec[0, 0].tolist() == [0.09375, -2.0, 5.0, 0.703125, -1.0, 5.0]
+    assert qt.dec[0, 1].tolist() == [0.0, -1.5, 5.0, 1.0, 3.0, 5.0]
+
+
+def _check_quant(b4, qt):
+    used = b4.ref4 != EMPTY
+    ex = b4.box4.astype(np.float64)
+    dec = qt.dec.astype(np.float64)
+    e = qt.ebias.astype(np.int64) - 127
+    step = np.ldexp(1.0, e)                                    # [n4, 3]
+    assert (qt.ebias >= 1).all()
+    for m in range(b4.n4):
+        u = used[m]
+        lo = ex[m, u, :3].min(0)
+        hi = ex[m, u, 3:].max(0)
+        assert (qt.lo[m].astype(np.float64) == lo).all()       # the corner is an exact child plane
+        ext = hi - lo
+        assert (255.0 * step[m] >= ext).all()
+        assert ((e[m] == -126) | (255.0 * step[m] / 2 < ext)).all()   # smallest such exponent
+        # containment, plane by plane
+        assert (dec[m, u, :3] <= ex[m, u, :3]).all() and (dec[m, u, 3:] >= ex[m, u, 3:]).all()
+        # within one step plus the float32 rounding of the decoded sum
+        ulp = np.spacing(np.maximum(np.abs(ex[m, u]), np.abs(dec[m, u])).astype(np.float32)).astype(np.float64)
+        st = np.concatenate([step[m], step[m]])[None, :]
+        assert (np.abs(dec[m, u] - ex[m, u]) <= st + ulp).all()
+        assert (qt.q[m, u, :3] <= qt.q[m, u, 3:]).all()
+        assert (qt.q[m, ~u] == 0).all() and (qt.dec[m, ~u] == 0).all()
+
+
+def test_quantised_boxes_small_scene(small_scene, small_oracle):
+    b4 = oracle.bvh4_collapse(small_oracle["bvh"])
+    qt = oracle.quantise4(b4)
+    _check_quant(b4, qt)
+    # the boxes really are coarsened somewhere (the test would be vacuous otherwise)
+    used = b4.ref4 != EMPTY
+    assert (qt.dec[used] != b4.box4[used]).mean() > 0.3
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_quantised_boxes_micro_scenes(seed):
+    tris = scenes.micro_scene(seed, 1 + (seed * 11) % 64)
+    b4 = oracle.bvh4_collapse(oracle.bvh_build(tris))
+    _check_quant(b4, oracle.quantise4(b4))
+
+
+def test_with_slot_boxes_replaces_only_used_slots(small_oracle):
+    bvh = small_oracle["bvh"]
+    b4 = oracle.bvh4_collapse(bvh)
+    d4 = oracle.decoded_bvh4(b4, oracle.quantise4(b4))
+    bq = oracle.with_slot_boxes(bvh, d4)
+    slots = bq.cbox.reshape(-1, 6)
+    orig = bvh.cbox.reshape(-1, 6)
+    used = d4.ref4 != EMPTY
+    s = d4.src4[used]
+    assert (slots[s].view(np.uint32) == d4.box4[used].view(np.uint32)).all()
+    rest = np.setdiff1d(np.arange(slots.shape[0]), s)
+    assert (slots[rest].view(np.uint32) == orig[rest].view(np.uint32)).all()
+    assert (bq.cref == bvh.cref).all() and (bq.range == bvh.range).all() and (bq.perm == bvh.perm).all()
+
+
+def _same(h, prim, t):
+    return (h.prim == prim).all() and (h.t.view(np.uint32) == t.view(np.uint32)).all()
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_decoded_traversal_micro_scenes(seed):
+    n = 1 + (seed * 13) % 64
+    tris = scenes.micro_scene(seed, n)
+    rays = np.concatenate([_aimed_rays(tris, 300, seed), scenes.random_rays(100, seed)])
+    bvh = oracle.bvh_build(tris)
+    b4 = oracle.bvh4_collapse(bvh)
+    d4 = oracle.decoded_bvh4(b4, oracle.quantise4(b4))
+    ob, delta = oracle.default_bounds(tris)
+    bp, bt = oracle.brute_closest(tris, rays)
+    assert _same(oracle.trace4(tris, bvh, d4, rays), bp, bt)
+    bq = oracle.with_slot_boxes(bvh, d4)
+    for R in (4, 6):
+        m = oracle.object_masks(tris, bq, R, delta)
+        h = oracle.trace4(tris, bq, d4, rays, mode="raw", R=R, masks=m, origin_bound=ob)
+        assert _same(h, bp, bt)
+
+
+def test_decoded_traversal_small_scene(small_scene, small_oracle):
+    tris, rays = small_scene
+    rays = np.concatenate([rays, _aimed_rays(tris, 20000, 33)])
+    bvh = small_oracle["bvh"]
+    b4 = oracle.bvh4_collapse(bvh)
+    d4 = oracle.decoded_bvh4(b4, oracle.quantise4(b4))
+    bq = oracle.with_slot_boxes(bvh, d4)
+    ob, delta = small_oracle["origin_bound"], small_oracle["delta"]
+    exact = oracle.trace4(tris, bvh, b4, rays, origin_bound=ob)
+    plain = oracle.trace4(tris, bq, d4, rays, origin_bound=ob)
+    assert _same(plain, exact.prim, exact.t)
+    assert plain.box_tests.sum() >= exact.box_tests.sum()     # coarser boxes are hit at least as often overall
+    m6 = oracle.object_masks(tris, bq, 6, delta)
+    raw = oracle.trace4(tris, bq, d4, rays, mode="raw", R=6, masks=m6, origin_bound=ob)
+    assert _same(raw, exact.prim, exact.t)
+    assert raw.mask_culls.sum() > 0 and (raw.box_tests <= plain.box_tests).all()
