@@ -15,7 +15,7 @@ re-runs the tuner, --sort switches Morton ray ordering); results never depend
 on it. Other workloads: curly_12m (12M curly diagonal strands, 8M incoherent
 bounce rays, LUT-compressed masks), batch64, placement, approx.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes raw6w4,raw6w4l,nonew4,none,raw6,raw4w4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes raw6w4,raw6w4l,nonew4,none,raw6,raw4w4,nonew4q,raw6w4q]
                     [--no-cpu-baseline] [--cpu-seconds S] [--autotune | --tune b,s,c,p,w,o,q,g,f]
                     [--workload hair_1m|curly_12m|batch64|placement|approx] [--sort stored|0|1]
 """
@@ -40,7 +40,7 @@ RAY_BYTES, HIT_BYTES, EXTRA_BYTES, TRI_BYTES = 32, 16, 8, 48
 # HBM-side bytes per trace launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, each scaled by the
 # same counter's reading for a 1 GiB plain copy (FETCH x2.0, WRITE x1.0). Valid only for the traversal
 # kernel source whose SHA-256 starts with this prefix; otherwise traffic is reported as null.
-MEASURED_TRAFFIC = {"source_sha256_16": "f438279241645b17", "raw6w4": 16.856e9, "none": 9.797e9}
+MEASURED_TRAFFIC = {"source_sha256_16": "63894407e75952d6", "raw6w4": 16.851e9, "none": 9.793e9}
 TRACE_SOURCE = os.path.join(ROOT, "paper_2305_08343_amd", "csrc", "kernels_trace.hip")
 
 # width 2: binary nodes (node_bytes per visit); width 4: 4-wide nodes of Sect. 3.2.4 (child records of
@@ -52,6 +52,11 @@ MODES = {
     "raw6w4l": dict(mode="raw", R=6, cull=True, width=4, mask_bytes=32, mask_slots="leaves", tune=(256, 12, 1, 8, 6, 0, 0, 12, 12)),
     "raw4w4l": dict(mode="raw", R=4, cull=True, width=4, mask_bytes=8, mask_slots="leaves", tune=(256, 12, 1, 8, 6, 0, 0, 12, 8)),
     "nonew4": dict(mode="none", R=6, cull=False, width=4, mask_bytes=0, tune=(128, 16, 1, 8, 6, 1, 0, 20, 20)),
+    # quantised child boxes: 64-byte nodes, 16 bytes per child (6 plane bytes, ref, a quarter of corner + aux)
+    "nonew4q": dict(mode="none", R=6, cull=False, width=4, mask_bytes=0, quantise=True, child_bytes=16,
+                    tune=(256, 12, 1, 8, 6, 0, 0, 12, 12)),
+    "raw6w4q": dict(mode="raw", R=6, cull=True, width=4, mask_bytes=32, quantise=True, child_bytes=16,
+                    tune=(256, 8, 1, 8, 0, 0, 0, 12, 12)),
     "lut6w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, tune=(256, 12, 1, 8, 6, 0)),
     "lut4k256w4": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 0, 0)),
     "lut6k256w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 6, 0)),
@@ -94,7 +99,7 @@ def algorithmic_bytes(box_tests, tri_tests, mask_tests, n_rays, spec):
     if spec["width"] == 2:
         nodes = tests / 2.0 * spec["node_bytes"]
     else:
-        nodes = tests * CHILD_BYTES_W4 + mask_tests.sum(dtype=np.float64) * spec["mask_bytes"]
+        nodes = tests * spec.get("child_bytes", CHILD_BYTES_W4) + mask_tests.sum(dtype=np.float64) * spec["mask_bytes"]
     return (n_rays * (RAY_BYTES + HIT_BYTES + EXTRA_BYTES) + nodes
             + tri_tests.sum(dtype=np.float64) * TRI_BYTES)
 
@@ -124,7 +129,8 @@ def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup, autotune=False, wo
     from paper_2305_08343_amd import binding, tune
     t0 = time.perf_counter()
     scene = binding.Scene(ctx, tris, R=spec["R"], mode=spec["mode"], K=spec.get("K", 4096), width=spec["width"],
-                          bit_table=spec.get("bit_table", False), mask_slots=spec.get("mask_slots", "all"))
+                          bit_table=spec.get("bit_table", False), mask_slots=spec.get("mask_slots", "all"),
+                          quantise=spec.get("quantise", False))
     build_s = time.perf_counter() - t0
     n = rays_dev.shape[0]
     hits = torch.empty((n, 4), dtype=torch.int32, device=rays_dev.device)
@@ -390,7 +396,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="raw6w4,raw6w4l,nonew4,none,raw6,raw4w4")
+    ap.add_argument("--modes", default="raw6w4,raw6w4l,nonew4,none,raw6,raw4w4,nonew4q,raw6w4q")
     ap.add_argument("--autotune", action="store_true",
                     help="pick each mode's launch shape live with the autotuner instead of the stored one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -472,7 +478,8 @@ def main():
     head = modes[0]
     for m in modes:
         # unculled reference: the plain traversal of the same node width, and the plain binary BVH
-        for key, ref in (("unculled", "nonew4" if MODES[m]["width"] == 4 else "none"), ("plain_binary", "none")):
+        plain = ("nonew4q" if MODES[m].get("quantise") else "nonew4") if MODES[m]["width"] == 4 else "none"
+        for key, ref in (("unculled", plain), ("plain_binary", "none")):
             if ref not in raw or ref == m:
                 continue
             same = bool((raw[m]["prim"] == raw[ref]["prim"]).all() and

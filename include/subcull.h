@@ -111,12 +111,21 @@ typedef struct {
                                get the full mask, which is never tested, so the
                                traversal tests masks where a cull saves
                                triangle tests (results unchanged)                */
+    uint32_t quantise;      /* width 4, modes NONE and RAW: 1 stores child boxes as
+                               8-bit steps from the node's minimum corner (one
+                               power-of-two step per axis, the smallest whose
+                               255 steps span the node; minima rounded down,
+                               maxima up), 64-byte nodes. Decoded boxes contain
+                               the exact ones, so hits are those of the exact
+                               boxes; the binary slots the 4-wide nodes use take
+                               the decoded boxes, and masks, exports and counts
+                               follow them (default 0)                           */
 } sc_build_params;
 
 typedef struct {
     uint32_t n_tris, n_inner, depth, root_ref;
     uint32_t R, mode, codebook_size, words;  /* words = 64-bit words per mask  */
-    uint32_t node_bytes;                     /* stride of one inner node        */
+    uint32_t node_bytes;                     /* stride of one inner node (4-wide: 128, quantised 64) */
     uint32_t n_masked;                       /* slots that carry a mask         */
     uint32_t width;                          /* 2 or 4                          */
     uint32_t n_nodes;                        /* inner nodes traversed: n_inner,

@@ -38,7 +38,8 @@ class sc_build_params(C.Structure):
                 ("depth_cap", C.c_uint32), ("mode", C.c_uint32), ("codebook_size", C.c_uint32),
                 ("delta", C.c_float), ("origin_bound", C.c_float),
                 ("mask_placement", C.c_void_p), ("placement_len", C.c_uint32), ("width", C.c_uint32),
-                ("approx_levels", C.c_uint32), ("bit_table", C.c_uint32), ("mask_slots", C.c_uint32)]
+                ("approx_levels", C.c_uint32), ("bit_table", C.c_uint32), ("mask_slots", C.c_uint32),
+                ("quantise", C.c_uint32)]
 
 
 class sc_scene_info(C.Structure):
@@ -281,7 +282,7 @@ class Scene:
     def __init__(self, ctx: Context, tris, *, R: int = 6, mode: str = "raw", K: int = 4096,
                  leaf_max: int = 4, bins: int = 32, depth_cap: int = 64, delta: float = 0.0,
                  origin_bound: float = 0.0, placement=None, width: int = 2, approx_levels: int = 0,
-                 bit_table: bool = False, mask_slots: str = "all", stream=None):
+                 bit_table: bool = False, mask_slots: str = "all", quantise: bool = False, stream=None):
         import torch
         lib = load()
         self.ctx = ctx
@@ -300,6 +301,7 @@ class Scene:
         p.approx_levels = approx_levels
         p.bit_table = int(bit_table)
         p.mask_slots = 1 if mask_slots == "leaves" else 0
+        p.quantise = 1 if quantise else 0
         self._placement = None
         if placement is not None:
             self._placement = np.ascontiguousarray(placement, np.uint8)

@@ -41,7 +41,8 @@ struct sc_scene {
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // vertex bounds (ray ordering keys)
     uint32_t stride2 = kNodeBytes;        // stride of the binary node array `nodes`
     HostBVH4 bvh4;                        // 4-wide scenes: host copy for export
-    unsigned char* nodes4 = nullptr;      // 4-wide nodes (kNode4Bytes each)
+    unsigned char* nodes4 = nullptr;      // 4-wide nodes (kNode4Bytes, or kNode4QBytes when quantised)
+    uint32_t quant4 = 0;                  // 4-wide: quantised child boxes
     uint64_t* masks4 = nullptr;           // 4-wide RAW: child masks [4*n4][W]
     uint32_t* src4 = nullptr;             // 4-wide: binary slot of each child [4*n4]
     uint32_t* bit_table = nullptr;        // LUT mode: 2-D bit table [R^6][K/32]
@@ -150,6 +151,10 @@ bool check_params(const sc_build_params& p, std::string& why) {
     if (p.mask_slots > 1) { why = "mask_slots must be 0 or 1"; return false; }
     if (p.bit_table > 1 || (p.bit_table && p.mode != SC_MASK_LUT)) { why = "bit_table needs LUT mode"; return false; }
     if (p.width == 4 && p.mode == SC_MASK_SPARSE) { why = "SPARSE needs width 2"; return false; }
+    if (p.quantise > 1 || (p.quantise && (p.width != 4 || (p.mode != SC_MASK_NONE && p.mode != SC_MASK_RAW)))) {
+        why = "quantise needs width 4 and mode NONE or RAW";
+        return false;
+    }
     if (!std::isfinite(p.delta) || !std::isfinite(p.origin_bound)) { why = "non-finite delta/origin_bound"; return false; }
     return true;
 }
@@ -319,6 +324,22 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
         r[3] = v[3] - v[0]; r[4] = v[4] - v[1]; r[5] = v[5] - v[2];
         r[6] = v[6] - v[0]; r[7] = v[7] - v[1]; r[8] = v[8] - v[2];
         std::memcpy(&r[9], &id, 4);
+    }
+    // 4-wide scenes collapse here; with quantised child boxes, every binary slot
+    // a 4-wide node uses takes the decoded box, so the masks, codebook
+    // importances and exports built below all belong to the boxes the 4-wide
+    // traversal tests (the collapse itself chose its expansions on exact boxes)
+    std::vector<unsigned char> q4;
+    if (P.width == 4) {
+        collapse_bvh4(B, sc->bvh4);
+        if (P.quantise) {
+            quantise_bvh4(sc->bvh4, q4);
+            sc->quant4 = 1;
+            const HostBVH4& B4 = sc->bvh4;
+            for (size_t k = 0; k < (size_t)B4.n4 * 4; ++k)
+                if (B4.ref[k] != kEmptyRef)
+                    std::memcpy(&sc->bvh.cbox[6 * (size_t)B4.src[k]], &B4.box[6 * k], 6 * sizeof(float));
+        }
     }
     // nodes
     const uint32_t stride = I.node_bytes;
@@ -496,18 +517,22 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
         }
     }
     if (P.width == 4) {
-        collapse_bvh4(B, sc->bvh4);
         const HostBVH4& B4 = sc->bvh4;
         if (B4.max_stack > kMaxStack4) return bail(SC_ERR_DEPTH, "4-wide traversal stack deeper than 128 entries");
         I.n_nodes = B4.n4;
-        I.node_bytes = kNode4Bytes;
+        I.node_bytes = sc->quant4 ? kNode4QBytes : kNode4Bytes;
         if (B4.n4 > 0) {
-            std::vector<unsigned char> n4((size_t)B4.n4 * kNode4Bytes, 0);
-            for (uint32_t m = 0; m < B4.n4; ++m) {
-                float* f = reinterpret_cast<float*>(&n4[(size_t)m * kNode4Bytes]);
-                for (int c = 0; c < 4; ++c)
-                    for (int j = 0; j < 6; ++j) f[4 * j + c] = B4.box[24 * (size_t)m + 6 * c + j];
-                std::memcpy(&n4[(size_t)m * kNode4Bytes + 96], &B4.ref[4 * (size_t)m], 16);
+            std::vector<unsigned char> n4;
+            if (sc->quant4) {
+                n4.swap(q4);
+            } else {
+                n4.assign((size_t)B4.n4 * kNode4Bytes, 0);
+                for (uint32_t m = 0; m < B4.n4; ++m) {
+                    float* f = reinterpret_cast<float*>(&n4[(size_t)m * kNode4Bytes]);
+                    for (int c = 0; c < 4; ++c)
+                        for (int j = 0; j < 6; ++j) f[4 * j + c] = B4.box[24 * (size_t)m + 6 * c + j];
+                    std::memcpy(&n4[(size_t)m * kNode4Bytes + 96], &B4.ref[4 * (size_t)m], 16);
+                }
             }
             sc->nodes4 = scene_alloc<unsigned char>(sc, n4.size(), s);
             sc->src4 = scene_alloc<uint32_t>(sc, B4.src.size() * 4, s);
@@ -521,7 +546,8 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                 if (!sc->masks4) return bail(SC_ERR_OOM, "4-wide mask allocation failed");
             }
             if (P.mode == SC_MASK_RAW || P.mode == SC_MASK_LUT) {
-                e = launch_pack4(P.mode, R, sc->src4, B4.n4, sc->masks, sc->cidx, sc->nodes4, sc->masks4, s);
+                e = launch_pack4(P.mode, R, sc->src4, B4.n4, sc->masks, sc->cidx, sc->nodes4, sc->masks4, sc->quant4,
+                                 s);
                 if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("4-wide pack: ") + hipGetErrorString(e));
             }
         }
@@ -649,6 +675,7 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     if (I.width == 4) {
         // the 4-wide root is node 0 exactly when the binary root is node 0 (else the same leaf or empty ref)
         a.nodes = scene->nodes4;
+        a.quant = scene->quant4;
         a.side_masks = scene->masks4;
         a.src4 = scene->src4;
     }

@@ -4,6 +4,7 @@
 // one of them is a binary inner node, that inner child with the largest
 // surface area (float64; the earliest in child order on ties) is replaced in
 // place by its own two children. Nodes are numbered in DFS pre-order.
+#include <cmath>
 #include <cstring>
 
 #include "internal.h"
@@ -77,6 +78,75 @@ void collapse_bvh4(const HostBVH& B, HostBVH4& out) {
     out.src.reserve((size_t)B.n_inner * 4);
     Collapser c{B, out};
     out.root = c.grow(B.root, 0);
+}
+
+// Child boxes as whole steps from the node's minimum corner, the child-box
+// compression of compressed wide BVHs (a layout choice; the paper keeps float
+// boxes). Per node and axis, over the used children: the corner is the least
+// child minimum, the step 2^e has the smallest e in [-126, 127] for which 255
+// steps cover the extent (taken exactly in double), minima round down and
+// maxima up to whole steps. Decoding corner + q * 2^e in float32 multiplies
+// exactly (8-bit q, a normal power of two) and rounds the sum to nearest, which
+// cannot cross the float child plane the exact sum lies beyond, so the decoded
+// box contains the child's box.
+namespace {
+
+int step_exponent(double ext) {
+    if (!(ext > 0.0)) return -126;
+    int k = 0;
+    (void)std::frexp(ext / 255.0, &k);
+    int e = k < -126 ? -126 : (k > 127 ? 127 : k);
+    while (e > -126 && std::ldexp(255.0, e - 1) >= ext) --e;
+    while (e < 127 && std::ldexp(255.0, e) < ext) ++e;
+    return e;
+}
+
+}  // namespace
+
+void quantise_bvh4(HostBVH4& B4, std::vector<unsigned char>& nodes) {
+    nodes.assign((size_t)B4.n4 * kNode4QBytes, 0);
+    for (uint32_t m = 0; m < B4.n4; ++m) {
+        unsigned char* np = &nodes[(size_t)m * kNode4QBytes];
+        const uint32_t* ref = &B4.ref[4 * (size_t)m];
+        float* box = &B4.box[24 * (size_t)m];
+        float corner[3];
+        uint8_t ebias[4] = {0, 0, 0, 0};
+        uint8_t q[2][3][4] = {};  // [lo / hi][axis][child]
+        for (int a = 0; a < 3; ++a) {
+            float lo = INFINITY, hi = -INFINITY;
+            for (int c = 0; c < 4; ++c) {
+                if (ref[c] == kEmptyRef) continue;
+                if (box[6 * c + a] < lo) lo = box[6 * c + a];
+                if (box[6 * c + 3 + a] > hi) hi = box[6 * c + 3 + a];
+            }
+            if (lo > hi) lo = hi = 0.0f;  // no used child
+            const int e = step_exponent((double)hi - (double)lo);
+            const double step = std::ldexp(1.0, e);
+            const float stepf = (float)step;
+            corner[a] = lo;
+            ebias[a] = (uint8_t)(e + 127);
+            for (int c = 0; c < 4; ++c) {
+                if (ref[c] == kEmptyRef) continue;
+                double ql = std::floor(((double)box[6 * c + a] - (double)lo) / step);
+                double qh = std::ceil(((double)box[6 * c + 3 + a] - (double)lo) / step);
+                ql = ql < 0.0 ? 0.0 : (ql > 255.0 ? 255.0 : ql);
+                qh = qh < 0.0 ? 0.0 : (qh > 255.0 ? 255.0 : qh);
+                q[0][a][c] = (uint8_t)ql;
+                q[1][a][c] = (uint8_t)qh;
+                const float dl = (float)q[0][a][c] * stepf, dh = (float)q[1][a][c] * stepf;
+                box[6 * c + a] = lo + dl;
+                box[6 * c + 3 + a] = lo + dh;
+            }
+        }
+        std::memcpy(np, corner, 12);
+        std::memcpy(np + 12, ebias, 4);
+        std::memcpy(np + kNode4QRefs, ref, 16);
+        // words 8..13: qlo.x qlo.y qlo.z qhi.x qhi.y qhi.z, child c in byte c
+        for (int a = 0; a < 3; ++a) {
+            std::memcpy(np + 32 + 4 * a, q[0][a], 4);
+            std::memcpy(np + 44 + 4 * a, q[1][a], 4);
+        }
+    }
 }
 
 }  // namespace sc

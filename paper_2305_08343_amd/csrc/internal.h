@@ -59,6 +59,13 @@ struct HostBVH4 {
 };
 void collapse_bvh4(const HostBVH& B, HostBVH4& out);
 constexpr uint32_t kNode4Bytes = 128;  // SoA boxes (96 B), refs (16 B), aux (16 B)
+// Quantised 4-wide node: corner lo xyz (12 B), step exponents + 127 (3 B, 1 B pad),
+// refs (16 B), planes as bytes (child c in byte c) qlo.x qlo.y qlo.z qhi.x | qhi.y qhi.z,
+// aux (8 B)
+constexpr uint32_t kNode4QBytes = 64;
+constexpr uint32_t kNode4QRefs = 16, kNode4QAux = 56;
+// Writes the quantised nodes of B4 (aux zero) and replaces B4.box by the decoded boxes.
+void quantise_bvh4(HostBVH4& B4, std::vector<unsigned char>& nodes);
 // 4-wide RAW nodes: bit 28 of a child's ref marks a full mask, so the traversal reads
 // the flags with the refs and needs no aux load. Leaf first-triangle and node indices
 // of 4-wide scenes stay below 2^28 (checked at build); the traversal clears the bit
@@ -120,6 +127,7 @@ struct TraceLaunch {
     uint32_t refill;            // idle lanes take rays once this many are idle or none is busy (0, 1 = at once)
     const uint32_t* order;      // single scene: rays are taken in this order (NULL = index order)
     uint32_t width;             // 2 (binary nodes) or 4 (4-wide nodes; side_masks = raw masks [4*node+c])
+    uint32_t quant = 0;         // width 4: 1 = quantised child boxes (kNode4QBytes nodes)
     const uint32_t* src4;       // 4-wide: binary slot of child [4*node+c] (shadow counts)
     const uint32_t* bit_table;  // LUT mode: [R^6][K/32] ray-mask key x codebook entry bits, or NULL
     const BatchItem* items;     // batched launch: per-scene descriptors sorted by ray_begin, else null
@@ -162,7 +170,8 @@ hipError_t launch_bit_table(uint32_t R, const uint64_t* lut, const uint64_t* cb,
                             hipStream_t s);
 // 4-wide nodes: gather each child's raw mask (and full flag) or codebook index from its binary slot
 hipError_t launch_pack4(uint32_t mode, uint32_t R, const uint32_t* src4, uint32_t n4, const uint64_t* masks,
-                        const uint16_t* cidx, unsigned char* nodes4, uint64_t* masks4, hipStream_t s);
+                        const uint16_t* cidx, unsigned char* nodes4, uint64_t* masks4, uint32_t quant,
+                        hipStream_t s);
 
 // learned placement
 constexpr int kMlpParams = SC_MLP_PARAMS;

@@ -455,11 +455,12 @@ __global__ void pack_lut_kernel(const uint16_t* __restrict__ idx, uint32_t n_inn
 template <int R>
 __global__ void pack4_kernel(uint32_t mode, const uint32_t* __restrict__ src4, uint32_t n4,
                              const uint64_t* __restrict__ masks, const uint16_t* __restrict__ cidx,
-                             unsigned char* __restrict__ nodes4, uint64_t* __restrict__ masks4) {
+                             unsigned char* __restrict__ nodes4, uint64_t* __restrict__ masks4,
+                             uint32_t stride, uint32_t refs_at, uint32_t aux_at) {
     constexpr int W = (R * R * R + 63) / 64;
     const size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n4) return;
-    uint32_t* aux = reinterpret_cast<uint32_t*>(nodes4 + m * kNode4Bytes + 112);
+    uint32_t* aux = reinterpret_cast<uint32_t*>(nodes4 + m * stride + aux_at);
     uint32_t full = 0, idx01 = 0, idx23 = 0;
     for (int c = 0; c < 4; ++c) {
         const uint32_t s = src4[4 * m + c];
@@ -482,7 +483,7 @@ __global__ void pack4_kernel(uint32_t mode, const uint32_t* __restrict__ src4, u
     aux[1] = (mode == SC_MASK_RAW) ? 0u : idx23;
     if (mode == SC_MASK_RAW) {
         // the full flags again in the refs (bit 28), where the traversal reads them
-        uint32_t* refs = reinterpret_cast<uint32_t*>(nodes4 + m * kNode4Bytes + 96);
+        uint32_t* refs = reinterpret_cast<uint32_t*>(nodes4 + m * stride + refs_at);
         for (int c = 0; c < 4; ++c)
             if (((full >> c) & 1u) && refs[c] != kEmptyRef) refs[c] |= kRef4Full;
     }
@@ -625,15 +626,19 @@ hipError_t launch_full_inner_slots(uint32_t R, const unsigned char* nodes, uint3
 }
 
 hipError_t launch_pack4(uint32_t mode, uint32_t R, const uint32_t* src4, uint32_t n4, const uint64_t* masks,
-                        const uint16_t* cidx, unsigned char* nodes4, uint64_t* masks4, hipStream_t s) {
+                        const uint16_t* cidx, unsigned char* nodes4, uint64_t* masks4, uint32_t quant,
+                        hipStream_t s) {
     if (n4 == 0) return hipSuccess;
     if (mode != SC_MASK_RAW && mode != SC_MASK_LUT) return hipErrorInvalidValue;
+    if (quant && mode != SC_MASK_RAW) return hipErrorInvalidValue;
+    const uint32_t stride = quant ? kNode4QBytes : kNode4Bytes;
+    const uint32_t refs_at = quant ? kNode4QRefs : 96u, aux_at = quant ? kNode4QAux : 112u;
     if (R == 4)
         hipLaunchKernelGGL(pack4_kernel<4>, dim3(blocks_for(n4, 256)), dim3(256), 0, s, mode, src4, n4, masks, cidx,
-                           nodes4, masks4);
+                           nodes4, masks4, stride, refs_at, aux_at);
     else if (R == 6)
         hipLaunchKernelGGL(pack4_kernel<6>, dim3(blocks_for(n4, 256)), dim3(256), 0, s, mode, src4, n4, masks, cidx,
-                           nodes4, masks4);
+                           nodes4, masks4, stride, refs_at, aux_at);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -215,7 +215,7 @@ struct MinWaves {
     static constexpr int value = (lds_waves < target) ? (lds_waves > 1 ? lds_waves : 1) : target;
 };
 
-template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH, int WIDTH>
+template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH, int WIDTH, bool QUANT = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MinWaves<MODE, R, WIDTH, BLOCK, STACK>::value)))
 void trace_kernel(TraceLaunch a) {
     static_assert(WIDTH == 2 || (WIDTH == 4 && !BATCH && MODE != kModeSparse), "4-wide: single scene, no sparse masks");
@@ -412,14 +412,43 @@ void trace_kernel(TraceLaunch a) {
                     }
                 }
             } else if constexpr (WIDTH == 4) {
-                // 4-wide node: SoA boxes lo.x[4] lo.y[4] lo.z[4] hi.x[4] hi.y[4] hi.z[4], refs[4], aux
-                const float4* np4 = reinterpret_cast<const float4*>(s_nodes + (size_t)ref * kNode4Bytes);
-                // near and far bounds of the four children, picked by address from the
-                // lo / hi rows (row j holds lo, row j + 3 hi, of axis j)
+                // 4-wide node: SoA boxes lo.x[4] lo.y[4] lo.z[4] hi.x[4] hi.y[4] hi.z[4], refs[4], aux;
+                // quantised: corner, step exponents, refs, 8-bit planes, aux in 64 bytes
+                static_assert(!QUANT || MODE == kModeNone || MODE == kModeRaw, "quantised nodes carry no codebook indices");
+                const float4* np4 =
+                    reinterpret_cast<const float4*>(s_nodes + (size_t)ref * (QUANT ? kNode4QBytes : kNode4Bytes));
                 const uint32_t sx = r.neg & 1u, sy = (r.neg >> 1) & 1u, sz = (r.neg >> 2) & 1u;
-                const float4 nx = np4[3 * sx], ny = np4[1 + 3 * sy], nz = np4[2 + 3 * sz];
-                const float4 fx = np4[3 - 3 * sx], fy = np4[4 - 3 * sy], fz = np4[5 - 3 * sz];
-                const uint4 cr = reinterpret_cast<const uint4*>(np4)[6];
+                float4 nx, ny, nz, fx, fy, fz;
+                uint4 cr;
+                if constexpr (QUANT) {
+                    // four line pieces: corner + exponents, refs, qlo.xyz qhi.x, qhi.yz aux
+                    const uint4 h = reinterpret_cast<const uint4*>(np4)[0];
+                    cr = reinterpret_cast<const uint4*>(np4)[1];
+                    const uint4 q0 = reinterpret_cast<const uint4*>(np4)[2];
+                    const uint4 q1 = reinterpret_cast<const uint4*>(np4)[3];
+                    const float cx = __uint_as_float(h.x), cy = __uint_as_float(h.y), cz = __uint_as_float(h.z);
+                    // step 2^(b - 127) from its biased exponent b (1..254): a normal float
+                    const float ux = __uint_as_float((h.w & 0xFFu) << 23);
+                    const float uy = __uint_as_float(((h.w >> 8) & 0xFFu) << 23);
+                    const float uz = __uint_as_float(((h.w >> 16) & 0xFFu) << 23);
+                    // near / far plane words of each axis, picked by the ray's direction signs
+                    const uint32_t wnx = sx ? q0.w : q0.x, wfx = sx ? q0.x : q0.w;
+                    const uint32_t wny = sy ? q1.x : q0.y, wfy = sy ? q0.y : q1.x;
+                    const uint32_t wnz = sz ? q1.y : q0.z, wfz = sz ? q0.z : q1.y;
+                    // corner + q * step: the product is exact, the sum rounds to nearest
+                    auto dq = [](uint32_t w, float c, float u) {
+                        return make_float4(c + (float)(w & 0xFFu) * u, c + (float)((w >> 8) & 0xFFu) * u,
+                                           c + (float)((w >> 16) & 0xFFu) * u, c + (float)(w >> 24) * u);
+                    };
+                    nx = dq(wnx, cx, ux); ny = dq(wny, cy, uy); nz = dq(wnz, cz, uz);
+                    fx = dq(wfx, cx, ux); fy = dq(wfy, cy, uy); fz = dq(wfz, cz, uz);
+                } else {
+                    // near and far bounds of the four children, picked by address from the
+                    // lo / hi rows (row j holds lo, row j + 3 hi, of axis j)
+                    nx = np4[3 * sx]; ny = np4[1 + 3 * sy]; nz = np4[2 + 3 * sz];
+                    fx = np4[3 - 3 * sx]; fy = np4[4 - 3 * sy]; fz = np4[5 - 3 * sz];
+                    cr = reinterpret_cast<const uint4*>(np4)[6];
+                }
                 // aux words at byte 112, for the LUT modes' four 16-bit codebook indices; raw
                 // nodes keep their full-mask flags in bit 28 of the refs, so they load one line
                 // piece less per visit (each lane's load costs the address path a line access)
@@ -597,7 +626,7 @@ void trace_kernel(TraceLaunch a) {
     }
 }
 
-template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH, int WIDTH>
+template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH, int WIDTH, bool QUANT = false>
 hipError_t launch_one(const TraceLaunch& a, hipStream_t s) {
     // blocks per CU that fit, and CUs: queried once per instance (on the device current at
     // the first launch; every GPU of an MI355X node is the same part), thread-safe
@@ -608,7 +637,7 @@ hipError_t launch_one(const TraceLaunch& a, hipStream_t s) {
         int dev = 0, c = 0, p = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, trace_kernel<MODE, R, BLOCK, STACK, BATCH, WIDTH>,
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, trace_kernel<MODE, R, BLOCK, STACK, BATCH, WIDTH, QUANT>,
                                                            BLOCK, 0);
         return Occupancy{p > 0 ? p : 4, c > 0 ? c : 256};
     }();
@@ -625,7 +654,7 @@ hipError_t launch_one(const TraceLaunch& a, hipStream_t s) {
     uint32_t blocks = (waves + BLOCK / kWave - 1) / (BLOCK / kWave);
     blocks = blocks < resident ? blocks : resident;
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(kQueueParts), 0, s, a.queue, kQueueParts);
-    hipLaunchKernelGGL((trace_kernel<MODE, R, BLOCK, STACK, BATCH, WIDTH>), dim3(blocks), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((trace_kernel<MODE, R, BLOCK, STACK, BATCH, WIDTH, QUANT>), dim3(blocks), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
@@ -654,6 +683,15 @@ hipError_t launch_cfg(const TraceLaunch& a, hipStream_t s) {
 
 template <int BLOCK, int STACK>
 hipError_t launch_cfg4(const TraceLaunch& a, hipStream_t s) {
+    if (a.quant) {
+        switch (a.mode) {
+            case SC_MASK_NONE: return launch_one<kModeNone, 6, BLOCK, STACK, false, 4, true>(a, s);
+            case SC_MASK_RAW:
+                return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK, false, 4, true>(a, s)
+                                : launch_one<kModeRaw, 6, BLOCK, STACK, false, 4, true>(a, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (a.mode) {
         case SC_MASK_NONE: return launch_one<kModeNone, 6, BLOCK, STACK, false, 4>(a, s);
         case SC_MASK_RAW:
