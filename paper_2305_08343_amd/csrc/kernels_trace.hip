@@ -435,10 +435,13 @@ void trace_kernel(TraceLaunch a) {
                     const uint32_t wnx = sx ? q0.w : q0.x, wfx = sx ? q0.x : q0.w;
                     const uint32_t wny = sy ? q1.x : q0.y, wfy = sy ? q0.y : q1.x;
                     const uint32_t wnz = sz ? q1.y : q0.z, wfz = sz ? q0.z : q1.y;
-                    // corner + q * step: the product is exact, the sum rounds to nearest
+                    // corner + q * step: the product is exact, so one fused multiply-add rounds the
+                    // sum exactly as a multiply then an add would
                     auto dq = [](uint32_t w, float c, float u) {
-                        return make_float4(c + (float)(w & 0xFFu) * u, c + (float)((w >> 8) & 0xFFu) * u,
-                                           c + (float)((w >> 16) & 0xFFu) * u, c + (float)(w >> 24) * u);
+                        return make_float4(__builtin_fmaf((float)(w & 0xFFu), u, c),
+                                           __builtin_fmaf((float)((w >> 8) & 0xFFu), u, c),
+                                           __builtin_fmaf((float)((w >> 16) & 0xFFu), u, c),
+                                           __builtin_fmaf((float)(w >> 24), u, c));
                     };
                     nx = dq(wnx, cx, ux); ny = dq(wny, cy, uy); nz = dq(wnz, cz, uz);
                     fx = dq(wfx, cx, ux); fy = dq(wfy, cy, uy); fz = dq(wfz, cz, uz);

@@ -2,7 +2,9 @@
 
 hair_1m (1,000,002 tris, 4,147,200 rays): BVH, masks (R = 4, 6), codebook and
 indices, and every ray's hit/t/counts in the plain, raw R = 6, raw R = 4 and
-compressed modes, all bit-exact against the oracle.
+compressed modes, all bit-exact against the oracle; the 4-wide modes the benchmark
+times (216-bit masks with exact and quantised child boxes, plain quantised) on
+every ray in their stored launch shapes.
 
 curly_12m (12,000,000 tris, 8,000,000 rays): BVH bit-exact; masks of a slot
 sample; every 64th ray bit-exact in every mode (oracle with all masks); and on
@@ -81,6 +83,40 @@ def test_hair_1m_all_rays_bit_exact(request, ctx, hair):
         dev = s.trace(rays).numpy()
         s.close()
         _compare(dev, oracle.trace(tris, bvh, rays, **kw))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", ["raw6w4q", "raw6w4", "nonew4q"])
+def test_hair_1m_4_wide_all_rays_bit_exact_in_bench_launch_shape(request, ctx, hair, name):
+    """The benchmark's 4-wide modes (216-bit masks with quantised and with exact child boxes,
+    and the plain quantised traversal) on every ray, in the launch shape bench.py stores for them."""
+    import bench
+    from paper_2305_08343_amd import binding
+    tris, rays, bvh = hair["tris"], hair["rays"], hair["bvh"]
+    spec = bench.MODES[name]
+    q = spec.get("quantise", False)
+    _say(request, f"hair_1m {name}: build, export, trace {rays.shape[0]} rays in shape {spec['tune']}")
+    b4 = oracle.bvh4_collapse(bvh)
+    if q:
+        b4 = oracle.decoded_bvh4(b4, oracle.quantise4(b4))
+        bq = oracle.with_slot_boxes(bvh, b4)
+    else:
+        bq = bvh
+    kw = dict(origin_bound=hair["ob"], nthreads=hair["nt"])
+    s = binding.Scene(ctx, tris, R=spec["R"], mode=spec["mode"], width=4, quantise=q)
+    e4 = s.export4()
+    assert (e4["box4"].view(np.uint32) == b4.box4.view(np.uint32)).all() and (e4["ref4"] == b4.ref4).all()
+    if spec["mode"] == "raw":
+        masks = hair["masks6"] if not q else oracle.object_masks(tris, bq, 6, hair["delta"], nthreads=hair["nt"])
+        assert (s.export()["masks"] == masks).all()
+        kw.update(mode="raw", R=6, masks=masks)
+    try:
+        ctx.set_tune(*spec["tune"])
+        dev = s.trace(rays).numpy()
+    finally:
+        ctx.set_tune()
+        s.close()
+    _compare(dev, oracle.trace4(tris, bq, b4, rays, **kw))
 
 
 @pytest.mark.timeout(600)
