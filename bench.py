@@ -59,6 +59,10 @@ MODES = {
                     tune=(256, 12, 1, 8, 6, 0, 0, 12, 12)),
     "raw6w4q": dict(mode="raw", R=6, cull=True, width=4, mask_bytes=32, quantise=True, child_bytes=16,
                     tune=(256, 12, 1, 8, 6, 0, 0, 12, 12)),
+    "raw4w4q": dict(mode="raw", R=4, cull=True, width=4, mask_bytes=8, quantise=True, child_bytes=16,
+                    tune=(256, 12, 1, 8, 6, 0, 0, 12, 8)),
+    "raw4w4lq": dict(mode="raw", R=4, cull=True, width=4, mask_bytes=8, mask_slots="leaves", quantise=True,
+                     child_bytes=16, tune=(256, 12, 1, 8, 6, 0, 0, 12, 8)),
     "lut6w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, tune=(256, 12, 1, 8, 6, 0)),
     "lut4k256w4": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 0, 0)),
     "lut6k256w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 6, 0)),
