@@ -418,8 +418,8 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
-                                   "part of this build (rays shard with no exchange)",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the library measures one GPU's "
+                                   "share (rays shard across GPUs with no exchange)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

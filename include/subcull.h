@@ -42,7 +42,7 @@ typedef enum {
     SC_ERR_OOM = 3,          /* an allocation (device or host) failed */
     SC_ERR_DEPTH = 4,        /* the BVH would exceed depth_cap */
     SC_ERR_HIP = 5,          /* a HIP runtime call failed */
-    SC_ERR_UNSUPPORTED = 6   /* valid request this build does not implement */
+    SC_ERR_UNSUPPORTED = 6   /* valid request the library does not implement */
 } sc_status;
 
 /* How object masks are stored (Sect. 3.2.2, 3.2.4). */
