@@ -3,8 +3,9 @@ the node's corner, rounded outward; a node layout of this library, not of the
 paper) against the oracle's decoded BVH4: the decoded boxes and the binary
 slot boxes, masks built on them, and per ray hit id, t, box / triangle / mask
 counts in modes NONE and RAW (every slot and leaf slots only), culled and in
-shadow mode, in every launch shape, plus micro scenes and degenerate inputs.
-Hits also equal those of the exact-box scene."""
+shadow mode, in every launch shape, plus micro scenes, degenerate inputs and
+extreme scales (a flat scene, scenes scaled by 1e15 and 1e-8). Hits also equal
+those of the exact-box scene."""
 import numpy as np
 import pytest
 
@@ -160,3 +161,28 @@ def test_degenerate_inputs_and_rejections(ctx, small_scene):
     for kw in (dict(mode="raw", width=2), dict(mode="lut", width=4)):
         with pytest.raises(binding.SubcullError):
             binding.Scene(ctx, tris, quantise=True, **kw)
+
+
+@pytest.mark.parametrize("name", ["flat", "huge", "tiny"])
+def test_extreme_scales_bit_exact(ctx, name):
+    """A flat scene (zero extent in z: the smallest step exponent) and scenes scaled by 1e15 and
+    1e-8, plain and with 216-bit masks on the decoded boxes."""
+    from paper_2305_08343_amd import binding
+    from tests.test_oracle_quant4 import extreme_case
+    tris, rays = extreme_case(name)
+    bvh = oracle.bvh_build(tris)
+    b4 = oracle.bvh4_collapse(bvh)
+    d4 = oracle.decoded_bvh4(b4, oracle.quantise4(b4))
+    bq = oracle.with_slot_boxes(bvh, d4)
+    ob, delta = oracle.default_bounds(tris)
+    print(f"[gpu-quant4] extreme scale {name}", flush=True)
+    for mode in ("none", "raw"):
+        s = binding.Scene(ctx, tris, R=6, mode=mode, width=4, quantise=True)
+        e4 = s.export4()
+        dev = s.trace(rays).numpy()
+        s.close()
+        assert (e4["box4"].view(np.uint32) == d4.box4.view(np.uint32)).all()
+        kw = dict(origin_bound=ob)
+        if mode == "raw":
+            kw.update(mode="raw", R=6, masks=oracle.object_masks(tris, bq, 6, delta))
+        _compare(dev, oracle.trace4(tris, bq, d4, rays, **kw), masks=(mode == "raw"))

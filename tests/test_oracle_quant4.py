@@ -147,3 +147,55 @@ def test_decoded_traversal_small_scene(small_scene, small_oracle):
     raw = oracle.trace4(tris, bq, d4, rays, mode="raw", R=6, masks=m6, origin_bound=ob)
     assert _same(raw, exact.prim, exact.t)
     assert raw.mask_culls.sum() > 0 and (raw.box_tests <= plain.box_tests).all()
+
+
+def _extreme_scenes():
+    """A flat scene (every node has a zero extent in z: the smallest exponent, -126), and
+    the same triangles scaled by 1e15 and 1e-8 (large and small exponents; far larger
+    factors would overflow or underflow the float32 triangle test itself)."""
+    base = scenes.isotropic_tris(7, 200, 0.2)
+    flat = base.copy()
+    flat[:, :, 2] = np.float32(0.5)
+    return {"flat": flat, "huge": (base.astype(np.float64) * 1e15).astype(np.float32),
+            "tiny": (base.astype(np.float64) * 1e-8).astype(np.float32)}
+
+
+def extreme_case(name):
+    """The scene and its rays: aimed and random rays of the unscaled scene with their origins
+    scaled like the vertices (the same rays in scaled units)."""
+    tris = _extreme_scenes()[name]
+    base = tris if name == "flat" else scenes.isotropic_tris(7, 200, 0.2)
+    rays = np.concatenate([_aimed_rays(base, 400, 5), scenes.random_rays(100, 5)])
+    f = {"flat": 1.0, "huge": 1e15, "tiny": 1e-8}[name]
+    rays[:, :3] = (rays[:, :3].astype(np.float64) * f).astype(np.float32)
+    return tris, rays
+
+
+@pytest.mark.parametrize("name", ["flat", "huge", "tiny"])
+def test_quantised_boxes_extreme_scales(name):
+    tris, rays = extreme_case(name)
+    bvh = oracle.bvh_build(tris)
+    b4 = oracle.bvh4_collapse(bvh)
+    qt = oracle.quantise4(b4)
+    _check_quant(b4, qt)
+    e = qt.ebias.astype(int) - 127
+    if name == "flat":
+        assert (e[:, 2] == -126).all() and (qt.q[:, :, [2, 5]] == 0).all()
+    elif name == "huge":
+        assert e.max() > 30
+    else:
+        assert e.min() < -30
+    d4 = oracle.decoded_bvh4(b4, qt)
+    bp, bt = oracle.brute_closest(tris, rays)
+    h = oracle.trace4(tris, oracle.with_slot_boxes(bvh, d4), d4, rays)
+    exact = oracle.trace4(tris, bvh, b4, rays)
+    assert (bp != oracle.NO_HIT).sum() > 200
+    # decoded boxes keep the exact boxes' hits
+    assert _same(h, exact.prim, exact.t)
+    if name == "flat":
+        # coplanar overlapping triangles: equal (or one-ulp apart) hit distances make the closest
+        # triangle ambiguous, so only the hit distance is fixed (to the rounding of the triangle test)
+        assert ((h.prim == oracle.NO_HIT) == (bp == oracle.NO_HIT)).all()
+        assert np.allclose(h.t, bt, rtol=1e-6, atol=0)
+    else:
+        assert _same(h, bp, bt)
