@@ -186,3 +186,19 @@ def test_extreme_scales_bit_exact(ctx, name):
         if mode == "raw":
             kw.update(mode="raw", R=6, masks=oracle.object_masks(tris, bq, 6, delta))
         _compare(dev, oracle.trace4(tris, bq, d4, rays, **kw), masks=(mode == "raw"))
+
+
+@pytest.mark.parametrize("L", [1, 3])
+def test_approximate_masks_on_decoded_boxes(ctx, small_scene, small_oracle, quant_oracle, L):
+    """Alg. 2 masks of a quantised scene are built on the decoded slot boxes, like exact ones."""
+    from paper_2305_08343_amd import binding
+    tris, rays = small_scene
+    bq, d4 = quant_oracle["bq"], quant_oracle["d4"]
+    print(f"[gpu-quant4] approximate masks L={L}", flush=True)
+    ref = oracle.approx_masks(tris, bq, 6, small_oracle["delta"], L)
+    s = binding.Scene(ctx, tris, R=6, mode="raw", approx_levels=L, width=4, quantise=True)
+    assert (s.export()["masks"] == ref).all()
+    dev = s.trace(rays).numpy()
+    s.close()
+    _compare(dev, oracle.trace4(tris, bq, d4, rays, mode="raw", R=6, masks=ref,
+                                origin_bound=small_oracle["origin_bound"]))
