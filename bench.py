@@ -42,7 +42,7 @@ RAY_BYTES, HIT_BYTES, EXTRA_BYTES, TRI_BYTES = 32, 16, 8, 48
 # HBM-side bytes per trace launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, each scaled by the
 # same counter's reading for a 1 GiB plain copy (FETCH x2.0, WRITE x1.0). Valid only for the traversal
 # kernel source whose SHA-256 starts with this prefix; otherwise traffic is reported as null.
-MEASURED_TRAFFIC = {"source_sha256_16": "7bbd9a07e005b894", "raw6w4q": 16.296e9, "raw6w4": 16.850e9, "none": 9.790e9}
+MEASURED_TRAFFIC = {"source_sha256_16": "fc241b489bbb5133", "raw6w4q": 16.295e9, "raw6w4": 16.850e9, "none": 9.791e9}
 TRACE_SOURCE = os.path.join(ROOT, "paper_2305_08343_amd", "csrc", "kernels_trace.hip")
 
 # width 2: binary nodes (node_bytes per visit); width 4: 4-wide nodes of Sect. 3.2.4 (child records of
@@ -63,6 +63,10 @@ MODES = {
                     tune=(256, 12, 1, 8, 6, 0, 0, 12, 8)),
     "raw4w4lq": dict(mode="raw", R=4, cull=True, width=4, mask_bytes=8, mask_slots="leaves", quantise=True,
                      child_bytes=16, tune=(256, 12, 1, 8, 6, 0, 0, 12, 8)),
+    "lut6w4q": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, quantise=True, child_bytes=16,
+                    tune=(256, 12, 1, 8, 6, 0)),
+    "lut4k256w4q": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, quantise=True, child_bytes=16,
+                        tune=(256, 8, 1, 8, 0, 0)),
     "lut6w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, tune=(256, 12, 1, 8, 6, 0)),
     "lut4k256w4": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 0, 0)),
     "lut6k256w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 6, 0)),

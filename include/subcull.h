@@ -111,7 +111,7 @@ typedef struct {
                                get the full mask, which is never tested, so the
                                traversal tests masks where a cull saves
                                triangle tests (results unchanged)                */
-    uint32_t quantise;      /* width 4, modes NONE and RAW: 1 stores child boxes as
+    uint32_t quantise;      /* width 4 (modes NONE, RAW, LUT): 1 stores child boxes as
                                8-bit steps from the node's minimum corner (one
                                power-of-two step per axis, the smallest whose
                                255 steps span the node; minima rounded down,

@@ -151,10 +151,7 @@ bool check_params(const sc_build_params& p, std::string& why) {
     if (p.mask_slots > 1) { why = "mask_slots must be 0 or 1"; return false; }
     if (p.bit_table > 1 || (p.bit_table && p.mode != SC_MASK_LUT)) { why = "bit_table needs LUT mode"; return false; }
     if (p.width == 4 && p.mode == SC_MASK_SPARSE) { why = "SPARSE needs width 2"; return false; }
-    if (p.quantise > 1 || (p.quantise && (p.width != 4 || (p.mode != SC_MASK_NONE && p.mode != SC_MASK_RAW)))) {
-        why = "quantise needs width 4 and mode NONE or RAW";
-        return false;
-    }
+    if (p.quantise > 1 || (p.quantise && p.width != 4)) { why = "quantise needs width 4"; return false; }
     if (!std::isfinite(p.delta) || !std::isfinite(p.origin_bound)) { why = "non-finite delta/origin_bound"; return false; }
     return true;
 }

@@ -127,7 +127,7 @@ struct TraceLaunch {
     uint32_t refill;            // idle lanes take rays once this many are idle or none is busy (0, 1 = at once)
     const uint32_t* order;      // single scene: rays are taken in this order (NULL = index order)
     uint32_t width;             // 2 (binary nodes) or 4 (4-wide nodes; side_masks = raw masks [4*node+c])
-    uint32_t quant = 0;         // width 4: 1 = quantised child boxes (kNode4QBytes nodes)
+    uint32_t quant = 0;         // width 4: 1 = quantised child boxes (kNode4QBytes nodes, aux in the last piece)
     const uint32_t* src4;       // 4-wide: binary slot of child [4*node+c] (shadow counts)
     const uint32_t* bit_table;  // LUT mode: [R^6][K/32] ray-mask key x codebook entry bits, or NULL
     const BatchItem* items;     // batched launch: per-scene descriptors sorted by ray_begin, else null

@@ -630,7 +630,6 @@ hipError_t launch_pack4(uint32_t mode, uint32_t R, const uint32_t* src4, uint32_
                         hipStream_t s) {
     if (n4 == 0) return hipSuccess;
     if (mode != SC_MASK_RAW && mode != SC_MASK_LUT) return hipErrorInvalidValue;
-    if (quant && mode != SC_MASK_RAW) return hipErrorInvalidValue;
     const uint32_t stride = quant ? kNode4QBytes : kNode4Bytes;
     const uint32_t refs_at = quant ? kNode4QRefs : 96u, aux_at = quant ? kNode4QAux : 112u;
     if (R == 4)

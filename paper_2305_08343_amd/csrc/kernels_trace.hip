@@ -414,12 +414,12 @@ void trace_kernel(TraceLaunch a) {
             } else if constexpr (WIDTH == 4) {
                 // 4-wide node: SoA boxes lo.x[4] lo.y[4] lo.z[4] hi.x[4] hi.y[4] hi.z[4], refs[4], aux;
                 // quantised: corner, step exponents, refs, 8-bit planes, aux in 64 bytes
-                static_assert(!QUANT || MODE == kModeNone || MODE == kModeRaw, "quantised nodes carry no codebook indices");
                 const float4* np4 =
                     reinterpret_cast<const float4*>(s_nodes + (size_t)ref * (QUANT ? kNode4QBytes : kNode4Bytes));
                 const uint32_t sx = r.neg & 1u, sy = (r.neg >> 1) & 1u, sz = (r.neg >> 2) & 1u;
                 float4 nx, ny, nz, fx, fy, fz;
                 uint4 cr;
+                uint32_t ax0 = 0u, ax1 = 0u;  // LUT modes: the four 16-bit codebook indices
                 if constexpr (QUANT) {
                     // four line pieces: corner + exponents, refs, qlo.xyz qhi.x, qhi.yz aux
                     const uint4 h = reinterpret_cast<const uint4*>(np4)[0];
@@ -445,6 +445,8 @@ void trace_kernel(TraceLaunch a) {
                     };
                     nx = dq(wnx, cx, ux); ny = dq(wny, cy, uy); nz = dq(wnz, cz, uz);
                     fx = dq(wfx, cx, ux); fy = dq(wfy, cy, uy); fz = dq(wfz, cz, uz);
+                    ax0 = q1.z;  // the aux words ride in the last piece
+                    ax1 = q1.w;
                 } else {
                     // near and far bounds of the four children, picked by address from the
                     // lo / hi rows (row j holds lo, row j + 3 hi, of axis j)
@@ -455,8 +457,7 @@ void trace_kernel(TraceLaunch a) {
                 // aux words at byte 112, for the LUT modes' four 16-bit codebook indices; raw
                 // nodes keep their full-mask flags in bit 28 of the refs, so they load one line
                 // piece less per visit (each lane's load costs the address path a line access)
-                uint32_t ax0 = 0u, ax1 = 0u;
-                if constexpr (MODE != kModeNone && MODE != kModeRaw) {  // raw: flags in the refs
+                if constexpr (!QUANT && MODE != kModeNone && MODE != kModeRaw) {  // raw: flags in the refs
                     const uint2 a2 = reinterpret_cast<const uint2*>(np4)[14];
                     ax0 = a2.x;
                     ax1 = a2.y;
@@ -692,6 +693,15 @@ hipError_t launch_cfg4(const TraceLaunch& a, hipStream_t s) {
             case SC_MASK_RAW:
                 return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK, false, 4, true>(a, s)
                                 : launch_one<kModeRaw, 6, BLOCK, STACK, false, 4, true>(a, s);
+            case SC_MASK_LUT:
+                if (a.bit_table)
+                    return a.R == 4 ? launch_one<kModeLutBits, 4, BLOCK, STACK, false, 4, true>(a, s)
+                                    : launch_one<kModeLutBits, 6, BLOCK, STACK, false, 4, true>(a, s);
+                if (!a.cb_global && (size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
+                    return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK, false, 4, true>(a, s)
+                                    : launch_one<kModeLutLds, 6, BLOCK, STACK, false, 4, true>(a, s);
+                return a.R == 4 ? launch_one<kModeLut, 4, BLOCK, STACK, false, 4, true>(a, s)
+                                : launch_one<kModeLut, 6, BLOCK, STACK, false, 4, true>(a, s);
             default: return hipErrorInvalidValue;
         }
     }

@@ -2,7 +2,8 @@
 the node's corner, rounded outward; a node layout of this library, not of the
 paper) against the oracle's decoded BVH4: the decoded boxes and the binary
 slot boxes, masks built on them, and per ray hit id, t, box / triangle / mask
-counts in modes NONE and RAW (every slot and leaf slots only), culled and in
+counts in modes NONE, RAW (every slot and leaf slots only) and LUT (codebook
+in LDS and through the caches, and the 2-D bit table), culled and in
 shadow mode, in every launch shape, plus micro scenes, degenerate inputs and
 extreme scales (a flat scene, scenes scaled by 1e15 and 1e-8). Hits also equal
 those of the exact-box scene."""
@@ -158,7 +159,7 @@ def test_degenerate_inputs_and_rejections(ctx, small_scene):
     _compare(s.trace(rays).numpy(), oracle.trace4(t, bvh, oracle.bvh4_collapse(bvh), rays), masks=False)
     s.close()
     tris, _ = small_scene
-    for kw in (dict(mode="raw", width=2), dict(mode="lut", width=4)):
+    for kw in (dict(mode="raw", width=2), dict(mode="sparse", placement=np.ones(2, np.uint8), width=4)):
         with pytest.raises(binding.SubcullError):
             binding.Scene(ctx, tris, quantise=True, **kw)
 
@@ -202,3 +203,33 @@ def test_approximate_masks_on_decoded_boxes(ctx, small_scene, small_oracle, quan
     s.close()
     _compare(dev, oracle.trace4(tris, bq, d4, rays, mode="raw", R=6, masks=ref,
                                 origin_bound=small_oracle["origin_bound"]))
+
+
+@pytest.mark.parametrize("R,K,bits", [(6, 4096, False), (6, 256, False), (4, 256, False), (6, 256, True)])
+def test_lut_modes_bit_exact(ctx, small_scene, small_oracle, quant_oracle, R, K, bits):
+    """Compressed masks of a quantised scene: codebook and indices from the masks on the decoded
+    slot boxes (importance weighted by their areas), indices read from the node's last piece."""
+    import torch
+    from paper_2305_08343_amd import binding
+    tris, rays = small_scene
+    rays = np.concatenate([rays, _aimed(tris, 20011, 54)])
+    bq, d4 = quant_oracle["bq"], quant_oracle["d4"]
+    cb, idx = oracle.compress(quant_oracle[f"masks{R}"], bq.slot_boxes(), R, K)
+    kw = dict(origin_bound=small_oracle["origin_bound"], mode="lut", R=R, codebook=cb, cidx=idx)
+    print(f"[gpu-quant4] LUT R={R} K={K} bit_table={bits}", flush=True)
+    s = binding.Scene(ctx, tris, R=R, mode="lut", K=K, width=4, quantise=True, bit_table=bits)
+    e = s.export()
+    assert (e["codebook"] == cb).all() and (e["cidx"] == idx).all()
+    try:
+        for cbg in (0, 1):
+            ctx.set_tune(codebook=cbg)
+            for cull in (True, False):
+                _compare(s.trace(rays, cull=cull).numpy(), oracle.trace4(tris, bq, d4, rays, cull=cull, **kw))
+    finally:
+        ctx.set_tune()
+    fp = torch.zeros(2 * bq.n_inner, dtype=torch.int32, device="cuda:0")
+    dev = s.trace(rays, cull=False, shadow=True, slot_fp=fp).numpy()
+    ora = oracle.trace4(tris, bq, d4, rays, cull=False, shadow=True, **kw)
+    s.close()
+    _compare(dev, ora)
+    assert (fp.cpu().numpy().view(np.uint32) == ora.slot_fp).all() and ora.slot_fp.sum() > 0
