@@ -235,11 +235,14 @@ sc_status sc_bvh_build_host(const float* h_tris, uint32_t n, const sc_build_para
 sc_status sc_scene_get_info(const sc_scene* scene, sc_scene_info* out);
 
 /* Copy the scene's BVH, masks and codebook into caller host buffers
- * (synchronous). Used to check the build against an independent reference. */
+ * (synchronous). Used to check the build against an independent reference.
+ * In a scene built with quantise = 1 the child slots that 4-wide nodes use
+ * hold their decoded boxes (the boxes the masks were built on). */
 sc_status sc_scene_export(const sc_scene* scene, sc_scene_host* out);
 
 /* Copy a 4-wide scene's nodes (host, synchronous): box4 float [n_nodes][4][6]
- * (child lo xyz, hi xyz), ref4 uint32 [n_nodes][4] (leaf refs as in the
+ * (child lo xyz, hi xyz; the decoded boxes when the scene was built with
+ * quantise = 1), ref4 uint32 [n_nodes][4] (leaf refs as in the
  * binary BVH, inner refs = 4-wide node index, 0xFFFFFFFF = unused child),
  * src4 uint32 [n_nodes][4] (the binary child slot each child came from; its
  * mask and codebook index). The collapse: a node starts from the two children
