@@ -42,7 +42,7 @@ RAY_BYTES, HIT_BYTES, EXTRA_BYTES, TRI_BYTES = 32, 16, 8, 48
 # HBM-side bytes per trace launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, each scaled by the
 # same counter's reading for a 1 GiB plain copy (FETCH x2.0, WRITE x1.0). Valid only for the traversal
 # kernel source whose SHA-256 starts with this prefix; otherwise traffic is reported as null.
-MEASURED_TRAFFIC = {"source_sha256_16": "fc241b489bbb5133", "raw6w4q": 16.295e9, "raw6w4": 16.850e9, "none": 9.791e9}
+MEASURED_TRAFFIC = {"source_sha256_16": "a0abc65170e68816", "raw6w4q": 16.625e9, "raw6w4": 16.850e9, "none": 9.788e9}
 TRACE_SOURCE = os.path.join(ROOT, "paper_2305_08343_amd", "csrc", "kernels_trace.hip")
 
 # width 2: binary nodes (node_bytes per visit); width 4: 4-wide nodes of Sect. 3.2.4 (child records of

@@ -202,21 +202,23 @@ constexpr uint32_t kLdsPerCu = 160u * 1024u;  // gfx950
 // The plain 4-wide kernel and the 4-wide kernels for R = 4 raw masks and for
 // the bit table run faster held to 80 VGPRs (6 waves); the other 4-wide mask
 // kernels spill on their hot path there and are held to 96 VGPRs (5 waves),
-// which they fit without spilling. Where LDS already allows fewer waves than
-// that, the target is what LDS allows: registers beyond it would buy nothing.
-template <uint32_t MODE, int R, int WIDTH, int BLOCK, int STACK>
+// which they fit without spilling, except the R = 6 raw kernel on quantised
+// boxes, which fits 80 without spilling and runs faster there. Where LDS already
+// allows fewer waves than that, the target is what LDS allows: registers beyond
+// it would buy nothing.
+template <uint32_t MODE, int R, int WIDTH, int BLOCK, int STACK, bool QUANT = false>
 struct MinWaves {
     static constexpr int target =
-        (WIDTH == 4 && (MODE == kModeNone || (MODE == kModeRaw && R == 4) || MODE == kModeLutBits)) ? 6
-        : (WIDTH == 4)                                                                              ? 5
-                                                                                                    : 1;
+        (WIDTH == 4 && (MODE == kModeNone || (MODE == kModeRaw && (R == 4 || QUANT)) || MODE == kModeLutBits)) ? 6
+        : (WIDTH == 4)                                                                                         ? 5
+                                                                                                               : 1;
     static constexpr int lds_waves =
         (int)((kLdsPerCu / trace_lds_bytes<MODE, R, BLOCK, STACK>()) * (uint32_t)(BLOCK / kWave) / 4u);
     static constexpr int value = (lds_waves < target) ? (lds_waves > 1 ? lds_waves : 1) : target;
 };
 
 template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH, int WIDTH, bool QUANT = false>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MinWaves<MODE, R, WIDTH, BLOCK, STACK>::value)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MinWaves<MODE, R, WIDTH, BLOCK, STACK, QUANT>::value)))
 void trace_kernel(TraceLaunch a) {
     static_assert(WIDTH == 2 || (WIDTH == 4 && !BATCH && MODE != kModeSparse), "4-wide: single scene, no sparse masks");
     constexpr int W = (R * R * R + 63) / 64;
