@@ -64,7 +64,7 @@ MODES = {
     "raw4w4lq": dict(mode="raw", R=4, cull=True, width=4, mask_bytes=8, mask_slots="leaves", quantise=True,
                      child_bytes=16, tune=(256, 12, 1, 8, 6, 0, 0, 12, 8)),
     "lut6w4q": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, quantise=True, child_bytes=16,
-                    tune=(256, 12, 1, 8, 6, 0)),
+                    tune=(256, 12, 1, 8, 0, 0, 1, 12, 12)),
     "lut4k256w4q": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, quantise=True, child_bytes=16,
                         tune=(256, 8, 1, 8, 0, 0)),
     "lut6w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, tune=(256, 12, 1, 8, 6, 0)),
