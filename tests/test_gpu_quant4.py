@@ -233,3 +233,24 @@ def test_lut_modes_bit_exact(ctx, small_scene, small_oracle, quant_oracle, R, K,
     s.close()
     _compare(dev, ora)
     assert (fp.cpu().numpy().view(np.uint32) == ora.slot_fp).all() and ora.slot_fp.sum() > 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_lut_micro_scenes(ctx, seed):
+    """Compressed masks (K = 64) on quantised micro scenes, every ray bit for bit."""
+    from paper_2305_08343_amd import binding
+    n = 2 + (seed * 19) % 63
+    tris = scenes.micro_scene(seed + 40, n)
+    rays = np.concatenate([_aimed(tris, 300, seed), scenes.random_rays(100, seed)])
+    bvh = oracle.bvh_build(tris)
+    b4 = oracle.bvh4_collapse(bvh)
+    d4 = oracle.decoded_bvh4(b4, oracle.quantise4(b4))
+    bq = oracle.with_slot_boxes(bvh, d4)
+    ob, delta = oracle.default_bounds(tris)
+    print(f"[gpu-quant4] LUT micro scene {seed} ({n} tris)", flush=True)
+    for R in (4, 6):
+        cb, idx = oracle.compress(oracle.object_masks(tris, bq, R, delta), bq.slot_boxes(), R, 64)
+        s = binding.Scene(ctx, tris, R=R, mode="lut", K=64, width=4, quantise=True)
+        dev = s.trace(rays).numpy()
+        s.close()
+        _compare(dev, oracle.trace4(tris, bq, d4, rays, mode="lut", R=R, codebook=cb, cidx=idx, origin_bound=ob))
