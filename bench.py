@@ -1,25 +1,24 @@
 """Benchmark: rays/s and (box + triangle) tests per ray, culled vs unculled, on one MI355X.
 
-Workload (the 1M-triangle hair configuration): 1,000,002 float32 triangles
-(20k helical ribbon strands x 25 segments x 2 triangles, width 1e-3, curl
-radius 5e-3, tilt up to 60 degrees, plus a 2-triangle ground plane) and
-4,147,200 rays (1920x1080 pinhole primaries followed by one cosine-diffuse
-surface ray per pixel). One step = one trace of the whole ray batch, rays
-and scene resident in HBM. The headline value is the 216-bit (R = 6) raw-mask
-culled trace on the 4-wide BVH (Sect. 3.2.4 node: four child boxes and
-masks); the same trace with child boxes stored as outward-rounded 8-bit
-steps (raw6w4q, 64-byte nodes), the plain traversal (4-wide float and
-quantised, binary), the binary culled trace and 64-bit (R = 4) masks are
-timed beside it, and raw6w4l: the same masks kept only on leaf children's
-slots (inner children carry the untested full mask). Each mode's launch shape is the one
-the autotuner picked for it on this workload (stored in MODES; --autotune
-re-runs the tuner, --sort switches Morton ray ordering); results never depend
-on it. Other workloads: curly_12m (12M curly diagonal strands, 8M incoherent
-bounce rays, LUT-compressed masks), batch64, placement, approx.
+Default workload (the 12M-triangle curly-hair configuration): 12,000,000
+float32 triangles (120k curly ribbon strands x 50 segments x 2 triangles,
+width 5e-4, curl radius 3e-3, within 15 degrees of the (1,1,1) diagonal) and
+8,000,000 incoherent bounce rays (cosine-diffuse rays leaving uniformly drawn
+surface points). One step = one trace of the whole ray batch, rays and scene
+resident in HBM. The headline value is the culled trace with 216-bit (R = 6)
+masks compressed to a 4,096-entry conservative codebook (Sect. 3.2.2-3.2.3,
+12-bit indices stored in 16 bits) on the 4-wide BVH (Sect. 3.2.4 node: four
+child boxes and their codebook indices), mode lut6w4; the plain traversals
+(4-wide float and quantised boxes, binary), the same codebook on quantised
+child boxes and 64-bit (R = 4) raw masks are timed beside it. Each mode's
+launch shape is the one the autotuner picked for it on this workload (stored
+in MODES; --autotune re-runs the tuner, --sort switches Morton ray ordering);
+results never depend on it. Other workloads: hair_1m (1M-triangle helical
+strands, 4.1M primary + surface rays, raw masks), batch64, placement, approx.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes raw6w4,raw6w4q,raw6w4l,nonew4,nonew4q,none,raw6,raw4w4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes lut6w4,nonew4q,...]
                     [--no-cpu-baseline] [--cpu-seconds S] [--autotune | --tune b,s,c,p,w,o,q,g,f]
-                    [--workload hair_1m|curly_12m|batch64|placement|approx] [--sort stored|0|1]
+                    [--workload curly_12m|hair_1m|batch64|placement|approx] [--sort stored|0|1]
 """
 from __future__ import annotations
 
@@ -42,7 +41,8 @@ RAY_BYTES, HIT_BYTES, EXTRA_BYTES, TRI_BYTES = 32, 16, 8, 48
 # HBM-side bytes per trace launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, each scaled by the
 # same counter's reading for a 1 GiB plain copy (FETCH x2.0, WRITE x1.0). Valid only for the traversal
 # kernel source whose SHA-256 starts with this prefix; otherwise traffic is reported as null.
-MEASURED_TRAFFIC = {"source_sha256_16": "a0abc65170e68816", "raw6w4q": 16.625e9, "raw6w4": 16.850e9, "none": 9.788e9}
+MEASURED_TRAFFIC = {"source_sha256_16": "a0abc65170e68816",
+                    "hair_1m": {"raw6w4q": 16.625e9, "raw6w4": 16.850e9, "none": 9.788e9}}
 TRACE_SOURCE = os.path.join(ROOT, "paper_2305_08343_amd", "csrc", "kernels_trace.hip")
 
 # width 2: binary nodes (node_bytes per visit); width 4: 4-wide nodes of Sect. 3.2.4 (child records of
@@ -82,16 +82,35 @@ MODES = {
 }
 CHILD_BYTES_W4 = 32  # 24-byte box + 4-byte ref + 4 bytes of the node's aux word, per tested child
 
+# Launch shapes the autotuner picked on the 12M-triangle curly workload (8M incoherent rays), where
+# they differ from the hair_1m ones above.
+CURLY_TUNE = {
+    "lut6w4": (256, 12, 1, 8, 6, 1, 0, 12, 12),
+    "lut6w4q": (256, 12, 1, 8, 0, 1, 1, 12, 12),
+    "nonew4": (128, 16, 1, 8, 6, 1, 0, 20, 20),
+    "nonew4q": (256, 12, 1, 8, 6, 1, 0, 12, 12),
+    "none": (256, 12, 1, 8, 0, 1, 0, 24, 20),
+    "raw4w4": (256, 12, 1, 8, 6, 1, 0, 12, 8),
+    "raw4w4q": (256, 12, 1, 8, 6, 1, 0, 12, 8),
+    "raw4w4l": (256, 12, 1, 8, 6, 1, 0, 12, 8),
+    "raw6w4": (256, 12, 1, 8, 6, 1, 0, 12, 12),
+}
 
-def measured_traffic(mode, workload="hair_1m"):
+
+def stored_tune(name, workload):
+    """The launch shape bench.py uses for mode `name` on `workload`."""
+    if workload == "curly_12m" and name in CURLY_TUNE:
+        return CURLY_TUNE[name]
+    return MODES[name].get("tune", ())
+
+
+def measured_traffic(mode, workload):
     import hashlib
-    if workload != "hair_1m":
-        return None
     with open(TRACE_SOURCE, "rb") as f:
         h = hashlib.sha256(f.read()).hexdigest()[:16]
     if h != MEASURED_TRAFFIC["source_sha256_16"]:
         return None
-    return MEASURED_TRAFFIC.get(mode)
+    return MEASURED_TRAFFIC.get(workload, {}).get(mode)
 
 
 def log(msg):
@@ -193,60 +212,84 @@ def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup, autotune=False, wo
     return out, res
 
 
-def cpu_baseline(tris, rays, target_s, width=2):
-    """The oracle as it stands, on this host's cores, on an every-k-th ray sample
-    (R = 6 raw masks, culled, on the binary or the 4-wide BVH)."""
+def cpu_model():
+    """The host CPU's model name as lscpu reports it (else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        return ""
+
+
+def cpu_baseline(tris, rays, target_s, spec):
+    """The oracle as it stands, on this host's cores, in the headline mode's configuration (mask
+    resolution, raw or codebook-compressed masks, binary or 4-wide BVH, exact or quantised child
+    boxes), traversal only, on an every-k-th ray sample sized to about target_s seconds."""
     import oracle
     cores = len(os.sched_getaffinity(0))
+    R, mode, width = spec["R"], spec["mode"], spec["width"]
+    quant = spec.get("quantise", False)
     t0 = time.perf_counter()
     bvh = oracle.bvh_build(tris)
     ob, delta = oracle.default_bounds(tris)
-    masks = oracle.object_masks(tris, bvh, 6, delta, nthreads=cores)
     b4 = oracle.bvh4_collapse(bvh) if width == 4 else None
-    setup = time.perf_counter() - t0
-    lut = oracle.raymask_lut(6)
-
-    def run(sample):
-        kw = dict(mode="raw", R=6, masks=masks, lut=lut, origin_bound=ob, nthreads=cores)
-        if b4 is not None:
-            oracle.trace4(tris, bvh, b4, sample, **kw)
+    if quant:
+        b4 = oracle.decoded_bvh4(b4, oracle.quantise4(b4))
+        bvh = oracle.with_slot_boxes(bvh, b4)
+    kw = dict(mode=mode, R=R, origin_bound=ob)
+    if mode != "none":
+        masks = oracle.object_masks(tris, bvh, R, delta, nthreads=cores)
+        if spec.get("mask_slots") == "leaves":
+            masks = oracle.leaf_slot_masks(masks, bvh, R)
+        if mode == "lut":
+            cb, idx = oracle.compress(masks, bvh.slot_boxes(), R, spec.get("K", 4096))
+            kw.update(codebook=cb, cidx=idx)
         else:
-            oracle.trace(tris, bvh, sample, **kw)
+            kw.update(masks=masks)
+        kw["lut"] = oracle.raymask_lut(R)
+    setup = time.perf_counter() - t0
 
-    # one thread on 65,536 rays spread evenly over the batch (rays/s per core; the first rays
-    # of the image are mostly sky and would flatter it)
-    first = rays[::max(1, rays.shape[0] // 65536)][:65536]
+    def run(sample, nthreads):
+        if b4 is not None:
+            return oracle.trace4(tris, bvh, b4, sample, nthreads=nthreads, **kw)
+        return oracle.trace(tris, bvh, sample, nthreads=nthreads, **kw)
+
+    # one thread on rays spread evenly over the batch (rays/s per core)
+    k1 = max(1, rays.shape[0] // 16384)
+    first = rays[::k1][:16384]
     t0 = time.perf_counter()
-    kw1 = dict(mode="raw", R=6, masks=masks, lut=lut, origin_bound=ob, nthreads=1)
-    if b4 is not None:
-        oracle.trace4(tris, bvh, b4, first, **kw1)
-    else:
-        oracle.trace(tris, bvh, first, **kw1)
+    run(first, 1)
     one = first.shape[0] / (time.perf_counter() - t0)
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
-    except OSError:
-        pass
 
     probe = rays[::4096]
     t0 = time.perf_counter()
-    run(probe)
+    run(probe, cores)
     dt = max(time.perf_counter() - t0, 1e-4)
     want = int(min(rays.shape[0], max(probe.shape[0], probe.shape[0] * target_s / dt)))
     step = max(1, rays.shape[0] // want)
     sample = rays[::step]
     t0 = time.perf_counter()
-    run(sample)
+    run(sample, cores)
     dt = time.perf_counter() - t0
-    return {"value": sample.shape[0] / dt, "unit": "rays/s", "cores": cores, "kind": "oracle", "cpu_model": model,
+    what = (f"{'LUT K=' + str(spec.get('K', 4096)) if mode == 'lut' else mode} masks R={R}"
+            f"{' on leaf slots' if spec.get('mask_slots') == 'leaves' else ''}, culled, "
+            f"{'4-wide' if width == 4 else 'binary'} BVH{' with quantised child boxes' if quant else ''}")
+    return {"value": sample.shape[0] / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "one_thread": {"value": one, "unit": "rays/s",
-                           "sample": f"every {max(1, rays.shape[0] // 65536)}th ray ({first.shape[0]:,} rays), 1 thread"},
+                           "sample": f"every {k1}th ray ({first.shape[0]:,} rays), 1 thread"},
             "sample": (f"all {rays.shape[0]:,} rays" if step == 1 else
-                       f"every {step}th ray of the {rays.shape[0]:,} ({sample.shape[0]} rays)") + ", R=6 raw masks, "
-                      f"culled, {'4-wide' if width == 4 else 'binary'} BVH; {dt:.1f} s of trace on {cores} "
-                      f"threads; oracle BVH+mask setup {setup:.1f} s not timed"}
+                       f"every {step}th ray of the {rays.shape[0]:,} ({sample.shape[0]:,} rays)") +
+                      f", {what}; {dt:.1f} s of traversal on {cores} threads; oracle BVH, mask and codebook "
+                      f"set-up {setup:.1f} s not timed"}
 
 
 def run_batch64(args, ctx):
@@ -406,14 +449,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="raw6w4,raw6w4q,raw6w4l,nonew4,nonew4q,none,raw6,raw4w4")
+    ap.add_argument("--modes", default="",
+                    help="comma-separated MODES keys; the first is the headline (default per workload)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick each mode's launch shape live with the autotuner instead of the stored one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tune", default="", help="block,stack,chunk,parts[,waves[,sort[,codebook[,gather[,refill]]]]] of the traversal launch")
-    ap.add_argument("--workload", default="hair_1m",
-                    choices=["hair_1m", "curly_12m", "batch64", "placement", "approx"])
+    ap.add_argument("--workload", default="curly_12m",
+                    choices=["curly_12m", "hair_1m", "batch64", "placement", "approx"])
     ap.add_argument("--sort", choices=["stored", "0", "1"], default="stored",
                     help="Morton ray ordering: as stored in each mode's launch shape, off, or on")
     ap.add_argument("--place-scenes", type=int, default=200)
@@ -433,7 +477,7 @@ def main():
 
     if args.workload == "batch64":
         ctx = binding.Context(0)
-        if args.modes == ap.get_default("modes"):
+        if not args.modes:
             args.modes = "raw6,none"
         run_batch64(args, ctx)
         ctx.close()
@@ -452,19 +496,21 @@ def main():
     if args.workload == "curly_12m":
         tris = scenes.scene_curly_12m(2)
         rays = scenes.rays_curly_12m(tris)
-        if args.modes == ap.get_default("modes"):
-            args.modes = "lut6w4,lut6,nonew4,none,raw4w4,lut4k256w4"
-        # the oracle's mask build alone takes minutes at 12M triangles: no CPU leg here
-        args.no_cpu_baseline = True
-        desc = ("curly_12m: 12,000,000 tris (120k curly strands x 50 segments x 2 tris, diagonal to the axes), "
-                "8,000,000 incoherent surface bounce rays, SAH BVH (binary; 4-wide in the w4 modes), "
-                "216-bit masks LUT-compressed to a 4,096-entry codebook in the lut6 modes")
+        if not args.modes:
+            args.modes = "lut6w4,lut6w4q,nonew4,nonew4q,none,raw4w4,raw4w4q,raw4w4l"
+        desc = ("curly_12m: 12,000,000 tris (120k curly strands x 50 segments x 2 tris, width 5e-4, curl "
+                "radius 3e-3, within 15 deg of the (1,1,1) diagonal), 8,000,000 incoherent bounce rays "
+                "(cosine-diffuse rays from uniformly drawn surface points), SAH BVH (4-wide in the w4 modes), "
+                "216-bit (R=6) masks LUT-compressed to a 4,096-entry conservative codebook in the lut6 modes")
     else:
         tris = scenes.scene_hair_1m(1)
         rays = scenes.rays_hair_1m(tris, 1)
+        if not args.modes:
+            args.modes = "raw6w4,raw6w4q,raw6w4l,nonew4,nonew4q,none,raw6,raw4w4"
         desc = ("hair_1m: 1,000,002 tris (20k helical strands x 25 segments x 2 tris, "
-                "width 1e-3, + ground plane), 4,147,200 rays (1920x1080 primary + 1 "
-                "diffuse surface ray per pixel), SAH BVH (binary; 4-wide in the w4 modes)")
+                "width 1e-3, + ground plane), 4,147,200 rays (1920x1080 pinhole primaries + 2,073,600 "
+                "uniform surface bounce rays: cosine-diffuse rays from uniformly drawn surface points, "
+                "not from the primary hits), SAH BVH (binary; 4-wide in the w4 modes)")
     log(f"generated {tris.shape[0]} tris, {rays.shape[0]} rays in {time.perf_counter() - t0:.1f}s")
     ctx = binding.Context(0)
     autotune = args.autotune and not args.tune
@@ -475,7 +521,7 @@ def main():
         if args.tune:
             ctx.set_tune(*(int(x) for x in args.tune.split(",")))
         else:
-            ctx.set_tune(*MODES[m].get("tune", ()))
+            ctx.set_tune(*stored_tune(m, args.workload))
         if args.sort != "stored":
             t = ctx.get_tune()
             ctx.set_tune(t["block"], t["stack"], t["chunk"], t["parts"], t["waves"], int(args.sort), t["codebook"],
@@ -531,7 +577,7 @@ def main():
         line["copy_probe_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(tris, rays, args.cpu_seconds, MODES[head]["width"])
+        line["cpu_baseline"] = cpu_baseline(tris, rays, args.cpu_seconds, MODES[head])
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -993,22 +993,31 @@ int orc_bvh4_collapse(const float* cbox, const uint32_t* cref, uint32_t n_inner,
  * compressed wide BVHs, applied to the 4-wide nodes above). Per node m and
  * axis a, over the used children only:
  *   lo_a  = min of the children's minima, hi_a = max of their maxima;
+ *   dec(q, e) = float32(lo_a + float32(q * 2^e)), the decoded plane of count q
+ *           at step 2^e: q * 2^e is exact in float32 (8 significant bits times
+ *           a normal power of two), so the sum rounds once;
  *   e_a   = the smallest integer in [-126, 127] with 255 * 2^e_a >= hi_a - lo_a
- *           (the difference taken exactly, in double);
- *   qlo   = floor((child min - lo_a) / 2^e_a), qhi = ceil((child max - lo_a) / 2^e_a),
- *           both in [0, 255];
- *   decoded plane = float32(lo_a + float32(q * 2^e_a)).
- * q * 2^e_a is exact in float32 (8 significant bits, a normal power of two),
- * and rounding the sum to nearest is monotone with the exact child plane a
- * float on the right side of it, so every decoded box contains its child's
- * box. Unused slots get q = 0 and a zero decoded box. Outputs: lo[3m + a],
- * ebias[3m + a] = e_a + 127, q[24m + 6c + j] (qlo xyz, qhi xyz), dec in the
- * layout of box4.
+ *           (that difference rounded to double), raised by one while some
+ *           child's maximum exceeds dec(255, e_a);
+ *   qlo   = floor((child min - lo_a) / 2^e_a) in [0, 255], lowered while
+ *           dec(qlo) > child min; qhi = ceil((child max - lo_a) / 2^e_a) in
+ *           [0, 255], raised while dec(qhi) < child max.
+ * The quotients are only first guesses: child min - lo_a rounds in double when
+ * the two differ greatly in magnitude, so the decoded plane itself is checked.
+ * dec(0) = lo_a <= every child min and dec(255) >= every child max at the
+ * final exponent, so every decoded box contains its child's box. Unused slots
+ * get q = 0 and a zero decoded box. Outputs: lo[3m + a], ebias[3m + a] =
+ * e_a + 127, q[24m + 6c + j] (qlo xyz, qhi xyz), dec in the layout of box4.
  * ---------------------------------------------------------------------- */
 static int quant_exponent(double ext) {
     int e = -126;
     while (e < 127 && 255.0 * ldexp(1.0, e) < ext) ++e;
     return e;
+}
+
+static float quant_decode(float l, uint32_t q, float stepf) {
+    const float p = (float)q * stepf;
+    return l + p;
 }
 
 int orc_quantise4(const float* box4, const uint32_t* ref4, uint32_t n4, float* lo, uint8_t* ebias,
@@ -1023,7 +1032,9 @@ int orc_quantise4(const float* box4, const uint32_t* ref4, uint32_t n4, float* l
                 if (b[3 + a] > h) h = b[3 + a];
             }
             if (l > h) { l = 0.0f; h = 0.0f; }  /* no used child */
-            const int e = quant_exponent((double)h - (double)l);
+            int e = quant_exponent((double)h - (double)l);
+            /* raise the exponent until the largest count reaches every child maximum */
+            while (e < 127 && quant_decode(l, 255u, (float)ldexp(1.0, e)) < h) ++e;
             const double step = ldexp(1.0, e);
             const float stepf = (float)step;
             lo[3 * (size_t)m + a] = l;
@@ -1035,17 +1046,20 @@ int orc_quantise4(const float* box4, const uint32_t* ref4, uint32_t n4, float* l
                     dec[k + a] = 0.0f; dec[k + 3 + a] = 0.0f;
                     continue;
                 }
-                double ql = floor(((double)box4[k + a] - (double)l) / step);
-                double qh = ceil(((double)box4[k + 3 + a] - (double)l) / step);
+                const float bl = box4[k + a], bh = box4[k + 3 + a];
+                double ql = floor(((double)bl - (double)l) / step);
+                double qh = ceil(((double)bh - (double)l) / step);
                 if (ql < 0.0) ql = 0.0;
                 if (ql > 255.0) ql = 255.0;
                 if (qh < 0.0) qh = 0.0;
                 if (qh > 255.0) qh = 255.0;
-                q[k + a] = (uint8_t)ql;
-                q[k + 3 + a] = (uint8_t)qh;
-                const float pl = (float)q[k + a] * stepf, ph = (float)q[k + 3 + a] * stepf;
-                dec[k + a] = l + pl;
-                dec[k + 3 + a] = l + ph;
+                uint32_t il = (uint32_t)ql, ih = (uint32_t)qh;
+                while (il > 0 && quant_decode(l, il, stepf) > bl) --il;
+                while (ih < 255 && quant_decode(l, ih, stepf) < bh) ++ih;
+                q[k + a] = (uint8_t)il;
+                q[k + 3 + a] = (uint8_t)ih;
+                dec[k + a] = quant_decode(l, il, stepf);
+                dec[k + 3 + a] = quant_decode(l, ih, stepf);
             }
         }
     }

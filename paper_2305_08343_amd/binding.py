@@ -148,6 +148,22 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _on_stream(stream):
+    """Context in which a call's input copies and output allocations are made on `stream`, the
+    stream the library runs the call on. A stream other than the current one first waits for the
+    current stream, so inputs produced there are complete before the library reads them, and
+    temporaries allocated under it belong to it in torch's caching allocator."""
+    import contextlib
+
+    import torch
+    if stream is None:
+        return contextlib.nullcontext()
+    cur = torch.cuda.current_stream(stream.device)
+    if stream != cur:
+        stream.wait_stream(cur)
+    return torch.cuda.stream(stream)
+
+
 class Context:
     """An sc_ctx on one device; scene memory comes from torch's allocator."""
 
@@ -290,7 +306,8 @@ class Scene:
             raise ValueError("mask_slots must be 'all' or 'leaves'")
         if not isinstance(tris, torch.Tensor):
             tris = torch.from_numpy(np.ascontiguousarray(tris, np.float32))
-        tris = tris.to(device=f"cuda:{ctx.device}", dtype=torch.float32).contiguous()
+        with _on_stream(stream):
+            tris = tris.to(device=f"cuda:{ctx.device}", dtype=torch.float32).contiguous()
         n = tris.shape[0]
         p = sc_build_params()
         lib.sc_build_params_default(C.byref(p))
@@ -365,8 +382,9 @@ class Scene:
         """Per-slot placement features, device float32 [2*n_inner, 12]."""
         import torch
         S = 2 * self.info["n_inner"]
-        out = torch.empty((max(S, 1), 12), dtype=torch.float32, device=f"cuda:{self.ctx.device}")
-        _check(load().sc_slot_features(self.handle, _ptr(out), _stream_ptr(stream)), "sc_slot_features")
+        with _on_stream(stream):
+            out = torch.empty((max(S, 1), 12), dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+            _check(load().sc_slot_features(self.handle, _ptr(out), _stream_ptr(stream)), "sc_slot_features")
         return out[:S]
 
     def trace(self, rays, *, cull: bool = True, shadow: bool = False, extra: bool = True, sort: bool = False,
@@ -376,17 +394,18 @@ class Scene:
         dev = f"cuda:{self.ctx.device}"
         if not isinstance(rays, torch.Tensor):
             rays = torch.from_numpy(np.ascontiguousarray(rays, np.float32))
-        rays = rays.to(device=dev, dtype=torch.float32).contiguous()
-        n = rays.shape[0]
-        if hits is None:
-            hits = torch.empty((max(n, 1), 4), dtype=torch.int32, device=dev)
-        if extra and extra_out is None:
-            extra_out = torch.empty((max(n, 1), 2), dtype=torch.int32, device=dev)
-        flags = ((SC_TRACE_CULL if cull else 0) | (SC_TRACE_SHADOW if shadow else 0) |
-                 (SC_TRACE_SORT if sort else 0))
-        _check(load().sc_trace(self.handle, _ptr(rays), n, flags, _ptr(hits),
-                               _ptr(extra_out) if extra else None, _ptr(slot_fp),
-                               _stream_ptr(stream)), "sc_trace")
+        with _on_stream(stream):
+            rays = rays.to(device=dev, dtype=torch.float32).contiguous()
+            n = rays.shape[0]
+            if hits is None:
+                hits = torch.empty((max(n, 1), 4), dtype=torch.int32, device=dev)
+            if extra and extra_out is None:
+                extra_out = torch.empty((max(n, 1), 2), dtype=torch.int32, device=dev)
+            flags = ((SC_TRACE_CULL if cull else 0) | (SC_TRACE_SHADOW if shadow else 0) |
+                     (SC_TRACE_SORT if sort else 0))
+            _check(load().sc_trace(self.handle, _ptr(rays), n, flags, _ptr(hits),
+                                   _ptr(extra_out) if extra else None, _ptr(slot_fp),
+                                   _stream_ptr(stream)), "sc_trace")
         return TraceResult(hits[:n], extra_out[:n] if extra else None)
 
     def ray_order(self, rays, stream=None):
@@ -395,10 +414,12 @@ class Scene:
         dev = f"cuda:{self.ctx.device}"
         if not isinstance(rays, torch.Tensor):
             rays = torch.from_numpy(np.ascontiguousarray(rays, np.float32))
-        rays = rays.to(device=dev, dtype=torch.float32).contiguous()
-        n = rays.shape[0]
-        out = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
-        _check(load().sc_ray_order(self.handle, _ptr(rays), n, _ptr(out), _stream_ptr(stream)), "sc_ray_order")
+        with _on_stream(stream):
+            rays = rays.to(device=dev, dtype=torch.float32).contiguous()
+            n = rays.shape[0]
+            out = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+            _check(load().sc_ray_order(self.handle, _ptr(rays), n, _ptr(out), _stream_ptr(stream)),
+                   "sc_ray_order")
         return out[:n]
 
 
@@ -450,6 +471,11 @@ class Batch:
             self.handle = h
 
     def launch(self, stream=None):
+        if stream is not None:
+            import torch
+            cur = torch.cuda.current_stream(stream.device)
+            if stream != cur:
+                stream.wait_stream(cur)  # the rays were copied on the stream current at construction
         if self.handle is not None:
             _check(load().sc_batch_launch(self.handle, _stream_ptr(stream)), "sc_batch_launch")
         else:

@@ -83,12 +83,16 @@ void collapse_bvh4(const HostBVH& B, HostBVH4& out) {
 // Child boxes as whole steps from the node's minimum corner, the child-box
 // compression of compressed wide BVHs (a layout choice; the paper keeps float
 // boxes). Per node and axis, over the used children: the corner is the least
-// child minimum, the step 2^e has the smallest e in [-126, 127] for which 255
-// steps cover the extent (taken exactly in double), minima round down and
-// maxima up to whole steps. Decoding corner + q * 2^e in float32 multiplies
-// exactly (8-bit q, a normal power of two) and rounds the sum to nearest, which
-// cannot cross the float child plane the exact sum lies beyond, so the decoded
-// box contains the child's box.
+// child minimum; the step 2^e starts at the smallest e in [-126, 127] for which
+// 255 steps cover the extent (rounded to double) and grows while the largest
+// count, decoded, falls short of the greatest child maximum; minima round down
+// and maxima up to whole steps. A plane decodes as corner + q * 2^e in float32
+// with one rounding (the product is exact: 8-bit q times a normal power of
+// two), exactly as the traversal's fused multiply-add does. The counts taken
+// from the double quotients are first guesses only -- a child plane minus a
+// corner of much larger magnitude rounds in double -- so each is moved outward
+// until its decoded plane contains the child's plane, and every decoded box
+// contains its child's box.
 namespace {
 
 int step_exponent(double ext) {
@@ -100,6 +104,9 @@ int step_exponent(double ext) {
     while (e < 127 && std::ldexp(255.0, e) < ext) ++e;
     return e;
 }
+
+// the plane the traversal decodes from count q: one rounding of corner + q * step
+inline float decode_plane(float corner, uint32_t q, float step) { return std::fma((float)q, step, corner); }
 
 }  // namespace
 
@@ -120,22 +127,28 @@ void quantise_bvh4(HostBVH4& B4, std::vector<unsigned char>& nodes) {
                 if (box[6 * c + 3 + a] > hi) hi = box[6 * c + 3 + a];
             }
             if (lo > hi) lo = hi = 0.0f;  // no used child
-            const int e = step_exponent((double)hi - (double)lo);
+            int e = step_exponent((double)hi - (double)lo);
+            while (e < 127 && decode_plane(lo, 255u, std::ldexp(1.0f, e)) < hi) ++e;
             const double step = std::ldexp(1.0, e);
             const float stepf = (float)step;
             corner[a] = lo;
             ebias[a] = (uint8_t)(e + 127);
             for (int c = 0; c < 4; ++c) {
                 if (ref[c] == kEmptyRef) continue;
-                double ql = std::floor(((double)box[6 * c + a] - (double)lo) / step);
-                double qh = std::ceil(((double)box[6 * c + 3 + a] - (double)lo) / step);
+                const float cmin = box[6 * c + a], cmax = box[6 * c + 3 + a];
+                double ql = std::floor(((double)cmin - (double)lo) / step);
+                double qh = std::ceil(((double)cmax - (double)lo) / step);
                 ql = ql < 0.0 ? 0.0 : (ql > 255.0 ? 255.0 : ql);
                 qh = qh < 0.0 ? 0.0 : (qh > 255.0 ? 255.0 : qh);
-                q[0][a][c] = (uint8_t)ql;
-                q[1][a][c] = (uint8_t)qh;
-                const float dl = (float)q[0][a][c] * stepf, dh = (float)q[1][a][c] * stepf;
-                box[6 * c + a] = lo + dl;
-                box[6 * c + 3 + a] = lo + dh;
+                uint32_t ul = (uint32_t)ql, uh = (uint32_t)qh;
+                for (; ul > 0 && decode_plane(lo, ul, stepf) > cmin; --ul) {
+                }
+                for (; uh < 255 && decode_plane(lo, uh, stepf) < cmax; ++uh) {
+                }
+                q[0][a][c] = (uint8_t)ul;
+                q[1][a][c] = (uint8_t)uh;
+                box[6 * c + a] = decode_plane(lo, ul, stepf);
+                box[6 * c + 3 + a] = decode_plane(lo, uh, stepf);
             }
         }
         std::memcpy(np, corner, 12);

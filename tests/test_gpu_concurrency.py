@@ -58,3 +58,33 @@ def test_two_threads_two_streams_one_fresh_context():
     ora4 = oracle.trace4(tris, bvh, oracle.bvh4_collapse(bvh), rays, mode="raw", R=6, masks=masks, origin_bound=ob)
     assert all(_same(d, ora2) for d in results[0])
     assert all(_same(d, ora4) for d in results[1])
+
+
+@pytest.mark.timeout(300)
+def test_trace_on_a_side_stream_from_host_rays():
+    """Scene build and traces on a stream that is not the current one, with host triangles and rays
+    (the binding copies them): the copies are ordered before the library's work on that stream, and
+    the results equal the oracle's and those of the current stream."""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2305_08343_amd import binding, scenes
+    tris = scenes.scene_small(0)
+    rays = scenes.rays_small(128)
+    ctx = binding.Context(0)
+    side = torch.cuda.Stream()
+    print("[gpu-conc] side stream, host inputs", flush=True)
+    sc = binding.Scene(ctx, tris, R=6, mode="raw", width=4, stream=side)
+    outs = [sc.trace(rays, stream=side) for _ in range(3)]
+    order = sc.ray_order(rays, stream=side)
+    side.synchronize()
+    base = sc.trace(rays).numpy()
+    got = [o.numpy() for o in outs]
+    ordr = order.cpu().numpy()
+    sc.close()
+    ctx.close()
+    bvh = oracle.bvh_build(tris)
+    ob, delta = oracle.default_bounds(tris)
+    masks = oracle.object_masks(tris, bvh, 6, delta)
+    ora4 = oracle.trace4(tris, bvh, oracle.bvh4_collapse(bvh), rays, mode="raw", R=6, masks=masks, origin_bound=ob)
+    assert _same(base, ora4) and all(_same(d, ora4) for d in got)
+    assert sorted(ordr.tolist()) == list(range(rays.shape[0]))

@@ -10,7 +10,14 @@ curly_12m (12,000,000 tris, 8,000,000 rays): BVH bit-exact; masks of a slot
 sample; every 64th ray bit-exact in every mode (oracle with all masks); and on
 all 8M rays the properties that hold at any size: culled hits equal unculled
 hits, per-ray counts none >= compressed >= raw, every stored codebook entry
-contains its slot's exact mask.
+contains its slot's exact mask. The 4-wide modes bench.py times on this
+workload (216-bit masks compressed to 4,096 codebook entries on exact and on
+quantised child boxes, 64-bit raw masks on every slot and on leaf slots, plain
+traversal), each traced in the launch shape bench.py stores for it: 4-wide
+nodes, codebook and indices bit-exact against the oracle, every 64th ray
+bit-exact against the oracle's 4-wide traversal, and on all 8M rays hits equal
+to the unculled ones with counts none >= compressed and none >= leaf-slot >=
+every-slot raw masks.
 """
 import numpy as np
 import pytest
@@ -200,25 +207,130 @@ def test_curly_12m_properties_all_rays(request, curly_dev):
     assert (np.diff(pc) >= 0).all()
 
 
+@pytest.fixture(scope="module")
+def curly_masks(request, curly):
+    """Oracle masks of every slot (R = 6) and the K = 4096 codebook with Alg. 3 indices."""
+    tris, bvh = curly["tris"], curly["bvh"]
+    _say(request, "curly_12m: oracle masks (all slots, R=6) and codebook K=4096 + Alg. 3")
+    masks = oracle.object_masks(tris, bvh, 6, curly["delta"], nthreads=curly["nt"])
+    cb, idx = oracle.compress(masks, bvh.slot_boxes(), 6, 4096)
+    return {"masks6": masks, "cb": cb, "idx": idx}
+
+
 @pytest.mark.timeout(900)
-def test_curly_12m_sampled_rays_bit_exact(request, curly, curly_dev):
+def test_curly_12m_sampled_rays_bit_exact(request, curly, curly_dev, curly_masks):
     tris, bvh, rays = curly["tris"], curly["bvh"], curly["rays"]
     sel = slice(None, None, 64)
     sample = rays[sel]
     _say(request, f"curly_12m: oracle traces of {sample.shape[0]} sampled rays, plain")
     _compare(curly_dev["none"], oracle.trace(tris, bvh, sample, origin_bound=curly["ob"],
                                              nthreads=curly["nt"]), sel)
-    _say(request, "curly_12m: oracle masks (all slots) for the masked modes")
-    masks = oracle.object_masks(tris, bvh, 6, curly["delta"], nthreads=curly["nt"])
+    masks = curly_masks["masks6"]
     assert (curly_dev["export_raw"]["masks"] == masks).all()
     _compare(curly_dev["raw"], oracle.trace(tris, bvh, sample, mode="raw", R=6, masks=masks,
                                             origin_bound=curly["ob"], nthreads=curly["nt"]), sel)
-    _say(request, "curly_12m: oracle codebook K=4096 + Alg. 3")
-    cb, idx = oracle.compress(masks, bvh.slot_boxes(), 6, 4096)
+    cb, idx = curly_masks["cb"], curly_masks["idx"]
     assert (curly_dev["export_lut"]["codebook"] == cb).all()
     assert (curly_dev["export_lut"]["cidx"] == idx).all()
     _compare(curly_dev["lut"], oracle.trace(tris, bvh, sample, mode="lut", R=6, codebook=cb, cidx=idx,
                                             origin_bound=curly["ob"], nthreads=curly["nt"]), sel)
+
+
+# 4-wide modes of the curly benchmark, each in the launch shape bench.py stores for it there
+CURLY4 = ["lut6w4", "lut6w4q", "raw4w4", "raw4w4l", "nonew4", "nonew4q"]
+
+
+@pytest.fixture(scope="module")
+def curly4_dev(request, ctx, curly):
+    import bench
+    from paper_2305_08343_amd import binding
+    out = {}
+    for name in CURLY4:
+        spec = bench.MODES[name]
+        shape = bench.stored_tune(name, "curly_12m")
+        _say(request, f"curly_12m {name}: device build + trace of 8M rays in shape {shape}")
+        s = binding.Scene(ctx, curly["tris"], R=spec["R"], mode=spec["mode"], K=spec.get("K", 4096), width=4,
+                          quantise=spec.get("quantise", False), mask_slots=spec.get("mask_slots", "all"))
+        try:
+            ctx.set_tune(*shape)
+            out[name] = s.trace(curly["rays"]).numpy()
+        finally:
+            ctx.set_tune()
+        out[f"{name}/export4"] = s.export4()
+        if spec["mode"] == "lut":
+            e = s.export()
+            out[f"{name}/cb"] = (e["codebook"], e["cidx"])
+        s.close()
+    return out
+
+
+@pytest.fixture(scope="module")
+def curly4_oracle(request, curly, curly_masks):
+    """The oracle's 4-wide BVH (exact and decoded quantised boxes) and the masks / codebooks on
+    the slot boxes each mode's traversal tests."""
+    tris, bvh, delta, nt = curly["tris"], curly["bvh"], curly["delta"], curly["nt"]
+    b4 = oracle.bvh4_collapse(bvh)
+    d4 = oracle.decoded_bvh4(b4, oracle.quantise4(b4))
+    bq = oracle.with_slot_boxes(bvh, d4)
+    _say(request, "curly_12m: oracle masks R=4 (exact boxes), R=6 and codebook on the decoded boxes")
+    masks4 = oracle.object_masks(tris, bvh, 4, delta, nthreads=nt)
+    masks6q = oracle.object_masks(tris, bq, 6, delta, nthreads=nt)
+    cbq, idxq = oracle.compress(masks6q, bq.slot_boxes(), 6, 4096)
+    return {"b4": b4, "d4": d4, "bq": bq,
+            "lut6w4": (bvh, b4, dict(mode="lut", R=6, codebook=curly_masks["cb"], cidx=curly_masks["idx"])),
+            "lut6w4q": (bq, d4, dict(mode="lut", R=6, codebook=cbq, cidx=idxq)),
+            "raw4w4": (bvh, b4, dict(mode="raw", R=4, masks=masks4)),
+            "raw4w4l": (bvh, b4, dict(mode="raw", R=4, masks=oracle.leaf_slot_masks(masks4, bvh, 4))),
+            "nonew4": (bvh, b4, {}),
+            "nonew4q": (bq, d4, {})}
+
+
+@pytest.mark.timeout(900)
+def test_curly_12m_4_wide_nodes_and_codebooks(request, curly4_dev, curly4_oracle, curly_masks):
+    _say(request, "curly_12m: 4-wide nodes, codebooks and indices vs oracle")
+    for name in CURLY4:
+        q = name.endswith("q")
+        ob4 = curly4_oracle["d4" if q else "b4"]
+        e4 = curly4_dev[f"{name}/export4"]
+        assert (e4["box4"].view(np.uint32) == ob4.box4.view(np.uint32)).all(), name
+        assert (e4["ref4"] == ob4.ref4).all() and (e4["src4"] == ob4.src4).all(), name
+    for name in ("lut6w4", "lut6w4q"):
+        cb, idx = curly4_dev[f"{name}/cb"]
+        want = curly4_oracle[name][2]
+        assert (cb == want["codebook"]).all() and (idx == want["cidx"]).all(), name
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", CURLY4)
+def test_curly_12m_4_wide_sampled_rays_bit_exact(request, curly, curly4_dev, curly4_oracle, name):
+    sel = slice(None, None, 64)
+    sample = curly["rays"][sel]
+    bvh, b4, kw = curly4_oracle[name]
+    _say(request, f"curly_12m {name}: oracle 4-wide trace of {sample.shape[0]} sampled rays")
+    ora = oracle.trace4(curly["tris"], bvh, b4, sample, origin_bound=curly["ob"], nthreads=curly["nt"], **kw)
+    _compare(curly4_dev[name], ora, sel)
+
+
+@pytest.mark.timeout(900)
+def test_curly_12m_4_wide_properties_all_rays(request, curly_dev, curly4_dev):
+    _say(request, "curly_12m: 4-wide properties over all 8M rays")
+    plain = curly4_dev["nonew4"]
+    for name in CURLY4:
+        d = curly4_dev[name]
+        assert (d["prim"] == plain["prim"]).all(), name
+        assert (d["t"].view(np.uint32) == plain["t"].view(np.uint32)).all(), name
+        assert (d["mask_culls"] <= d["mask_tests"]).all(), name
+    # and the binary BVH's hits
+    assert (curly_dev["none"]["prim"] == plain["prim"]).all()
+    assert (curly_dev["none"]["t"].view(np.uint32) == plain["t"].view(np.uint32)).all()
+    for f in ("box_tests", "tri_tests"):
+        # same tree: culling only removes tests; leaf-slot masks are a superset of all-slot masks
+        assert (plain[f] >= curly4_dev["lut6w4"][f]).all(), f
+        assert (plain[f] >= curly4_dev["raw4w4l"][f]).all(), f
+        assert (curly4_dev["raw4w4l"][f] >= curly4_dev["raw4w4"][f]).all(), f
+        assert (curly4_dev["nonew4q"][f] >= curly4_dev["lut6w4q"][f]).all(), f
+    for name in ("lut6w4", "lut6w4q", "raw4w4", "raw4w4l"):
+        assert curly4_dev[name]["mask_culls"].sum() > 0, name
 
 
 # --------------------------------------------------------------------- batch64

@@ -254,3 +254,29 @@ def test_lut_micro_scenes(ctx, seed):
         dev = s.trace(rays).numpy()
         s.close()
         _compare(dev, oracle.trace4(tris, bq, d4, rays, mode="lut", R=R, codebook=cb, cidx=idx, origin_bound=ob))
+
+
+@pytest.mark.parametrize("kind", ["low", "high"])
+def test_mixed_magnitude_nodes_bit_exact(ctx, kind):
+    """Child planes far smaller than the node's corner (and a greatest maximum the covering step
+    cannot reach): the library's counts, decoded boxes and traces equal the oracle's, whose decoded
+    boxes contain every child box."""
+    from paper_2305_08343_amd import binding
+    from tests.test_oracle_quant4 import mixed_magnitude_case
+    tris, rays = mixed_magnitude_case(kind)
+    bvh = oracle.bvh_build(tris)
+    b4 = oracle.bvh4_collapse(bvh)
+    d4 = oracle.decoded_bvh4(b4, oracle.quantise4(b4))
+    bq = oracle.with_slot_boxes(bvh, d4)
+    ob, delta = oracle.default_bounds(tris)
+    print(f"[gpu-quant4] mixed magnitudes {kind}", flush=True)
+    for mode in ("none", "raw"):
+        s = binding.Scene(ctx, tris, R=6, mode=mode, width=4, quantise=True)
+        e4 = s.export4()
+        dev = s.trace(rays).numpy()
+        s.close()
+        assert (e4["box4"].view(np.uint32) == d4.box4.view(np.uint32)).all()
+        kw = dict(origin_bound=ob)
+        if mode == "raw":
+            kw.update(mode="raw", R=6, masks=oracle.object_masks(tris, bq, 6, delta))
+        _compare(dev, oracle.trace4(tris, bq, d4, rays, **kw), masks=(mode == "raw"))

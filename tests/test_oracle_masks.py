@@ -162,3 +162,42 @@ def test_micro_scene_masks(seed):
         slots = list(range(2 * bvh.n_inner))
         _check_conservative(tris, bvh, m, R, delta, slots, k=12)
         _check_tight(tris, bvh, m, R, delta, slots, k=24)
+
+
+@pytest.mark.parametrize("R", [4, 6])
+def test_slot_masks_equal_rows_of_all_slot_masks(small_scene, small_oracle, R):
+    """The per-slot builder (used to check sampled slots of large scenes) gives exactly the
+    rows of the all-slot builder, for slot lists that mix child 0 and child 1, leaf and inner
+    children, the root's slots, repeated and unsorted slots, and the empty list."""
+    tris, _ = small_scene
+    bvh = small_oracle["bvh"]
+    full = small_oracle[f"masks{R}"]
+    S = 2 * bvh.n_inner
+    leaf = (bvh.cref.reshape(-1) & np.uint32(oracle.LEAF_BIT)) != 0
+    rng = np.random.default_rng(R)
+    picks = [
+        np.arange(4),                                                 # root's and its children's slots
+        rng.integers(0, S, 500),                                       # random, repeats, any order
+        rng.choice(np.flatnonzero(leaf), 200),                         # leaf children only
+        rng.choice(np.flatnonzero(~leaf), 200),                        # inner children only
+        np.array([S - 1, 0, S - 2, 1]),                                # last slots first
+    ]
+    for slots in picks:
+        slots = np.asarray(slots, np.uint32)
+        assert (slots % 2 == 0).any() and (slots % 2 == 1).any()
+        got = oracle.slot_masks(tris, bvh, slots, R, small_oracle["delta"])
+        assert got.shape == (slots.size, oracle.words_for(R))
+        assert (got == full[slots]).all()
+    assert oracle.slot_masks(tris, bvh, np.zeros(0, np.uint32), R, small_oracle["delta"]).shape[0] == 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_slot_masks_micro_scenes(seed):
+    tris = scenes.micro_scene(seed, 5 + (seed * 17) % 60)
+    bvh = oracle.bvh_build(tris)
+    if bvh.n_inner == 0:
+        pytest.skip("a single leaf has no child slots")
+    _, delta = oracle.default_bounds(tris)
+    full = oracle.object_masks(tris, bvh, 6, delta)
+    slots = np.arange(2 * bvh.n_inner, dtype=np.uint32)[::-1].copy()
+    assert (oracle.slot_masks(tris, bvh, slots, 6, delta) == full[slots]).all()

@@ -10,8 +10,13 @@ own code:
   * for every node of real collapses: each decoded box contains the exact
     child box (the property the traversal relies on), each decoded plane lies
     within one step (and the final rounding) of the exact one, the exponent is
-    the smallest whose 255 steps cover the extent, and the corner is an exact
-    child plane;
+    the smallest whose 255 steps cover the extent unless the float32 decode of
+    255 steps at a smaller one falls short of the greatest child maximum, and
+    the corner is an exact child plane;
+  * hand-worked nodes whose child planes differ greatly in magnitude from the
+    corner (where the double quotient alone would give a count whose decoded
+    plane cuts into the child, or the covering step would fall short), with
+    the counts worked out on paper;
   * Alg. 4 over the decoded boxes, plain and with masks built on the decoded
     boxes, returns the brute-force closest hit (closest hit and ties as in the
     binary traversal).
@@ -53,6 +58,49 @@ def test_hand_worked_node():
     assert qt.dec[0, 1].tolist() == [0.0, -1.5, 5.0, 1.0, 3.0, 5.0]
 
 
+def _dec32(corner, q, e):
+    """The float32 decode of count q at step 2^e: exact product, one rounding of the sum."""
+    return np.float32(np.float32(corner) + np.float32(np.float32(q) * np.float32(2.0 ** e)))
+
+
+def test_mixed_magnitude_node_contains_children():
+    # x: child 0 spans [-1, 1], so the corner is -1 and the step 2^-6 (255 * 2^-7 < 2 <= 255 * 2^-6).
+    # Child 1 spans [-2^-60, 2^-60]. In double, -2^-60 - (-1) rounds to 1 and 2^-60 - (-1) to 1, so the
+    # quotients give counts 64 and 64, decoding both planes to exactly 0.0 -- outside the child on the
+    # minimum side. Checked with the decode itself, the minimum moves down to 63 (-0.015625) and the
+    # maximum up to 65 (0.015625).
+    box4 = np.zeros((1, 4, 6), np.float32)
+    box4[0, 0] = [-1.0, -1.0, -1.0, 1.0, 1.0, 1.0]
+    box4[0, 1] = [-2.0 ** -60, 0.0, 0.0, 2.0 ** -60, 0.5, 0.5]
+    ref4 = np.array([[LEAF | 0, LEAF | 1, EMPTY, EMPTY]], np.uint32)
+    b4 = oracle.BVH4(box4, ref4, np.array([[0, 1, EMPTY, EMPTY]], np.uint32), 0, 1)
+    qt = oracle.quantise4(b4)
+    assert qt.ebias[0, 0] == 127 - 6
+    assert (qt.q[0, 1, 0], qt.q[0, 1, 3]) == (63, 65)
+    assert (qt.dec[0, 1, 0], qt.dec[0, 1, 3]) == (-0.015625, 0.015625)
+    _check_quant(b4, qt)
+
+
+def test_exponent_raised_when_the_largest_count_falls_short():
+    # x: corner -255 * 2^40 (child 0 spans [-255 * 2^40, -1]), greatest maximum 2^-40 (child 1 spans
+    # [-1, 2^-40]). The extent 255 * 2^40 + 2^-40 rounds to 255 * 2^40 in double, so 2^40 would be the
+    # covering step, but 255 steps from the corner decode to 0.0 < 2^-40. The step becomes 2^41: child 1's
+    # maximum needs ceil(127.5) = 128 steps (decoded 2^40), its minimum floor(127.49...) = 127 steps
+    # (decoded -2^40); child 0 keeps 0 and 128 (-1 + 255 * 2^40 = 127.49... * 2^41, rounded up).
+    big = np.float32(255.0 * 2.0 ** 40)
+    box4 = np.zeros((1, 4, 6), np.float32)
+    box4[0, 0] = [-big, 0.0, 0.0, -1.0, 1.0, 1.0]
+    box4[0, 1] = [-1.0, 0.0, 0.0, 2.0 ** -40, 1.0, 1.0]
+    ref4 = np.array([[LEAF | 0, LEAF | 1, EMPTY, EMPTY]], np.uint32)
+    b4 = oracle.BVH4(box4, ref4, np.array([[0, 1, EMPTY, EMPTY]], np.uint32), 0, 1)
+    qt = oracle.quantise4(b4)
+    assert qt.ebias[0, 0] == 127 + 41
+    assert qt.q[0, 0, [0, 3]].tolist() == [0, 128]
+    assert qt.q[0, 1, [0, 3]].tolist() == [127, 128]
+    assert qt.dec[0, 1, 0] == -(2.0 ** 40) and qt.dec[0, 1, 3] == 2.0 ** 40
+    _check_quant(b4, qt)
+
+
 def _check_quant(b4, qt):
     used = b4.ref4 != EMPTY
     ex = b4.box4.astype(np.float64)
@@ -67,7 +115,15 @@ def _check_quant(b4, qt):
         assert (qt.lo[m].astype(np.float64) == lo).all()       # the corner is an exact child plane
         ext = hi - lo
         assert (255.0 * step[m] >= ext).all()
-        assert ((e[m] == -126) | (255.0 * step[m] / 2 < ext)).all()   # smallest such exponent
+        # the smallest covering exponent, raised only while the largest count decoded in
+        # float32 falls short of the greatest child maximum
+        for a in range(3):
+            e0 = -126
+            while e0 < 127 and 255.0 * 2.0 ** e0 < ext[a]:
+                e0 += 1
+            assert e[m, a] >= e0
+            for k in range(e0, int(e[m, a])):
+                assert _dec32(qt.lo[m, a], 255, k) < np.float32(hi[a])
         # containment, plane by plane
         assert (dec[m, u, :3] <= ex[m, u, :3]).all() and (dec[m, u, 3:] >= ex[m, u, 3:]).all()
         # within one step plus the float32 rounding of the decoded sum
@@ -199,3 +255,42 @@ def test_quantised_boxes_extreme_scales(name):
         assert np.allclose(h.t, bt, rtol=1e-6, atol=0)
     else:
         assert _same(h, bp, bt)
+
+
+def mixed_magnitude_case(kind):
+    """Eight triangles in two clusters of four, apart in y, so the BVH is one inner node over two
+    leaves and the 4-wide root holds two children whose x ranges are those of the hand-worked
+    nodes above: "low" [-1, 1] and [-2^-60, 2^-60] (counts from the double quotients would cut
+    into the second child), "high" [-255 * 2^40, -1] and [-1, 2^-40] (the covering step would fall
+    short of the second child's maximum). Rays aimed at the triangles plus random rays."""
+    if kind == "low":
+        xa, xb = (-1.0, 1.0), (-(2.0 ** -60), 2.0 ** -60)
+    else:
+        xa, xb = (-255.0 * 2.0 ** 40, -1.0), (-1.0, 2.0 ** -40)
+    tris = []
+    for k in range(4):
+        z = 0.1 * k
+        tris.append([[xa[0], 2.0, z], [xa[1], 2.5, z + 0.05], [0.5 * (xa[0] + xa[1]), 3.0, z + 0.1]])
+        tris.append([[xb[0], 0.1 * k, z], [xb[1], 0.1 * k + 0.2, z + 0.05], [0.0, 0.1 * k + 0.4, z + 0.1]])
+    tris = np.asarray(tris, np.float32)
+    rays = np.concatenate([_aimed_rays(tris, 400, 9), scenes.random_rays(100, 9)])
+    return tris, rays
+
+
+@pytest.mark.parametrize("kind", ["low", "high"])
+def test_mixed_magnitude_scene(kind):
+    tris, rays = mixed_magnitude_case(kind)
+    bvh = oracle.bvh_build(tris)
+    b4 = oracle.bvh4_collapse(bvh)
+    assert b4.n4 == 1 and (b4.ref4[0, :2] & LEAF).all() and (b4.ref4[0, 2:] == EMPTY).all()
+    xs = sorted((float(b4.box4[0, c, 0]), float(b4.box4[0, c, 3])) for c in range(2))
+    want = {"low": [(-1.0, 1.0), (-(2.0 ** -60), 2.0 ** -60)],
+            "high": [(-255.0 * 2.0 ** 40, -1.0), (-1.0, 2.0 ** -40)]}[kind]
+    assert xs == sorted(want)
+    qt = oracle.quantise4(b4)
+    _check_quant(b4, qt)
+    d4 = oracle.decoded_bvh4(b4, qt)
+    bp, bt = oracle.brute_closest(tris, rays)
+    assert (bp != oracle.NO_HIT).sum() > 100
+    h = oracle.trace4(tris, oracle.with_slot_boxes(bvh, d4), d4, rays)
+    assert _same(h, bp, bt)
