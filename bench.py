@@ -71,6 +71,8 @@ MODES = {
     "lut4k256w4": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 0, 0)),
     "lut6k256w4": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=256, tune=(256, 8, 1, 8, 6, 0)),
     "lut6w4b": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, bit_table=True, tune=(256, 12, 1, 8, 0, 0, 0, 8, 16)),
+    "lut6w4bq": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=4096, bit_table=True, quantise=True,
+                     child_bytes=16, tune=(256, 12, 1, 8, 6, 0, 0, 12, 12)),
     "lut6k256w4b": dict(mode="lut", R=6, cull=True, width=4, mask_bytes=0, K=256, bit_table=True, tune=(256, 12, 1, 8, 6, 0)),
     "lut4k256w4b": dict(mode="lut", R=4, cull=True, width=4, mask_bytes=0, K=256, bit_table=True, tune=(256, 12, 1, 8, 0, 0)),
     "raw6": dict(mode="raw", R=6, cull=True, width=2, node_bytes=128, tune=(256, 12, 1, 8, 6, 1, 0, 12, 32)),
@@ -94,6 +96,8 @@ CURLY_TUNE = {
     "raw4w4q": (256, 12, 1, 8, 6, 1, 0, 12, 8),
     "raw4w4l": (256, 12, 1, 8, 6, 1, 0, 12, 8),
     "raw6w4": (256, 12, 1, 8, 6, 1, 0, 12, 12),
+    "lut6w4b": (256, 12, 1, 8, 6, 1, 0, 12, 24),
+    "lut6w4bq": (256, 12, 1, 8, 6, 1, 0, 12, 24),
 }
 
 
@@ -166,12 +170,16 @@ def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup, autotune=False, wo
     extra = torch.empty((n, 2), dtype=torch.int32, device=rays_dev.device)
     tuned = None
     if autotune:
-        key = f"{workload}|{name}|{tris.shape[0]}|{n}"
+        # shapes are compared on an evenly strided subsample of about 1M rays (still many times the
+        # waves the GPU holds at once); the timed run below confirms the pick on every ray
+        k = max(1, n // 1_000_000)
+        sub = rays_dev[::k].contiguous()
+        key = f"{workload}|{name}|{tris.shape[0]}|{n}|every{k}"
         lut = spec["mode"] == "lut" and not spec.get("bit_table", False)
-        cfg, entry = tune.tuned(ctx, key, lambda: scene.trace(rays_dev, cull=spec["cull"], hits=hits,
+        cfg, entry = tune.tuned(ctx, key, lambda: scene.trace(sub, cull=spec["cull"], hits=hits,
                                                               extra_out=extra), log=log,
                                 cands=tune.candidates(lut=lut))
-        tuned = {"config": list(cfg), "seconds": entry.get("seconds")}
+        tuned = {"config": list(cfg), "seconds": entry.get("seconds"), "subsample": f"every {k}th ray"}
     res = scene.trace(rays_dev, cull=spec["cull"], hits=hits, extra_out=extra).numpy()
     for _ in range(warmup):
         scene.trace(rays_dev, cull=spec["cull"], hits=hits, extra_out=extra)
@@ -279,10 +287,16 @@ def cpu_baseline(tris, rays, target_s, spec):
     t0 = time.perf_counter()
     run(sample, cores)
     dt = time.perf_counter() - t0
-    what = (f"{'LUT K=' + str(spec.get('K', 4096)) if mode == 'lut' else mode} masks R={R}"
-            f"{' on leaf slots' if spec.get('mask_slots') == 'leaves' else ''}, culled, "
-            f"{'4-wide' if width == 4 else 'binary'} BVH{' with quantised child boxes' if quant else ''}")
-    return {"value": sample.shape[0] / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
+    # untimed: how deep each sampled ray's stack gets (entries beneath the visited node, the stack
+    # the GPU kernel keeps in LDS up to the launch shape's depth and in private memory beyond it)
+    deep = None
+    if b4 is not None:
+        deep = oracle.trace4(tris, bvh, b4, sample, nthreads=cores, stack_depth=True, **kw).deepest
+    masks_txt = ("no masks (plain traversal)" if mode == "none" else
+                 f"{'LUT K=' + str(spec.get('K', 4096)) if mode == 'lut' else mode} masks R={R}"
+                 f"{' on leaf slots' if spec.get('mask_slots') == 'leaves' else ''}, culled")
+    what = f"{masks_txt}, {'4-wide' if width == 4 else 'binary'} BVH{' with quantised child boxes' if quant else ''}"
+    out = {"value": sample.shape[0] / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
             "cpu_model": cpu_model(),
             "one_thread": {"value": one, "unit": "rays/s",
                            "sample": f"every {k1}th ray ({first.shape[0]:,} rays), 1 thread"},
@@ -290,6 +304,16 @@ def cpu_baseline(tris, rays, target_s, spec):
                        f"every {step}th ray of the {rays.shape[0]:,} ({sample.shape[0]:,} rays)") +
                       f", {what}; {dt:.1f} s of traversal on {cores} threads; oracle BVH, mask and codebook "
                       f"set-up {setup:.1f} s not timed"}
+    return out, deep
+
+
+def stack_report(deep, lds_entries):
+    """Stack depth of the sampled rays against the launch shape's LDS stack."""
+    d = np.asarray(deep, np.int64)
+    return {"lds_entries": int(lds_entries), "rays_sampled": int(d.size), "max_entries": int(d.max()),
+            "mean_deepest": float(d.mean()), "p99_deepest": float(np.percentile(d, 99)),
+            "frac_rays_beyond_lds": float((d > lds_entries).mean()),
+            "source": "oracle 4-wide traversal of the cpu_baseline sample (the same visit sequence as the kernel)"}
 
 
 def run_batch64(args, ctx):
@@ -577,7 +601,9 @@ def main():
         line["copy_probe_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(tris, rays, args.cpu_seconds, MODES[head])
+        line["cpu_baseline"], deep = cpu_baseline(tris, rays, args.cpu_seconds, MODES[head])
+        if deep is not None:
+            line["lds_stack"] = stack_report(deep, r["tune"]["stack"])
     print(json.dumps(line), flush=True)
     ctx.close()
 

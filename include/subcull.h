@@ -114,8 +114,10 @@ typedef struct {
     uint32_t quantise;      /* width 4 (modes NONE, RAW, LUT): 1 stores child boxes as
                                8-bit steps from the node's minimum corner (one
                                power-of-two step per axis, the smallest whose
-                               255 steps span the node; minima rounded down,
-                               maxima up), 64-byte nodes. Decoded boxes contain
+                               255 steps, decoded in float32, reach the node's
+                               maximum; each plane moved outward until its
+                               float32 decode contains the child's plane),
+                               64-byte nodes. Decoded boxes contain
                                the exact ones, so hits are those of the exact
                                boxes; the binary slots the 4-wide nodes use take
                                the decoded boxes, and masks, exports and counts

@@ -23,7 +23,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_SAN_LIB = os.path.join(_HERE, "liboracle_san.so")
 _lib = None
+# ORACLE_SANITIZE=1 builds and loads liboracle_san.so (AddressSanitizer + UBSan; run with gcc's
+# libasan preloaded) instead
+_SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
 
 MODES = {"none": 0, "raw": 1, "lut": 2, "sparse": 3}
 FLAG_CULL = 1
@@ -33,23 +37,29 @@ EMPTY_REF = 0xFFFFFFFF
 NO_HIT = 0xFFFFFFFF
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no FMA contraction, no fast math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast math); sanitize=True builds the
+    AddressSanitizer + UBSan variant liboracle_san.so."""
+    out = _SAN_LIB if sanitize else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        if sanitize:
+            cmd[1:1] = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                        "-fno-omit-frame-pointer", "-g"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        _lib = C.CDLL(_LIB)
+        path = _SAN_LIB if _SANITIZE else _LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            build(force=True, sanitize=_SANITIZE)
+        _lib = C.CDLL(path)
     return _lib
 
 
@@ -185,6 +195,7 @@ class Hits:
     mask_tests: np.ndarray
     mask_culls: np.ndarray
     slot_fp: np.ndarray | None = None
+    deepest: np.ndarray | None = None  # trace4(stack_depth=True): stack entries beneath the visited node
 
 
 RAY_MASKS = {"lut": 0, "lut2r": 1, "ideal": 2}
@@ -324,9 +335,11 @@ def with_slot_boxes(bvh: BVH, bvh4: BVH4) -> BVH:
 
 
 def trace4(tris, bvh: BVH, bvh4: BVH4, rays, *, mode="none", R=6, masks=None, codebook=None, cidx=None,
-           placed=None, lut=None, origin_bound=None, cull=True, shadow=False, nthreads=0) -> Hits:
+           placed=None, lut=None, origin_bound=None, cull=True, shadow=False, nthreads=0,
+           stack_depth=False) -> Hits:
     """Alg. 4 on the 4-wide BVH; masks, codebook indices and shadow counts are
-    per binary child slot, as for trace()."""
+    per binary child slot, as for trace(). stack_depth=True also returns, per
+    ray, the most stack entries held beneath the node being visited (Hits.deepest)."""
     tris = np.ascontiguousarray(tris, np.float32)
     rays = np.ascontiguousarray(rays, np.float32)
     n = rays.shape[0]
@@ -346,15 +359,16 @@ def trace4(tris, bvh: BVH, bvh4: BVH4, rays, *, mode="none", R=6, masks=None, co
     b4 = np.ascontiguousarray(bvh4.box4) if bvh4.n4 else np.zeros((1, 4, 6), np.float32)
     r4 = np.ascontiguousarray(bvh4.ref4) if bvh4.n4 else np.zeros((1, 4), np.uint32)
     s4 = np.ascontiguousarray(bvh4.src4) if bvh4.n4 else np.zeros((1, 4), np.uint32)
+    deep = np.zeros(max(n, 1), np.uint32) if stack_depth else None
     rc = lib().orc_trace4(_p(tris), _p(bvh.perm), _p(b4), _p(r4), _p(s4), C.c_uint32(bvh4.root),
                           C.c_uint32(bvh4.depth), C.c_uint32(R), C.c_uint32(mcode), _p(masks), _p(codebook),
                           _p(cidx), _p(placed), _p(lut), C.c_float(origin_bound), C.c_uint32(flags), _p(rays),
-                          C.c_uint32(n), _p(hits), _p(extra), _p(fp), C.c_int(nthreads))
+                          C.c_uint32(n), _p(hits), _p(extra), _p(fp), C.c_int(nthreads), _p(deep))
     _check(rc, "trace4")
     hits, extra = hits[:n], extra[:n]
     return Hits(hits[:, 0].copy(), hits[:, 1].view(np.float32).copy(), hits[:, 2].copy(),
                 hits[:, 3].copy(), extra[:, 0].copy(), extra[:, 1].copy(),
-                None if fp is None else fp[:2 * bvh.n_inner])
+                None if fp is None else fp[:2 * bvh.n_inner], None if deep is None else deep[:n])
 
 
 def bit_table(R: int, cb, lut=None) -> np.ndarray:

@@ -1075,9 +1075,13 @@ typedef struct {
  * it hits, the mask test of its binary slot; surviving children are visited
  * nearest t0 first (the lower child on equal t0), the others stacked with
  * their t0 and dropped on pop when t0 > best_t. */
-static void trace4_one(const Trace4Ctx* T, const float* ray, uint32_t* hit, uint32_t* extra) {
+/* deepest (optional): the most entries the stack holds while a popped entry is being visited --
+ * the far children waiting beneath the current node, i.e. the stack a traversal that keeps the
+ * current node out of its stack needs for this ray */
+static void trace4_one(const Trace4Ctx* T, const float* ray, uint32_t* hit, uint32_t* extra,
+                       uint32_t* deepest) {
     const TraceCtx* C = &T->base;
-    uint32_t box_tests = 0, tri_tests = 0, mask_tests = 0, mask_culls = 0;
+    uint32_t box_tests = 0, tri_tests = 0, mask_tests = 0, mask_culls = 0, most = 0;
     uint32_t best = NO_HIT;
     float best_t = INFINITY;
     if (ray_valid(ray) && C->root != EMPTY_REF) {
@@ -1101,6 +1105,7 @@ static void trace4_one(const Trace4Ctx* T, const float* ray, uint32_t* hit, uint
             uint32_t ref = st_ref[sp];
             float tn = st_t[sp];
             if (tn > best_t) continue;
+            if ((uint32_t)sp > most) most = (uint32_t)sp;
             if (ref & LEAF_BIT) {
                 leaf_tests(C, ref, o, d, tmin, &best_t, &best, &tri_tests);
                 continue;
@@ -1146,13 +1151,15 @@ static void trace4_one(const Trace4Ctx* T, const float* ray, uint32_t* hit, uint
     hit[2] = box_tests;
     hit[3] = tri_tests;
     if (extra) { extra[0] = mask_tests; extra[1] = mask_culls; }
+    if (deepest) *deepest = most;
 }
 
 int orc_trace4(const float* tris, const uint32_t* perm, const float* box4, const uint32_t* ref4,
                const uint32_t* src4, uint32_t root4, uint32_t depth, uint32_t R, uint32_t mode,
                const uint64_t* masks, const uint64_t* codebook, const uint16_t* cidx, const uint8_t* placed,
                const uint64_t* lut, float origin_bound, uint32_t flags, const float* rays, uint32_t nrays,
-               uint32_t* out_hits, uint32_t* out_extra, uint32_t* slot_fp, int nthreads) {
+               uint32_t* out_hits, uint32_t* out_extra, uint32_t* slot_fp, int nthreads,
+               uint32_t* out_deepest) {
     if (3 * depth + 1 > 256) return ORC_ERR_DEPTH;
     if (mode > MODE_SPARSE) return ORC_ERR_ARG;
     if (mode != MODE_NONE && (R < 1 || R > 6 || !lut)) return ORC_ERR_ARG;
@@ -1175,7 +1182,7 @@ int orc_trace4(const float* tris, const uint32_t* perm, const float* box4, const
 #endif
     for (int64_t i = 0; i < (int64_t)nrays; ++i)
         trace4_one(&T, &rays[8 * (size_t)i], &out_hits[4 * (size_t)i],
-                   out_extra ? &out_extra[2 * (size_t)i] : NULL);
+                   out_extra ? &out_extra[2 * (size_t)i] : NULL, out_deepest ? &out_deepest[i] : NULL);
     return ORC_OK;
 }
 

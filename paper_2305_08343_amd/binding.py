@@ -14,7 +14,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsubcull.so")
+# SUBCULL_LIB may name another build of the same library (e.g. libsubcull_san.so, host code
+# under AddressSanitizer); there is no fallback of any kind
+LIB_PATH = os.environ.get("SUBCULL_LIB") or os.path.join(_HERE, "libsubcull.so")
 
 SC_OK = 0
 SC_MASK_NONE, SC_MASK_RAW, SC_MASK_LUT, SC_MASK_SPARSE = 0, 1, 2, 3

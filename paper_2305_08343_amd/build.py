@@ -1,6 +1,12 @@
 """Build libsubcull.so for gfx950 with hipcc (no torch extension machinery).
 
-    python -m paper_2305_08343_amd.build
+    python -m paper_2305_08343_amd.build             # libsubcull.so
+    python -m paper_2305_08343_amd.build --sanitize  # libsubcull_san.so: host code under
+                                                     # AddressSanitizer + UBSan (device code as usual)
+
+The sanitized library is for CPU-side checks of the host code (argument
+checks, the BVH builder, the 4-wide collapse, the codebook): load it with
+SUBCULL_LIB pointing at it and the clang ASan runtime preloaded.
 
 Flags that matter for reproducibility: -ffp-contract=off (no fused
 multiply-add, so every float32 product rounds before it is added),
@@ -41,9 +47,16 @@ def hipcc() -> str:
     return exe
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
-    cmd = [hipcc()] + COMMON
+# host-side sanitizers only: each -fsanitize= applies to the host compilation (-Xarch_host)
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+SAN_DIR = os.path.join(HERE, "_build_san")
+SAN_LIB = os.path.join(HERE, "libsubcull_san.so")
+
+
+def _compile(src: str, sanitize: bool = False) -> str:
+    obj = os.path.join(SAN_DIR if sanitize else OUT_DIR, os.path.basename(src) + ".o")
+    cmd = [hipcc()] + COMMON + (SANITIZE if sanitize else [])
     if src.endswith(".hip"):
         cmd += DEVICE + ["-x", "hip"]
     cmd += ["-I", os.path.join(HERE, "..", "include"), "-c", os.path.join(SRC, src), "-o", obj]
@@ -53,21 +66,24 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OUT_DIR, exist_ok=True)
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    out_dir, lib = (SAN_DIR, SAN_LIB) if sanitize else (OUT_DIR, LIB)
+    os.makedirs(out_dir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, sanitize), SOURCES))
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    if sanitize:
+        cmd += ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--sanitize" in sys.argv[1:])
     sys.exit(0)

@@ -145,6 +145,20 @@ __device__ __forceinline__ bool bit_overlap(const float* lo, const float* hi, co
     return (table[(size_t)key * (K >> 5) + (idx >> 5)] >> (idx & 31u)) & 1u;
 }
 
+// R = 4: the ray mask of cells (b, e) is displacement pattern pidx (x made
+// non-negative by the symmetry of the sweep) moved to the componentwise minimum
+// corner, bit `shift`: the test is ((mask >> shift) AND pattern) != 0
+__device__ __forceinline__ void r4_pattern(int bx, int by, int bz, int ex, int ey, int ez, uint32_t& pidx,
+                                           uint32_t& shift) {
+    int qx = bx, qy = by, qz = bz, fx = ex, fy = ey, fz = ez;
+    if (fx < qx) {
+        qx = ex; qy = ey; qz = ez; fx = bx; fy = by; fz = bz;
+    }
+    pidx = (uint32_t)(((fx - qx) * 7 + (fy - qy + 3)) * 7 + (fz - qz + 3));
+    const int my = qy < fy ? qy : fy, mz = qz < fz ? qz : fz;
+    shift = (uint32_t)(qx + 4 * my + 16 * mz);
+}
+
 // (ray mask of the cells holding o + t0 d and o + t1 d) AND (object mask om) != 0
 template <int R>
 __device__ __forceinline__ bool mask_overlap(const float* lo, const float* hi, const Ray& r, float t0, float t1,
@@ -156,13 +170,9 @@ __device__ __forceinline__ bool mask_overlap(const float* lo, const float* hi, c
     load_mask<W>(om, ob);
     if constexpr (R == 4) {
         // displacement pattern (LDS) against the mask moved to its corner
-        int qx = bx, qy = by, qz = bz, fx = ex, fy = ey, fz = ez;
-        if (fx < qx) {
-            qx = ex; qy = ey; qz = ez; fx = bx; fy = by; fz = bz;
-        }
-        const int pidx = ((fx - qx) * 7 + (fy - qy + 3)) * 7 + (fz - qz + 3);
-        const int my = qy < fy ? qy : fy, mz = qz < fz ? qz : fz;
-        return ((ob[0] >> (uint32_t)(qx + 4 * my + 16 * mz)) & lds_pat[pidx]) != 0;
+        uint32_t pidx, shift;
+        r4_pattern(bx, by, bz, ex, ey, ez, pidx, shift);
+        return ((ob[0] >> shift) & lds_pat[pidx]) != 0;
     } else {
         const uint32_t key = (uint32_t)(((((bx * R + by) * R + bz) * R + ex) * R + ey) * R + ez);
         uint64_t rm[W];
@@ -225,6 +235,10 @@ void trace_kernel(TraceLaunch a) {
     constexpr uint32_t kStride = (MODE == kModeRaw) ? kRawNodeBytes : kNodeBytes;
     constexpr bool kPatLds = (R == 4) && (MODE != kModeNone) && (MODE != kModeLutBits);
     constexpr bool kCbLds = (MODE == kModeLutLds);
+    // 4-wide nodes: issue the mask reads of several children before deciding any
+    // (where a test reads one word: the bit table, or an R = 4 mask; an R = 6 test reads two 32-byte
+    // rows, and holding them for several children costs more waves than the overlap gains)
+    constexpr bool kPhased = (WIDTH == 4) && (MODE == kModeLutBits || (R == 4 && MODE != kModeNone));
     __shared__ uint2 lds_stack[STACK * BLOCK];
     __shared__ uint64_t lds_pat[kPatLds ? kPatterns<4> : 1];
     __shared__ __attribute__((aligned(16))) uint64_t lds_cb[kCbLds ? kCbLdsWords : 2];
@@ -475,6 +489,90 @@ void trace_kernel(TraceLaunch a) {
                 float key[4];
                 uint32_t kid[4], kref[4];
                 uint32_t alive = 0;
+                if constexpr (kPhased) {
+                    // Three passes: the slab tests of all four children (which use every piece of
+                    // the node, so no later wait for the node holds up a mask read); for each
+                    // child whose mask is tested, its ray-mask cells and the read the test needs;
+                    // then the mask decisions. The reads of all tested children are in flight
+                    // together instead of one round trip after another; every child is still
+                    // tested in order and every count is the same.
+                    bool ckeep[4], cneed[4];
+                    float ct0[4], ct1[4];
+                    uint32_t cidx4[4];             // LUT modes: codebook index per child
+                    uint32_t pw[4], pb[4], pp[4];  // bit table word + bit; R = 4 pattern + shift
+                    uint64_t pm[4];                // R = 4: the object mask
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        // without a branch: an unused child's slab result is computed and dropped, so
+                        // the node's pieces are waited for once, on every path
+                        kref[c] = (crf[c] == kEmptyRef) ? kEmptyRef : (crf[c] & ~kRef4Full);
+                        const bool used = crf[c] != kEmptyRef;
+                        float t0, t1;
+                        const float nr[3] = {cnx[c], cny[c], cnz[c]}, fr[3] = {cfx[c], cfy[c], cfz[c]};
+                        slab_nf(nr, fr, r, best_t, t0, t1);
+                        box_tests += used ? 1u : 0u;
+                        ckeep[c] = used && t0 <= t1;
+                        ct0[c] = t0;
+                        ct1[c] = t1;
+                        // whether the child's mask is tested (reads the refs' full flags or the
+                        // codebook indices here, before any mask read is in flight)
+                        bool test;
+                        if constexpr (MODE == kModeRaw) {
+                            test = !(crf[c] & kRef4Full);
+                        } else {
+                            cidx4[c] = ((c < 2 ? ax0 : ax1) >> (16 * (c & 1))) & 0xFFFFu;
+                            test = cidx4[c] < s_full;
+                        }
+                        cneed[c] = ckeep[c] && use_mask && test;
+                    }
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        pw[c] = 0u;
+                        pb[c] = 0u;
+                        pp[c] = 0u;
+                        pm[c] = 0u;
+                        const uint32_t idx = (MODE == kModeRaw) ? 0u : cidx4[c];
+                        if (cneed[c]) {
+                            const float lo[3] = {sx ? cfx[c] : cnx[c], sy ? cfy[c] : cny[c], sz ? cfz[c] : cnz[c]};
+                            const float hi[3] = {sx ? cnx[c] : cfx[c], sy ? cny[c] : cfy[c], sz ? cnz[c] : cfz[c]};
+                            int bx, by, bz, ex, ey, ez;
+                            ray_cells<R>(lo, hi, r, ct0[c], ct1[c], bx, by, bz, ex, ey, ez);
+                            if constexpr (MODE == kModeLutBits) {
+                                const uint32_t k6 =
+                                    (uint32_t)(((((bx * R + by) * R + bz) * R + ex) * R + ey) * R + ez);
+                                pw[c] = a.bit_table[(size_t)k6 * (a.K >> 5) + (idx >> 5)];
+                                pb[c] = idx & 31u;
+                            } else {
+                                if constexpr (MODE == kModeRaw) pm[c] = s_side[(size_t)ref * 4 + c];
+                                if constexpr (MODE == kModeLut) pm[c] = s_codebook[idx];
+                                if constexpr (MODE == kModeLutLds) pm[c] = lds_cb[idx];
+                                r4_pattern(bx, by, bz, ex, ey, ez, pp[c], pb[c]);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        bool keep = ckeep[c];
+                        if (cneed[c]) {
+                            ++mask_tests;
+                            bool any;
+                            if constexpr (MODE == kModeLutBits) any = ((pw[c] >> pb[c]) & 1u) != 0u;
+                            else any = ((pm[c] >> pb[c]) & lds_pat[pp[c]]) != 0;
+                            if (!any) {
+                                ++mask_culls;
+                                if (shadow_flag && s_fp) atomicAdd(&s_fp[a.src4[(size_t)ref * 4 + c]], 1u);
+                                keep = !cull;
+                            }
+                        }
+                        key[c] = __builtin_inff();
+                        kid[c] = 4u + (uint32_t)c;
+                        if (keep) {
+                            key[c] = ct0[c];
+                            kid[c] = (uint32_t)c;
+                            ++alive;
+                        }
+                    }
+                } else {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     key[c] = __builtin_inff();
@@ -522,6 +620,7 @@ void trace_kernel(TraceLaunch a) {
                         kid[c] = (uint32_t)c;
                         ++alive;
                     }
+                }
                 }
                 // sorting network for four (t0, child) pairs
                 order2(key[0], kid[0], kref[0], key[1], kid[1], kref[1]);

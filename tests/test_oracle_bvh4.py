@@ -172,7 +172,7 @@ def _recursive_trace4(tris, bvh, b4, ray, masks=None, lut=None, R=6, ob=np.inf):
     o, d, tmin = ray[:3].astype(f32), ray[4:7].astype(f32), f32(ray[3])
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
         inv = f32(1) / d
-    st = {"best": NO_HIT, "t": f32(ray[7]), "box": 0, "tri": 0, "mt": 0, "mc": 0}
+    st = {"best": NO_HIT, "t": f32(ray[7]), "box": 0, "tri": 0, "mt": 0, "mc": 0, "deep": 0}
     use_mask = masks is not None and max(abs(o)) <= ob
     bits = None if masks is None else oracle.mask_bits(masks, R)
     lbits = None if lut is None else oracle.mask_bits(lut, R)
@@ -221,9 +221,12 @@ def _recursive_trace4(tris, bvh, b4, ray, masks=None, lut=None, R=6, ob=np.inf):
             if t < st["t"] or (t == st["t"] and idx < st["best"]):
                 st["t"], st["best"] = t, idx
 
-    def visit(ref, tn):
+    def visit(ref, tn, pending):
+        # pending: children that an iterative traversal would hold on its stack beneath this
+        # node -- the not yet visited siblings of every node on the recursion path
         if tn > st["t"]:
             return
+        st["deep"] = max(st["deep"], pending)
         if ref & LEAF:
             leaf(ref)
             return
@@ -254,10 +257,10 @@ def _recursive_trace4(tris, bvh, b4, ray, masks=None, lut=None, R=6, ob=np.inf):
                     st["mc"] += 1
                     continue
             alive.append((t0, c))
-        for t0, c in sorted(alive):
-            visit(int(b4.ref4[ref, c]), t0)
+        for i, (t0, c) in enumerate(sorted(alive)):
+            visit(int(b4.ref4[ref, c]), t0, pending + len(alive) - 1 - i)
 
-    visit(b4.root, tmin)
+    visit(b4.root, tmin, 0)
     return st
 
 
@@ -267,10 +270,13 @@ def test_recursive_formulation_counts_bvh4(small_scene, small_oracle):
     bvh = small_oracle["bvh"]
     b4 = oracle.bvh4_collapse(bvh)
     for masks, lut, mode in ((None, None, "none"), (small_oracle["masks6"], small_oracle["lut6"], "raw")):
-        h = oracle.trace4(tris, bvh, b4, sel, mode=mode, R=6, masks=masks, origin_bound=small_oracle["origin_bound"])
+        h = oracle.trace4(tris, bvh, b4, sel, mode=mode, R=6, masks=masks, origin_bound=small_oracle["origin_bound"],
+                          stack_depth=True)
+        assert h.deepest.max() >= 3  # the stack really grows
         for i in range(sel.shape[0]):
             st = _recursive_trace4(tris, bvh, b4, sel[i], masks, lut, 6, small_oracle["origin_bound"])
             assert st["best"] == h.prim[i]
             assert (st["box"], st["tri"]) == (h.box_tests[i], h.tri_tests[i]), i
+            assert st["deep"] == h.deepest[i], i
             if mode == "raw":
                 assert (st["mt"], st["mc"]) == (h.mask_tests[i], h.mask_culls[i]), i
