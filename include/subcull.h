@@ -278,6 +278,22 @@ sc_status sc_scene_export_bit_table(const sc_scene* scene, uint32_t* out);
 sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags,
                    sc_hit* d_hits, uint32_t* d_extra, uint32_t* d_slot_fp, void* stream);
 
+/* sc_trace without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation). Arguments, results and errors as sc_trace. The ray-queue
+ * counters and, when the trace sorts its rays (SC_TRACE_SORT or the context's
+ * launch shape), the sort workspace live in a fixed device array of this
+ * library, one per GPU (about 65 MiB, held until the process ends), instead
+ * of the context's counters and allocator: a sorted trace takes at most
+ * 4,194,304 rays (SC_ERR_INVALID_ARG beyond, before any HIP call); an
+ * unsorted one any count sc_trace takes. Every call on a GPU shares that
+ * GPU's array and leaves its contents behind (each launch clears its counters
+ * itself), so calls that overlap on one GPU -- on different streams, or from
+ * different contexts or threads -- race and must not be issued; serialise
+ * them on one stream. */
+sc_status sc_trace_noalloc(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags,
+                           sc_hit* d_hits, uint32_t* d_extra, uint32_t* d_slot_fp, void* stream);
+
 /* The order in which a sorted trace takes the rays: d_order (device uint32
  * [n], 4-byte aligned, written) lists ray indices by ascending Morton code
  * of the ray origin, quantised to 256 cells per axis of the scene's vertex

@@ -89,6 +89,8 @@ _SIGS = {
     "sc_scene_export": (C.c_int, [C.c_void_p, C.POINTER(sc_scene_host)]),
     "sc_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
+    "sc_trace_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p]),
     "sc_scene_export4": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sc_scene_export_bit_table": (C.c_int, [C.c_void_p, C.c_void_p]),
     "sc_ray_order": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),

@@ -26,7 +26,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsubcull.so")
 SOURCES = ["api.cpp", "bvh.cpp", "codebook.cpp", "kernels_build.hip", "kernels_trace.hip", "placement.hip",
-           "raysort.hip", "bvh4.cpp"]
+           "raysort.hip", "bvh4.cpp", "noalloc.hip"]
 ARCH = os.environ.get("SUBCULL_ARCH", "gfx950")
 
 COMMON = [

@@ -205,6 +205,12 @@ sc_status sc_create(int device, const sc_allocator* alloc, sc_ctx** out) {
         ctx->alloc = *alloc;
         ctx->has_alloc = true;
     }
+    // the device address of this GPU's allocation-free scratch (taken once per device)
+    const hipError_t se = scratch_init(device);
+    if (se != hipSuccess) {
+        delete ctx;
+        return hip_fail(se, "scratch symbol address");
+    }
     ctx->counters = static_cast<uint32_t*>(dev_alloc(ctx, kQueueRing * kQueueParts * 4, nullptr));
     if (!ctx->counters) {
         delete ctx;
@@ -639,8 +645,11 @@ sc_status sc_scene_export4(const sc_scene* scene, float* box4, uint32_t* ref4, u
     return SC_OK;
 }
 
-sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags, sc_hit* d_hits,
-                   uint32_t* d_extra, uint32_t* d_slot_fp, void* stream) {
+namespace {
+
+// Argument checks shared by the trace entry points (no HIP call).
+sc_status check_trace_args(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags,
+                           const sc_hit* d_hits, const uint32_t* d_extra, const uint32_t* d_slot_fp) {
     if (!scene) return fail(SC_ERR_INVALID_ARG, "scene is NULL");
     if (n > 0 && (!d_rays || !d_hits)) return fail(SC_ERR_INVALID_ARG, "d_rays and d_hits must be non-NULL");
     if (n > (1u << 31)) return fail(SC_ERR_INVALID_ARG, "at most 2^31 rays per call");
@@ -649,9 +658,13 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     if (((uintptr_t)d_rays & 15) || ((uintptr_t)d_hits & 15) || ((uintptr_t)d_extra & 7) ||
         ((uintptr_t)d_slot_fp & 3))
         return fail(SC_ERR_INVALID_ARG, "d_rays and d_hits must be 16-byte aligned, d_extra 8-byte");
-    if (n == 0) return SC_OK;
-    sc_status st = use_device(scene->ctx->device);
-    if (st != SC_OK) return st;
+    return SC_OK;
+}
+
+// The launch record of a single-scene trace in the context's launch shape (queue and ray order
+// are set by the caller).
+TraceLaunch trace_launch(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags, sc_hit* d_hits,
+                         uint32_t* d_extra, uint32_t* d_slot_fp) {
     const sc_scene_info& I = scene->info;
     TraceLaunch a{};
     a.rays = d_rays;
@@ -682,9 +695,7 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     a.extra = d_extra;
     a.slot_fp = d_slot_fp;
     if (a.mode == SC_MASK_SPARSE && I.n_masked == 0) a.mode = SC_MASK_NONE;
-    sc_ctx* ctx = scene->ctx;
-    a.queue = ctx->counters +
-              (size_t)(ctx->next_counter.fetch_add(1, std::memory_order_relaxed) % kQueueRing) * kQueueParts;
+    const sc_ctx* ctx = scene->ctx;
     a.parts = ctx->tune.parts;
     a.chunk = ctx->tune.chunk;
     a.block = ctx->tune.block;
@@ -693,6 +704,22 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     a.cb_global = ctx->tune.codebook;
     a.gather = ctx->tune.gather;
     a.refill = ctx->tune.refill;
+    return a;
+}
+
+}  // namespace
+
+sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags, sc_hit* d_hits,
+                   uint32_t* d_extra, uint32_t* d_slot_fp, void* stream) {
+    sc_status st = check_trace_args(scene, d_rays, n, flags, d_hits, d_extra, d_slot_fp);
+    if (st != SC_OK) return st;
+    if (n == 0) return SC_OK;
+    st = use_device(scene->ctx->device);
+    if (st != SC_OK) return st;
+    TraceLaunch a = trace_launch(scene, d_rays, n, flags, d_hits, d_extra, d_slot_fp);
+    sc_ctx* ctx = scene->ctx;
+    a.queue = ctx->counters +
+              (size_t)(ctx->next_counter.fetch_add(1, std::memory_order_relaxed) % kQueueRing) * kQueueParts;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const bool sort = (flags & SC_TRACE_SORT) || ctx->tune.sort;
     void* ws = nullptr;
@@ -710,6 +737,36 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
     }
     const hipError_t e = launch_trace(a, s);
     if (ws) dev_free(ctx, ws, ws_bytes, s);  // stream-ordered: the allocator reuses it after the trace
+    if (e != hipSuccess) return hip_fail(e, "trace launch");
+    return SC_OK;
+}
+
+sc_status sc_trace_noalloc(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags, sc_hit* d_hits,
+                           uint32_t* d_extra, uint32_t* d_slot_fp, void* stream) {
+    sc_status st = check_trace_args(scene, d_rays, n, flags, d_hits, d_extra, d_slot_fp);
+    if (st != SC_OK) return st;
+    const bool sort = (flags & SC_TRACE_SORT) || scene->ctx->tune.sort;
+    if (sort && !scratch_fits_sort(n))
+        return fail(SC_ERR_INVALID_ARG, "sc_trace_noalloc sorts at most " + std::to_string(kNoAllocMaxSortRays) +
+                                            " rays (its fixed scratch); got " + std::to_string(n));
+    if (n == 0) return SC_OK;
+    st = use_device(scene->ctx->device);
+    if (st != SC_OK) return st;
+    void* scr = nullptr;
+    size_t scr_bytes = 0;
+    hipError_t e = scratch_get(scene->ctx->device, &scr, &scr_bytes);
+    if (e != hipSuccess) return hip_fail(e, "no-allocation scratch");
+    TraceLaunch a = trace_launch(scene, d_rays, n, flags, d_hits, d_extra, d_slot_fp);
+    a.queue = static_cast<uint32_t*>(scr);  // cleared by the launch's reset kernel
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (sort) {
+        uint32_t* order = nullptr;
+        e = launch_ray_order(d_rays, n, scene->lo, scene->hi, static_cast<unsigned char*>(scr) + scratch_counter_bytes(),
+                             &order, s);
+        if (e != hipSuccess) return hip_fail(e, "ray order");
+        a.order = order;
+    }
+    e = launch_trace(a, s);
     if (e != hipSuccess) return hip_fail(e, "trace launch");
     return SC_OK;
 }

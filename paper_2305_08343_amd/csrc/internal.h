@@ -141,6 +141,15 @@ constexpr uint32_t kQueueRing = 1024;  // launch counter sets per context
 constexpr uint32_t kQueueParts = 8;    // counters per set (one per XCD of an MI355X)
 
 hipError_t launch_trace(const TraceLaunch& a, hipStream_t s);
+
+// Allocation-free traces (noalloc.hip): a file-scope device array per GPU holds the queue
+// counters and the sort workspace for up to kNoAllocMaxSortRays rays. scratch_init takes its
+// device address once per device (the device current); scratch_get returns it and its size.
+constexpr uint32_t kNoAllocMaxSortRays = 1u << 22;
+hipError_t scratch_init(int device);
+hipError_t scratch_get(int device, void** ptr, size_t* bytes);
+size_t scratch_counter_bytes();
+bool scratch_fits_sort(uint32_t n);
 // ray order by Morton code of the origin in [lo, hi] (stable radix sort); *order points into workspace
 size_t ray_order_workspace_bytes(uint32_t n);
 hipError_t launch_ray_order(const float* rays, uint32_t n, const float lo[3], const float hi[3], void* workspace,

@@ -26,7 +26,7 @@ def test_header_declares_the_api():
                  "sc_get_tune", "sc_trace_batch", "sc_batch_create", "sc_batch_launch",
                  "sc_batch_destroy", "sc_bvh_build_host", "sc_slot_features", "sc_mlp_forward",
                  "sc_mlp_backward", "sc_mlp_adam", "sc_place_top", "sc_ray_order",
-                 "sc_scene_export4", "sc_scene_export_bit_table"):
+                 "sc_scene_export4", "sc_scene_export_bit_table", "sc_trace_noalloc"):
         assert must in names
 
 
@@ -61,6 +61,7 @@ def test_null_arguments_rejected_before_hip():
     assert lib.sc_scene_build(None, None, 0, None, None, None) == 1
     assert b"non-NULL" in lib.sc_last_error()
     assert lib.sc_trace(None, None, 0, 0, None, None, None, None) == 1
+    assert lib.sc_trace_noalloc(None, None, 0, 0, None, None, None, None) == 1
     assert lib.sc_scene_get_info(None, None) == 1
     assert lib.sc_scene_export(None, None) == 1
     assert lib.sc_raymask_lut(None, 6, None, None) == 1
