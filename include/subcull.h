@@ -168,8 +168,8 @@ typedef struct {
  * queue (waves start on partition block % parts, i.e. per XCD when parts is
  * 8, and steal from the others), and a cap on the waves resident per SIMD
  * (the persistent grid is sized to it; 0 = as many as registers and LDS
- * allow), whether single-scene traces sort their rays as with
- * SC_TRACE_SORT, and where LUT-mode single-scene traces read the codebook
+ * allow), whether traces sort their rays as with SC_TRACE_SORT (single-scene
+ * and batched launches), and where LUT-mode single-scene traces read the codebook
  * (Sect. 3.2.2): 0 = a copy in LDS when it fits (K * words <= 1024 64-bit
  * words), 1 = from global memory through the caches, and leaf gathering:
  * a lane whose ray stands at a leaf waits (its ray does not advance) while
@@ -314,8 +314,10 @@ sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune);
 sc_status sc_get_tune(const sc_ctx* ctx, sc_tune* out);
 
 /* One scene's rays in a batched launch. All items of a batch must come from
- * one context and share the mask mode and R. d_rays/d_hits as in sc_trace;
- * d_extra and d_slot_fp may be NULL. */
+ * one context and share the mask mode, R, the node width (2 or 4) and, for
+ * 4-wide scenes, the child-box storage (float or quantised). d_rays/d_hits as
+ * in sc_trace; d_extra and d_slot_fp may be NULL. Compressed masks are read
+ * from each scene's codebook (no LDS copy, no bit table). */
 typedef struct {
     const sc_scene* scene;
     const float* d_rays;
@@ -330,14 +332,21 @@ typedef struct sc_batch sc_batch;
 /* Trace several scenes' rays in one persistent launch: the items form one
  * ray queue (largest estimated work first), every lane takes its next ray
  * from any item, so uneven scene sizes keep the GPU busy. Results equal
- * sc_trace on each item alone. Synchronises `stream` (the descriptor table
- * uploaded for the call is released afterwards); sc_batch_launch does not. */
+ * sc_trace on each item alone. flags: SC_TRACE_CULL, SC_TRACE_SHADOW and
+ * SC_TRACE_SORT; with SC_TRACE_SORT (or the launch shape's sort) the rays are
+ * taken in the order of (item, Morton code of the origin in that item's
+ * scene bounds), which keeps the items' order (at most 256 items, else
+ * SC_ERR_UNSUPPORTED; workspace of 16 bytes per ray plus counts from the
+ * context allocator, or held by the batch for sc_batch_create).
+ * Synchronises `stream` (the descriptor table uploaded for the call is
+ * released afterwards); sc_batch_launch does not. */
 sc_status sc_trace_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_items, uint32_t flags,
                          void* stream);
 
 /* The same launch recorded once into a HIP graph (counter reset kernel +
- * traversal kernel, with the context's current launch shape) for cheap
- * replays: sc_batch_launch replays it on `stream`. The item buffers are
+ * traversal kernel, with the context's current launch shape; a sorted batch
+ * also records the ordering kernels, so every replay orders the rays' current
+ * contents) for cheap replays: sc_batch_launch replays it on `stream`. The item buffers are
  * bound at creation; their contents may change between replays. Replays of
  * one batch share its queue counters: keep them on one stream. */
 sc_status sc_batch_create(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_items, uint32_t flags,

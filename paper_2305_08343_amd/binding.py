@@ -445,7 +445,7 @@ class Batch:
     """
 
     def __init__(self, ctx: Context, items, *, cull: bool = True, shadow: bool = False,
-                 extra: bool = True, graph: bool = True, slot_fp=None):
+                 extra: bool = True, graph: bool = True, slot_fp=None, sort: bool = False):
         import torch
         self.ctx = ctx
         dev = f"cuda:{ctx.device}"
@@ -467,7 +467,8 @@ class Batch:
                                    None if e is None else e.data_ptr(), None if fp is None else fp.data_ptr())
         self._arr = arr
         self._n = len(items)
-        self.flags = (SC_TRACE_CULL if cull else 0) | (SC_TRACE_SHADOW if shadow else 0)
+        self.flags = ((SC_TRACE_CULL if cull else 0) | (SC_TRACE_SHADOW if shadow else 0) |
+                      (SC_TRACE_SORT if sort else 0))
         self.handle = None
         if graph:
             h = C.c_void_p()

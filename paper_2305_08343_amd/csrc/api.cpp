@@ -799,7 +799,10 @@ namespace {
 sc_status prepare_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_items, uint32_t flags,
                         TraceLaunch& a, std::vector<BatchItem>& desc) {
     if (!ctx || !items || n_items == 0) return fail(SC_ERR_INVALID_ARG, "ctx and a non-empty item list are required");
-    if (flags & ~(uint32_t)(SC_TRACE_CULL | SC_TRACE_SHADOW)) return fail(SC_ERR_INVALID_ARG, "unsupported batch flag");
+    if (flags & ~(uint32_t)(SC_TRACE_CULL | SC_TRACE_SHADOW | SC_TRACE_SORT))
+        return fail(SC_ERR_INVALID_ARG, "unsupported batch flag");
+    if (((flags & SC_TRACE_SORT) || ctx->tune.sort) && n_items > kBatchSortItems)
+        return fail(SC_ERR_UNSUPPORTED, "a sorted batch takes at most 256 items");
     const sc_scene* first = items[0].scene;
     if (!first) return fail(SC_ERR_INVALID_ARG, "item scene is NULL");
     uint64_t total = 0;
@@ -809,7 +812,8 @@ sc_status prepare_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_item
         if (!it.scene || it.scene->ctx != ctx) return fail(SC_ERR_INVALID_ARG, "item scene missing or from another context");
         if (it.scene->info.mode != first->info.mode || it.scene->info.R != first->info.R)
             return fail(SC_ERR_INVALID_ARG, "all batch items need the same mask mode and R");
-        if (it.scene->info.width != 2) return fail(SC_ERR_UNSUPPORTED, "batches take binary-BVH scenes only");
+        if (it.scene->info.width != first->info.width || it.scene->quant4 != first->quant4)
+            return fail(SC_ERR_INVALID_ARG, "all batch items need the same node width and child-box storage");
         if (it.n > 0 && (!it.d_rays || !it.d_hits)) return fail(SC_ERR_INVALID_ARG, "item rays/hits are NULL");
         if (((uintptr_t)it.d_rays & 15) || ((uintptr_t)it.d_hits & 15) || ((uintptr_t)it.d_extra & 7) ||
             ((uintptr_t)it.d_slot_fp & 3))
@@ -826,10 +830,11 @@ sc_status prepare_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_item
         const sc_batch_item& it = items[o.second];
         const sc_scene* sc = it.scene;
         BatchItem d{};
-        d.nodes = sc->nodes;
+        d.nodes = sc->info.width == 4 ? sc->nodes4 : sc->nodes;
         d.tris = sc->tris;
         d.codebook = sc->codebook;
-        d.side_masks = sc->side_masks;
+        d.side_masks = sc->info.width == 4 ? sc->masks4 : sc->side_masks;
+        d.src4 = sc->src4;
         d.rays = it.d_rays;
         d.hits = it.d_hits;
         d.extra = it.d_extra;
@@ -839,6 +844,12 @@ sc_status prepare_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_item
         d.ray_begin = begin;
         d.n_rays = it.n;
         d.origin_bound = sc->info.origin_bound;
+        for (int j = 0; j < 3; ++j) {  // Morton keys of the origins in the scene's vertex bounds
+            const float e = sc->hi[j] - sc->lo[j];
+            const float q = 256.0f / e;
+            d.key_lo[j] = sc->lo[j];
+            d.key_scale[j] = (e > 0.0f && q < std::numeric_limits<float>::infinity()) ? q : 0.0f;
+        }
         begin += it.n;
         desc.push_back(d);
     }
@@ -857,7 +868,9 @@ sc_status prepare_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_item
     a.parts = ctx->tune.parts;
     a.gather = ctx->tune.gather;
     a.refill = ctx->tune.refill;
-    a.width = 2;
+    a.width = I.width;
+    a.quant = first->quant4;
+    a.K = I.codebook_size;
     a.n_items = n_items;
     if (I.mode != SC_MASK_NONE && !a.lut) {  // masks exist only if the LUT was built
         for (uint32_t k = 0; k < n_items; ++k)
@@ -873,6 +886,8 @@ struct sc_batch {
     BatchItem* items = nullptr;
     size_t items_bytes = 0;
     uint32_t* counters = nullptr;
+    void* sort_ws = nullptr;  // ray ordering workspace of a sorted batch
+    size_t sort_bytes = 0;
     hipStream_t capture = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -895,10 +910,21 @@ sc_status sc_trace_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_ite
     a.items = d;
     a.queue = ctx->counters +
               (size_t)(ctx->next_counter.fetch_add(1, std::memory_order_relaxed) % kQueueRing) * kQueueParts;
+    const bool sort = (flags & SC_TRACE_SORT) || ctx->tune.sort;
+    const size_t ws_bytes = sort ? ray_order_workspace_bytes(a.n) : 0;
+    void* ws = sort ? dev_alloc(ctx, ws_bytes, s) : nullptr;
+    if (sort && !ws) e = hipErrorOutOfMemory;
+    if (e == hipSuccess && sort) {
+        uint32_t* order = nullptr;
+        e = launch_batch_order(d, n_items, a.n, ws, &order, s);
+        a.order = order;
+    }
     if (e == hipSuccess) e = launch_trace(a, s);
-    // the descriptors must outlive the launch: wait before releasing them
+    // the descriptors and the ordering must outlive the launch: wait before releasing them
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (ws) dev_free(ctx, ws, ws_bytes, s);
     dev_free(ctx, d, bytes, s);
+    if (e == hipErrorOutOfMemory) return fail(SC_ERR_OOM, "batch ray ordering workspace");
     return e == hipSuccess ? SC_OK : hip_fail(e, "batched trace");
 }
 
@@ -927,11 +953,24 @@ sc_status sc_batch_create(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_it
     if (e != hipSuccess) return cleanup(SC_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
     a.items = b->items;
     a.queue = b->counters;
+    const bool sort = ((flags & SC_TRACE_SORT) || ctx->tune.sort) && a.n > 0;
+    if (sort) {
+        b->sort_bytes = ray_order_workspace_bytes(a.n);
+        b->sort_ws = dev_alloc(ctx, b->sort_bytes, nullptr);
+        if (!b->sort_ws) return cleanup(SC_ERR_OOM, "batch ray ordering workspace");
+    }
     e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
     if (e != hipSuccess) return cleanup(SC_ERR_HIP, std::string("stream: ") + hipGetErrorString(e));
     e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        const hipError_t le = (a.n > 0) ? launch_trace(a, b->capture) : hipSuccess;
+        // the ordering kernels (keys of the current ray contents + radix sort) are part of the graph
+        hipError_t le = hipSuccess;
+        if (sort) {
+            uint32_t* order = nullptr;
+            le = launch_batch_order(b->items, n_items, a.n, b->sort_ws, &order, b->capture);
+            a.order = order;
+        }
+        if (le == hipSuccess && a.n > 0) le = launch_trace(a, b->capture);
         e = hipStreamEndCapture(b->capture, &b->graph);
         if (e == hipSuccess) e = le;
     }
@@ -959,6 +998,7 @@ sc_status sc_batch_destroy(sc_batch* batch) {
     if (batch->capture) (void)hipStreamDestroy(batch->capture);
     dev_free(batch->ctx, batch->items, batch->items_bytes, nullptr);
     dev_free(batch->ctx, batch->counters, kQueueParts * 4, nullptr);
+    if (batch->sort_ws) dev_free(batch->ctx, batch->sort_ws, batch->sort_bytes, nullptr);
     delete batch;
     return SC_OK;
 }

@@ -95,8 +95,13 @@ struct BatchItem {
     uint32_t* slot_fp;
     uint32_t root, full_start, ray_begin, n_rays;
     float origin_bound;
-    uint32_t pad[3];
+    uint32_t pad;
+    const uint32_t* src4;  // 4-wide scenes: binary slot of child [4*node+c] (shadow counts)
+    float key_lo[3];       // ray ordering: the scene's vertex bounds' minimum corner and
+    float key_scale[3];    // 256 / extent per axis (0 for a flat axis)
+    uint32_t pad2[2];
 };
+static_assert(sizeof(BatchItem) == 128, "batch descriptor layout");
 
 struct TraceLaunch {
     const float* rays;
@@ -154,6 +159,11 @@ bool scratch_fits_sort(uint32_t n);
 size_t ray_order_workspace_bytes(uint32_t n);
 hipError_t launch_ray_order(const float* rays, uint32_t n, const float lo[3], const float hi[3], void* workspace,
                             uint32_t** order, hipStream_t s);
+// batched launches: the n rays of n_items (<= kBatchSortItems) descriptors (sorted by ray_begin)
+// ordered by (item, Morton code of the origin in the item's key bounds); the same workspace size
+constexpr uint32_t kBatchSortItems = 256;
+hipError_t launch_batch_order(const BatchItem* items, uint32_t n_items, uint32_t n, void* workspace,
+                              uint32_t** order, hipStream_t s);
 hipError_t launch_raymask_patterns(uint32_t R, uint64_t* patterns, hipStream_t s);
 hipError_t launch_raymask_lut(uint32_t R, const uint64_t* patterns, uint64_t* out, hipStream_t s);
 inline size_t pattern_count(uint32_t R) { return (size_t)R * (2 * R - 1) * (2 * R - 1); }

@@ -71,11 +71,26 @@ __device__ __forceinline__ bool ray_is_valid(float4 r0, float4 r1) {
     return fin && dir && !isnan(r1.w) && (r0.w <= r1.w);
 }
 
+// R / ext rounded correctly, 0 when ext is not positive or the quotient is infinite. For ext in
+// [2^-100, 2^100] the hardware reciprocal and one correction of the quotient by its exact
+// residual (fused multiply-add) give the correctly rounded quotient -- checked on gfx950 for
+// every float of that range, R = 4 and 6 -- in four operations instead of the full division's
+// ten; any other extent takes the full division.
+template <int R>
+__device__ __forceinline__ float grid_scale_ext(float ext) {
+    if (ext >= 0x1p-100f && ext <= 0x1p100f) {
+        const float rc = __builtin_amdgcn_rcpf(ext);
+        const float q = (float)R * rc;
+        const float e = __builtin_fmaf(-ext, q, (float)R);
+        return __builtin_fmaf(e, rc, q);
+    }
+    const float s = (ext > 0.0f) ? (float)R / ext : 0.0f;
+    return isinf(s) ? 0.0f : s;
+}
+
 template <int R>
 __device__ __forceinline__ float grid_scale(float lo, float hi) {
-    const float ext = hi - lo;
-    float s = (ext > 0.0f) ? (float)R / ext : 0.0f;
-    return isinf(s) ? 0.0f : s;
+    return grid_scale_ext<R>(hi - lo);
 }
 
 template <int R>
@@ -135,6 +150,24 @@ __device__ __forceinline__ void ray_cells(const float* lo, const float* hi, cons
     ez = cell_of<R>(lo[2], sz, r.oz, r.dz, t1);
 }
 
+// the same cells from a box given by its near and far bound per axis (sign bit j of `neg` set:
+// the far bound is the lower one); hi - lo is |far - near|, exactly, as a difference and its
+// negation round alike
+template <int R>
+__device__ __forceinline__ void ray_cells_nf(const float* nr, const float* fr, uint32_t neg, const Ray& r, float t0,
+                                             float t1, int& bx, int& by, int& bz, int& ex, int& ey, int& ez) {
+    const float lo[3] = {(neg & 1u) ? fr[0] : nr[0], (neg & 2u) ? fr[1] : nr[1], (neg & 4u) ? fr[2] : nr[2]};
+    const float sx = grid_scale_ext<R>(fabsf(fr[0] - nr[0]));
+    const float sy = grid_scale_ext<R>(fabsf(fr[1] - nr[1]));
+    const float sz = grid_scale_ext<R>(fabsf(fr[2] - nr[2]));
+    bx = cell_of<R>(lo[0], sx, r.ox, r.dx, t0);
+    by = cell_of<R>(lo[1], sy, r.oy, r.dy, t0);
+    bz = cell_of<R>(lo[2], sz, r.oz, r.dz, t0);
+    ex = cell_of<R>(lo[0], sx, r.ox, r.dx, t1);
+    ey = cell_of<R>(lo[1], sy, r.oy, r.dy, t1);
+    ez = cell_of<R>(lo[2], sz, r.oz, r.dz, t1);
+}
+
 // the 2-D bit table answers (ray mask of key) AND (codebook entry idx) != 0 with one bit
 template <int R>
 __device__ __forceinline__ bool bit_overlap(const float* lo, const float* hi, const Ray& r, float t0, float t1,
@@ -142,7 +175,7 @@ __device__ __forceinline__ bool bit_overlap(const float* lo, const float* hi, co
     int bx, by, bz, ex, ey, ez;
     ray_cells<R>(lo, hi, r, t0, t1, bx, by, bz, ex, ey, ez);
     const uint32_t key = (uint32_t)(((((bx * R + by) * R + bz) * R + ex) * R + ey) * R + ez);
-    return (table[(size_t)key * (K >> 5) + (idx >> 5)] >> (idx & 31u)) & 1u;
+    return (table[key * (K >> 5) + (idx >> 5)] >> (idx & 31u)) & 1u;
 }
 
 // R = 4: the ray mask of cells (b, e) is displacement pattern pidx (x made
@@ -159,13 +192,11 @@ __device__ __forceinline__ void r4_pattern(int bx, int by, int bz, int ex, int e
     shift = (uint32_t)(qx + 4 * my + 16 * mz);
 }
 
-// (ray mask of the cells holding o + t0 d and o + t1 d) AND (object mask om) != 0
+// (ray mask of cells b, e) AND (object mask om) != 0
 template <int R>
-__device__ __forceinline__ bool mask_overlap(const float* lo, const float* hi, const Ray& r, float t0, float t1,
-                                             const uint64_t* om, const uint64_t* lut, const uint64_t* lds_pat) {
+__device__ __forceinline__ bool mask_overlap_cells(int bx, int by, int bz, int ex, int ey, int ez,
+                                                   const uint64_t* om, const uint64_t* lut, const uint64_t* lds_pat) {
     constexpr int W = (R * R * R + 63) / 64;
-    int bx, by, bz, ex, ey, ez;
-    ray_cells<R>(lo, hi, r, t0, t1, bx, by, bz, ex, ey, ez);
     uint64_t ob[W];
     load_mask<W>(om, ob);
     if constexpr (R == 4) {
@@ -182,6 +213,15 @@ __device__ __forceinline__ bool mask_overlap(const float* lo, const float* hi, c
         for (int w = 0; w < W; ++w) acc |= rm[w] & ob[w];
         return acc != 0;
     }
+}
+
+// (ray mask of the cells holding o + t0 d and o + t1 d) AND (object mask om) != 0
+template <int R>
+__device__ __forceinline__ bool mask_overlap(const float* lo, const float* hi, const Ray& r, float t0, float t1,
+                                             const uint64_t* om, const uint64_t* lut, const uint64_t* lds_pat) {
+    int bx, by, bz, ex, ey, ez;
+    ray_cells<R>(lo, hi, r, t0, t1, bx, by, bz, ex, ey, ez);
+    return mask_overlap_cells<R>(bx, by, bz, ex, ey, ez, om, lut, lds_pat);
 }
 
 // order by (key, id): swap when b comes first
@@ -209,17 +249,18 @@ constexpr uint32_t trace_lds_bytes() {
 constexpr uint32_t kLdsPerCu = 160u * 1024u;  // gfx950
 
 // Minimum waves per SIMD the register allocation must allow (1 = no constraint).
-// The plain 4-wide kernel and the 4-wide kernels for R = 4 raw masks and for
-// the bit table run faster held to 80 VGPRs (6 waves); the other 4-wide mask
-// kernels spill on their hot path there and are held to 96 VGPRs (5 waves),
-// which they fit without spilling, except the R = 6 raw kernel on quantised
-// boxes, which fits 80 without spilling and runs faster there. Where LDS already
-// allows fewer waves than that, the target is what LDS allows: registers beyond
-// it would buy nothing.
+// Held to 80 VGPRs (6 waves): the plain 4-wide kernel, the bit-table kernels, the
+// R = 4 raw kernel on float boxes and the R = 6 raw kernel on quantised boxes
+// (their few spilled registers sit in the ray set-up, not in the traversal
+// step). The other 4-wide mask kernels -- among them the quantised R = 4 raw
+// kernel, whose four in-flight mask reads need the room -- spill inside the
+// step at 80 and are held to 96 VGPRs (5 waves). Where LDS already allows fewer
+// waves than that, the target is what LDS allows: registers beyond it would buy
+// nothing.
 template <uint32_t MODE, int R, int WIDTH, int BLOCK, int STACK, bool QUANT = false>
 struct MinWaves {
     static constexpr int target =
-        (WIDTH == 4 && (MODE == kModeNone || (MODE == kModeRaw && (R == 4 || QUANT)) || MODE == kModeLutBits)) ? 6
+        (WIDTH == 4 && (MODE == kModeNone || (MODE == kModeRaw && (R == 4) != QUANT) || MODE == kModeLutBits)) ? 6
         : (WIDTH == 4)                                                                                         ? 5
                                                                                                                : 1;
     static constexpr int lds_waves =
@@ -230,7 +271,8 @@ struct MinWaves {
 template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH, int WIDTH, bool QUANT = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MinWaves<MODE, R, WIDTH, BLOCK, STACK, QUANT>::value)))
 void trace_kernel(TraceLaunch a) {
-    static_assert(WIDTH == 2 || (WIDTH == 4 && !BATCH && MODE != kModeSparse), "4-wide: single scene, no sparse masks");
+    static_assert(WIDTH == 2 || (WIDTH == 4 && MODE != kModeSparse), "4-wide: no sparse masks");
+    static_assert(!BATCH || (MODE != kModeLutLds && MODE != kModeLutBits), "batches read each scene's codebook");
     constexpr int W = (R * R * R + 63) / 64;
     constexpr uint32_t kStride = (MODE == kModeRaw) ? kRawNodeBytes : kNodeBytes;
     constexpr bool kPatLds = (R == 4) && (MODE != kModeNone) && (MODE != kModeLutBits);
@@ -275,6 +317,7 @@ void trace_kernel(TraceLaunch a) {
     sc_hit* s_hits = a.hits;
     uint32_t* s_extra = a.extra;
     uint32_t* s_fp = a.slot_fp;
+    const uint32_t* s_src4 = a.src4;
 
     // The rays are split into a.parts contiguous partitions, one queue counter
     // each. Workgroups are dispatched round-robin over the XCDs, so a wave
@@ -326,23 +369,22 @@ void trace_kernel(TraceLaunch a) {
                     if (!has) {
                         const uint32_t gid = cursor + (uint32_t)__popcll(idle & lanes_below);
                         if (gid < end) {
-                            uint32_t id = gid;
-                            if constexpr (!BATCH) {
-                                if (a.order) id = a.order[gid];
-                            } else {
-                                // item holding this ray: the last one whose first ray is <= gid
+                            uint32_t id = a.order ? a.order[gid] : gid;
+                            if constexpr (BATCH) {
+                                // item holding this ray: the last one whose first ray is <= its index
+                                const uint32_t g = id;
                                 uint32_t lo = 0, hi = a.n_items;
                                 while (hi - lo > 1) {
                                     const uint32_t mid = (lo + hi) >> 1;
-                                    if (a.items[mid].ray_begin <= gid) lo = mid;
+                                    if (a.items[mid].ray_begin <= g) lo = mid;
                                     else hi = mid;
                                 }
                                 const BatchItem& it = a.items[lo];
                                 s_nodes = it.nodes; s_tris = it.tris; s_codebook = it.codebook;
                                 s_side = it.side_masks; s_rays = it.rays; s_full = it.full_start;
                                 s_root = it.root; s_bound = it.origin_bound; s_hits = it.hits;
-                                s_extra = it.extra; s_fp = it.slot_fp;
-                                id = gid - it.ray_begin;
+                                s_extra = it.extra; s_fp = it.slot_fp; s_src4 = it.src4;
+                                id = g - it.ray_begin;
                             }
                             const float4 r0 = reinterpret_cast<const float4*>(s_rays)[2 * (size_t)id];
                             const float4 r1 = reinterpret_cast<const float4*>(s_rays)[2 * (size_t)id + 1];
@@ -533,14 +575,14 @@ void trace_kernel(TraceLaunch a) {
                         pm[c] = 0u;
                         const uint32_t idx = (MODE == kModeRaw) ? 0u : cidx4[c];
                         if (cneed[c]) {
-                            const float lo[3] = {sx ? cfx[c] : cnx[c], sy ? cfy[c] : cny[c], sz ? cfz[c] : cnz[c]};
-                            const float hi[3] = {sx ? cnx[c] : cfx[c], sy ? cny[c] : cfy[c], sz ? cnz[c] : cfz[c]};
+                            const float nr[3] = {cnx[c], cny[c], cnz[c]}, fr[3] = {cfx[c], cfy[c], cfz[c]};
                             int bx, by, bz, ex, ey, ez;
-                            ray_cells<R>(lo, hi, r, ct0[c], ct1[c], bx, by, bz, ex, ey, ez);
+                            ray_cells_nf<R>(nr, fr, r.neg, r, ct0[c], ct1[c], bx, by, bz, ex, ey, ez);
                             if constexpr (MODE == kModeLutBits) {
                                 const uint32_t k6 =
                                     (uint32_t)(((((bx * R + by) * R + bz) * R + ex) * R + ey) * R + ez);
-                                pw[c] = a.bit_table[(size_t)k6 * (a.K >> 5) + (idx >> 5)];
+                                // R^6 rows of K / 32 words: below 2^23 words for R <= 6, K <= 4096
+                                pw[c] = a.bit_table[k6 * (a.K >> 5) + (idx >> 5)];
                                 pb[c] = idx & 31u;
                             } else {
                                 if constexpr (MODE == kModeRaw) pm[c] = s_side[(size_t)ref * 4 + c];
@@ -560,7 +602,7 @@ void trace_kernel(TraceLaunch a) {
                             else any = ((pm[c] >> pb[c]) & lds_pat[pp[c]]) != 0;
                             if (!any) {
                                 ++mask_culls;
-                                if (shadow_flag && s_fp) atomicAdd(&s_fp[a.src4[(size_t)ref * 4 + c]], 1u);
+                                if (shadow_flag && s_fp) atomicAdd(&s_fp[s_src4[(size_t)ref * 4 + c]], 1u);
                                 keep = !cull;
                             }
                         }
@@ -602,14 +644,12 @@ void trace_kernel(TraceLaunch a) {
                             }
                             if (test) {
                                 ++mask_tests;
-                                const float lo[3] = {sx ? fr[0] : nr[0], sy ? fr[1] : nr[1], sz ? fr[2] : nr[2]};
-                                const float hi[3] = {sx ? nr[0] : fr[0], sy ? nr[1] : fr[1], sz ? nr[2] : fr[2]};
-                                bool any;
-                                if constexpr (MODE == kModeLutBits) any = bit_overlap<R>(lo, hi, r, t0, t1, a.bit_table, a.K, idx);
-                                else any = mask_overlap<R>(lo, hi, r, t0, t1, om, a.lut, lds_pat);
+                                int bx, by, bz, ex, ey, ez;
+                                ray_cells_nf<R>(nr, fr, r.neg, r, t0, t1, bx, by, bz, ex, ey, ez);
+                                const bool any = mask_overlap_cells<R>(bx, by, bz, ex, ey, ez, om, a.lut, lds_pat);
                                 if (!any) {
                                     ++mask_culls;
-                                    if (shadow_flag && s_fp) atomicAdd(&s_fp[a.src4[(size_t)ref * 4 + c]], 1u);
+                                    if (shadow_flag && s_fp) atomicAdd(&s_fp[s_src4[(size_t)ref * 4 + c]], 1u);
                                     keep = !cull;
                                 }
                             }
@@ -786,52 +826,42 @@ hipError_t launch_cfg(const TraceLaunch& a, hipStream_t s) {
     }
 }
 
-template <int BLOCK, int STACK>
-hipError_t launch_cfg4(const TraceLaunch& a, hipStream_t s) {
-    if (a.quant) {
-        switch (a.mode) {
-            case SC_MASK_NONE: return launch_one<kModeNone, 6, BLOCK, STACK, false, 4, true>(a, s);
-            case SC_MASK_RAW:
-                return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK, false, 4, true>(a, s)
-                                : launch_one<kModeRaw, 6, BLOCK, STACK, false, 4, true>(a, s);
-            case SC_MASK_LUT:
-                if (a.bit_table)
-                    return a.R == 4 ? launch_one<kModeLutBits, 4, BLOCK, STACK, false, 4, true>(a, s)
-                                    : launch_one<kModeLutBits, 6, BLOCK, STACK, false, 4, true>(a, s);
-                if (!a.cb_global && (size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
-                    return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK, false, 4, true>(a, s)
-                                    : launch_one<kModeLutLds, 6, BLOCK, STACK, false, 4, true>(a, s);
-                return a.R == 4 ? launch_one<kModeLut, 4, BLOCK, STACK, false, 4, true>(a, s)
-                                : launch_one<kModeLut, 6, BLOCK, STACK, false, 4, true>(a, s);
-            default: return hipErrorInvalidValue;
-        }
-    }
+template <int BLOCK, int STACK, bool BATCH, bool QUANT>
+hipError_t launch_cfg4q(const TraceLaunch& a, hipStream_t s) {
     switch (a.mode) {
-        case SC_MASK_NONE: return launch_one<kModeNone, 6, BLOCK, STACK, false, 4>(a, s);
+        case SC_MASK_NONE: return launch_one<kModeNone, 6, BLOCK, STACK, BATCH, 4, QUANT>(a, s);
         case SC_MASK_RAW:
-            return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK, false, 4>(a, s)
-                            : launch_one<kModeRaw, 6, BLOCK, STACK, false, 4>(a, s);
+            return a.R == 4 ? launch_one<kModeRaw, 4, BLOCK, STACK, BATCH, 4, QUANT>(a, s)
+                            : launch_one<kModeRaw, 6, BLOCK, STACK, BATCH, 4, QUANT>(a, s);
         case SC_MASK_LUT:
-            if (a.bit_table)
-                return a.R == 4 ? launch_one<kModeLutBits, 4, BLOCK, STACK, false, 4>(a, s)
-                                : launch_one<kModeLutBits, 6, BLOCK, STACK, false, 4>(a, s);
-            if (!a.cb_global && (size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
-                return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK, false, 4>(a, s)
-                                : launch_one<kModeLutLds, 6, BLOCK, STACK, false, 4>(a, s);
-            return a.R == 4 ? launch_one<kModeLut, 4, BLOCK, STACK, false, 4>(a, s)
-                            : launch_one<kModeLut, 6, BLOCK, STACK, false, 4>(a, s);
+            if constexpr (!BATCH) {
+                // single scene: the 2-D bit table, or the codebook copied into LDS when it fits
+                if (a.bit_table)
+                    return a.R == 4 ? launch_one<kModeLutBits, 4, BLOCK, STACK, false, 4, QUANT>(a, s)
+                                    : launch_one<kModeLutBits, 6, BLOCK, STACK, false, 4, QUANT>(a, s);
+                if (!a.cb_global && (size_t)a.K * (a.R == 4 ? 1 : 4) <= kCbLdsWords)
+                    return a.R == 4 ? launch_one<kModeLutLds, 4, BLOCK, STACK, false, 4, QUANT>(a, s)
+                                    : launch_one<kModeLutLds, 6, BLOCK, STACK, false, 4, QUANT>(a, s);
+            }
+            return a.R == 4 ? launch_one<kModeLut, 4, BLOCK, STACK, BATCH, 4, QUANT>(a, s)
+                            : launch_one<kModeLut, 6, BLOCK, STACK, BATCH, 4, QUANT>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
+template <int BLOCK, int STACK, bool BATCH>
+hipError_t launch_cfg4(const TraceLaunch& a, hipStream_t s) {
+    return a.quant ? launch_cfg4q<BLOCK, STACK, BATCH, true>(a, s) : launch_cfg4q<BLOCK, STACK, BATCH, false>(a, s);
+}
+
 template <bool BATCH>
 hipError_t launch_any(const TraceLaunch& a, hipStream_t s) {
-    if (!BATCH && a.width == 4) {
-        if (a.block == 256 && a.stack == 8) return launch_cfg4<256, 8>(a, s);
-        if (a.block == 128 && a.stack == 8) return launch_cfg4<128, 8>(a, s);
-        if (a.block == 256 && a.stack == 12) return launch_cfg4<256, 12>(a, s);
-        if (a.block == 256 && a.stack == 4) return launch_cfg4<256, 4>(a, s);
-        if (a.block == 128 && a.stack == 16) return launch_cfg4<128, 16>(a, s);
+    if (a.width == 4) {
+        if (a.block == 256 && a.stack == 8) return launch_cfg4<256, 8, BATCH>(a, s);
+        if (a.block == 128 && a.stack == 8) return launch_cfg4<128, 8, BATCH>(a, s);
+        if (a.block == 256 && a.stack == 12) return launch_cfg4<256, 12, BATCH>(a, s);
+        if (a.block == 256 && a.stack == 4) return launch_cfg4<256, 4, BATCH>(a, s);
+        if (a.block == 128 && a.stack == 16) return launch_cfg4<128, 16, BATCH>(a, s);
         return hipErrorInvalidValue;
     }
     if (a.width != 2) return hipErrorInvalidValue;

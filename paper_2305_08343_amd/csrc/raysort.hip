@@ -55,6 +55,26 @@ __global__ __launch_bounds__(256) void ray_key_kernel(const float* __restrict__ 
     vals[i] = i;
 }
 
+// batched launches: key = item index (bits 24..31) | Morton code of the origin in the item's bounds
+__global__ __launch_bounds__(256) void batch_ray_key_kernel(const BatchItem* __restrict__ items, uint32_t n_items,
+                                                            uint32_t n, uint32_t* __restrict__ keys,
+                                                            uint32_t* __restrict__ vals) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t lo = 0, hi = n_items;  // the last item whose first ray is <= i
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (items[mid].ray_begin <= i) lo = mid;
+        else hi = mid;
+    }
+    const BatchItem& it = items[lo];
+    const float4 o = reinterpret_cast<const float4*>(it.rays)[2 * (size_t)(i - it.ray_begin)];
+    keys[i] = (lo << 24) | (spread3(cell8(o.x, it.key_lo[0], it.key_scale[0])) << 2) |
+              (spread3(cell8(o.y, it.key_lo[1], it.key_scale[1])) << 1) |
+              spread3(cell8(o.z, it.key_lo[2], it.key_scale[2]));
+    vals[i] = i;
+}
+
 __global__ __launch_bounds__(kSortThreads) void digit_hist_kernel(const uint32_t* __restrict__ keys, uint32_t n,
                                                                   uint32_t shift, uint32_t ntiles,
                                                                   uint32_t* __restrict__ counts) {
@@ -189,29 +209,23 @@ size_t ray_order_workspace_bytes(uint32_t n) {
     return 16 * (size_t)n + 4 * m + 4 * nb;
 }
 
-hipError_t launch_ray_order(const float* rays, uint32_t n, const float lo[3], const float hi[3], void* workspace,
-                            uint32_t** order, hipStream_t s) {
-    if (n == 0) return hipSuccess;
+namespace {
+
+// LSD radix sort of the n (key, value) pairs in the first two workspace arrays, 8 bits per pass
+// from bit 0; returns the sorted values (in the second or the fourth array)
+uint32_t* sort_pairs(void* workspace, uint32_t n, uint32_t passes, hipStream_t s) {
     const size_t ntiles = ((size_t)n + kSortTile - 1) / kSortTile;
     const size_t m = ntiles * kDigits;
     const size_t nb = (m + kScanTile - 1) / kScanTile;
-    if (nb > 0xFFFFFFFFull) return hipErrorInvalidValue;
     auto* k0 = static_cast<uint32_t*>(workspace);
     uint32_t* v0 = k0 + n;
     uint32_t* k1 = v0 + n;
     uint32_t* v1 = k1 + n;
     uint32_t* counts = v1 + n;
     uint32_t* sums = counts + m;
-    float sc[3];
-    for (int j = 0; j < 3; ++j) {
-        const float e = hi[j] - lo[j];
-        const float q = 256.0f / e;
-        sc[j] = (e > 0.0f && q < __builtin_inff()) ? q : 0.0f;
-    }
-    hipLaunchKernelGGL(ray_key_kernel, dim3((n + 255) / 256), dim3(256), 0, s, rays, n, lo[0], lo[1], lo[2],
-                       sc[0], sc[1], sc[2], k0, v0);
     uint32_t *kin = k0, *vin = v0, *kout = k1, *vout = v1;
-    for (uint32_t shift = 0; shift < 24; shift += 8) {
+    for (uint32_t p = 0; p < passes; ++p) {
+        const uint32_t shift = 8 * p;
         hipLaunchKernelGGL(digit_hist_kernel, dim3((uint32_t)ntiles), dim3(kSortThreads), 0, s, kin, n, shift,
                            (uint32_t)ntiles, counts);
         hipLaunchKernelGGL(scan_blocks_kernel, dim3((uint32_t)nb), dim3(kSortThreads), 0, s, counts, m, sums);
@@ -222,7 +236,41 @@ hipError_t launch_ray_order(const float* rays, uint32_t n, const float lo[3], co
         uint32_t* t = kin; kin = kout; kout = t;
         t = vin; vin = vout; vout = t;
     }
-    *order = vin;  // after an odd number of passes the result sits in the second buffers
+    return vin;
+}
+
+bool sort_fits(uint32_t n) {
+    const size_t ntiles = ((size_t)n + kSortTile - 1) / kSortTile;
+    const size_t nb = (ntiles * kDigits + kScanTile - 1) / kScanTile;
+    return nb <= 0xFFFFFFFFull && ntiles <= 0xFFFFFFFFull;
+}
+
+}  // namespace
+
+hipError_t launch_ray_order(const float* rays, uint32_t n, const float lo[3], const float hi[3], void* workspace,
+                            uint32_t** order, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (!sort_fits(n)) return hipErrorInvalidValue;
+    float sc[3];
+    for (int j = 0; j < 3; ++j) {
+        const float e = hi[j] - lo[j];
+        const float q = 256.0f / e;
+        sc[j] = (e > 0.0f && q < __builtin_inff()) ? q : 0.0f;
+    }
+    auto* k0 = static_cast<uint32_t*>(workspace);
+    hipLaunchKernelGGL(ray_key_kernel, dim3((n + 255) / 256), dim3(256), 0, s, rays, n, lo[0], lo[1], lo[2],
+                       sc[0], sc[1], sc[2], k0, k0 + n);
+    *order = sort_pairs(workspace, n, 3, s);  // 24-bit keys
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_order(const BatchItem* items, uint32_t n_items, uint32_t n, void* workspace,
+                              uint32_t** order, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (!sort_fits(n) || n_items == 0 || n_items > kBatchSortItems) return hipErrorInvalidValue;
+    auto* k0 = static_cast<uint32_t*>(workspace);
+    hipLaunchKernelGGL(batch_ray_key_kernel, dim3((n + 255) / 256), dim3(256), 0, s, items, n_items, n, k0, k0 + n);
+    *order = sort_pairs(workspace, n, 4, s);  // item index above the 24-bit Morton code
     return hipGetLastError();
 }
 

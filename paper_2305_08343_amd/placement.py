@@ -11,15 +11,21 @@ placement returns the same hits as all masks and as no masks.
 Training data: for each training scene, the shadow trace (culling off,
 masks evaluated) counts per slot the slab hits whose mask test fails; the
 label is log2(1 + 1e6 * count / rays). Placement only ranks the slots of one
-scene against each other, so the regression target is the label
-standardised within its scene (minus the scene's mean, over its standard
-deviation): the scene-wide level of false positives, which the geometric
-features cannot see, no longer has to be fitted. Each scene contributes its
-highest-label slots (a quarter of its sample) plus a uniform draw of the
-rest, since the budget places masks on the top few percent only. Training
-runs on the GPU through the
-library's MLP kernels (forward, backward, Adam). This module only
-orchestrates: sampling of batches, the label transform and bookkeeping use
+scene against each other, so labels are standardised within their scene
+(minus the scene's mean, over its standard deviation): the scene-wide level
+of false positives, which the geometric features cannot see, no longer has
+to be fitted. The network learns a correction to the importance the paper
+gives a mask (surface area, here times emptiness, Sect. 3.2.2): with h the
+log2 of area x emptiness standardised within its scene, and a the
+least-squares slope of the standardised label on h over all training
+samples, the regression target is label - a * h, and a slot's placement score
+is a * h + the network's output. A network that outputs zero ranks exactly as
+the heuristic; training moves the ranking where the features say the
+heuristic is wrong. Each scene contributes its highest-label slots (a quarter
+of its sample) plus a uniform draw of the rest, since the budget places masks
+on the top few percent only. Training runs on the GPU through the library's
+MLP kernels (forward, backward, Adam). This module only orchestrates:
+sampling of batches, the label and heuristic transforms and bookkeeping use
 torch tensors as plumbing.
 """
 from __future__ import annotations
@@ -60,8 +66,39 @@ def slot_dataset(ctx, tris, rays, R: int = 6):
     return X.contiguous(), y.contiguous(), info
 
 
-def train(ctx, X, y, *, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, seed: int = 0, log=None):
-    """Adam on the mean squared error; returns (params device tensor, loss history)."""
+def save_checkpoint(path: str, params, m, v, step: int, epoch: int, rng, hist) -> None:
+    """Training state after `epoch` epochs: parameters, Adam moments and step, the batch-order
+    generator's state and the loss history (an .npz written atomically)."""
+    import json
+    import os
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, params=params.cpu().numpy(), m=m.cpu().numpy(), v=v.cpu().numpy(),
+             step=np.int64(step), epoch=np.int64(epoch), hist=np.asarray(hist, np.float64),
+             rng=np.frombuffer(json.dumps(rng.bit_generator.state).encode(), np.uint8))
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path: str, device):
+    """(params, m, v, step, epoch, rng, hist) as written by save_checkpoint."""
+    import json
+
+    import torch
+    with np.load(path, allow_pickle=False) as z:
+        rng = np.random.default_rng()
+        rng.bit_generator.state = json.loads(bytes(z["rng"]).decode())
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        return (t(z["params"]), t(z["m"]), t(z["v"]), int(z["step"]), int(z["epoch"]), rng,
+                [float(x) for x in z["hist"]])
+
+
+def train(ctx, X, y, *, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, seed: int = 0, log=None,
+          checkpoint: str | None = None, resume: bool = False):
+    """Adam on the mean squared error; returns (params device tensor, loss history). With
+    `checkpoint`, the training state is written there after every epoch; with `resume` as well,
+    training continues from the state stored there (the same result as an uninterrupted run: the
+    kernels are deterministic and the batch order's generator is restored)."""
+    import os
+
     import torch
     dev = X.device
     N = X.shape[0]
@@ -73,8 +110,12 @@ def train(ctx, X, y, *, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, s
     work = torch.empty(batch * 130, dtype=torch.float32, device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     rng = np.random.default_rng(seed)
-    step, hist = 0, []
-    for ep in range(epochs):
+    step, hist, start = 0, [], 0
+    if checkpoint and resume and os.path.exists(checkpoint):
+        params, m, v, step, start, rng, hist = load_checkpoint(checkpoint, dev)
+        if log:
+            log(f"resumed from {checkpoint} after epoch {start} (step {step})")
+    for ep in range(start, epochs):
         perm = torch.from_numpy(rng.permutation(N)).to(dev)
         acc, nb = 0.0, 0
         for b0 in range(0, N - batch + 1, batch):
@@ -90,6 +131,8 @@ def train(ctx, X, y, *, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, s
         hist.append(acc / max(1, (nb + 63) // 64))
         if log:
             log(f"epoch {ep + 1}/{epochs}: {nb} steps, sampled mse {hist[-1]:.4f}")
+        if checkpoint:
+            save_checkpoint(checkpoint, params, m, v, step, ep + 1, rng, hist)
     return params, hist
 
 
@@ -104,6 +147,21 @@ def predict(ctx, params, X, chunk: int = 1 << 20):
 def budget_masks(beta: float, n_inner: int, mask_bytes: int = MASK_BYTES_R6) -> int:
     """Masks affordable with beta bytes per inner node."""
     return int(math.floor(beta * n_inner / mask_bytes))
+
+
+def heuristic_log(X):
+    """log2 of surface area (relative to the root) times emptiness, from the slot features
+    (feature 3 = log2(area / root area) / 32, feature 6 = occupied fraction); emptiness is
+    floored at 2^-9 (a mask that is not full at R = 6 has at least 1/216 empty)."""
+    import torch
+    return X[:, 3] * 32.0 + torch.log2(torch.clamp(1.0 - X[:, 6], min=2.0 ** -9))
+
+
+def standardise(v):
+    """(v - mean) / std over all entries (zeros where the std is 0), float64 numpy."""
+    vv = np.asarray(v, np.float64)
+    sd = float(vv.std()) if vv.size else 0.0
+    return (vv - vv.mean()) / sd if sd > 0.0 else np.zeros_like(vv)
 
 
 def heuristic_scores(X) -> np.ndarray:
@@ -189,31 +247,53 @@ def scene_targets(y, max_slots: int, seed: int, top_share: float = 0.25):
     return idx, t[idx].astype(np.float32)
 
 
+def residual_targets(ts, hs):
+    """Least-squares slope a of the standardised labels on the standardised log heuristic over
+    all training samples, and the targets label - a * h. ts, hs: per-scene float arrays."""
+    t = np.concatenate(ts).astype(np.float64) if ts else np.zeros(0)
+    h = np.concatenate(hs).astype(np.float64) if hs else np.zeros(0)
+    hh = float((h * h).sum())
+    a = float((t * h).sum()) / hh if hh > 0.0 else 0.0
+    return a, (t - a * h).astype(np.float32)
+
+
 def build_training_set(ctx, specs, *, max_slots: int = 65536, log=None):
-    """Concatenated features / standardised targets over training scenes (device tensors)."""
+    """Concatenated features (device tensor), residual targets (device tensor) and the slope a
+    over the training scenes."""
     import torch
     from . import scenes
-    Xs, ys = [], []
+    Xs, ts, hs = [], [], []
     for i, sp in enumerate(specs):
         tris, rays = scenes.placement_scene(sp)
         X, y, info = slot_dataset(ctx, tris, rays)
         idx, t = scene_targets(y, max_slots, sp.seed)
-        Xs.append(X[torch.from_numpy(idx).to(X.device)])
-        ys.append(torch.from_numpy(t).to(X.device))
+        h = standardise(heuristic_log(X).cpu().numpy())
+        sel = torch.from_numpy(idx).to(X.device)
+        Xs.append(X[sel])
+        ts.append(t)
+        hs.append(h[idx])
         if log and (i % 10 == 0 or i == len(specs) - 1):
             log(f"train scene {i + 1}/{len(specs)}: {sp.kind} {tris.shape[0]} tris, "
                 f"{info['n_inner']} inner nodes, mean label {y.mean().item():.3f}")
-    return torch.cat(Xs).contiguous(), torch.cat(ys).contiguous()
+    a, r = residual_targets(ts, hs)
+    X = torch.cat(Xs).contiguous()
+    return X, torch.from_numpy(r).to(X.device).contiguous(), a
 
 
-def evaluate_scene(ctx, params, tris, rays, *, betas=(0.5, 1.0, 2.0), seed: int = 0, reps: int = 5,
+def learned_scores(ctx, params, a: float, X) -> np.ndarray:
+    """Placement scores of one scene's slots: a * h + the network's correction."""
+    h = standardise(heuristic_log(X).cpu().numpy())
+    return (a * h + predict(ctx, params, X).cpu().numpy().astype(np.float64)).astype(np.float32)
+
+
+def evaluate_scene(ctx, params, a, tris, rays, *, betas=(0.5, 1.0, 2.0), seed: int = 0, reps: int = 5,
                    log=None) -> list:
     """All placements of one held-out scene: learned, heuristic, random and
     true-label at each budget, plus all masks (raw) and no masks."""
     import torch
     X, y, info = slot_dataset(ctx, tris, rays)
     S = X.shape[0]
-    pred = predict(ctx, params, X).cpu().numpy()
+    pred = learned_scores(ctx, params, a, X)
     rng = np.random.default_rng(seed)
     scores = {"learned": pred, "heuristic": heuristic_scores(X),
               "random": rng.random(S).astype(np.float32), "true_label": y.cpu().numpy()}
@@ -239,9 +319,10 @@ def run_experiment(ctx, train_specs, heldout, *, betas=(0.5, 1.0, 2.0), epochs: 
     """Train on the training scenes, evaluate every placement on each held-out
     (tris, rays) pair. Returns (params, loss history, [[Evaluation]])."""
     t0 = time.time()
-    X, y = build_training_set(ctx, train_specs, max_slots=max_slots, log=log)
+    X, y, a = build_training_set(ctx, train_specs, max_slots=max_slots, log=log)
     if log:
-        log(f"training set: {X.shape[0]} slots from {len(train_specs)} scenes ({time.time() - t0:.1f} s)")
+        log(f"training set: {X.shape[0]} slots from {len(train_specs)} scenes ({time.time() - t0:.1f} s), "
+            f"heuristic slope a = {a:.4f}")
     t1 = time.time()
     params, hist = train(ctx, X, y, epochs=epochs, batch=min(batch, X.shape[0]), lr=lr, seed=seed, log=log)
     if log:
@@ -250,5 +331,5 @@ def run_experiment(ctx, train_specs, heldout, *, betas=(0.5, 1.0, 2.0), epochs: 
     for k, (tris, rays) in enumerate(heldout):
         if log:
             log(f"held-out scene {k}: {tris.shape[0]} tris, {rays.shape[0]} rays")
-        results.append(evaluate_scene(ctx, params, tris, rays, betas=betas, seed=seed + k, log=log))
+        results.append(evaluate_scene(ctx, params, a, tris, rays, betas=betas, seed=seed + k, log=log))
     return params, hist, results

@@ -179,19 +179,28 @@ def test_sorted_and_every_launch_shape(ctx, small_scene, small_oracle):
         s.close()
 
 
-def test_batches_reject_4_wide_scenes(ctx, small_scene):
+def test_batches_take_4_wide_scenes(ctx, small_scene):
+    """A 4-wide scene in a batched launch (graph and direct) gives its single-scene results; a
+    batch mixing it with a binary scene is refused."""
     import torch
     from paper_2305_08343_amd import binding
     tris, rays = small_scene
     s = binding.Scene(ctx, tris, R=6, mode="raw", width=4)
-    items = [(s, torch.from_numpy(rays[:100]).cuda())]
-    with pytest.raises(binding.SubcullError):
-        binding.Batch(ctx, items, graph=True)
-    b = binding.Batch(ctx, items, graph=False)
-    with pytest.raises(binding.SubcullError):
+    s2 = binding.Scene(ctx, tris, R=6, mode="raw", width=2)
+    rd = torch.from_numpy(rays[:5000]).cuda()
+    single = s.trace(rd).numpy()
+    for graph in (True, False):
+        b = binding.Batch(ctx, [(s, rd)], graph=graph)
         b.launch()
-    b.close()
+        torch.cuda.synchronize()
+        got = b.results(0).numpy()
+        for f in ("prim", "box_tests", "tri_tests", "mask_tests", "mask_culls"):
+            assert (got[f] == single[f]).all(), (graph, f)
+        b.close()
+    with pytest.raises(binding.SubcullError):
+        binding.Batch(ctx, [(s, rd), (s2, rd)], graph=False).launch()
     s.close()
+    s2.close()
 
 
 def test_features_of_4_wide_scene_are_the_binary_slot_features(ctx, small_scene):

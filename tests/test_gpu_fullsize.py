@@ -12,9 +12,10 @@ all 8M rays the properties that hold at any size: culled hits equal unculled
 hits, per-ray counts none >= compressed >= raw, every stored codebook entry
 contains its slot's exact mask. The 4-wide modes bench.py times on this
 workload (216-bit masks compressed to 4,096 codebook entries on exact and on
-quantised child boxes, 64-bit raw masks on every slot and on leaf slots, plain
-traversal), each traced in the launch shape bench.py stores for it: 4-wide
-nodes, codebook and indices bit-exact against the oracle, every 64th ray
+quantised child boxes, tested through the 2-D bit table or by codebook fetch,
+64-bit raw masks on every slot and on leaf slots, plain traversal), each
+traced in the launch shape bench.py stores for it: 4-wide nodes, codebook,
+indices and bit table bit-exact against the oracle, every 64th ray
 bit-exact against the oracle's 4-wide traversal, and on all 8M rays hits equal
 to the unculled ones with counts none >= compressed and none >= leaf-slot >=
 every-slot raw masks.
@@ -237,7 +238,7 @@ def test_curly_12m_sampled_rays_bit_exact(request, curly, curly_dev, curly_masks
 
 
 # 4-wide modes of the curly benchmark, each in the launch shape bench.py stores for it there
-CURLY4 = ["lut6w4", "lut6w4q", "raw4w4", "raw4w4l", "nonew4", "nonew4q"]
+CURLY4 = ["lut6w4b", "lut6w4", "lut6w4q", "raw4w4", "raw4w4l", "nonew4", "nonew4q"]
 
 
 @pytest.fixture(scope="module")
@@ -250,7 +251,8 @@ def curly4_dev(request, ctx, curly):
         shape = bench.stored_tune(name, "curly_12m")
         _say(request, f"curly_12m {name}: device build + trace of 8M rays in shape {shape}")
         s = binding.Scene(ctx, curly["tris"], R=spec["R"], mode=spec["mode"], K=spec.get("K", 4096), width=4,
-                          quantise=spec.get("quantise", False), mask_slots=spec.get("mask_slots", "all"))
+                          quantise=spec.get("quantise", False), mask_slots=spec.get("mask_slots", "all"),
+                          bit_table=spec.get("bit_table", False))
         try:
             ctx.set_tune(*shape)
             out[name] = s.trace(curly["rays"]).numpy()
@@ -260,6 +262,8 @@ def curly4_dev(request, ctx, curly):
         if spec["mode"] == "lut":
             e = s.export()
             out[f"{name}/cb"] = (e["codebook"], e["cidx"])
+        if spec.get("bit_table"):
+            out[f"{name}/bits"] = s.export_bit_table()
         s.close()
     return out
 
@@ -278,6 +282,8 @@ def curly4_oracle(request, curly, curly_masks):
     cbq, idxq = oracle.compress(masks6q, bq.slot_boxes(), 6, 4096)
     return {"b4": b4, "d4": d4, "bq": bq,
             "lut6w4": (bvh, b4, dict(mode="lut", R=6, codebook=curly_masks["cb"], cidx=curly_masks["idx"])),
+            # the bit table answers the same test as codebook fetch + AND
+            "lut6w4b": (bvh, b4, dict(mode="lut", R=6, codebook=curly_masks["cb"], cidx=curly_masks["idx"])),
             "lut6w4q": (bq, d4, dict(mode="lut", R=6, codebook=cbq, cidx=idxq)),
             "raw4w4": (bvh, b4, dict(mode="raw", R=4, masks=masks4)),
             "raw4w4l": (bvh, b4, dict(mode="raw", R=4, masks=oracle.leaf_slot_masks(masks4, bvh, 4))),
@@ -294,10 +300,12 @@ def test_curly_12m_4_wide_nodes_and_codebooks(request, curly4_dev, curly4_oracle
         e4 = curly4_dev[f"{name}/export4"]
         assert (e4["box4"].view(np.uint32) == ob4.box4.view(np.uint32)).all(), name
         assert (e4["ref4"] == ob4.ref4).all() and (e4["src4"] == ob4.src4).all(), name
-    for name in ("lut6w4", "lut6w4q"):
+    for name in ("lut6w4b", "lut6w4", "lut6w4q"):
         cb, idx = curly4_dev[f"{name}/cb"]
         want = curly4_oracle[name][2]
         assert (cb == want["codebook"]).all() and (idx == want["cidx"]).all(), name
+    _say(request, "curly_12m: 2-D bit table (R^6 x 4096 bits) vs oracle")
+    assert (curly4_dev["lut6w4b/bits"] == oracle.bit_table(6, curly_masks["cb"])).all()
 
 
 @pytest.mark.timeout(900)
@@ -331,6 +339,10 @@ def test_curly_12m_4_wide_properties_all_rays(request, curly_dev, curly4_dev):
         assert (curly4_dev["nonew4q"][f] >= curly4_dev["lut6w4q"][f]).all(), f
     for name in ("lut6w4", "lut6w4q", "raw4w4", "raw4w4l"):
         assert curly4_dev[name]["mask_culls"].sum() > 0, name
+    # the bit table and the codebook fetch answer every test alike: identical results per ray
+    for f in ("prim", "box_tests", "tri_tests", "mask_tests", "mask_culls"):
+        assert (curly4_dev["lut6w4b"][f] == curly4_dev["lut6w4"][f]).all(), f
+    assert (curly4_dev["lut6w4b"]["t"].view(np.uint32) == curly4_dev["lut6w4"]["t"].view(np.uint32)).all()
 
 
 # --------------------------------------------------------------------- batch64

@@ -117,3 +117,25 @@ def test_training_steps_track_the_oracle(ctx):
         P, M, V = omlp.adam_step(P, omlp.grad(P, x.astype(np.float64), t.astype(np.float64)), M, V, step, lr=1e-2)
     assert losses[-1] < losses[0]
     assert np.allclose(dp.cpu().numpy(), P, rtol=1e-3, atol=1e-4)
+
+
+def test_training_checkpoint_resume_equals_uninterrupted(ctx, tmp_path):
+    """Six epochs in one run, and two runs of three epochs with the state written to a checkpoint
+    and read back in between: parameters, Adam state and loss history are bit-identical."""
+    import torch
+    from paper_2305_08343_amd import placement
+    rng = np.random.default_rng(11)
+    X = _dev(rng.normal(size=(8192 + 37, 12)))
+    y = _dev(rng.normal(size=8192 + 37))
+    print("[gpu] checkpoint / resume", flush=True)
+    p_all, h_all = placement.train(ctx, X, y, epochs=6, batch=1024, seed=3)
+    ck = str(tmp_path / "mlp.npz")
+    p_half, h_half = placement.train(ctx, X, y, epochs=3, batch=1024, seed=3, checkpoint=ck)
+    assert len(h_half) == 3
+    p_res, h_res = placement.train(ctx, X, y, epochs=6, batch=1024, seed=3, checkpoint=ck, resume=True)
+    torch.cuda.synchronize()
+    assert torch.equal(p_all, p_res)
+    assert h_all == h_res
+    params, m, v, step, epoch, _, hist = placement.load_checkpoint(ck, X.device)
+    assert epoch == 6 and step == 6 * 8 and torch.equal(params, p_res) and hist == h_res
+    assert not torch.equal(p_half, p_res)

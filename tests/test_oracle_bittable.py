@@ -41,3 +41,17 @@ def test_bit_table_properties(small_oracle, R):
         i, j = rng.integers(1, K, 2)
         if ((cb[i] & ~cb[j]) == 0).all():  # cb[j] contains cb[i]
             assert (bits[:, j] >= bits[:, i]).all()
+
+
+@pytest.mark.parametrize("R", [4, 6])
+def test_bit_table_rows_symmetric_in_entry_and_exit(small_oracle, R):
+    """Row (b, e) equals row (e, b): the traversal looks up the ordered pair only."""
+    lut = small_oracle[f"lut{R}"]
+    rng = np.random.default_rng(R)
+    cb = np.unique(rng.integers(0, 2 ** 63, size=(256, oracle.words_for(R)), dtype=np.int64).astype(np.uint64),
+                   axis=0)[:128]
+    table = oracle.bit_table(R, cb, lut)
+    c3 = R ** 3
+    key = np.arange(R ** 6)
+    b, e = key // c3, key % c3
+    assert (table[key] == table[e * c3 + b]).all()
