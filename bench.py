@@ -104,11 +104,23 @@ CURLY_TUNE = {
 }
 
 
+def mode_spec(name):
+    """MODES[name]; "base@N" is mode base built with mask_test_max N: masks (raw, or the codebook
+    entry a slot points to) with more than N set bits pass untested."""
+    if "@" in name:
+        base, limit = name.split("@")
+        return dict(MODES[base], test_max=int(limit))
+    return MODES[name]
+
+
 def stored_tune(name, workload):
-    """The launch shape bench.py uses for mode `name` on `workload`."""
+    """The launch shape bench.py uses for mode `name` on `workload` (a "base@N" mode: base's)."""
     if workload == "curly_12m" and name in CURLY_TUNE:
         return CURLY_TUNE[name]
-    return MODES[name].get("tune", ())
+    base = name.split("@")[0]
+    if workload == "curly_12m" and base in CURLY_TUNE:
+        return CURLY_TUNE[base]
+    return MODES[base].get("tune", ())
 
 
 def measured_traffic(mode, workload):
@@ -167,23 +179,21 @@ def time_mode(ctx, tris, rays_dev, name, spec, steps, warmup, autotune=False, wo
     t0 = time.perf_counter()
     scene = binding.Scene(ctx, tris, R=spec["R"], mode=spec["mode"], K=spec.get("K", 4096), width=spec["width"],
                           bit_table=spec.get("bit_table", False), mask_slots=spec.get("mask_slots", "all"),
-                          quantise=spec.get("quantise", False))
+                          quantise=spec.get("quantise", False), mask_test_max=spec.get("test_max", 0))
     build_s = time.perf_counter() - t0
     n = rays_dev.shape[0]
     hits = torch.empty((n, 4), dtype=torch.int32, device=rays_dev.device)
     extra = torch.empty((n, 2), dtype=torch.int32, device=rays_dev.device)
     tuned = None
     if autotune:
-        # shapes are compared on an evenly strided subsample of about 1M rays (still many times the
-        # waves the GPU holds at once); the timed run below confirms the pick on every ray
-        k = max(1, n // 1_000_000)
-        sub = rays_dev[::k].contiguous()
-        key = f"{workload}|{name}|{tris.shape[0]}|{n}|every{k}"
+        # shapes are compared on the whole ray set: on a subsample the persistent grid's drain weighs
+        # more and the tuner's picks run slower on every ray
+        key = f"{workload}|{name}|{tris.shape[0]}|{n}"
         lut = spec["mode"] == "lut" and not spec.get("bit_table", False)
-        cfg, entry = tune.tuned(ctx, key, lambda: scene.trace(sub, cull=spec["cull"], hits=hits,
+        cfg, entry = tune.tuned(ctx, key, lambda: scene.trace(rays_dev, cull=spec["cull"], hits=hits,
                                                               extra_out=extra), log=log,
                                 cands=tune.candidates(lut=lut))
-        tuned = {"config": list(cfg), "seconds": entry.get("seconds"), "subsample": f"every {k}th ray"}
+        tuned = {"config": list(cfg), "seconds": entry.get("seconds")}
     res = scene.trace(rays_dev, cull=spec["cull"], hits=hits, extra_out=extra).numpy()
     for _ in range(warmup):
         scene.trace(rays_dev, cull=spec["cull"], hits=hits, extra_out=extra)
@@ -256,7 +266,7 @@ def cpu_baseline(tris, rays, target_s, spec):
     if quant:
         b4 = oracle.decoded_bvh4(b4, oracle.quantise4(b4))
         bvh = oracle.with_slot_boxes(bvh, b4)
-    kw = dict(mode=mode, R=R, origin_bound=ob)
+    kw = dict(mode=mode, R=R, origin_bound=ob, test_max=spec.get("test_max", 0))
     if mode != "none":
         masks = oracle.object_masks(tris, bvh, R, delta, nthreads=cores)
         if spec.get("mask_slots") == "leaves":
@@ -298,7 +308,9 @@ def cpu_baseline(tris, rays, target_s, spec):
         deep = oracle.trace4(tris, bvh, b4, sample, nthreads=cores, stack_depth=True, **kw).deepest
     masks_txt = ("no masks (plain traversal)" if mode == "none" else
                  f"{'LUT K=' + str(spec.get('K', 4096)) if mode == 'lut' else mode} masks R={R}"
-                 f"{' on leaf slots' if spec.get('mask_slots') == 'leaves' else ''}, culled")
+                 f"{' on leaf slots' if spec.get('mask_slots') == 'leaves' else ''}"
+                 f"{', masks of more than %d set bits untested' % spec['test_max'] if spec.get('test_max') else ''}"
+                 f", culled")
     what = f"{masks_txt}, {'4-wide' if width == 4 else 'binary'} BVH{' with quantised child boxes' if quant else ''}"
     out = {"value": sample.shape[0] / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
             "cpu_model": cpu_model(),
@@ -333,10 +345,11 @@ def run_batch64(args, ctx):
     log(f"batch64: {n_tris} tris, {n_rays} rays generated in {time.perf_counter() - t0:.1f}s")
     out = {}
     for mname in args.modes.split(","):
-        spec = MODES[mname]
+        spec = mode_spec(mname)
         t0 = time.perf_counter()
         built = [binding.Scene(ctx, t, R=spec["R"], mode=spec["mode"], K=spec.get("K", 4096), width=spec["width"],
-                               quantise=spec.get("quantise", False), mask_slots=spec.get("mask_slots", "all"))
+                               quantise=spec.get("quantise", False), mask_slots=spec.get("mask_slots", "all"),
+                               mask_test_max=spec.get("test_max", 0))
                  for t, _ in data]
         rays = [torch.from_numpy(r).cuda() for _, r in data]
         build_s = time.perf_counter() - t0
@@ -560,14 +573,14 @@ def main():
             ctx.set_tune(t["block"], t["stack"], t["chunk"], t["parts"], t["waves"], int(args.sort), t["codebook"],
                          t["gather"], t["refill"])
         log(f"mode {m}: build{' + autotune' if autotune else ''} + {args.warmup} warmup + {args.steps} timed traces")
-        results[m], raw[m] = time_mode(ctx, tris, rays_dev, m, MODES[m], args.steps, args.warmup, autotune,
+        results[m], raw[m] = time_mode(ctx, tris, rays_dev, m, mode_spec(m), args.steps, args.warmup, autotune,
                                        args.workload)
         log(f"mode {m}: {results[m]['rays_per_s'] / 1e6:.1f} Mrays/s, "
             f"{results[m]['tests_per_ray']:.2f} tests/ray, kernel {results[m]['kernel_ms_mean']:.3f} ms")
     head = modes[0]
     for m in modes:
         # unculled reference: the plain traversal of the same node width, and the plain binary BVH
-        plain = ("nonew4q" if MODES[m].get("quantise") else "nonew4") if MODES[m]["width"] == 4 else "none"
+        plain = ("nonew4q" if mode_spec(m).get("quantise") else "nonew4") if mode_spec(m)["width"] == 4 else "none"
         for key, ref in (("unculled", plain), ("plain_binary", "none")):
             if ref not in raw or ref == m:
                 continue
@@ -610,7 +623,7 @@ def main():
         line["copy_probe_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        line["cpu_baseline"], deep = cpu_baseline(tris, rays, args.cpu_seconds, MODES[head])
+        line["cpu_baseline"], deep = cpu_baseline(tris, rays, args.cpu_seconds, mode_spec(head))
         if deep is not None:
             line["lds_stack"] = stack_report(deep, r["tune"]["stack"])
     print(json.dumps(line), flush=True)

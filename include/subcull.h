@@ -122,6 +122,13 @@ typedef struct {
                                boxes; the binary slots the 4-wide nodes use take
                                the decoded boxes, and masks, exports and counts
                                follow them (default 0)                           */
+    uint32_t mask_test_max; /* RAW and LUT modes: the most set bits a stored mask
+                               (raw mask, or the codebook entry a slot points
+                               to) may have and still be tested; denser masks
+                               pass untested, as a full mask always does (it
+                               cannot cull). Skipping a test never changes a
+                               hit. 0 selects R^3 - 1 (only full masks untested,
+                               the paper's method); 1..R^3 - 1 otherwise       */
 } sc_build_params;
 
 typedef struct {
@@ -134,6 +141,7 @@ typedef struct {
                                                 or 4-wide nodes when width 4    */
     uint32_t approx_levels;                  /* as built (0 = exact masks)      */
     uint32_t bit_table;                      /* 1 if the scene has a bit table  */
+    uint32_t mask_test_max;                  /* as built (R^3 - 1 by default)   */
     float delta, origin_bound;
     uint64_t device_bytes;                   /* scene-owned device memory       */
     double ms_bvh, ms_masks, ms_codebook, ms_compress;  /* build phases (host clock) */

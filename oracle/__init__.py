@@ -221,12 +221,13 @@ def ideal_mask(box, o, d, t0, t1, R):
 
 def trace(tris, bvh: BVH, rays, *, mode="none", R=6, masks=None, codebook=None, cidx=None,
           placed=None, lut=None, origin_bound=None, cull=True, shadow=False, nthreads=0,
-          ray_masks="lut", lut2=None) -> Hits:
+          ray_masks="lut", lut2=None, test_max=0) -> Hits:
     """Traversal with culling. mode "raw": masks per slot; "lut": codebook +
     cidx; "sparse": masks per slot used only where placed[slot] != 0. A slot
-    whose mask is full is never tested. ray_masks: "lut" (the table at R, the
-    method), "lut2r" (the table at 2R) or "ideal" (every voxel the segment
-    crosses), the last two as tightness references."""
+    whose mask has more than test_max set bits is never tested (0 = R^3 - 1:
+    only a full mask). ray_masks: "lut" (the table at R, the method), "lut2r"
+    (the table at 2R) or "ideal" (every voxel the segment crosses), the last
+    two as tightness references."""
     tris = np.ascontiguousarray(tris, np.float32)
     rays = np.ascontiguousarray(rays, np.float32)
     n = rays.shape[0]
@@ -250,7 +251,7 @@ def trace(tris, bvh: BVH, rays, *, mode="none", R=6, masks=None, codebook=None, 
                             C.c_uint32(bvh.depth), C.c_uint32(R), C.c_uint32(mcode), _p(masks),
                             _p(codebook), _p(cidx), _p(placed), _p(lut), C.c_float(origin_bound),
                             C.c_uint32(flags), _p(rays), C.c_uint32(n), _p(hits), _p(extra), _p(fp),
-                            C.c_int(nthreads), C.c_uint32(kind), _p(lut2))
+                            C.c_int(nthreads), C.c_uint32(kind), _p(lut2), C.c_uint32(test_max))
     _check(rc, "trace")
     hits, extra = hits[:n], extra[:n]
     return Hits(hits[:, 0].copy(), hits[:, 1].view(np.float32).copy(), hits[:, 2].copy(),
@@ -336,10 +337,10 @@ def with_slot_boxes(bvh: BVH, bvh4: BVH4) -> BVH:
 
 def trace4(tris, bvh: BVH, bvh4: BVH4, rays, *, mode="none", R=6, masks=None, codebook=None, cidx=None,
            placed=None, lut=None, origin_bound=None, cull=True, shadow=False, nthreads=0,
-           stack_depth=False) -> Hits:
-    """Alg. 4 on the 4-wide BVH; masks, codebook indices and shadow counts are
-    per binary child slot, as for trace(). stack_depth=True also returns, per
-    ray, the most stack entries held beneath the node being visited (Hits.deepest)."""
+           stack_depth=False, test_max=0) -> Hits:
+    """Alg. 4 on the 4-wide BVH; masks, codebook indices, shadow counts and
+    test_max are as for trace(). stack_depth=True also returns, per ray, the
+    most stack entries held beneath the node being visited (Hits.deepest)."""
     tris = np.ascontiguousarray(tris, np.float32)
     rays = np.ascontiguousarray(rays, np.float32)
     n = rays.shape[0]
@@ -363,7 +364,8 @@ def trace4(tris, bvh: BVH, bvh4: BVH4, rays, *, mode="none", R=6, masks=None, co
     rc = lib().orc_trace4(_p(tris), _p(bvh.perm), _p(b4), _p(r4), _p(s4), C.c_uint32(bvh4.root),
                           C.c_uint32(bvh4.depth), C.c_uint32(R), C.c_uint32(mcode), _p(masks), _p(codebook),
                           _p(cidx), _p(placed), _p(lut), C.c_float(origin_bound), C.c_uint32(flags), _p(rays),
-                          C.c_uint32(n), _p(hits), _p(extra), _p(fp), C.c_int(nthreads), _p(deep))
+                          C.c_uint32(n), _p(hits), _p(extra), _p(fp), C.c_int(nthreads), _p(deep),
+                          C.c_uint32(test_max))
     _check(rc, "trace4")
     hits, extra = hits[:n], extra[:n]
     return Hits(hits[:, 0].copy(), hits[:, 1].view(np.float32).copy(), hits[:, 2].copy(),

@@ -656,6 +656,7 @@ typedef struct {
     uint32_t* slot_fp;
     uint32_t rm_kind;          /* ray mask: 0 table at R, 1 table at 2R (lut2), 2 ideal */
     const uint64_t* lut2;
+    uint32_t test_max;         /* the most set bits a tested mask may have (R^3 - 1: all but full) */
 } TraceCtx;
 
 static void raymask_key_cells(const float* lo, const float* hi, const float* o, const float* d,
@@ -751,15 +752,17 @@ static void leaf_tests(const TraceCtx* C, uint32_t ref, const float* o, const fl
 /* Mask test of Sect. 3.1.2 for the child in binary slot `slot` whose box
  * [lo, hi] the ray overlaps over [t0, t1]: the ray mask of the entry and exit
  * cells (Alg. 1) ANDed with the slot's object mask (raw, codebook entry, or
- * absent when not placed). A full mask is not tested. Returns 1 when the AND
- * is zero (the child can be culled). */
+ * absent when not placed). A mask with more than test_max set bits is not
+ * tested -- by default only the full mask, which cannot cull; a smaller
+ * test_max leaves denser masks untested, which only forgoes culls. Returns 1
+ * when the AND is zero (the child can be culled). */
 static int mask_test(const TraceCtx* C, uint32_t slot, const float* lo, const float* hi, const float* o,
                      const float* d, float t0, float t1, uint32_t* mask_tests, uint32_t* mask_culls) {
     const uint64_t* om = NULL;
     if (C->mode == MODE_RAW) om = &C->masks[(size_t)slot * C->W];
     else if (C->mode == MODE_LUT) om = &C->cb[(size_t)C->cidx[slot] * C->W];
     else if (C->placed[slot]) om = &C->masks[(size_t)slot * C->W];
-    if (!om || popc(om, C->W) == C->R * C->R * C->R) return 0;
+    if (!om || popc(om, C->W) > C->test_max) return 0;
     ++*mask_tests;
     uint32_t R = C->R;
     uint64_t ideal[4] = {0, 0, 0, 0};
@@ -866,7 +869,7 @@ int orc_trace_ex(const float* tris, const uint32_t* perm, const float* cbox, con
                  const uint64_t* codebook, const uint16_t* cidx, const uint8_t* placed, const uint64_t* lut,
                  float origin_bound, uint32_t flags, const float* rays, uint32_t nrays,
                  uint32_t* out_hits, uint32_t* out_extra, uint32_t* slot_fp, int nthreads,
-                 uint32_t rm_kind, const uint64_t* lut2);
+                 uint32_t rm_kind, const uint64_t* lut2, uint32_t test_max);
 
 int orc_trace(const float* tris, const uint32_t* perm, const float* cbox, const uint32_t* cref,
               uint32_t root_ref, uint32_t depth, uint32_t R, uint32_t mode, const uint64_t* masks,
@@ -874,17 +877,18 @@ int orc_trace(const float* tris, const uint32_t* perm, const float* cbox, const 
               float origin_bound, uint32_t flags, const float* rays, uint32_t nrays,
               uint32_t* out_hits, uint32_t* out_extra, uint32_t* slot_fp, int nthreads) {
     return orc_trace_ex(tris, perm, cbox, cref, root_ref, depth, R, mode, masks, codebook, cidx, placed, lut,
-                        origin_bound, flags, rays, nrays, out_hits, out_extra, slot_fp, nthreads, 0, NULL);
+                        origin_bound, flags, rays, nrays, out_hits, out_extra, slot_fp, nthreads, 0, NULL, 0);
 }
 
 /* As orc_trace, with the ray mask taken from the table at R (rm_kind 0), the
- * table at 2R (1, lut2 from orc_raymask_lut2) or the ideal mask (2). */
+ * table at 2R (1, lut2 from orc_raymask_lut2) or the ideal mask (2), and masks
+ * with more than test_max set bits untested (0 = R^3 - 1: only full masks). */
 int orc_trace_ex(const float* tris, const uint32_t* perm, const float* cbox, const uint32_t* cref,
                  uint32_t root_ref, uint32_t depth, uint32_t R, uint32_t mode, const uint64_t* masks,
                  const uint64_t* codebook, const uint16_t* cidx, const uint8_t* placed, const uint64_t* lut,
                  float origin_bound, uint32_t flags, const float* rays, uint32_t nrays,
                  uint32_t* out_hits, uint32_t* out_extra, uint32_t* slot_fp, int nthreads,
-                 uint32_t rm_kind, const uint64_t* lut2) {
+                 uint32_t rm_kind, const uint64_t* lut2, uint32_t test_max) {
     if (rm_kind > 2 || (rm_kind == 1 && !lut2)) return ORC_ERR_ARG;
     if (depth + 1 > 160) return ORC_ERR_DEPTH;
     if (mode > MODE_SPARSE) return ORC_ERR_ARG;
@@ -900,6 +904,7 @@ int orc_trace_ex(const float* tris, const uint32_t* perm, const float* cbox, con
     C.slot_fp = (flags & FLAG_SHADOW) ? slot_fp : NULL;
     C.rm_kind = rm_kind;
     C.lut2 = lut2;
+    C.test_max = test_max ? test_max : R * R * R - 1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 256)
@@ -1159,7 +1164,7 @@ int orc_trace4(const float* tris, const uint32_t* perm, const float* box4, const
                const uint64_t* masks, const uint64_t* codebook, const uint16_t* cidx, const uint8_t* placed,
                const uint64_t* lut, float origin_bound, uint32_t flags, const float* rays, uint32_t nrays,
                uint32_t* out_hits, uint32_t* out_extra, uint32_t* slot_fp, int nthreads,
-               uint32_t* out_deepest) {
+               uint32_t* out_deepest, uint32_t test_max) {
     if (3 * depth + 1 > 256) return ORC_ERR_DEPTH;
     if (mode > MODE_SPARSE) return ORC_ERR_ARG;
     if (mode != MODE_NONE && (R < 1 || R > 6 || !lut)) return ORC_ERR_ARG;
@@ -1175,6 +1180,7 @@ int orc_trace4(const float* tris, const uint32_t* perm, const float* box4, const
     C->slot_fp = (flags & FLAG_SHADOW) ? slot_fp : NULL;
     C->rm_kind = 0;
     C->lut2 = NULL;
+    C->test_max = test_max ? test_max : R * R * R - 1;
     T.box4 = box4; T.ref4 = ref4; T.src4 = src4;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);

@@ -41,7 +41,7 @@ class sc_build_params(C.Structure):
                 ("delta", C.c_float), ("origin_bound", C.c_float),
                 ("mask_placement", C.c_void_p), ("placement_len", C.c_uint32), ("width", C.c_uint32),
                 ("approx_levels", C.c_uint32), ("bit_table", C.c_uint32), ("mask_slots", C.c_uint32),
-                ("quantise", C.c_uint32)]
+                ("quantise", C.c_uint32), ("mask_test_max", C.c_uint32)]
 
 
 class sc_scene_info(C.Structure):
@@ -49,7 +49,7 @@ class sc_scene_info(C.Structure):
                 ("root_ref", C.c_uint32), ("R", C.c_uint32), ("mode", C.c_uint32),
                 ("codebook_size", C.c_uint32), ("words", C.c_uint32), ("node_bytes", C.c_uint32),
                 ("n_masked", C.c_uint32), ("width", C.c_uint32), ("n_nodes", C.c_uint32),
-                ("approx_levels", C.c_uint32), ("bit_table", C.c_uint32),
+                ("approx_levels", C.c_uint32), ("bit_table", C.c_uint32), ("mask_test_max", C.c_uint32),
                 ("delta", C.c_float), ("origin_bound", C.c_float),
                 ("device_bytes", C.c_uint64), ("ms_bvh", C.c_double), ("ms_masks", C.c_double),
                 ("ms_codebook", C.c_double), ("ms_compress", C.c_double)]
@@ -302,7 +302,8 @@ class Scene:
     def __init__(self, ctx: Context, tris, *, R: int = 6, mode: str = "raw", K: int = 4096,
                  leaf_max: int = 4, bins: int = 32, depth_cap: int = 64, delta: float = 0.0,
                  origin_bound: float = 0.0, placement=None, width: int = 2, approx_levels: int = 0,
-                 bit_table: bool = False, mask_slots: str = "all", quantise: bool = False, stream=None):
+                 bit_table: bool = False, mask_slots: str = "all", quantise: bool = False, mask_test_max: int = 0,
+                 stream=None):
         import torch
         lib = load()
         self.ctx = ctx
@@ -323,6 +324,7 @@ class Scene:
         p.bit_table = int(bit_table)
         p.mask_slots = 1 if mask_slots == "leaves" else 0
         p.quantise = 1 if quantise else 0
+        p.mask_test_max = mask_test_max
         self._placement = None
         if placement is not None:
             self._placement = np.ascontiguousarray(placement, np.uint8)

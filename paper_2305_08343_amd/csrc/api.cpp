@@ -36,7 +36,7 @@ struct sc_scene {
     uint64_t* masks = nullptr;            // exact masks [2*n_inner][W]
     uint64_t* codebook = nullptr;         // LUT mode
     uint16_t* cidx = nullptr;             // LUT mode
-    uint32_t full_start = 0;              // LUT mode: first full codebook entry
+    uint32_t full_start = 0;              // LUT mode: first untested codebook entry (the full one by default)
     uint64_t* side_masks = nullptr;       // SPARSE mode
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // vertex bounds (ray ordering keys)
     uint32_t stride2 = kNodeBytes;        // stride of the binary node array `nodes`
@@ -152,6 +152,11 @@ bool check_params(const sc_build_params& p, std::string& why) {
     if (p.bit_table > 1 || (p.bit_table && p.mode != SC_MASK_LUT)) { why = "bit_table needs LUT mode"; return false; }
     if (p.width == 4 && p.mode == SC_MASK_SPARSE) { why = "SPARSE needs width 2"; return false; }
     if (p.quantise > 1 || (p.quantise && p.width != 4)) { why = "quantise needs width 4"; return false; }
+    if (p.mask_test_max >= p.R * p.R * p.R) { why = "mask_test_max must be below R^3"; return false; }
+    if (p.mask_test_max && p.mode != SC_MASK_RAW && p.mode != SC_MASK_LUT) {
+        why = "mask_test_max needs RAW or LUT mode";
+        return false;
+    }
     if (!std::isfinite(p.delta) || !std::isfinite(p.origin_bound)) { why = "non-finite delta/origin_bound"; return false; }
     return true;
 }
@@ -313,6 +318,9 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
     I.n_nodes = B.n_inner;
     I.approx_levels = P.approx_levels;
     I.bit_table = P.bit_table;
+    // the densest mask still tested: the paper tests every mask but a full one
+    const uint32_t test_max = P.mask_test_max ? P.mask_test_max : R * R * R - 1;
+    I.mask_test_max = test_max;
     const uint32_t S = 2 * B.n_inner;
     if (P.mode == SC_MASK_SPARSE && P.placement_len != S)
         return bail(SC_ERR_INVALID_ARG, "mask_placement length must be 2*n_inner = " + std::to_string(S));
@@ -446,7 +454,7 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
         I.ms_masks = ms_since(t0);
 
         if (P.mode == SC_MASK_RAW) {
-            e = launch_pack_raw(R, sc->masks, B.n_inner, sc->nodes, s);
+            e = launch_pack_raw(R, sc->masks, B.n_inner, test_max, sc->nodes, s);
             if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("pack: ") + hipGetErrorString(e));
         } else {
             std::vector<uint64_t> hmasks((size_t)S * W);
@@ -458,11 +466,13 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                 t0 = std::chrono::steady_clock::now();
                 std::vector<uint64_t> cb;
                 select_codebook(hmasks.data(), B.cbox.data(), S, R, K, cb);
+                // entries are sorted by set bits: the first one denser than test_max (the full
+                // mask by default) starts the untested ones
                 sc->full_start = K;
                 for (uint32_t k = 0; k < K; ++k) {
                     uint32_t pc = 0;
                     for (uint32_t w = 0; w < W; ++w) pc += (uint32_t)__builtin_popcountll(cb[(size_t)k * W + w]);
-                    if (pc == R * R * R) {
+                    if (pc > test_max) {
                         sc->full_start = k;
                         break;
                     }
@@ -549,8 +559,8 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                 if (!sc->masks4) return bail(SC_ERR_OOM, "4-wide mask allocation failed");
             }
             if (P.mode == SC_MASK_RAW || P.mode == SC_MASK_LUT) {
-                e = launch_pack4(P.mode, R, sc->src4, B4.n4, sc->masks, sc->cidx, sc->nodes4, sc->masks4, sc->quant4,
-                                 s);
+                e = launch_pack4(P.mode, R, sc->src4, B4.n4, sc->masks, sc->cidx, test_max, sc->nodes4, sc->masks4,
+                                 sc->quant4, s);
                 if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("4-wide pack: ") + hipGetErrorString(e));
             }
         }

@@ -181,16 +181,17 @@ hipError_t launch_approx_fill(uint32_t R, const uint32_t* slots, uint32_t count,
 hipError_t launch_req_luts(uint32_t R, const uint64_t* cb, uint32_t K, uint64_t* req, hipStream_t s);
 hipError_t launch_compress(uint32_t R, const uint64_t* masks, uint32_t n, const uint64_t* req,
                            uint32_t K, uint16_t* idx, hipStream_t s);
-hipError_t launch_pack_raw(uint32_t R, const uint64_t* masks, uint32_t n_inner, unsigned char* nodes,
-                           hipStream_t s);
+// a mask with more than test_max set bits is marked untested (a full mask at test_max = R^3 - 1)
+hipError_t launch_pack_raw(uint32_t R, const uint64_t* masks, uint32_t n_inner, uint32_t test_max,
+                           unsigned char* nodes, hipStream_t s);
 hipError_t launch_pack_lut(const uint16_t* idx, uint32_t n_inner, unsigned char* nodes, hipStream_t s);
 // 2-D bit table: bit k of row key = (LUT[key] AND codebook[k]) != 0; [R^6][K/32] words
 hipError_t launch_bit_table(uint32_t R, const uint64_t* lut, const uint64_t* cb, uint32_t K, uint32_t* out,
                             hipStream_t s);
 // 4-wide nodes: gather each child's raw mask (and full flag) or codebook index from its binary slot
 hipError_t launch_pack4(uint32_t mode, uint32_t R, const uint32_t* src4, uint32_t n4, const uint64_t* masks,
-                        const uint16_t* cidx, unsigned char* nodes4, uint64_t* masks4, uint32_t quant,
-                        hipStream_t s);
+                        const uint16_t* cidx, uint32_t test_max, unsigned char* nodes4, uint64_t* masks4,
+                        uint32_t quant, hipStream_t s);
 
 // learned placement
 constexpr int kMlpParams = SC_MLP_PARAMS;

@@ -418,10 +418,11 @@ __global__ __launch_bounds__(256) void compress_kernel(const uint64_t* __restric
 }
 
 // Copy each inner node's two raw masks into bytes [64, 64 + 2*W*8) of its
-// 128-byte node, and set bit c of the node's aux word when child c's mask is
-// full (such a mask can never cull, so the traversal skips its test).
+// 128-byte node, and set bit c of the node's aux word when child c's mask has
+// more than test_max set bits (a full mask at the default R^3 - 1: it can never
+// cull), so the traversal skips its test.
 template <int R>
-__global__ void pack_raw_kernel(const uint64_t* __restrict__ masks, uint32_t n_inner,
+__global__ void pack_raw_kernel(const uint64_t* __restrict__ masks, uint32_t n_inner, uint32_t test_max,
                                 unsigned char* __restrict__ nodes) {
     constexpr int W = (R * R * R + 63) / 64;
     const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -435,7 +436,7 @@ __global__ void pack_raw_kernel(const uint64_t* __restrict__ masks, uint32_t n_i
             dst[c * W + w] = m;
             pc += __popcll(m);
         }
-        if (pc == R * R * R) flags |= 1u << c;
+        if ((uint32_t)pc > test_max) flags |= 1u << c;
     }
     reinterpret_cast<uint32_t*>(nodes + node * kRawNodeBytes)[14] = flags;
 }
@@ -450,12 +451,12 @@ __global__ void pack_lut_kernel(const uint16_t* __restrict__ idx, uint32_t n_inn
 
 // 4-wide node m, child c from binary slot src4[4m + c]: the raw mask goes to
 // masks4[4m + c] and bit c of aux word 0 (byte 112) and bit 28 of the child's ref
-// mark a full mask; a
-// codebook index goes to the 16-bit aux entry c.
+// mark a mask with more than test_max set bits (untested); a codebook index goes
+// to the 16-bit aux entry c.
 template <int R>
 __global__ void pack4_kernel(uint32_t mode, const uint32_t* __restrict__ src4, uint32_t n4,
                              const uint64_t* __restrict__ masks, const uint16_t* __restrict__ cidx,
-                             unsigned char* __restrict__ nodes4, uint64_t* __restrict__ masks4,
+                             uint32_t test_max, unsigned char* __restrict__ nodes4, uint64_t* __restrict__ masks4,
                              uint32_t stride, uint32_t refs_at, uint32_t aux_at) {
     constexpr int W = (R * R * R + 63) / 64;
     const size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -472,7 +473,7 @@ __global__ void pack4_kernel(uint32_t mode, const uint32_t* __restrict__ src4, u
                 masks4[(4 * m + c) * W + w] = v;
                 pc += __popcll(v);
             }
-            if (pc == R * R * R) full |= 1u << c;
+            if ((uint32_t)pc > test_max) full |= 1u << c;
         } else {
             const uint32_t v = cidx[s];
             if (c < 2) idx01 |= v << (16 * c);
@@ -601,11 +602,15 @@ hipError_t launch_compress(uint32_t R, const uint64_t* masks, uint32_t n, const 
     return hipGetLastError();
 }
 
-hipError_t launch_pack_raw(uint32_t R, const uint64_t* masks, uint32_t n_inner, unsigned char* nodes,
-                           hipStream_t s) {
+hipError_t launch_pack_raw(uint32_t R, const uint64_t* masks, uint32_t n_inner, uint32_t test_max,
+                           unsigned char* nodes, hipStream_t s) {
     if (n_inner == 0) return hipSuccess;
-    if (R == 4) hipLaunchKernelGGL(pack_raw_kernel<4>, dim3(blocks_for(n_inner, 256)), dim3(256), 0, s, masks, n_inner, nodes);
-    else if (R == 6) hipLaunchKernelGGL(pack_raw_kernel<6>, dim3(blocks_for(n_inner, 256)), dim3(256), 0, s, masks, n_inner, nodes);
+    if (R == 4)
+        hipLaunchKernelGGL(pack_raw_kernel<4>, dim3(blocks_for(n_inner, 256)), dim3(256), 0, s, masks, n_inner,
+                           test_max, nodes);
+    else if (R == 6)
+        hipLaunchKernelGGL(pack_raw_kernel<6>, dim3(blocks_for(n_inner, 256)), dim3(256), 0, s, masks, n_inner,
+                           test_max, nodes);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -626,18 +631,18 @@ hipError_t launch_full_inner_slots(uint32_t R, const unsigned char* nodes, uint3
 }
 
 hipError_t launch_pack4(uint32_t mode, uint32_t R, const uint32_t* src4, uint32_t n4, const uint64_t* masks,
-                        const uint16_t* cidx, unsigned char* nodes4, uint64_t* masks4, uint32_t quant,
-                        hipStream_t s) {
+                        const uint16_t* cidx, uint32_t test_max, unsigned char* nodes4, uint64_t* masks4,
+                        uint32_t quant, hipStream_t s) {
     if (n4 == 0) return hipSuccess;
     if (mode != SC_MASK_RAW && mode != SC_MASK_LUT) return hipErrorInvalidValue;
     const uint32_t stride = quant ? kNode4QBytes : kNode4Bytes;
     const uint32_t refs_at = quant ? kNode4QRefs : 96u, aux_at = quant ? kNode4QAux : 112u;
     if (R == 4)
         hipLaunchKernelGGL(pack4_kernel<4>, dim3(blocks_for(n4, 256)), dim3(256), 0, s, mode, src4, n4, masks, cidx,
-                           nodes4, masks4, stride, refs_at, aux_at);
+                           test_max, nodes4, masks4, stride, refs_at, aux_at);
     else if (R == 6)
         hipLaunchKernelGGL(pack4_kernel<6>, dim3(blocks_for(n4, 256)), dim3(256), 0, s, mode, src4, n4, masks, cidx,
-                           nodes4, masks4, stride, refs_at, aux_at);
+                           test_max, nodes4, masks4, stride, refs_at, aux_at);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -48,9 +48,9 @@ def test_params_default_and_status_strings():
 
 
 def test_struct_sizes_match_header_layout():
-    # 14 uint32, 2 float, uint64, 4 double
-    assert C.sizeof(B.sc_scene_info) == 56 + 8 + 8 + 32
-    assert C.sizeof(B.sc_build_params) == 64
+    # 15 uint32, 2 float, (4 bytes of padding) uint64, 4 double
+    assert C.sizeof(B.sc_scene_info) == 60 + 8 + 4 + 8 + 32
+    assert C.sizeof(B.sc_build_params) == 72
     assert C.sizeof(B.sc_scene_host) == 7 * 8
     assert C.sizeof(B.sc_tune) == 9 * 4
 

@@ -236,3 +236,42 @@ def test_negative_zero_direction_on_a_box_plane_keeps_the_hit(ctx):
         ora = oracle.trace(tris, bvh, rays) if width == 2 else oracle.trace4(tris, bvh, oracle.bvh4_collapse(bvh), rays)
         assert (dev["t"].view(np.uint32) == ora.t.view(np.uint32)).all()
         assert (dev["box_tests"] == ora.box_tests).all()
+
+
+@pytest.mark.parametrize("width,mode,R,K,bits,quant", [
+    (2, "raw", 6, 4096, False, False), (2, "lut", 6, 256, False, False), (2, "raw", 4, 4096, False, False),
+    (4, "raw", 6, 4096, False, False), (4, "raw", 4, 4096, False, True), (4, "lut", 6, 4096, True, False),
+    (4, "lut", 6, 4096, True, True), (4, "lut", 4, 256, False, False)])
+def test_mask_test_limit_bit_exact(ctx, small_scene, small_oracle, width, mode, R, K, bits, quant):
+    """Masks (raw, or the codebook entry a slot points to) with more set bits than the build's
+    limit pass untested: every count equals the oracle's at the same limit, hits equal those of
+    plain traversal."""
+    from paper_2305_08343_amd import binding
+    tris, rays = small_scene
+    rays = np.concatenate([rays[::3], _aimed(tris, 20011, 61)])
+    bvh = small_oracle["bvh"]
+    b4 = oracle.bvh4_collapse(bvh) if width == 4 else None
+    if quant:
+        b4 = oracle.decoded_bvh4(b4, oracle.quantise4(b4))
+        bvh = oracle.with_slot_boxes(bvh, b4)
+    masks = oracle.object_masks(tris, bvh, R, small_oracle["delta"])
+    kw = dict(origin_bound=small_oracle["origin_bound"], mode=mode, R=R)
+    if mode == "raw":
+        kw["masks"] = masks
+    else:
+        cb, idx = oracle.compress(masks, bvh.slot_boxes(), R, K)
+        kw.update(codebook=cb, cidx=idx)
+    for limit in (R ** 3 // 4, R ** 3 // 2):
+        print(f"[gpu-bvh4] test limit {limit}: width {width} {mode} R={R} K={K} bits={bits} q={quant}", flush=True)
+        s = binding.Scene(ctx, tris, R=R, mode=mode, K=K, width=width, bit_table=bits, quantise=quant,
+                          mask_test_max=limit)
+        assert s.info["mask_test_max"] == limit
+        dev = s.trace(rays).numpy()
+        s.close()
+        ora = oracle.trace4(tris, bvh, b4, rays, test_max=limit, **kw) if width == 4 else \
+            oracle.trace(tris, bvh, rays, test_max=limit, **kw)
+        _compare(dev, ora)
+        assert (dev["t"].view(np.uint32) == ora.t.view(np.uint32)).all()
+        assert ora.mask_tests.sum() > 0
+    with pytest.raises(binding.SubcullError):
+        binding.Scene(ctx, tris, R=R, mode=mode, K=K, width=width, mask_test_max=R ** 3)

@@ -7,10 +7,14 @@ per inner node on a held-out 1M-tri hair scene with 1M rays. Checked:
   * hits are identical under every placement, all masks and no masks;
   * all masks <= any placement <= no masks in tests per ray;
   * the learned placement removes tests at every budget, more at larger
-    budgets, at least twice what random placement removes, at least 70% of
-    what placement by the true (measured) counts removes and at least 90% of
-    what the surface-area x emptiness heuristic removes (trained on 16 small
-    scenes the two are within a few percent of each other).
+    budgets, at least twice what random placement removes and at least 70% of
+    what placement by the true (measured) counts removes;
+  * it stays within 0.5% (in tests per ray) of the surface-area x emptiness
+    heuristic it learns a correction to. It does NOT beat that heuristic: on
+    this scene it trails it by 0.07-0.21 tests/ray at the three budgets (the
+    twelve geometric features carry little beyond area x emptiness, while
+    placement by the true counts is about one test/ray better); the check is
+    written so that this shortfall is visible, not hidden.
 Times (rays/s) are printed, not asserted: they depend on the launch.
 """
 import numpy as np
@@ -49,5 +53,8 @@ def test_learned_placement_gain(request):
         assert gain > prev
         assert gain >= 2.0 * (none.tests_per_ray - Rn.tests_per_ray)
         assert gain >= 0.7 * (none.tests_per_ray - T.tests_per_ray)
-        assert gain >= 0.9 * (none.tests_per_ray - ev[("heuristic", beta)].tests_per_ray)
+        H = ev[("heuristic", beta)]
+        _say(request, f"beta={beta}: learned - heuristic = {L.tests_per_ray - H.tests_per_ray:+.3f} tests/ray, "
+                      f"true counts - heuristic = {T.tests_per_ray - H.tests_per_ray:+.3f}")
+        assert L.tests_per_ray <= 1.005 * H.tests_per_ray
         prev = gain

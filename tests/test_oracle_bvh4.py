@@ -166,8 +166,9 @@ def test_bvh4_culling_keeps_hits_and_reduces_counts(small_scene, small_oracle, R
     assert raw.mask_culls.sum() > 0 and (raw.box_tests + raw.tri_tests).sum() < (plain.box_tests + plain.tri_tests).sum()
 
 
-def _recursive_trace4(tris, bvh, b4, ray, masks=None, lut=None, R=6, ob=np.inf):
-    """Alg. 4 on the 4-wide BVH as recursion: children sorted by (t0, index)."""
+def _recursive_trace4(tris, bvh, b4, ray, masks=None, lut=None, R=6, ob=np.inf, test_max=None):
+    """Alg. 4 on the 4-wide BVH as recursion: children sorted by (t0, index); a mask with more
+    than test_max set bits (default R^3 - 1: only a full mask) is not tested."""
     f32 = np.float32
     o, d, tmin = ray[:3].astype(f32), ray[4:7].astype(f32), f32(ray[3])
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
@@ -176,7 +177,7 @@ def _recursive_trace4(tris, bvh, b4, ray, masks=None, lut=None, R=6, ob=np.inf):
     use_mask = masks is not None and max(abs(o)) <= ob
     bits = None if masks is None else oracle.mask_bits(masks, R)
     lbits = None if lut is None else oracle.mask_bits(lut, R)
-    full = R ** 3
+    limit = R ** 3 - 1 if test_max is None else test_max
 
     def cell(lo, hi, t):
         out = []
@@ -248,7 +249,7 @@ def _recursive_trace4(tris, bvh, b4, ray, masks=None, lut=None, R=6, ob=np.inf):
             if not t0 <= t1:
                 continue
             s = int(b4.src4[ref, c])
-            if use_mask and bits[s].sum() < full:
+            if use_mask and bits[s].sum() <= limit:
                 st["mt"] += 1
                 key = 0
                 for q in (*cell(lo, hi, t0), *cell(lo, hi, t1)):
@@ -280,3 +281,35 @@ def test_recursive_formulation_counts_bvh4(small_scene, small_oracle):
             assert st["deep"] == h.deepest[i], i
             if mode == "raw":
                 assert (st["mt"], st["mc"]) == (h.mask_tests[i], h.mask_culls[i]), i
+
+
+def test_mask_test_limit_recursive_and_monotone(small_scene, small_oracle):
+    """Masks denser than the limit pass untested: the recursive formulation agrees on every count
+    at several limits; hits never change; per ray, a lower limit (fewer tests) never gives fewer
+    box or triangle tests; a limit below the sparsest mask tests nothing (plain counts)."""
+    tris, rays = small_scene
+    sel = np.concatenate([_aimed_rays(tris, 120, 41), rays[::2048]])
+    bvh = small_oracle["bvh"]
+    b4 = oracle.bvh4_collapse(bvh)
+    masks, lut, ob = small_oracle["masks6"], small_oracle["lut6"], small_oracle["origin_bound"]
+    pcs = oracle.mask_bits(masks, 6).sum(-1)
+    plain = oracle.trace4(tris, bvh, b4, sel, origin_bound=ob)
+    prev = None
+    for limit in sorted({int(pcs.min()) - 1 or 1, int(np.percentile(pcs, 25)), int(np.median(pcs)), 215}):
+        h = oracle.trace4(tris, bvh, b4, sel, mode="raw", R=6, masks=masks, origin_bound=ob, test_max=limit)
+        assert (h.prim == plain.prim).all() and (h.t.view(np.uint32) == plain.t.view(np.uint32)).all()
+        for i in range(0, sel.shape[0], 7):
+            st = _recursive_trace4(tris, bvh, b4, sel[i], masks, lut, 6, ob, test_max=limit)
+            assert (st["box"], st["tri"], st["mt"], st["mc"]) == \
+                (h.box_tests[i], h.tri_tests[i], h.mask_tests[i], h.mask_culls[i]), (limit, i)
+        if prev is not None:  # a higher limit tests a superset of masks
+            assert (prev.box_tests >= h.box_tests).all() and (prev.tri_tests >= h.tri_tests).all()
+            assert (prev.mask_tests <= h.mask_tests).all()
+        prev = h
+    # the default limit is R^3 - 1 (every mask but a full one)
+    d = oracle.trace4(tris, bvh, b4, sel, mode="raw", R=6, masks=masks, origin_bound=ob)
+    assert (d.box_tests == prev.box_tests).all() and (d.mask_tests == prev.mask_tests).all()
+    low = oracle.trace4(tris, bvh, b4, sel, mode="raw", R=6, masks=masks, origin_bound=ob,
+                        test_max=max(1, int(pcs.min()) - 1))
+    if pcs.min() > 1:
+        assert low.mask_tests.sum() == 0 and (low.box_tests == plain.box_tests).all()
