@@ -254,22 +254,26 @@ constexpr uint32_t kLdsPerCu = 160u * 1024u;  // gfx950
 // (their few spilled registers sit in the ray set-up, not in the traversal
 // step). The other 4-wide mask kernels -- among them the quantised R = 4 raw
 // kernel, whose four in-flight mask reads need the room -- spill inside the
-// step at 80 and are held to 96 VGPRs (5 waves). Where LDS already allows fewer
+// step at 80 and are held to 96 VGPRs (5 waves). Batched launches keep each
+// lane's scene pointers in registers as well: their mask kernels are held to 96
+// VGPRs, the float-box R = 6 ones to 128 (4 waves). Where LDS already allows fewer
 // waves than that, the target is what LDS allows: registers beyond it would buy
 // nothing.
-template <uint32_t MODE, int R, int WIDTH, int BLOCK, int STACK, bool QUANT = false>
+template <uint32_t MODE, int R, int WIDTH, int BLOCK, int STACK, bool QUANT = false, bool BATCH = false>
 struct MinWaves {
     static constexpr int target =
-        (WIDTH == 4 && (MODE == kModeNone || (MODE == kModeRaw && (R == 4) != QUANT) || MODE == kModeLutBits)) ? 6
-        : (WIDTH == 4)                                                                                         ? 5
-                                                                                                               : 1;
+        (WIDTH == 4 && BATCH && MODE != kModeNone && R == 6 && !QUANT) ? 4
+        : (WIDTH == 4 && BATCH && MODE != kModeNone)                   ? 5
+        : (WIDTH == 4 && (MODE == kModeNone || (MODE == kModeRaw && (R == 4) != QUANT) || MODE == kModeLutBits)) ? 6
+        : (WIDTH == 4) ? 5
+                       : 1;
     static constexpr int lds_waves =
         (int)((kLdsPerCu / trace_lds_bytes<MODE, R, BLOCK, STACK>()) * (uint32_t)(BLOCK / kWave) / 4u);
     static constexpr int value = (lds_waves < target) ? (lds_waves > 1 ? lds_waves : 1) : target;
 };
 
 template <uint32_t MODE, int R, int BLOCK, int STACK, bool BATCH, int WIDTH, bool QUANT = false>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MinWaves<MODE, R, WIDTH, BLOCK, STACK, QUANT>::value)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MinWaves<MODE, R, WIDTH, BLOCK, STACK, QUANT, BATCH>::value)))
 void trace_kernel(TraceLaunch a) {
     static_assert(WIDTH == 2 || (WIDTH == 4 && MODE != kModeSparse), "4-wide: no sparse masks");
     static_assert(!BATCH || (MODE != kModeLutLds && MODE != kModeLutBits), "batches read each scene's codebook");
@@ -531,49 +535,48 @@ void trace_kernel(TraceLaunch a) {
                 float key[4];
                 uint32_t kid[4], kref[4];
                 uint32_t alive = 0;
-                if constexpr (kPhased) {
-                    // Three passes: the slab tests of all four children (which use every piece of
-                    // the node, so no later wait for the node holds up a mask read); for each
-                    // child whose mask is tested, its ray-mask cells and the read the test needs;
-                    // then the mask decisions. The reads of all tested children are in flight
-                    // together instead of one round trip after another; every child is still
-                    // tested in order and every count is the same.
-                    bool ckeep[4], cneed[4];
-                    float ct0[4], ct1[4];
-                    uint32_t cidx4[4];             // LUT modes: codebook index per child
-                    uint32_t pw[4], pb[4], pp[4];  // bit table word + bit; R = 4 pattern + shift
-                    uint64_t pm[4];                // R = 4: the object mask
+                // Slab tests of all four children first, without a branch (an unused child's
+                // result is computed and dropped), so the node's pieces are waited for once on
+                // every path. Where a mask read takes one load (the bit table, R = 4 masks), the
+                // reads of all tested children are then issued together before any is decided,
+                // instead of one round trip after another; otherwise each tested child reads and
+                // decides in turn. Children are still decided in order and every count is the same.
+                bool ckeep[4], cneed[4];
+                float ct0[4], ct1[4];
+                uint32_t cidx4[4];  // LUT modes: codebook index per child
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        // without a branch: an unused child's slab result is computed and dropped, so
-                        // the node's pieces are waited for once, on every path
-                        kref[c] = (crf[c] == kEmptyRef) ? kEmptyRef : (crf[c] & ~kRef4Full);
-                        const bool used = crf[c] != kEmptyRef;
-                        float t0, t1;
-                        const float nr[3] = {cnx[c], cny[c], cnz[c]}, fr[3] = {cfx[c], cfy[c], cfz[c]};
-                        slab_nf(nr, fr, r, best_t, t0, t1);
-                        box_tests += used ? 1u : 0u;
-                        ckeep[c] = used && t0 <= t1;
-                        ct0[c] = t0;
-                        ct1[c] = t1;
-                        // whether the child's mask is tested (reads the refs' full flags or the
-                        // codebook indices here, before any mask read is in flight)
-                        bool test;
-                        if constexpr (MODE == kModeRaw) {
-                            test = !(crf[c] & kRef4Full);
-                        } else {
-                            cidx4[c] = ((c < 2 ? ax0 : ax1) >> (16 * (c & 1))) & 0xFFFFu;
-                            test = cidx4[c] < s_full;
-                        }
-                        cneed[c] = ckeep[c] && use_mask && test;
+                for (int c = 0; c < 4; ++c) {
+                    kref[c] = (crf[c] == kEmptyRef) ? kEmptyRef : (crf[c] & ~kRef4Full);
+                    const bool used = crf[c] != kEmptyRef;
+                    float t0, t1;
+                    const float nr[3] = {cnx[c], cny[c], cnz[c]}, fr[3] = {cfx[c], cfy[c], cfz[c]};
+                    slab_nf(nr, fr, r, best_t, t0, t1);
+                    box_tests += used ? 1u : 0u;
+                    ckeep[c] = used && t0 <= t1;
+                    ct0[c] = t0;
+                    ct1[c] = t1;
+                    // whether the child's mask is tested (reads the refs' full flags or the
+                    // codebook indices here, before any mask read is in flight)
+                    bool test = false;
+                    cidx4[c] = 0u;
+                    if constexpr (MODE == kModeRaw) {
+                        test = !(crf[c] & kRef4Full);
+                    } else if constexpr (MODE != kModeNone) {
+                        cidx4[c] = ((c < 2 ? ax0 : ax1) >> (16 * (c & 1))) & 0xFFFFu;
+                        test = cidx4[c] < s_full;
                     }
+                    cneed[c] = (MODE != kModeNone) && ckeep[c] && use_mask && test;
+                }
+                uint32_t pw[4], pb[4], pp[4];  // phased: bit table word + bit; R = 4 pattern + shift
+                uint64_t pm[4];                // phased R = 4: the object mask
+                if constexpr (kPhased) {
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
                         pw[c] = 0u;
                         pb[c] = 0u;
                         pp[c] = 0u;
                         pm[c] = 0u;
-                        const uint32_t idx = (MODE == kModeRaw) ? 0u : cidx4[c];
+                        const uint32_t idx = cidx4[c];
                         if (cneed[c]) {
                             const float nr[3] = {cnx[c], cny[c], cnz[c]}, fr[3] = {cfx[c], cfy[c], cfz[c]};
                             int bx, by, bz, ex, ey, ez;
@@ -592,75 +595,41 @@ void trace_kernel(TraceLaunch a) {
                             }
                         }
                     }
+                }
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        bool keep = ckeep[c];
+                for (int c = 0; c < 4; ++c) {
+                    bool keep = ckeep[c];
+                    if constexpr (MODE != kModeNone) {
                         if (cneed[c]) {
                             ++mask_tests;
                             bool any;
-                            if constexpr (MODE == kModeLutBits) any = ((pw[c] >> pb[c]) & 1u) != 0u;
-                            else any = ((pm[c] >> pb[c]) & lds_pat[pp[c]]) != 0;
+                            if constexpr (kPhased) {
+                                if constexpr (MODE == kModeLutBits) any = ((pw[c] >> pb[c]) & 1u) != 0u;
+                                else any = ((pm[c] >> pb[c]) & lds_pat[pp[c]]) != 0;
+                            } else {
+                                const uint64_t* om = nullptr;
+                                if constexpr (MODE == kModeRaw) om = s_side + ((size_t)ref * 4 + c) * W;
+                                if constexpr (MODE == kModeLutLds) om = lds_cb + cidx4[c] * W;
+                                if constexpr (MODE == kModeLut) om = s_codebook + (size_t)cidx4[c] * W;
+                                const float nr[3] = {cnx[c], cny[c], cnz[c]}, fr[3] = {cfx[c], cfy[c], cfz[c]};
+                                int bx, by, bz, ex, ey, ez;
+                                ray_cells_nf<R>(nr, fr, r.neg, r, ct0[c], ct1[c], bx, by, bz, ex, ey, ez);
+                                any = mask_overlap_cells<R>(bx, by, bz, ex, ey, ez, om, a.lut, lds_pat);
+                            }
                             if (!any) {
                                 ++mask_culls;
                                 if (shadow_flag && s_fp) atomicAdd(&s_fp[s_src4[(size_t)ref * 4 + c]], 1u);
                                 keep = !cull;
                             }
                         }
-                        key[c] = __builtin_inff();
-                        kid[c] = 4u + (uint32_t)c;
-                        if (keep) {
-                            key[c] = ct0[c];
-                            kid[c] = (uint32_t)c;
-                            ++alive;
-                        }
                     }
-                } else {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
                     key[c] = __builtin_inff();
                     kid[c] = 4u + (uint32_t)c;
-                    kref[c] = (crf[c] == kEmptyRef) ? kEmptyRef : (crf[c] & ~kRef4Full);
-                    bool keep = false;
-                    float t0 = 0.0f, t1 = 0.0f;
-                    const float nr[3] = {cnx[c], cny[c], cnz[c]}, fr[3] = {cfx[c], cfy[c], cfz[c]};
-                    if (crf[c] != kEmptyRef) {
-                        ++box_tests;
-                        slab_nf(nr, fr, r, best_t, t0, t1);
-                        keep = t0 <= t1;
-                    }
-                    if constexpr (MODE != kModeNone) {
-                        if (keep && use_mask) {
-                            const uint64_t* om = nullptr;
-                            bool test;
-                            uint32_t idx = 0;
-                            if constexpr (MODE == kModeRaw) {
-                                test = !(crf[c] & kRef4Full);
-                                om = s_side + ((size_t)ref * 4 + c) * W;
-                            } else {
-                                idx = ((c < 2 ? ax0 : ax1) >> (16 * (c & 1))) & 0xFFFFu;
-                                test = idx < s_full;
-                                if constexpr (MODE == kModeLutLds) om = lds_cb + (test ? idx : 0u) * W;
-                                if constexpr (MODE == kModeLut) om = s_codebook + (size_t)idx * W;
-                            }
-                            if (test) {
-                                ++mask_tests;
-                                int bx, by, bz, ex, ey, ez;
-                                ray_cells_nf<R>(nr, fr, r.neg, r, t0, t1, bx, by, bz, ex, ey, ez);
-                                const bool any = mask_overlap_cells<R>(bx, by, bz, ex, ey, ez, om, a.lut, lds_pat);
-                                if (!any) {
-                                    ++mask_culls;
-                                    if (shadow_flag && s_fp) atomicAdd(&s_fp[s_src4[(size_t)ref * 4 + c]], 1u);
-                                    keep = !cull;
-                                }
-                            }
-                        }
-                    }
                     if (keep) {
-                        key[c] = t0;
+                        key[c] = ct0[c];
                         kid[c] = (uint32_t)c;
                         ++alive;
                     }
-                }
                 }
                 // sorting network for four (t0, child) pairs
                 order2(key[0], kid[0], kref[0], key[1], kid[1], kref[1]);
