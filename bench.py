@@ -44,8 +44,10 @@ RAY_BYTES, HIT_BYTES, EXTRA_BYTES, TRI_BYTES = 32, 16, 8, 48
 # HBM-side bytes per trace launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, each scaled by the
 # same counter's reading for a 1 GiB plain copy (FETCH x2.0, WRITE x1.0). Valid only for the traversal
 # kernel source whose SHA-256 starts with this prefix; otherwise traffic is reported as null.
-MEASURED_TRAFFIC = {"source_sha256_16": "a0abc65170e68816",
-                    "hair_1m": {"raw6w4q": 16.625e9, "raw6w4": 16.850e9, "none": 9.788e9}}
+MEASURED_TRAFFIC = {"source_sha256_16": "1b071749ee04b067",
+                    "curly_12m": {"lut6w4b": 89.53e9, "nonew4q": 42.87e9, "raw4w4q": 42.19e9, "lut6w4": 49.94e9},
+                    "hair_1m": {"raw6w4": 16.85e9, "raw6w4q": 19.73e9, "raw4w4q": 13.02e9, "lut6w4b": 22.76e9,
+                                "nonew4q": 11.47e9}}
 TRACE_SOURCE = os.path.join(ROOT, "paper_2305_08343_amd", "csrc", "kernels_trace.hip")
 
 # width 2: binary nodes (node_bytes per visit); width 4: 4-wide nodes of Sect. 3.2.4 (child records of
@@ -239,10 +241,12 @@ def cpu_model():
     import subprocess
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
-        for line in out.splitlines():
-            if line.strip().startswith("Model name:"):
-                return line.split(":", 1)[1].strip()
-    except (OSError, subprocess.SubprocessError):
+        f = {k.strip(): v.strip() for k, v in (l.split(":", 1) for l in out.splitlines() if ":" in l)}
+        if f.get("Model name"):
+            # a virtual machine may report the bare family name; the family / model numbers identify the part
+            ids = ", ".join(f"{k.lower()} {f[k]}" for k in ("CPU family", "Model", "Stepping") if f.get(k))
+            return f"{f['Model name']} ({ids})" if ids else f["Model name"]
+    except (OSError, subprocess.SubprocessError, ValueError):
         pass
     try:
         with open("/proc/cpuinfo") as f:
@@ -313,7 +317,7 @@ def cpu_baseline(tris, rays, target_s, spec):
                  f", culled")
     what = f"{masks_txt}, {'4-wide' if width == 4 else 'binary'} BVH{' with quantised child boxes' if quant else ''}"
     out = {"value": sample.shape[0] / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
-            "cpu_model": cpu_model(),
+            "cpu_model": cpu_model(), "rays_timed": int(sample.shape[0]), "seconds_timed": dt,
             "one_thread": {"value": one, "unit": "rays/s",
                            "sample": f"every {k1}th ray ({first.shape[0]:,} rays), 1 thread"},
             "sample": (f"all {rays.shape[0]:,} rays" if step == 1 else
@@ -368,24 +372,41 @@ def run_batch64(args, ctx):
                 s_.trace(r_, cull=spec["cull"], hits=h_, extra=False)
 
         res = {}
+        stream = torch.cuda.current_stream()
         for name, fn in (("graph_batch", graph.launch), ("per_scene_launches", per_scene)):
             for _ in range(args.warmup):
                 fn()
             torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.steps)]
             t1 = time.perf_counter()
-            for _ in range(args.steps):
+            for k in range(args.steps):
+                ev[k][0].record(stream)
                 fn()
+                ev[k][1].record(stream)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t1) / args.steps
-            res[name] = {"ms_per_step": dt * 1e3, "rays_per_s": n_rays / dt}
+            res[name] = {"ms_per_step": dt * 1e3, "rays_per_s": n_rays / dt,
+                         "launch_ms_mean": float(np.mean([a.elapsed_time(b) for a, b in ev]))}
         graph.launch()
         per_scene()
         torch.cuda.synchronize()
         same = all((graph.hits[k][:r.shape[0]].cpu().numpy() == hits[k][:r.shape[0]].cpu().numpy()).all()
                    for k, r in enumerate(rays) if r.shape[0])
         tests = sum(float(graph.hits[k][:r.shape[0], 2:4].sum().item()) for k, r in enumerate(rays))
+        # algorithmic bytes of one batched launch: the single-scene byte model summed over the scenes,
+        # from the batch's own per-ray counters
+        alg = 0.0
+        for k, r in enumerate(rays):
+            n_k = r.shape[0]
+            if not n_k:
+                continue
+            tr = graph.results(k).numpy()
+            alg += algorithmic_bytes(tr["box_tests"], tr["tri_tests"], tr["mask_tests"], n_k, spec)
         res.update({"tune": list(cfg), "tune_seconds": entry.get("seconds"), "build_s": build_s,
-                    "results_equal_per_scene": bool(same), "tests_per_ray": tests / n_rays})
+                    "results_equal_per_scene": bool(same), "tests_per_ray": tests / n_rays,
+                    "alg_bytes_per_launch": alg,
+                    "alg_gbs": alg / (res["graph_batch"]["launch_ms_mean"] * 1e-3) / 1e9})
         log(f"batch64 {mname}: graph {res['graph_batch']['rays_per_s'] / 1e6:.1f} Mrays/s, per-scene "
             f"{res['per_scene_launches']['rays_per_s'] / 1e6:.1f} Mrays/s, tune {cfg}")
         out[mname] = res
@@ -393,17 +414,46 @@ def run_batch64(args, ctx):
         direct.close()
         for s_ in built:
             s_.close()
-    head = out[args.modes.split(",")[0]]
+    head_name = args.modes.split(",")[0]
+    head = out[head_name]
     line = {
         "metric": METRIC, "value": head["graph_batch"]["rays_per_s"], "unit": "rays/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["graph_batch"]["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batch64: 64 scenes (10k-500k tris, strands/thin quads/isotropic), 16k-2M rays "
-                               "each (half pinhole, half random), one persistent launch replayed from a HIP graph",
+                               f"each (half pinhole, half random), one persistent launch replayed from a HIP graph, "
+                               f"mode {head_name}",
                    "n_tris": n_tris, "n_rays": n_rays},
+        "tests_per_ray": head["tests_per_ray"],
+        "roofline": {"bound": "hbm", "achieved": head["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": head["alg_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "trace_kernel (batched, one graph launch)",
+                     "kernel_ms": head["graph_batch"]["launch_ms_mean"],
+                     "alg_bytes_per_launch": head["alg_bytes_per_launch"],
+                     "alg_bytes_per_ray": head["alg_bytes_per_launch"] / n_rays},
         "modes": out,
     }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, four of the scenes)")
+        line["cpu_baseline"] = batch_cpu_baseline(data, mode_spec(head_name), args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def batch_cpu_baseline(data, spec, target_s):
+    """The oracle on four of the batch's scenes (the first, the last and two between), each on an
+    every-k-th ray sample of about target_s / 4 seconds: rays/s over the four samples together."""
+    picks = sorted({0, len(data) // 3, 2 * len(data) // 3, len(data) - 1})
+    rays_t, secs, parts, one = 0, 0.0, [], None
+    for k in picks:
+        tris, rays = data[k]
+        o, _ = cpu_baseline(tris, rays, target_s / len(picks), spec)
+        rays_t += o["rays_timed"]
+        secs += o["seconds_timed"]
+        one = one or o["one_thread"]
+        parts.append(f"scene {k} ({tris.shape[0]:,} tris): {o['sample']}")
+    return {"value": rays_t / secs, "unit": "rays/s", "cores": o["cores"], "kind": "oracle",
+            "cpu_model": o["cpu_model"], "rays_timed": rays_t, "seconds_timed": secs,
+            "sample": f"scenes {picks} of the 64, traced one after another; " + "; ".join(parts)}
 
 
 def run_placement(args, ctx):

@@ -66,6 +66,21 @@ def _compile(src: str, sanitize: bool = False) -> str:
     return obj
 
 
+PROBE_SRC = os.path.join(HERE, "probes", "valu_rate.hip")
+PROBE_BIN = os.path.join(HERE, "probes", "valu_rate")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The vector-ALU issue-rate probe (a stand-alone program, not part of the library)."""
+    cmd = [hipcc()] + COMMON + DEVICE + ["-o", PROBE_BIN, PROBE_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print("built", PROBE_BIN)
+    return PROBE_BIN
+
+
 def build(verbose: bool = False, sanitize: bool = False) -> str:
     out_dir, lib = (SAN_DIR, SAN_LIB) if sanitize else (OUT_DIR, LIB)
     os.makedirs(out_dir, exist_ok=True)
@@ -86,4 +101,6 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
 
 if __name__ == "__main__":
     build(verbose=True, sanitize="--sanitize" in sys.argv[1:])
+    if "--sanitize" not in sys.argv[1:]:
+        build_probe(verbose=True)
     sys.exit(0)
