@@ -434,26 +434,30 @@ def run_batch64(args, ctx):
         "modes": out,
     }
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, four of the scenes)")
+        log("cpu baseline (oracle, every scene)")
         line["cpu_baseline"] = batch_cpu_baseline(data, mode_spec(head_name), args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 
 def batch_cpu_baseline(data, spec, target_s):
-    """The oracle on four of the batch's scenes (the first, the last and two between), each on an
-    every-k-th ray sample of about target_s / 4 seconds: rays/s over the four samples together."""
-    picks = sorted({0, len(data) // 3, 2 * len(data) // 3, len(data) - 1})
-    rays_t, secs, parts, one = 0, 0.0, [], None
-    for k in picks:
-        tris, rays = data[k]
-        o, _ = cpu_baseline(tris, rays, target_s / len(picks), spec)
+    """The oracle on the batch's scenes one after another, each on an every-k-th ray sample of about
+    target_s / 64 seconds (all rays of nearly every scene): rays/s over the samples together."""
+    rays_t, secs, setup, parts, o = 0, 0.0, 0.0, [], None
+    for k, (tris, rays) in enumerate(data):
+        t0 = time.perf_counter()
+        o, _ = cpu_baseline(tris, rays, target_s / len(data), spec)
         rays_t += o["rays_timed"]
         secs += o["seconds_timed"]
-        one = one or o["one_thread"]
-        parts.append(f"scene {k} ({tris.shape[0]:,} tris): {o['sample']}")
+        setup += time.perf_counter() - t0 - o["seconds_timed"]
+        if o["rays_timed"] < rays.shape[0]:
+            parts.append(f"scene {k}: {o['rays_timed']:,} of {rays.shape[0]:,} rays")
+    total = sum(r.shape[0] for _, r in data)
     return {"value": rays_t / secs, "unit": "rays/s", "cores": o["cores"], "kind": "oracle",
             "cpu_model": o["cpu_model"], "rays_timed": rays_t, "seconds_timed": secs,
-            "sample": f"scenes {picks} of the 64, traced one after another; " + "; ".join(parts)}
+            "sample": f"the {len(data)} scenes one after another, {rays_t:,} of the {total:,} rays "
+                      f"({'all' if not parts else 'every-k-th samples in ' + '; '.join(parts)}), "
+                      f"{o['sample'].split(', ', 1)[1].split(';')[0]}; {secs:.1f} s of traversal on {o['cores']} "
+                      f"threads; oracle set-up and single-thread probes {setup:.1f} s not timed"}
 
 
 def run_placement(args, ctx):

@@ -321,6 +321,35 @@ sc_status sc_ray_order(const sc_scene* scene, const float* d_rays, uint32_t n, u
 sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune);
 sc_status sc_get_tune(const sc_ctx* ctx, sc_tune* out);
 
+/* Device checks, a debugging aid for callers (not part of the method).
+ * With on != 0, later sc_trace / sc_trace_noalloc / sc_trace_batch calls and
+ * batches created afterwards (a batch keeps the kernels it was recorded with)
+ * run kernels that compare every inner-node reference with the scene's node
+ * count, every leaf's triangle range with its triangle count, every stack push
+ * with the lane's stack capacity and every tested codebook index with K before
+ * using it. A failed check does not read or write out of range: it ORs its bit
+ * into the context's check word (SC_CHECK_NODE, SC_CHECK_TRI, SC_CHECK_STACK,
+ * SC_CHECK_INDEX), and the ray ends with the hit it has, or the stack entry is
+ * dropped; results then differ from an unchecked trace. Passing checks change
+ * no result. Enabling allocates the 4-byte check word once (synchronous,
+ * zeroed). Errors: SC_ERR_INVALID_ARG (ctx NULL), SC_ERR_OOM. */
+#define SC_CHECK_NODE 1u
+#define SC_CHECK_TRI 2u
+#define SC_CHECK_STACK 4u
+#define SC_CHECK_INDEX 8u
+sc_status sc_set_device_checks(sc_ctx* ctx, int on);
+/* The bits the failed checks set since the last reset (0 before checks were
+ * ever enabled); synchronises the device; reset != 0 clears the word.
+ * Errors: SC_ERR_INVALID_ARG (NULL pointer), SC_ERR_HIP. */
+sc_status sc_get_check_flags(sc_ctx* ctx, uint32_t* out, int reset);
+/* Lower the checked limits below the scene's own (0 keeps a limit at the
+ * scene's value): at most max_stack stack entries a lane, inner-node
+ * references below max_nodes, triangle ranges ending at or below max_tris.
+ * The buffers stay as large as they are, so a lowered limit makes a check
+ * fail without any access out of range -- how the checks themselves are
+ * tested. Read when a trace is issued. Errors: SC_ERR_INVALID_ARG. */
+sc_status sc_set_check_limits(sc_ctx* ctx, uint32_t max_stack, uint32_t max_nodes, uint32_t max_tris);
+
 /* One scene's rays in a batched launch. All items of a batch must come from
  * one context and share the mask mode, R, the node width (2 or 4) and, for
  * 4-wide scenes, the child-box storage (float or quantised). d_rays/d_hits as

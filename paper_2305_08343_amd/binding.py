@@ -101,6 +101,9 @@ _SIGS = {
     "sc_batch_destroy": (C.c_int, [C.c_void_p]),
     "sc_set_tune": (C.c_int, [C.c_void_p, C.POINTER(sc_tune)]),
     "sc_get_tune": (C.c_int, [C.c_void_p, C.POINTER(sc_tune)]),
+    "sc_set_device_checks": (C.c_int, [C.c_void_p, C.c_int]),
+    "sc_get_check_flags": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.c_int]),
+    "sc_set_check_limits": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32]),
     "sc_raymask_lut": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "sc_compress_masks": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
                                     C.c_uint32, C.c_void_p, C.c_void_p]),
@@ -168,10 +171,16 @@ def _on_stream(stream):
     return torch.cuda.stream(stream)
 
 
-class Context:
-    """An sc_ctx on one device; scene memory comes from torch's allocator."""
+SC_CHECK_NODE, SC_CHECK_TRI, SC_CHECK_STACK, SC_CHECK_INDEX = 1, 2, 4, 8
 
-    def __init__(self, device: int = 0, torch_memory: bool = True):
+
+class Context:
+    """An sc_ctx on one device; scene memory comes from torch's allocator.
+
+    ``checks=True`` (or the environment variable SUBCULL_DEBUG=1 when ``checks`` is None) runs
+    the traversal kernels with device checks; ``check_flags()`` reads what failed."""
+
+    def __init__(self, device: int = 0, torch_memory: bool = True, checks=None):
         import torch
         lib = load()
         self.device = device
@@ -195,6 +204,25 @@ class Context:
         torch.cuda.set_device(device)
         _check(lib.sc_create(device, alloc_p, C.byref(h)), "sc_create")
         self.handle = h
+        if checks is None:
+            checks = os.environ.get("SUBCULL_DEBUG") == "1"
+        if checks:
+            _check(lib.sc_set_device_checks(self.handle, 1), "sc_set_device_checks")
+        self.checks = bool(checks)
+
+    def set_device_checks(self, on: bool):
+        _check(load().sc_set_device_checks(self.handle, 1 if on else 0), "sc_set_device_checks")
+        self.checks = bool(on)
+
+    def check_flags(self, reset: bool = False) -> int:
+        """OR of the SC_CHECK_* bits of every failed device check since the last reset."""
+        v = C.c_uint32(0)
+        _check(load().sc_get_check_flags(self.handle, C.byref(v), 1 if reset else 0), "sc_get_check_flags")
+        return int(v.value)
+
+    def set_check_limits(self, stack: int = 0, nodes: int = 0, tris: int = 0):
+        """Lower the checked limits below the scene's own (0 = the scene's value)."""
+        _check(load().sc_set_check_limits(self.handle, stack, nodes, tris), "sc_set_check_limits")
 
     def close(self):
         if getattr(self, "handle", None):

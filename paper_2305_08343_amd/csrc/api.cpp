@@ -25,6 +25,9 @@ struct sc_ctx {
     uint32_t* counters = nullptr;           // kQueueRing ray-queue counters
     std::atomic<uint32_t> next_counter{0};
     sc_tune tune{256, 8, 1, kQueueParts, 0, 0, 0, 16, 16};
+    bool checks = false;                    // traces run the instances with device checks
+    uint32_t* chk_flags = nullptr;          // their failed-check bits (device word)
+    uint32_t chk_stack = 0, chk_nodes = 0, chk_tris = 0;  // lowered limits (0 = the scene's own)
 };
 
 struct sc_scene {
@@ -234,6 +237,7 @@ sc_status sc_destroy(sc_ctx* ctx) {
         if (ctx->patterns[R]) dev_free(ctx, ctx->patterns[R], pattern_bytes(R), nullptr);
     }
     dev_free(ctx, ctx->counters, kQueueRing * kQueueParts * 4, nullptr);
+    if (ctx->chk_flags) dev_free(ctx, ctx->chk_flags, 4, nullptr);
     delete ctx;
     return SC_OK;
 }
@@ -657,6 +661,23 @@ sc_status sc_scene_export4(const sc_scene* scene, float* box4, uint32_t* ref4, u
 
 namespace {
 
+// The device-check fields of a launch record: the scene's node and triangle counts (a batch passes
+// the largest; each descriptor carries its own) and the stack capacity of its width, each lowered
+// to the context's test limit where one is set.
+void set_check_limits(const sc_ctx* ctx, TraceLaunch& a, uint32_t n_nodes, uint32_t n_tris) {
+    if (!ctx->checks) return;
+    auto lower = [](uint32_t own, uint32_t lim) { return (lim && lim < own) ? lim : own; };
+    a.chk_flags = ctx->chk_flags;
+    a.chk_nodes = lower(n_nodes, ctx->chk_nodes);
+    a.chk_tris = lower(n_tris, ctx->chk_tris);
+    a.chk_stack = lower(trace_stack_capacity(a.width), ctx->chk_stack);
+}
+
+// The traversal launch: the checked instances when the context asks for them.
+hipError_t run_trace(const sc_ctx* ctx, const TraceLaunch& a, hipStream_t s) {
+    return ctx->checks ? launch_trace_checked(a, s) : launch_trace(a, s);
+}
+
 // Argument checks shared by the trace entry points (no HIP call).
 sc_status check_trace_args(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags,
                            const sc_hit* d_hits, const uint32_t* d_extra, const uint32_t* d_slot_fp) {
@@ -714,6 +735,7 @@ TraceLaunch trace_launch(const sc_scene* scene, const float* d_rays, uint32_t n,
     a.cb_global = ctx->tune.codebook;
     a.gather = ctx->tune.gather;
     a.refill = ctx->tune.refill;
+    set_check_limits(ctx, a, I.n_nodes, I.n_tris);
     return a;
 }
 
@@ -745,7 +767,7 @@ sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint3
         }
         a.order = order;
     }
-    const hipError_t e = launch_trace(a, s);
+    const hipError_t e = run_trace(ctx, a, s);
     if (ws) dev_free(ctx, ws, ws_bytes, s);  // stream-ordered: the allocator reuses it after the trace
     if (e != hipSuccess) return hip_fail(e, "trace launch");
     return SC_OK;
@@ -776,7 +798,7 @@ sc_status sc_trace_noalloc(const sc_scene* scene, const float* d_rays, uint32_t 
         if (e != hipSuccess) return hip_fail(e, "ray order");
         a.order = order;
     }
-    e = launch_trace(a, s);
+    e = run_trace(scene->ctx, a, s);
     if (e != hipSuccess) return hip_fail(e, "trace launch");
     return SC_OK;
 }
@@ -860,6 +882,8 @@ sc_status prepare_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_item
             d.key_lo[j] = sc->lo[j];
             d.key_scale[j] = (e > 0.0f && q < std::numeric_limits<float>::infinity()) ? q : 0.0f;
         }
+        d.n_nodes = sc->info.n_nodes;
+        d.n_tris = sc->info.n_tris;
         begin += it.n;
         desc.push_back(d);
     }
@@ -882,6 +906,8 @@ sc_status prepare_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_item
     a.quant = first->quant4;
     a.K = I.codebook_size;
     a.n_items = n_items;
+    // each descriptor carries its scene's counts; the record holds the lowered limits alone
+    set_check_limits(ctx, a, ~0u, ~0u);
     if (I.mode != SC_MASK_NONE && !a.lut) {  // masks exist only if the LUT was built
         for (uint32_t k = 0; k < n_items; ++k)
             if (items[k].scene->info.n_inner) return fail(SC_ERR_INVALID_ARG, "scene without its ray-mask LUT");
@@ -929,7 +955,7 @@ sc_status sc_trace_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_ite
         e = launch_batch_order(d, n_items, a.n, ws, &order, s);
         a.order = order;
     }
-    if (e == hipSuccess) e = launch_trace(a, s);
+    if (e == hipSuccess) e = run_trace(ctx, a, s);
     // the descriptors and the ordering must outlive the launch: wait before releasing them
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (ws) dev_free(ctx, ws, ws_bytes, s);
@@ -980,7 +1006,7 @@ sc_status sc_batch_create(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_it
             le = launch_batch_order(b->items, n_items, a.n, b->sort_ws, &order, b->capture);
             a.order = order;
         }
-        if (le == hipSuccess && a.n > 0) le = launch_trace(a, b->capture);
+        if (le == hipSuccess && a.n > 0) le = run_trace(ctx, a, b->capture);
         e = hipStreamEndCapture(b->capture, &b->graph);
         if (e == hipSuccess) e = le;
     }
@@ -1031,6 +1057,41 @@ sc_status sc_set_tune(sc_ctx* ctx, const sc_tune* tune) {
 sc_status sc_get_tune(const sc_ctx* ctx, sc_tune* out) {
     if (!ctx || !out) return fail(SC_ERR_INVALID_ARG, "ctx and out must be non-NULL");
     *out = ctx->tune;
+    return SC_OK;
+}
+
+sc_status sc_set_device_checks(sc_ctx* ctx, int on) {
+    if (!ctx) return fail(SC_ERR_INVALID_ARG, "ctx is NULL");
+    if (on && !ctx->chk_flags) {
+        sc_status st = use_device(ctx->device);
+        if (st != SC_OK) return st;
+        ctx->chk_flags = static_cast<uint32_t*>(dev_alloc(ctx, 4, nullptr));
+        if (!ctx->chk_flags) return fail(SC_ERR_OOM, "check word allocation failed");
+        const hipError_t e = hipMemset(ctx->chk_flags, 0, 4);
+        if (e != hipSuccess) return hip_fail(e, "check word");
+    }
+    ctx->checks = on != 0;
+    return SC_OK;
+}
+
+sc_status sc_get_check_flags(sc_ctx* ctx, uint32_t* out, int reset) {
+    if (!ctx || !out) return fail(SC_ERR_INVALID_ARG, "ctx and out must be non-NULL");
+    *out = 0;
+    if (!ctx->chk_flags) return SC_OK;
+    sc_status st = use_device(ctx->device);
+    if (st != SC_OK) return st;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(out, ctx->chk_flags, 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && reset) e = hipMemset(ctx->chk_flags, 0, 4);
+    if (e == hipSuccess && reset) e = hipDeviceSynchronize();
+    return e == hipSuccess ? SC_OK : hip_fail(e, "check word");
+}
+
+sc_status sc_set_check_limits(sc_ctx* ctx, uint32_t max_stack, uint32_t max_nodes, uint32_t max_tris) {
+    if (!ctx) return fail(SC_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->chk_stack = max_stack;
+    ctx->chk_nodes = max_nodes;
+    ctx->chk_tris = max_tris;
     return SC_OK;
 }
 

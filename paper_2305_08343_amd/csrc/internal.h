@@ -99,7 +99,8 @@ struct BatchItem {
     const uint32_t* src4;  // 4-wide scenes: binary slot of child [4*node+c] (shadow counts)
     float key_lo[3];       // ray ordering: the scene's vertex bounds' minimum corner and
     float key_scale[3];    // 256 / extent per axis (0 for a flat axis)
-    uint32_t pad2[2];
+    uint32_t n_nodes;      // device checks: the scene's inner nodes (at its width) and triangles
+    uint32_t n_tris;
 };
 static_assert(sizeof(BatchItem) == 128, "batch descriptor layout");
 
@@ -137,7 +138,19 @@ struct TraceLaunch {
     const uint32_t* bit_table;  // LUT mode: [R^6][K/32] ray-mask key x codebook entry bits, or NULL
     const BatchItem* items;     // batched launch: per-scene descriptors sorted by ray_begin, else null
     uint32_t n_items;
+    // Device checks (the instances compiled with SC_DEVICE_CHECKS; ignored by the others): every
+    // inner-node reference must be below chk_nodes, every leaf's triangle range end at or below
+    // chk_tris (a batch: also below its scene's own counts), a lane hold at most chk_stack stack
+    // entries, a tested codebook index be below K. A failed check sets its kChk bit in *chk_flags
+    // and the access does not happen (the ray ends, or the entry is not pushed).
+    uint32_t* chk_flags;
+    uint32_t chk_nodes, chk_tris, chk_stack;
 };
+
+constexpr uint32_t kChkNode = SC_CHECK_NODE, kChkTri = SC_CHECK_TRI, kChkStack = SC_CHECK_STACK, kChkIndex = SC_CHECK_INDEX;
+
+// stack entries one lane can hold (LDS + private), by node width
+constexpr uint32_t trace_stack_capacity(uint32_t width) { return width == 2 ? kMaxDepth + 1 : kMaxStack4; }
 
 // (block, stack) pairs with compiled traversal kernels.
 constexpr uint32_t kTraceConfigs[][2] = {{256, 8}, {128, 8}, {256, 12}, {256, 4}, {128, 16}};
@@ -146,6 +159,8 @@ constexpr uint32_t kQueueRing = 1024;  // launch counter sets per context
 constexpr uint32_t kQueueParts = 8;    // counters per set (one per XCD of an MI355X)
 
 hipError_t launch_trace(const TraceLaunch& a, hipStream_t s);
+// the same kernels with the device checks compiled in (kernels_trace_checked.hip)
+hipError_t launch_trace_checked(const TraceLaunch& a, hipStream_t s);
 
 // Allocation-free traces (noalloc.hip): a file-scope device array per GPU holds the queue
 // counters and the sort workspace for up to kNoAllocMaxSortRays rays. scratch_init takes its

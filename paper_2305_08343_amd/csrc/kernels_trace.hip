@@ -46,8 +46,20 @@
 #include "internal.h"
 #include "raymask.h"
 
+// 1: compile the device checks into every traversal kernel (kernels_trace_checked.hip does, for
+// the library's checked instances; a failed check sets a bit and skips the access it guards)
+#ifndef SC_DEVICE_CHECKS
+#define SC_DEVICE_CHECKS 0
+#endif
+
 namespace sc {
 namespace {
+
+constexpr bool kChecks = SC_DEVICE_CHECKS != 0;
+
+__device__ __forceinline__ void chk_fail(uint32_t* flags, uint32_t bit) {
+    if (flags) atomicOr(flags, bit);
+}
 
 constexpr int kWave = 64;
 constexpr uint32_t kModeNone = SC_MASK_NONE, kModeRaw = SC_MASK_RAW, kModeLut = SC_MASK_LUT,
@@ -322,6 +334,7 @@ void trace_kernel(TraceLaunch a) {
     uint32_t* s_extra = a.extra;
     uint32_t* s_fp = a.slot_fp;
     const uint32_t* s_src4 = a.src4;
+    uint32_t s_nlim = a.chk_nodes, s_tlim = a.chk_tris;  // device checks: the lane's scene's limits
 
     // The rays are split into a.parts contiguous partitions, one queue counter
     // each. Workgroups are dispatched round-robin over the XCDs, so a wave
@@ -388,6 +401,10 @@ void trace_kernel(TraceLaunch a) {
                                 s_side = it.side_masks; s_rays = it.rays; s_full = it.full_start;
                                 s_root = it.root; s_bound = it.origin_bound; s_hits = it.hits;
                                 s_extra = it.extra; s_fp = it.slot_fp; s_src4 = it.src4;
+                                if constexpr (kChecks) {
+                                    s_nlim = min(a.chk_nodes, it.n_nodes);
+                                    s_tlim = min(a.chk_tris, it.n_tris);
+                                }
                                 id = g - it.ray_begin;
                             }
                             const float4 r0 = reinterpret_cast<const float4*>(s_rays)[2 * (size_t)id];
@@ -440,7 +457,21 @@ void trace_kernel(TraceLaunch a) {
 
             // one traversal step of this lane's ray
             bool pop = true;
-            if (ref & kLeafBit) {
+            bool bad = false;  // device checks: the node or leaf reference is out of range
+            if constexpr (kChecks) {
+                if (ref & kLeafBit) {
+                    const uint32_t first = ref & 0x1FFFFFFFu, count = ((ref >> 29) & 3u) + 1u;
+                    bad = first >= s_tlim || count > s_tlim - first;
+                    if (bad) chk_fail(a.chk_flags, kChkTri);
+                } else if (ref >= s_nlim) {
+                    bad = true;
+                    chk_fail(a.chk_flags, kChkNode);
+                }
+                if (bad) sp = 0;  // the ray ends with the hit it has
+            }
+            if (bad) {
+                // nothing is read
+            } else if (ref & kLeafBit) {
                 const uint32_t first = ref & 0x1FFFFFFFu;
                 const uint32_t count = ((ref >> 29) & 3u) + 1u;
                 for (uint32_t k = 0; k < count; ++k) {
@@ -566,6 +597,12 @@ void trace_kernel(TraceLaunch a) {
                         test = cidx4[c] < s_full;
                     }
                     cneed[c] = (MODE != kModeNone) && ckeep[c] && use_mask && test;
+                    if constexpr (kChecks && !BATCH && MODE != kModeNone && MODE != kModeRaw) {
+                        if (cneed[c] && cidx4[c] >= a.K) {
+                            chk_fail(a.chk_flags, kChkIndex);
+                            cneed[c] = false;
+                        }
+                    }
                 }
                 uint32_t pw[4], pb[4], pp[4];  // phased: bit table word + bit; R = 4 pattern + shift
                 uint64_t pm[4];                // phased R = 4: the object mask
@@ -643,9 +680,13 @@ void trace_kernel(TraceLaunch a) {
                     for (int j = 3; j >= 1; --j) {
                         if ((uint32_t)j < alive) {
                             const uint2 e = make_uint2(kref[j], __float_as_uint(key[j]));
-                            if (sp < STACK) lds_stack[sp * BLOCK + tid] = e;
-                            else spill[sp - STACK] = e;
-                            ++sp;
+                            if (kChecks && (uint32_t)sp >= a.chk_stack) {
+                                chk_fail(a.chk_flags, kChkStack);
+                            } else {
+                                if (sp < STACK) lds_stack[sp * BLOCK + tid] = e;
+                                else spill[sp - STACK] = e;
+                                ++sp;
+                            }
                         }
                     }
                     ref = kref[0];
@@ -678,6 +719,12 @@ void trace_kernel(TraceLaunch a) {
                             } else if constexpr (MODE == kModeLut || MODE == kModeLutLds || MODE == kModeLutBits) {
                                 idx = c ? (n3.z >> 16) : (n3.z & 0xFFFFu);
                                 test = idx < s_full;
+                                if constexpr (kChecks && !BATCH) {
+                                    if (test && idx >= a.K) {
+                                        chk_fail(a.chk_flags, kChkIndex);
+                                        test = false;
+                                    }
+                                }
                                 if constexpr (MODE == kModeLut) om = s_codebook + (size_t)idx * W;
                                 if constexpr (MODE == kModeLutLds) om = lds_cb + (test ? idx : 0u) * W;
                             } else {
@@ -708,9 +755,13 @@ void trace_kernel(TraceLaunch a) {
                 if (h0 && h1) {
                     const bool near1 = t01 < t00;
                     const uint2 e = make_uint2(near1 ? n3.x : n3.y, __float_as_uint(near1 ? t00 : t01));
-                    if (sp < STACK) lds_stack[sp * BLOCK + tid] = e;
-                    else spill[sp - STACK] = e;
-                    ++sp;
+                    if (kChecks && (uint32_t)sp >= a.chk_stack) {
+                        chk_fail(a.chk_flags, kChkStack);
+                    } else {
+                        if (sp < STACK) lds_stack[sp * BLOCK + tid] = e;
+                        else spill[sp - STACK] = e;
+                        ++sp;
+                    }
                     ref = near1 ? n3.y : n3.x;
                     pop = false;
                 } else if (h0 || h1) {
@@ -844,13 +895,20 @@ hipError_t launch_any(const TraceLaunch& a, hipStream_t s) {
 
 }  // namespace
 
+#if !SC_DEVICE_CHECKS
 bool trace_config_supported(uint32_t block, uint32_t stack) {
     for (const auto& c : kTraceConfigs)
         if (c[0] == block && c[1] == stack) return true;
     return false;
 }
 
+#endif
+
+#if SC_DEVICE_CHECKS
+hipError_t launch_trace_checked(const TraceLaunch& a, hipStream_t s) {
+#else
 hipError_t launch_trace(const TraceLaunch& a, hipStream_t s) {
+#endif
     if (a.n == 0) return hipSuccess;
     if (a.chunk < 1 || !a.queue || a.parts < 1 || a.parts > kQueueParts) return hipErrorInvalidValue;
     return a.items ? launch_any<true>(a, s) : launch_any<false>(a, s);

@@ -26,7 +26,8 @@ def test_header_declares_the_api():
                  "sc_get_tune", "sc_trace_batch", "sc_batch_create", "sc_batch_launch",
                  "sc_batch_destroy", "sc_bvh_build_host", "sc_slot_features", "sc_mlp_forward",
                  "sc_mlp_backward", "sc_mlp_adam", "sc_place_top", "sc_ray_order",
-                 "sc_scene_export4", "sc_scene_export_bit_table", "sc_trace_noalloc"):
+                 "sc_scene_export4", "sc_scene_export_bit_table", "sc_trace_noalloc",
+                 "sc_set_device_checks", "sc_get_check_flags", "sc_set_check_limits"):
         assert must in names
 
 
@@ -73,7 +74,18 @@ def test_null_arguments_rejected_before_hip():
     assert lib.sc_trace_batch(None, None, 0, 0, None) == 1
     assert lib.sc_batch_create(None, None, 0, 0, None) == 1
     assert lib.sc_batch_launch(None, None) == 1 and lib.sc_batch_destroy(None) == 0
+    assert lib.sc_set_device_checks(None, 1) == 1
+    assert lib.sc_get_check_flags(None, None, 0) == 1
+    assert lib.sc_set_check_limits(None, 0, 0, 0) == 1
     assert lib.sc_destroy(None) == 0 and lib.sc_scene_destroy(None) == 0
+
+
+def test_check_bits_match_header():
+    text = open(HEADER).read()
+    bits = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define (SC_CHECK_[A-Z]+) (\d+)u", text)}
+    assert bits == {"SC_CHECK_NODE": B.SC_CHECK_NODE, "SC_CHECK_TRI": B.SC_CHECK_TRI,
+                    "SC_CHECK_STACK": B.SC_CHECK_STACK, "SC_CHECK_INDEX": B.SC_CHECK_INDEX}
+    assert len(set(bits.values())) == 4 and all(v & (v - 1) == 0 for v in bits.values())
 
 
 def test_bad_build_params_rejected_before_hip():
