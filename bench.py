@@ -307,9 +307,11 @@ def cpu_baseline(tris, rays, target_s, spec):
     dt = time.perf_counter() - t0
     # untimed: how deep each sampled ray's stack gets (entries beneath the visited node, the stack
     # the GPU kernel keeps in LDS up to the launch shape's depth and in private memory beyond it)
-    deep = None
+    deep, refs = None, None
     if b4 is not None:
-        deep = oracle.trace4(tris, bvh, b4, sample, nthreads=cores, stack_depth=True, **kw).deepest
+        h = oracle.trace4(tris, bvh, b4, sample, nthreads=cores, stack_depth=True, codebook_refs=(mode == "lut"),
+                          **kw)
+        deep, refs = h.deepest, h.cb_refs
     masks_txt = ("no masks (plain traversal)" if mode == "none" else
                  f"{'LUT K=' + str(spec.get('K', 4096)) if mode == 'lut' else mode} masks R={R}"
                  f"{' on leaf slots' if spec.get('mask_slots') == 'leaves' else ''}"
@@ -324,7 +326,22 @@ def cpu_baseline(tris, rays, target_s, spec):
                        f"every {step}th ray of the {rays.shape[0]:,} ({sample.shape[0]:,} rays)") +
                       f", {what}; {dt:.1f} s of traversal on {cores} threads; oracle BVH, mask and codebook "
                       f"set-up {setup:.1f} s not timed"}
+    if refs is not None:
+        out["codebook_refs"] = codebook_ref_report(refs, R)
     return out, deep
+
+
+def codebook_ref_report(refs, R):
+    """How the sample's mask tests spread over the codebook entries: the share of tests that read the
+    most-read k entries (what an LDS copy of k entries, k * entry bytes, would serve)."""
+    r = np.sort(np.asarray(refs, np.float64))[::-1]
+    total = float(r.sum())
+    cum = np.cumsum(r) / max(total, 1.0)
+    words = (R ** 3 + 63) // 64
+    return {"tests": int(total), "entries": int(r.size), "entries_read": int((r > 0).sum()),
+            "entry_bytes": 8 * words,
+            "share_of_tests_in_most_read": {str(k): float(cum[min(k, r.size) - 1]) for k in (16, 64, 256, 1024)
+                                            if r.size}}
 
 
 def stack_report(deep, lds_entries):

@@ -196,6 +196,7 @@ class Hits:
     mask_culls: np.ndarray
     slot_fp: np.ndarray | None = None
     deepest: np.ndarray | None = None  # trace4(stack_depth=True): stack entries beneath the visited node
+    cb_refs: np.ndarray | None = None  # trace4(codebook_refs=True), LUT mode: mask tests per codebook entry
 
 
 RAY_MASKS = {"lut": 0, "lut2r": 1, "ideal": 2}
@@ -337,10 +338,12 @@ def with_slot_boxes(bvh: BVH, bvh4: BVH4) -> BVH:
 
 def trace4(tris, bvh: BVH, bvh4: BVH4, rays, *, mode="none", R=6, masks=None, codebook=None, cidx=None,
            placed=None, lut=None, origin_bound=None, cull=True, shadow=False, nthreads=0,
-           stack_depth=False, test_max=0) -> Hits:
+           stack_depth=False, test_max=0, codebook_refs=False) -> Hits:
     """Alg. 4 on the 4-wide BVH; masks, codebook indices, shadow counts and
     test_max are as for trace(). stack_depth=True also returns, per ray, the
-    most stack entries held beneath the node being visited (Hits.deepest)."""
+    most stack entries held beneath the node being visited (Hits.deepest);
+    codebook_refs=True (LUT mode) the number of mask tests that read each
+    codebook entry (Hits.cb_refs)."""
     tris = np.ascontiguousarray(tris, np.float32)
     rays = np.ascontiguousarray(rays, np.float32)
     n = rays.shape[0]
@@ -361,16 +364,18 @@ def trace4(tris, bvh: BVH, bvh4: BVH4, rays, *, mode="none", R=6, masks=None, co
     r4 = np.ascontiguousarray(bvh4.ref4) if bvh4.n4 else np.zeros((1, 4), np.uint32)
     s4 = np.ascontiguousarray(bvh4.src4) if bvh4.n4 else np.zeros((1, 4), np.uint32)
     deep = np.zeros(max(n, 1), np.uint32) if stack_depth else None
+    refs = np.zeros(max(codebook.shape[0], 1), np.uint32) if (codebook_refs and mode == "lut") else None
     rc = lib().orc_trace4(_p(tris), _p(bvh.perm), _p(b4), _p(r4), _p(s4), C.c_uint32(bvh4.root),
                           C.c_uint32(bvh4.depth), C.c_uint32(R), C.c_uint32(mcode), _p(masks), _p(codebook),
                           _p(cidx), _p(placed), _p(lut), C.c_float(origin_bound), C.c_uint32(flags), _p(rays),
                           C.c_uint32(n), _p(hits), _p(extra), _p(fp), C.c_int(nthreads), _p(deep),
-                          C.c_uint32(test_max))
+                          C.c_uint32(test_max), _p(refs))
     _check(rc, "trace4")
     hits, extra = hits[:n], extra[:n]
     return Hits(hits[:, 0].copy(), hits[:, 1].view(np.float32).copy(), hits[:, 2].copy(),
                 hits[:, 3].copy(), extra[:, 0].copy(), extra[:, 1].copy(),
-                None if fp is None else fp[:2 * bvh.n_inner], None if deep is None else deep[:n])
+                None if fp is None else fp[:2 * bvh.n_inner], None if deep is None else deep[:n],
+                None if refs is None else refs[:codebook.shape[0]])
 
 
 def bit_table(R: int, cb, lut=None) -> np.ndarray:

@@ -657,6 +657,7 @@ typedef struct {
     uint32_t rm_kind;          /* ray mask: 0 table at R, 1 table at 2R (lut2), 2 ideal */
     const uint64_t* lut2;
     uint32_t test_max;         /* the most set bits a tested mask may have (R^3 - 1: all but full) */
+    uint32_t* cb_refs;         /* LUT mode, optional: mask tests per codebook entry */
 } TraceCtx;
 
 static void raymask_key_cells(const float* lo, const float* hi, const float* o, const float* d,
@@ -764,6 +765,12 @@ static int mask_test(const TraceCtx* C, uint32_t slot, const float* lo, const fl
     else if (C->placed[slot]) om = &C->masks[(size_t)slot * C->W];
     if (!om || popc(om, C->W) > C->test_max) return 0;
     ++*mask_tests;
+    if (C->cb_refs && C->mode == MODE_LUT) {
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+        C->cb_refs[C->cidx[slot]] += 1u;
+    }
     uint32_t R = C->R;
     uint64_t ideal[4] = {0, 0, 0, 0};
     const uint64_t* rm;
@@ -905,6 +912,7 @@ int orc_trace_ex(const float* tris, const uint32_t* perm, const float* cbox, con
     C.rm_kind = rm_kind;
     C.lut2 = lut2;
     C.test_max = test_max ? test_max : R * R * R - 1;
+    C.cb_refs = NULL;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 256)
@@ -1164,7 +1172,7 @@ int orc_trace4(const float* tris, const uint32_t* perm, const float* box4, const
                const uint64_t* masks, const uint64_t* codebook, const uint16_t* cidx, const uint8_t* placed,
                const uint64_t* lut, float origin_bound, uint32_t flags, const float* rays, uint32_t nrays,
                uint32_t* out_hits, uint32_t* out_extra, uint32_t* slot_fp, int nthreads,
-               uint32_t* out_deepest, uint32_t test_max) {
+               uint32_t* out_deepest, uint32_t test_max, uint32_t* out_cb_refs) {
     if (3 * depth + 1 > 256) return ORC_ERR_DEPTH;
     if (mode > MODE_SPARSE) return ORC_ERR_ARG;
     if (mode != MODE_NONE && (R < 1 || R > 6 || !lut)) return ORC_ERR_ARG;
@@ -1181,6 +1189,7 @@ int orc_trace4(const float* tris, const uint32_t* perm, const float* box4, const
     C->rm_kind = 0;
     C->lut2 = NULL;
     C->test_max = test_max ? test_max : R * R * R - 1;
+    C->cb_refs = (mode == MODE_LUT) ? out_cb_refs : NULL;
     T.box4 = box4; T.ref4 = ref4; T.src4 = src4;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);

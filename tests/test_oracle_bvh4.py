@@ -166,14 +166,16 @@ def test_bvh4_culling_keeps_hits_and_reduces_counts(small_scene, small_oracle, R
     assert raw.mask_culls.sum() > 0 and (raw.box_tests + raw.tri_tests).sum() < (plain.box_tests + plain.tri_tests).sum()
 
 
-def _recursive_trace4(tris, bvh, b4, ray, masks=None, lut=None, R=6, ob=np.inf, test_max=None):
+def _recursive_trace4(tris, bvh, b4, ray, masks=None, lut=None, R=6, ob=np.inf, test_max=None, cidx=None):
     """Alg. 4 on the 4-wide BVH as recursion: children sorted by (t0, index); a mask with more
-    than test_max set bits (default R^3 - 1: only a full mask) is not tested."""
+    than test_max set bits (default R^3 - 1: only a full mask) is not tested. With cidx (the
+    codebook index of each slot, masks then being the slots' codebook entries), st["refs"]
+    counts the tests that read each codebook index."""
     f32 = np.float32
     o, d, tmin = ray[:3].astype(f32), ray[4:7].astype(f32), f32(ray[3])
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
         inv = f32(1) / d
-    st = {"best": NO_HIT, "t": f32(ray[7]), "box": 0, "tri": 0, "mt": 0, "mc": 0, "deep": 0}
+    st = {"best": NO_HIT, "t": f32(ray[7]), "box": 0, "tri": 0, "mt": 0, "mc": 0, "deep": 0, "refs": {}}
     use_mask = masks is not None and max(abs(o)) <= ob
     bits = None if masks is None else oracle.mask_bits(masks, R)
     lbits = None if lut is None else oracle.mask_bits(lut, R)
@@ -251,6 +253,8 @@ def _recursive_trace4(tris, bvh, b4, ray, masks=None, lut=None, R=6, ob=np.inf, 
             s = int(b4.src4[ref, c])
             if use_mask and bits[s].sum() <= limit:
                 st["mt"] += 1
+                if cidx is not None:
+                    st["refs"][int(cidx[s])] = st["refs"].get(int(cidx[s]), 0) + 1
                 key = 0
                 for q in (*cell(lo, hi, t0), *cell(lo, hi, t1)):
                     key = key * R + q
@@ -281,6 +285,42 @@ def test_recursive_formulation_counts_bvh4(small_scene, small_oracle):
             assert st["deep"] == h.deepest[i], i
             if mode == "raw":
                 assert (st["mt"], st["mc"]) == (h.mask_tests[i], h.mask_culls[i]), i
+
+
+def test_codebook_reference_counts(small_scene, small_oracle):
+    """Tests per codebook entry (LUT mode): equal to the recursive formulation's own tally, summing
+    to the per-ray mask tests, the same on one thread as on several, and zero for every entry no
+    slot uses and for the full entries at the end of the codebook (never tested)."""
+    tris, rays = small_scene
+    sel = np.concatenate([_aimed_rays(tris, 150, 43), rays[::1024]])
+    bvh = small_oracle["bvh"]
+    b4 = oracle.bvh4_collapse(bvh)
+    ob, lut = small_oracle["origin_bound"], small_oracle["lut6"]
+    cb, idx = oracle.compress(small_oracle["masks6"], bvh.slot_boxes(), 6, 256)
+    kw = dict(mode="lut", R=6, codebook=cb, cidx=idx, origin_bound=ob, codebook_refs=True)
+    h = oracle.trace4(tris, bvh, b4, sel, nthreads=4, **kw)
+    h1 = oracle.trace4(tris, bvh, b4, sel, nthreads=1, **kw)
+    assert h.cb_refs.shape == (cb.shape[0],) and (h.cb_refs == h1.cb_refs).all()
+    assert h.cb_refs.sum() == h.mask_tests.sum() > 0
+    used = np.zeros(cb.shape[0], bool)
+    used[idx] = True
+    assert (h.cb_refs[~used] == 0).all()
+    full = oracle.mask_bits(cb, 6).sum(-1) == 216
+    assert full.any() and (h.cb_refs[full] == 0).all()
+    tally = {}
+    slot_masks = cb[idx]
+    for i in range(sel.shape[0]):
+        st = _recursive_trace4(tris, bvh, b4, sel[i], slot_masks, lut, 6, ob, cidx=idx)
+        assert st["mt"] == h.mask_tests[i], i
+        for k, v in st["refs"].items():
+            tally[k] = tally.get(k, 0) + v
+    want = np.zeros(cb.shape[0], np.uint64)
+    for k, v in tally.items():
+        want[k] = v
+    assert (h.cb_refs.astype(np.uint64) == want).all()
+    # raw mode has no codebook: nothing is counted
+    assert oracle.trace4(tris, bvh, b4, sel[:50], mode="raw", R=6, masks=small_oracle["masks6"],
+                         origin_bound=ob, codebook_refs=True).cb_refs is None
 
 
 def test_mask_test_limit_recursive_and_monotone(small_scene, small_oracle):
