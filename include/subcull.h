@@ -102,7 +102,10 @@ typedef struct {
                                mask                                              */
     uint32_t bit_table;     /* LUT mode: 1 builds the 2-D bit table of Sect. 3.2.2
                                (bit (key, k) = ray mask LUT[key] AND codebook
-                               entry k is nonzero; R^6 * K / 8 bytes) and single
+                               entry k is nonzero; a key's row equals its
+                               reversed pair's, so the device keeps one row per
+                               unordered cell pair: R^3 (R^3 + 1) / 2 * K / 8
+                               bytes) and single
                                scene traces test a compressed mask with one bit
                                of it; results are unchanged (default 0)           */
     uint32_t mask_slots;    /* which child slots keep a testable mask: 0 = every
@@ -263,8 +266,10 @@ sc_status sc_scene_export(const sc_scene* scene, sc_scene_host* out);
 sc_status sc_scene_export4(const sc_scene* scene, float* box4, uint32_t* ref4, uint32_t* src4);
 
 /* Copy a LUT scene's 2-D bit table to host `out` (uint32 [R^6][K/32]; bit k
- * % 32 of word k / 32 of row key), synchronous. SC_ERR_INVALID_ARG if the
- * scene was built without one. */
+ * % 32 of word k / 32 of row key: every ordered key, each expanded from the
+ * device's row of its unordered cell pair), synchronous. SC_ERR_INVALID_ARG
+ * if the scene was built without one; SC_ERR_OOM if the host staging buffer
+ * cannot be allocated. */
 sc_status sc_scene_export_bit_table(const sc_scene* scene, uint32_t* out);
 
 /*

@@ -48,7 +48,7 @@ struct sc_scene {
     uint32_t quant4 = 0;                  // 4-wide: quantised child boxes
     uint64_t* masks4 = nullptr;           // 4-wide RAW: child masks [4*n4][W]
     uint32_t* src4 = nullptr;             // 4-wide: binary slot of each child [4*n4]
-    uint32_t* bit_table = nullptr;        // LUT mode: 2-D bit table [R^6][K/32]
+    uint32_t* bit_table = nullptr;        // LUT mode: 2-D bit table [R^3 (R^3 + 1) / 2 cell pairs][K/32]
     std::vector<std::pair<void*, size_t>> owned;
 };
 
@@ -497,7 +497,7 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                 if (e == hipSuccess) e = launch_compress(R, sc->masks, S, d_req, K, sc->cidx, s);
                 if (e == hipSuccess) e = launch_pack_lut(sc->cidx, B.n_inner, sc->nodes, s);
                 if (e == hipSuccess && P.bit_table) {
-                    const size_t tb = (size_t)R * R * R * R * R * R * (K / 32) * 4;
+                    const size_t tb = (size_t)bit_table_rows(R) * (K / 32) * 4;
                     sc->bit_table = scene_alloc<uint32_t>(sc, tb, s);
                     if (!sc->bit_table) {
                         dev_free(ctx, d_req, req_bytes, s);
@@ -642,10 +642,20 @@ sc_status sc_scene_export_bit_table(const sc_scene* scene, uint32_t* out) {
     if (!scene->bit_table) return fail(SC_ERR_INVALID_ARG, "the scene has no bit table");
     sc_status st = use_device(scene->ctx->device);
     if (st != SC_OK) return st;
-    const uint32_t R = scene->info.R;
-    const size_t bytes = (size_t)R * R * R * R * R * R * (scene->info.codebook_size / 32) * 4;
-    const hipError_t e = hipMemcpy(out, scene->bit_table, bytes, hipMemcpyDeviceToHost);
+    // the device keeps one row per unordered cell pair; the export lists every ordered key
+    const uint32_t R = scene->info.R, cells = R * R * R, kw = scene->info.codebook_size / 32;
+    std::vector<uint32_t> rows;
+    try {
+        rows.resize((size_t)bit_table_rows(R) * kw);
+    } catch (const std::bad_alloc&) {
+        return fail(SC_ERR_OOM, "bit table export buffer");
+    }
+    const hipError_t e = hipMemcpy(rows.data(), scene->bit_table, rows.size() * 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "bit table export");
+    for (uint32_t fb = 0; fb < cells; ++fb)
+        for (uint32_t fe = 0; fe < cells; ++fe)
+            std::memcpy(out + ((size_t)fb * cells + fe) * kw, rows.data() + (size_t)bit_row(fb, fe) * kw,
+                        (size_t)kw * 4);
     return SC_OK;
 }
 

@@ -33,6 +33,18 @@ constexpr uint32_t kTriBytes = 48;  // v0.xyz e1.xyz e2.xyz id pad pad
 
 inline uint32_t words_for(uint32_t R) { return (R * R * R + 63u) / 64u; }
 
+// The 2-D bit table is stored by unordered cell pair: its row for (b, e) equals the row for (e, b)
+// (a ray mask is symmetric in its two cells), so only pairs with flat cell indices lo <= hi are
+// kept, row hi * (hi + 1) / 2 + lo, with f = (x * R + y) * R + z; R^3 (R^3 + 1) / 2 rows.
+template <int R>
+constexpr uint32_t kBitRows = (uint32_t)(R * R * R) * (uint32_t)(R * R * R + 1) / 2u;
+inline uint32_t bit_table_rows(uint32_t R) { return (R * R * R) * (R * R * R + 1u) / 2u; }
+
+__host__ __device__ inline uint32_t bit_row(uint32_t fb, uint32_t fe) {
+    const uint32_t lo = fb < fe ? fb : fe, hi = fb < fe ? fe : fb;
+    return ((hi * (hi + 1u)) >> 1) + lo;
+}
+
 // -------------------------------------------------------------- host BVH
 struct HostBVH {
     uint32_t n_inner = 0;

@@ -490,18 +490,25 @@ __global__ void pack4_kernel(uint32_t mode, const uint32_t* __restrict__ src4, u
     }
 }
 
-// 2-D bit table (Sect. 3.2.2): one thread per (ray-mask key, 32 codebook entries).
+// 2-D bit table (Sect. 3.2.2), stored by unordered cell pair (bit_row): one thread per (row,
+// 32 codebook entries); the row of cells lo <= hi reads the LUT entry of key lo * R^3 + hi.
 template <int R>
 __global__ __launch_bounds__(256) void bit_table_kernel(const uint64_t* __restrict__ lut,
                                                         const uint64_t* __restrict__ cb, uint32_t K,
                                                         uint32_t* __restrict__ out) {
     constexpr int W = (R * R * R + 63) / 64;
-    constexpr size_t kKeys = (size_t)R * R * R * R * R * R;
+    constexpr uint32_t kCells = R * R * R;
     const uint32_t kw = K / 32;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= kKeys * kw) return;
-    const size_t key = gid / kw;
+    if (gid >= (size_t)kBitRows<R> * kw) return;
+    const uint32_t row = (uint32_t)(gid / kw);
     const uint32_t w = (uint32_t)(gid % kw);
+    // hi: the largest h with h (h + 1) / 2 <= row (a float guess, then exact integer steps)
+    uint32_t hi = (uint32_t)((sqrtf(8.0f * (float)row + 1.0f) - 1.0f) * 0.5f);
+    while (hi > 0 && ((hi * (hi + 1u)) >> 1) > row) --hi;
+    while ((((hi + 1u) * (hi + 2u)) >> 1) <= row) ++hi;
+    const uint32_t lo = row - ((hi * (hi + 1u)) >> 1);
+    const size_t key = (size_t)lo * kCells + hi;
     uint64_t rm[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) rm[q] = lut[key * W + q];
@@ -651,7 +658,7 @@ hipError_t launch_pack4(uint32_t mode, uint32_t R, const uint32_t* src4, uint32_
 hipError_t launch_bit_table(uint32_t R, const uint64_t* lut, const uint64_t* cb, uint32_t K, uint32_t* out,
                             hipStream_t s) {
     if (K == 0 || K % 32) return hipErrorInvalidValue;
-    const size_t n = (size_t)R * R * R * R * R * R * (K / 32);
+    const size_t n = (size_t)(R == 4 ? kBitRows<4> : kBitRows<6>) * (K / 32);
     if (R == 4) hipLaunchKernelGGL(bit_table_kernel<4>, dim3(blocks_for(n, 256)), dim3(256), 0, s, lut, cb, K, out);
     else if (R == 6) hipLaunchKernelGGL(bit_table_kernel<6>, dim3(blocks_for(n, 256)), dim3(256), 0, s, lut, cb, K, out);
     else return hipErrorInvalidValue;

@@ -186,8 +186,8 @@ __device__ __forceinline__ bool bit_overlap(const float* lo, const float* hi, co
                                             const uint32_t* table, uint32_t K, uint32_t idx) {
     int bx, by, bz, ex, ey, ez;
     ray_cells<R>(lo, hi, r, t0, t1, bx, by, bz, ex, ey, ez);
-    const uint32_t key = (uint32_t)(((((bx * R + by) * R + bz) * R + ex) * R + ey) * R + ez);
-    return (table[key * (K >> 5) + (idx >> 5)] >> (idx & 31u)) & 1u;
+    const uint32_t row = bit_row((uint32_t)((bx * R + by) * R + bz), (uint32_t)((ex * R + ey) * R + ez));
+    return (table[row * (K >> 5) + (idx >> 5)] >> (idx & 31u)) & 1u;
 }
 
 // R = 4: the ray mask of cells (b, e) is displacement pattern pidx (x made
@@ -619,10 +619,10 @@ void trace_kernel(TraceLaunch a) {
                             int bx, by, bz, ex, ey, ez;
                             ray_cells_nf<R>(nr, fr, r.neg, r, ct0[c], ct1[c], bx, by, bz, ex, ey, ez);
                             if constexpr (MODE == kModeLutBits) {
-                                const uint32_t k6 =
-                                    (uint32_t)(((((bx * R + by) * R + bz) * R + ex) * R + ey) * R + ez);
-                                // R^6 rows of K / 32 words: below 2^23 words for R <= 6, K <= 4096
-                                pw[c] = a.bit_table[k6 * (a.K >> 5) + (idx >> 5)];
+                                const uint32_t row = bit_row((uint32_t)((bx * R + by) * R + bz),
+                                                             (uint32_t)((ex * R + ey) * R + ez));
+                                // R^3 (R^3 + 1) / 2 rows of K / 32 words: below 2^22 words for R <= 6, K <= 4096
+                                pw[c] = a.bit_table[row * (a.K >> 5) + (idx >> 5)];
                                 pb[c] = idx & 31u;
                             } else {
                                 if constexpr (MODE == kModeRaw) pm[c] = s_side[(size_t)ref * 4 + c];
