@@ -37,8 +37,15 @@ struct sc_scene {
     unsigned char* nodes = nullptr;
     float* tris = nullptr;
     uint64_t* masks = nullptr;            // exact masks [2*n_inner][W]
-    uint64_t* codebook = nullptr;         // LUT mode
-    uint16_t* cidx = nullptr;             // LUT mode
+    uint64_t* codebook = nullptr;         // LUT mode (exported order)
+    uint16_t* cidx = nullptr;             // LUT mode (exported order)
+    // LUT mode, traversal copies: the tested entries re-ordered by how often a test is expected to read
+    // them (the surface area of the slots using them), so the ones most read share the first cache
+    // line of every bit-table row; the nodes hold these indices, and trace_order[k] is the position of
+    // exported entry k
+    uint64_t* codebook_trace = nullptr;
+    uint16_t* cidx_trace = nullptr;
+    std::vector<uint32_t> trace_order;
     uint32_t full_start = 0;              // LUT mode: first untested codebook entry (the full one by default)
     uint64_t* side_masks = nullptr;       // SPARSE mode
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // vertex bounds (ray ordering keys)
@@ -92,6 +99,49 @@ T* scene_alloc(sc_scene* sc, size_t bytes, hipStream_t s) {
         sc->info.device_bytes += bytes;
     }
     return static_cast<T*>(p);
+}
+
+// Traversal order of a LUT scene's tested codebook entries [0, full_start): by the summed surface
+// area of the slots the traversal tests that use each entry (how often a test reads it, for rays
+// spread over the scene), largest first, ties by exported index; the untested tail keeps its place.
+// Fills codebook_trace, cidx_trace and trace_order; waits for the stream (host temporaries).
+hipError_t order_codebook_for_trace(sc_scene* sc, const std::vector<uint64_t>& cb, uint32_t S, uint32_t W,
+                                    uint32_t K, uint32_t width, hipStream_t s) {
+    std::vector<uint16_t> hc(S);
+    hipError_t e = S ? hipMemcpyAsync(hc.data(), sc->cidx, (size_t)S * 2, hipMemcpyDeviceToHost, s) : hipSuccess;
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    std::vector<double> weight(K, 0.0);
+    auto add = [&](uint32_t slot) {
+        const float* b = &sc->bvh.cbox[6 * (size_t)slot];
+        const double dx = (double)b[3] - b[0], dy = (double)b[4] - b[1], dz = (double)b[5] - b[2];
+        weight[hc[slot]] += 2.0 * ((dx * dy + dy * dz) + dz * dx);
+    };
+    if (width == 4) {  // the binary slots the 4-wide nodes' children came from
+        const HostBVH4& B4 = sc->bvh4;
+        for (size_t k = 0; k < B4.ref.size(); ++k)
+            if (B4.ref[k] != kEmptyRef) add(B4.src[k]);
+    } else {
+        for (uint32_t q = 0; q < S; ++q) add(q);
+    }
+    const uint32_t F = sc->full_start;
+    std::vector<uint32_t> by(F);
+    for (uint32_t k = 0; k < F; ++k) by[k] = k;
+    std::stable_sort(by.begin(), by.end(), [&](uint32_t a, uint32_t b) { return weight[a] > weight[b]; });
+    sc->trace_order.assign(K, 0);
+    for (uint32_t i = 0; i < F; ++i) sc->trace_order[by[i]] = i;
+    for (uint32_t k = F; k < K; ++k) sc->trace_order[k] = k;
+    std::vector<uint64_t> cbt(cb.size());
+    for (uint32_t k = 0; k < K; ++k)
+        std::memcpy(&cbt[(size_t)sc->trace_order[k] * W], &cb[(size_t)k * W], (size_t)W * 8);
+    for (auto& c : hc) c = (uint16_t)sc->trace_order[c];
+    sc->codebook_trace = scene_alloc<uint64_t>(sc, cbt.size() * 8, s);
+    sc->cidx_trace = scene_alloc<uint16_t>(sc, (size_t)(S ? S : 1) * 2, s);
+    if (!sc->codebook_trace || !sc->cidx_trace) return hipErrorOutOfMemory;
+    e = hipMemcpyAsync(sc->codebook_trace, cbt.data(), cbt.size() * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && S) e = hipMemcpyAsync(sc->cidx_trace, hc.data(), (size_t)S * 2, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
 }
 
 void scene_free_all(sc_scene* sc, hipStream_t s) {
@@ -495,7 +545,8 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                 e = hipMemcpyAsync(sc->codebook, cb.data(), cb.size() * 8, hipMemcpyHostToDevice, s);
                 if (e == hipSuccess) e = launch_req_luts(R, sc->codebook, K, d_req, s);
                 if (e == hipSuccess) e = launch_compress(R, sc->masks, S, d_req, K, sc->cidx, s);
-                if (e == hipSuccess) e = launch_pack_lut(sc->cidx, B.n_inner, sc->nodes, s);
+                if (e == hipSuccess) e = order_codebook_for_trace(sc, cb, S, W, K, P.width, s);
+                if (e == hipSuccess) e = launch_pack_lut(sc->cidx_trace, B.n_inner, sc->nodes, s);
                 if (e == hipSuccess && P.bit_table) {
                     const size_t tb = (size_t)bit_table_rows(R) * (K / 32) * 4;
                     sc->bit_table = scene_alloc<uint32_t>(sc, tb, s);
@@ -503,7 +554,7 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                         dev_free(ctx, d_req, req_bytes, s);
                         return bail(SC_ERR_OOM, "bit table allocation failed");
                     }
-                    e = launch_bit_table(R, ctx->lut[R], sc->codebook, K, sc->bit_table, s);
+                    e = launch_bit_table(R, ctx->lut[R], sc->codebook_trace, K, sc->bit_table, s);
                 }
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
                 dev_free(ctx, d_req, req_bytes, s);
@@ -563,8 +614,8 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                 if (!sc->masks4) return bail(SC_ERR_OOM, "4-wide mask allocation failed");
             }
             if (P.mode == SC_MASK_RAW || P.mode == SC_MASK_LUT) {
-                e = launch_pack4(P.mode, R, sc->src4, B4.n4, sc->masks, sc->cidx, test_max, sc->nodes4, sc->masks4,
-                                 sc->quant4, s);
+                e = launch_pack4(P.mode, R, sc->src4, B4.n4, sc->masks, sc->cidx_trace, test_max, sc->nodes4,
+                                 sc->masks4, sc->quant4, s);
                 if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("4-wide pack: ") + hipGetErrorString(e));
             }
         }
@@ -652,6 +703,17 @@ sc_status sc_scene_export_bit_table(const sc_scene* scene, uint32_t* out) {
     }
     const hipError_t e = hipMemcpy(rows.data(), scene->bit_table, rows.size() * 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "bit table export");
+    // the device's columns follow the traversal order: exported entry k is column trace_order[k]
+    const std::vector<uint32_t>& ord = scene->trace_order;
+    const uint32_t K = scene->info.codebook_size;
+    std::vector<uint32_t> row(kw);
+    for (size_t r = 0; r < (size_t)bit_table_rows(R); ++r) {
+        uint32_t* dev = rows.data() + r * kw;
+        std::fill(row.begin(), row.end(), 0u);
+        for (uint32_t k = 0; k < K; ++k)
+            if ((dev[ord[k] >> 5] >> (ord[k] & 31u)) & 1u) row[k >> 5] |= 1u << (k & 31u);
+        std::copy(row.begin(), row.end(), dev);
+    }
     for (uint32_t fb = 0; fb < cells; ++fb)
         for (uint32_t fe = 0; fe < cells; ++fe)
             std::memcpy(out + ((size_t)fb * cells + fe) * kw, rows.data() + (size_t)bit_row(fb, fe) * kw,
@@ -714,7 +776,7 @@ TraceLaunch trace_launch(const sc_scene* scene, const float* d_rays, uint32_t n,
     a.tris = scene->tris;
     a.lut = (I.mode != SC_MASK_NONE) ? scene->ctx->lut[I.R] : nullptr;
     a.patterns = (I.mode != SC_MASK_NONE) ? scene->ctx->patterns[I.R] : nullptr;
-    a.codebook = scene->codebook;
+    a.codebook = scene->codebook_trace;
     a.K = I.codebook_size;
     a.full_start = scene->full_start;
     a.side_masks = scene->side_masks;
@@ -874,7 +936,7 @@ sc_status prepare_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_item
         BatchItem d{};
         d.nodes = sc->info.width == 4 ? sc->nodes4 : sc->nodes;
         d.tris = sc->tris;
-        d.codebook = sc->codebook;
+        d.codebook = sc->codebook_trace;
         d.side_masks = sc->info.width == 4 ? sc->masks4 : sc->side_masks;
         d.src4 = sc->src4;
         d.rays = it.d_rays;
