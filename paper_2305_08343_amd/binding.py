@@ -172,6 +172,8 @@ def _on_stream(stream):
 
 
 SC_CHECK_NODE, SC_CHECK_TRI, SC_CHECK_STACK, SC_CHECK_INDEX = 1, 2, 4, 8
+# (device, bits) of every context closed with device checks on and a failed check not reset
+CHECK_FAILURES = []
 
 
 class Context:
@@ -226,6 +228,13 @@ class Context:
 
     def close(self):
         if getattr(self, "handle", None):
+            if getattr(self, "checks", False):
+                try:
+                    bits = self.check_flags()
+                except SubcullError:
+                    bits = 0  # the device is in error; the destroy below still runs
+                if bits:
+                    CHECK_FAILURES.append((self.device, bits))
             load().sc_destroy(self.handle)
             self.handle = None
 

@@ -732,6 +732,7 @@ sc_status sc_scene_export4(const sc_scene* scene, float* box4, uint32_t* ref4, u
 }
 
 namespace {
+extern "C++" {  // C++ helpers of the C entry points (they take and return C++ types)
 
 // The device-check fields of a launch record: the scene's node and triangle counts (a batch passes
 // the largest; each descriptor carries its own) and the stack capacity of its width, each lowered
@@ -811,6 +812,7 @@ TraceLaunch trace_launch(const sc_scene* scene, const float* d_rays, uint32_t n,
     return a;
 }
 
+}  // extern "C++"
 }  // namespace
 
 sc_status sc_trace(const sc_scene* scene, const float* d_rays, uint32_t n, uint32_t flags, sc_hit* d_hits,
