@@ -432,8 +432,12 @@ sc_status sc_mlp_forward(sc_ctx* ctx, const float* d_params, const float* d_x, u
 
 /* Gradient of the mean squared error (1/n) sum (y - t)^2 with respect to the
  * parameters (d_grad [SC_MLP_PARAMS]), from the forward pass's d_y and d_act.
- * d_work: device scratch of n * 130 floats. d_loss (one float) or NULL.
- * Batch sums run in a fixed order, so the result is deterministic. */
+ * d_work: device scratch of SC_MLP_WORK_FLOATS(n) floats. d_loss (one float)
+ * or NULL. Batch sums run in a fixed order (SC_MLP_GRAD_PARTS contiguous
+ * sample ranges, each summed in index order, then the ranges in order), so the
+ * result is deterministic. */
+#define SC_MLP_GRAD_PARTS 32
+#define SC_MLP_WORK_FLOATS(n) ((size_t)(n) * 130 + (size_t)SC_MLP_GRAD_PARTS * SC_MLP_PARAMS)
 sc_status sc_mlp_backward(sc_ctx* ctx, const float* d_params, const float* d_x, const float* d_act,
                           const float* d_y, const float* d_t, uint32_t n, float* d_grad, float* d_work,
                           float* d_loss, void* stream);

@@ -172,6 +172,12 @@ def _on_stream(stream):
 
 
 SC_CHECK_NODE, SC_CHECK_TRI, SC_CHECK_STACK, SC_CHECK_INDEX = 1, 2, 4, 8
+SC_MLP_PARAMS, SC_MLP_GRAD_PARTS = 5057, 32
+
+
+def mlp_work_floats(n: int) -> int:
+    """Floats of the scratch sc_mlp_backward needs for a batch of n (SC_MLP_WORK_FLOATS)."""
+    return n * 130 + SC_MLP_GRAD_PARTS * SC_MLP_PARAMS
 # (device, bits) of every context closed with device checks on and a failed check not reset
 CHECK_FAILURES = []
 

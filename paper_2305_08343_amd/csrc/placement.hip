@@ -225,45 +225,67 @@ __global__ __launch_bounds__(256) void mlp_delta_kernel(const float* __restrict_
     }
 }
 
-// One thread per parameter, samples summed in index order.
+// One thread per (parameter, range of samples): the samples of range blockIdx.y (SC_MLP_GRAD_PARTS
+// contiguous ranges) summed in index order into part[range][parameter].
 __global__ void mlp_grad_kernel(const float* __restrict__ x, const float* __restrict__ act,
                                 const float* __restrict__ delta, const float* __restrict__ dyv, uint32_t n,
-                                float* __restrict__ grad) {
+                                float* __restrict__ part) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= kMlpParams) return;
+    const uint32_t r = blockIdx.y;
+    const uint32_t s0 = (uint32_t)(((uint64_t)n * r) / SC_MLP_GRAD_PARTS);
+    const uint32_t s1 = (uint32_t)(((uint64_t)n * (r + 1)) / SC_MLP_GRAD_PARTS);
     float g = 0.0f;
     if (p < oB1) {
         const int k = p / kIn, q = p % kIn;
-        for (uint32_t s = 0; s < n; ++s) g += delta[(size_t)s * 128 + k] * x[(size_t)s * kIn + q];
+        for (uint32_t s = s0; s < s1; ++s) g += delta[(size_t)s * 128 + k] * x[(size_t)s * kIn + q];
     } else if (p < oW2) {
         const int k = p - oB1;
-        for (uint32_t s = 0; s < n; ++s) g += delta[(size_t)s * 128 + k];
+        for (uint32_t s = s0; s < s1; ++s) g += delta[(size_t)s * 128 + k];
     } else if (p < oB2) {
         const int j = (p - oW2) / kHid, k = (p - oW2) % kHid;
-        for (uint32_t s = 0; s < n; ++s) {
+        for (uint32_t s = s0; s < s1; ++s) {
             const float z1 = act[(size_t)s * 128 + k];
             g += delta[(size_t)s * 128 + 64 + j] * (z1 > 0.0f ? z1 : 0.0f);
         }
     } else if (p < oW3) {
         const int j = p - oB2;
-        for (uint32_t s = 0; s < n; ++s) g += delta[(size_t)s * 128 + 64 + j];
+        for (uint32_t s = s0; s < s1; ++s) g += delta[(size_t)s * 128 + 64 + j];
     } else if (p < oB3) {
         const int j = p - oW3;
-        for (uint32_t s = 0; s < n; ++s) {
+        for (uint32_t s = s0; s < s1; ++s) {
             const float z2 = act[(size_t)s * 128 + 64 + j];
             g += dyv[s] * (z2 > 0.0f ? z2 : 0.0f);
         }
     } else {
-        for (uint32_t s = 0; s < n; ++s) g += dyv[s];
+        for (uint32_t s = s0; s < s1; ++s) g += dyv[s];
     }
+    part[(size_t)r * kMlpParams + p] = g;
+}
+
+// grad[p] = the ranges' partial sums, added in range order
+__global__ void mlp_grad_sum_kernel(const float* __restrict__ part, float* __restrict__ grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kMlpParams) return;
+    float g = 0.0f;
+    for (int r = 0; r < SC_MLP_GRAD_PARTS; ++r) g += part[(size_t)r * kMlpParams + p];
     grad[p] = g;
 }
 
-__global__ void sum_kernel(const float* __restrict__ v, uint32_t n, float* __restrict__ out) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// mean of v[n] in float64: thread t adds samples t, t + 256, ... in order, then a fixed pairwise tree
+constexpr int kSumThreads = 256;
+__global__ __launch_bounds__(kSumThreads) void sum_kernel(const float* __restrict__ v, uint32_t n,
+                                                          float* __restrict__ out) {
+    __shared__ double acc[kSumThreads];
     double t = 0.0;
-    for (uint32_t s = 0; s < n; ++s) t += v[s];
-    *out = (float)(t / (double)(n ? n : 1));
+    for (uint32_t s = threadIdx.x; s < n; s += kSumThreads) t += v[s];
+    acc[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) acc[threadIdx.x] += acc[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = (float)(acc[0] / (double)(n ? n : 1));
 }
 
 // Adam (Kingma & Ba 2015); bc1 = 1 - beta1^step, bc2 = 1 - beta2^step.
@@ -327,10 +349,13 @@ hipError_t launch_mlp_backward(const float* prm, const float* x, const float* ac
     float* delta = work;                  // [n][128]
     float* dyv = work + (size_t)n * 128;  // [n]
     float* sqerr = dyv + n;               // [n]
+    float* part = sqerr + n;              // [SC_MLP_GRAD_PARTS][kMlpParams]
     hipLaunchKernelGGL(mlp_delta_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, prm, act, y, t, n, delta, dyv,
                        sqerr);
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3(blocks_for(kMlpParams, 64)), dim3(64), 0, s, x, act, delta, dyv, n, grad);
-    if (loss) hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(1), 0, s, sqerr, n, loss);
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(blocks_for(kMlpParams, 64), SC_MLP_GRAD_PARTS), dim3(64), 0, s, x, act,
+                       delta, dyv, n, part);
+    hipLaunchKernelGGL(mlp_grad_sum_kernel, dim3(blocks_for(kMlpParams, 256)), dim3(256), 0, s, part, grad);
+    if (loss) hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kSumThreads), 0, s, sqerr, n, loss);
     return hipGetLastError();
 }
 

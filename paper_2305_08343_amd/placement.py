@@ -107,7 +107,7 @@ def train(ctx, X, y, *, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, s
     v = torch.zeros_like(params)
     act = torch.empty((batch, 128), dtype=torch.float32, device=dev)
     grad = torch.empty_like(params)
-    work = torch.empty(batch * 130, dtype=torch.float32, device=dev)
+    work = torch.empty(binding.mlp_work_floats(batch), dtype=torch.float32, device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     rng = np.random.default_rng(seed)
     step, hist, start = 0, [], 0

@@ -80,6 +80,14 @@ def test_null_arguments_rejected_before_hip():
     assert lib.sc_destroy(None) == 0 and lib.sc_scene_destroy(None) == 0
 
 
+def test_mlp_constants_match_header():
+    text = open(HEADER).read()
+    assert int(re.search(r"#define SC_MLP_PARAMS (\d+)", text).group(1)) == B.SC_MLP_PARAMS
+    assert int(re.search(r"#define SC_MLP_GRAD_PARTS (\d+)", text).group(1)) == B.SC_MLP_GRAD_PARTS
+    assert "#define SC_MLP_WORK_FLOATS(n) ((size_t)(n) * 130 + (size_t)SC_MLP_GRAD_PARTS * SC_MLP_PARAMS)" in text
+    assert B.mlp_work_floats(1000) == 1000 * 130 + B.SC_MLP_GRAD_PARTS * B.SC_MLP_PARAMS
+
+
 def test_check_bits_match_header():
     text = open(HEADER).read()
     bits = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define (SC_CHECK_[A-Z]+) (\d+)u", text)}

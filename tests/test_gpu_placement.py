@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 from oracle import features as ofeat
+from paper_2305_08343_amd import binding
 from oracle import mlp as omlp
 
 pytestmark = pytest.mark.gpu
@@ -53,7 +54,7 @@ def test_mlp_forward_and_gradients_match_oracle(ctx):
     y_ref, _ = omlp.forward(p32.astype(np.float64), x32.astype(np.float64))
     assert np.allclose(y.cpu().numpy(), y_ref, rtol=1e-4, atol=1e-5)
     grad = torch.empty(omlp.N_PARAMS, dtype=torch.float32, device="cuda")
-    work = torch.empty(n * 130, dtype=torch.float32, device="cuda")
+    work = torch.empty(binding.mlp_work_floats(n), dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     ctx.mlp_backward(dp, dx, act, y, dt, grad, work, loss)
     g_ref = omlp.grad(p32.astype(np.float64), x32.astype(np.float64), t32.astype(np.float64))
@@ -105,7 +106,7 @@ def test_training_steps_track_the_oracle(ctx):
     dv = torch.zeros(omlp.N_PARAMS, device="cuda")
     act = torch.empty((n, 128), device="cuda")
     grad = torch.empty(omlp.N_PARAMS, device="cuda")
-    work = torch.empty(n * 130, device="cuda")
+    work = torch.empty(binding.mlp_work_floats(n), device="cuda")
     loss = torch.empty(1, device="cuda")
     P, M, V = p.astype(np.float64), np.zeros(omlp.N_PARAMS), np.zeros(omlp.N_PARAMS)
     losses = []
