@@ -102,7 +102,7 @@ CURLY_TUNE = {
     "raw4w4l": (256, 12, 1, 8, 6, 1, 0, 12, 8),
     "raw6w4": (256, 12, 1, 8, 6, 1, 0, 12, 12),
     "lut6w4b": (256, 12, 1, 8, 6, 1, 0, 12, 24),
-    "lut6w4bq": (256, 12, 1, 8, 6, 1, 0, 12, 24),
+    "lut6w4bq": (256, 12, 1, 8, 6, 1, 0, 12, 12),
 }
 
 
