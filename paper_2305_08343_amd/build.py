@@ -25,8 +25,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsubcull.so")
-SOURCES = ["api.cpp", "bvh.cpp", "codebook.cpp", "kernels_build.hip", "kernels_trace.hip", "kernels_trace_checked.hip",
-           "placement.hip", "raysort.hip", "bvh4.cpp", "noalloc.hip"]
+SOURCES = ["api.cpp", "bvh.cpp", "codebook.cpp", "codebook.hip", "kernels_build.hip", "kernels_trace.hip",
+           "kernels_trace_checked.hip", "placement.hip", "raysort.hip", "bvh4.cpp", "noalloc.hip"]
 ARCH = os.environ.get("SUBCULL_ARCH", "gfx950")
 
 COMMON = [

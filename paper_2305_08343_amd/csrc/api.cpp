@@ -511,15 +511,17 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
             e = launch_pack_raw(R, sc->masks, B.n_inner, test_max, sc->nodes, s);
             if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("pack: ") + hipGetErrorString(e));
         } else {
-            std::vector<uint64_t> hmasks((size_t)S * W);
-            e = hipMemcpyAsync(hmasks.data(), sc->masks, mask_bytes, hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("mask download: ") + hipGetErrorString(e));
             if (P.mode == SC_MASK_LUT) {
                 const uint32_t K = P.codebook_size;
                 t0 = std::chrono::steady_clock::now();
-                std::vector<uint64_t> cb;
-                select_codebook(hmasks.data(), B.cbox.data(), S, R, K, cb);
+                std::vector<uint64_t> cb, chosen;
+                const size_t ws_bytes = codebook_workspace_bytes(S, R, K);
+                void* ws = dev_alloc(ctx, ws_bytes, s);
+                if (!ws) return bail(SC_ERR_OOM, "codebook workspace");
+                e = select_codebook_device(sc->nodes, stride, sc->masks, S, R, K, ws, chosen, s);
+                dev_free(ctx, ws, ws_bytes, s);
+                if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("codebook: ") + hipGetErrorString(e));
+                finish_codebook(chosen, R, K, cb);
                 // entries are sorted by set bits: the first one denser than test_max (the full
                 // mask by default) starts the untested ones
                 sc->full_start = K;
@@ -561,6 +563,10 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                 if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("compression: ") + hipGetErrorString(e));
                 I.ms_compress = ms_since(t0);
             } else {  // SPARSE: gather the placed masks (a full mask counts as none)
+                std::vector<uint64_t> hmasks((size_t)S * W);
+                e = hipMemcpyAsync(hmasks.data(), sc->masks, mask_bytes, hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("mask download: ") + hipGetErrorString(e));
                 n_masked = 0;
                 for (uint32_t q = 0; q < S; ++q) {
                     if (side_of_slot[q] == kNoMask) continue;

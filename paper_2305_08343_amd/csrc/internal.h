@@ -89,10 +89,16 @@ constexpr uint32_t kMaxStack4 = 128;   // traversal stack entries per ray for th
 sc_status build_bvh(const float* tris, uint32_t n, uint32_t leaf_max, uint32_t bins,
                     uint32_t depth_cap, HostBVH& out);
 
-// Codebook of K masks (Eq. 2 importance, Sect. 3.2.2), sorted by set-bit
-// count then value. slot_boxes [S][6] lo.xyz hi.xyz.
-void select_codebook(const uint64_t* masks, const float* slot_boxes, size_t S, uint32_t R,
-                     uint32_t K, std::vector<uint64_t>& cb);
+// Codebook of K masks (Eq. 2 importance, Sect. 3.2.2) in two steps: on the device, the up to K-1
+// most important distinct masks other than the full one (importance descending, ties by value
+// ascending; slot s's box is child s & 1 of binary node s >> 1 in `nodes`), returned as `chosen`
+// (W words each), with codebook_workspace_bytes(S, R, K) bytes of device workspace; then on the
+// host, the full mask appended up to K entries and the whole sorted by set-bit count then value.
+size_t codebook_workspace_bytes(uint32_t S, uint32_t R, uint32_t K);
+hipError_t select_codebook_device(const unsigned char* nodes, uint32_t stride, const uint64_t* masks, uint32_t S,
+                                  uint32_t R, uint32_t K, void* workspace, std::vector<uint64_t>& chosen,
+                                  hipStream_t s);
+void finish_codebook(const std::vector<uint64_t>& chosen, uint32_t R, uint32_t K, std::vector<uint64_t>& cb);
 
 // ------------------------------------------------------ kernel launchers
 // One scene's share of a batched launch (device-resident descriptor).
@@ -184,6 +190,13 @@ size_t scratch_counter_bytes();
 bool scratch_fits_sort(uint32_t n);
 // ray order by Morton code of the origin in [lo, hi] (stable radix sort); *order points into workspace
 size_t ray_order_workspace_bytes(uint32_t n);
+// Stable LSD radix sort (8 bits a pass, from bit 0) of the n (key, value) pairs held in the first
+// two n-word arrays of `workspace` (ray_order_workspace_bytes(n) bytes); returns the sorted values,
+// which an even number of passes leaves in the second array.
+uint32_t* sort_pairs_u32(void* workspace, uint32_t n, uint32_t passes, hipStream_t s);
+// Exclusive prefix sum of a[m] in place; `sums` holds scan_u32_sums(m) words of scratch.
+size_t scan_u32_sums(size_t m);
+hipError_t exclusive_scan_u32(uint32_t* a, size_t m, uint32_t* sums, hipStream_t s);
 hipError_t launch_ray_order(const float* rays, uint32_t n, const float lo[3], const float hi[3], void* workspace,
                             uint32_t** order, hipStream_t s);
 // batched launches: the n rays of n_items (<= kBatchSortItems) descriptors (sorted by ray_begin)

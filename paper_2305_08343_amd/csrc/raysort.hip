@@ -239,6 +239,26 @@ uint32_t* sort_pairs(void* workspace, uint32_t n, uint32_t passes, hipStream_t s
     return vin;
 }
 
+}  // namespace
+
+uint32_t* sort_pairs_u32(void* workspace, uint32_t n, uint32_t passes, hipStream_t s) {
+    return sort_pairs(workspace, n, passes, s);
+}
+
+size_t scan_u32_sums(size_t m) { return (m + kScanTile - 1) / kScanTile; }
+
+hipError_t exclusive_scan_u32(uint32_t* a, size_t m, uint32_t* sums, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    const size_t nb = scan_u32_sums(m);
+    if (nb > 0xFFFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3((uint32_t)nb), dim3(kSortThreads), 0, s, a, m, sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kSortThreads), 0, s, sums, (uint32_t)nb);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((uint32_t)nb), dim3(kSortThreads), 0, s, a, m, sums);
+    return hipGetLastError();
+}
+
+namespace {
+
 bool sort_fits(uint32_t n) {
     const size_t ntiles = ((size_t)n + kSortTile - 1) / kSortTile;
     const size_t nb = (ntiles * kDigits + kScanTile - 1) / kScanTile;
