@@ -312,6 +312,32 @@ def micro_scene(seed: int, n: int) -> np.ndarray:
     return t
 
 
+def lattice_copies(kinds: int) -> np.ndarray:
+    """Translated copies of `kinds` small random triangles on a 16 x 16 x 8 lattice of spacing 1/8:
+    many child slots share one mask."""
+    rng = np.random.default_rng(kinds)
+    shapes = rng.uniform(0.0, 0.08, size=(kinds, 3, 3)).astype(np.float32)
+    g = np.stack(np.meshgrid(np.arange(16), np.arange(16), np.arange(8), indexing="ij"), -1).reshape(-1, 3)
+    tris = shapes[np.arange(g.shape[0]) % kinds] + (g.astype(np.float32) * np.float32(0.125))[:, None, :]
+    return np.ascontiguousarray(tris, np.float32)
+
+
+def segment_rows(seed: int) -> np.ndarray:
+    """Zero-area triangles along x (3 to 12 per row) in 10 x 10 rows of constant (y, z): leaf boxes
+    are line segments of surface area 0, so many distinct masks have importance 0."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for y in range(10):
+        for z in range(10):
+            n = int(rng.integers(3, 13))
+            x0 = np.sort(rng.uniform(0, 1, n)).astype(np.float32)
+            ln = rng.uniform(0.01, 0.1, n).astype(np.float32)
+            for a, l in zip(x0, ln):
+                v0 = np.array([a, y * 0.2, z * 0.2], np.float32)
+                out.append([v0, v0 + np.array([l, 0, 0], np.float32), v0 + np.array([l * 0.5, 0, 0], np.float32)])
+    return np.ascontiguousarray(np.array(out, np.float32))
+
+
 @dataclass(frozen=True)
 class BatchSpec:
     seed: int

@@ -181,9 +181,33 @@ def test_micro_scenes_bit_exact(ctx, seed):
                 kw.update(mode="raw", R=R, masks=m)
             else:
                 cb, idx = oracle.compress(m, bvh.slot_boxes(), R, 64)
+                assert (exp["codebook"] == cb).all() and (exp["cidx"] == idx).all()
                 kw.update(mode="lut", R=R, codebook=cb, cidx=idx)
         _compare_hits(s.trace(rays).numpy(), oracle.trace(tris, bvh, rays, **kw))
         s.close()
+
+
+@pytest.mark.parametrize("scene", ["lattice1", "lattice40", "segments"])
+def test_codebook_selection_matches_oracle(ctx, scene):
+    """Device codebook selection (importance sums per distinct mask in slot order, importance
+    descending, ties by value) against the oracle: one mask shared by hundreds of slots, more
+    distinct masks than K - 1 (lattice of 40 shapes: 94 at R = 4, 118 at R = 6), and the last
+    chosen place falling among distinct masks tied at importance 0 (segments, R = 4, K = 64)."""
+    from paper_2305_08343_amd import binding
+    tris = scenes.segment_rows(0) if scene == "segments" else scenes.lattice_copies(int(scene[7:]))
+    bvh = oracle.bvh_build(tris)
+    _, delta = oracle.default_bounds(tris)
+    for R in (4, 6):
+        m = oracle.object_masks(tris, bvh, R, delta)
+        for K in (64, 256, 4096):
+            print(f"[gpu] codebook {scene} R={R} K={K} slots={m.shape[0]}", flush=True)
+            s = binding.Scene(ctx, tris, R=R, mode="lut", K=K)
+            exp = s.export()
+            s.close()
+            cb, idx = oracle.compress(m, bvh.slot_boxes(), R, K)
+            assert (exp["masks"] == m).all()
+            assert (exp["codebook"] == cb).all()
+            assert (exp["cidx"] == idx).all()
 
 
 def test_degenerate_inputs(ctx, small_scene):

@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paper_2305_08343_amd import scenes
 from tests.conftest import popcount64
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_layout_facts.json")
@@ -74,10 +75,22 @@ def test_alg3_equals_naive_random_codebooks(seed):
         assert pcs[i] == pcs[sup].min()
 
 
-def test_codebook_structure_and_importance(small_oracle):
-    R, K = 6, 256
-    masks = small_oracle["masks6"]
-    boxes = small_oracle["bvh"].slot_boxes()
+def _scene_masks(name, R, small_oracle):
+    if name == "small":
+        return small_oracle[f"masks{R}"], small_oracle["bvh"].slot_boxes()
+    tris = scenes.segment_rows(0) if name == "segments" else scenes.lattice_copies(40)
+    bvh = oracle.bvh_build(tris)
+    _, delta = oracle.default_bounds(tris)
+    return oracle.object_masks(tris, bvh, R, delta), bvh.slot_boxes()
+
+
+@pytest.mark.parametrize("name,R,K", [("small", 6, 256), ("small", 4, 64), ("segments", 6, 64),
+                                      ("segments", 4, 64), ("lattice40", 6, 64), ("lattice40", 4, 64)])
+def test_codebook_structure_and_importance(small_oracle, name, R, K):
+    """Ranking recomputed from its definition. Segment rows: at R = 4 and K = 64 the last chosen
+    place falls among three distinct masks tied at importance 0, so the value order decides it;
+    the lattice has more distinct masks than K - 1."""
+    masks, boxes = _scene_masks(name, R, small_oracle)
     cb = oracle.codebook(masks, boxes, R, K)
     full = _full(R)
     assert (cb == full).all(axis=1).any()
@@ -99,6 +112,8 @@ def test_codebook_structure_and_importance(small_oracle):
         assert got == want
     else:
         assert got == set(acc)
+    # padding: the full mask fills every entry the chosen patterns leave
+    assert int((cb == full).all(axis=1).sum()) == K - min(len(acc), K - 1)
 
 
 def test_paper_layout_facts():
