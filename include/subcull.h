@@ -419,10 +419,11 @@ sc_status sc_compress_masks(sc_ctx* ctx, uint32_t R, const uint64_t* d_codebook,
 /* 12 float features per child slot (d_out [2*n_inner][12], device), for a
  * scene built with masks (RAW, LUT or SPARSE): extents relative to the parent
  * box (x, y, z), log2(area / root area) / 32, parent depth / tree depth,
- * log2(1 + triangles) / 24, occupied fraction of its exact mask, and the
- * means over its triangles of thinness (1 - 4 sqrt(3) area / sum of squared
- * edges) and of |cos| between the longest edge and the x, y, z axes, then
- * 1 if the child is a leaf. Synchronises `stream`. */
+ * log2(1 + triangles) / 24, occupied fraction of its exact mask, the mean
+ * over its triangles of thinness (1 - 4 sqrt(3) area / sum of squared
+ * edges), the centre of its box relative to the root box (x, y, z: 0 at the
+ * root's low face, 1 at its high face; 0 on an axis where the root is flat),
+ * then 1 if the child is a leaf. Synchronises `stream`. */
 sc_status sc_slot_features(const sc_scene* scene, float* d_out, void* stream);
 
 /* y[n] = MLP(x[n][12]); d_act [n][128] receives both pre-activation layers

@@ -8,7 +8,8 @@ library header for the same list):
   5    log2(1 + triangles under the child) / 24
   6    set bits of the child's exact mask / R^3
   7    mean thinness 1 - 4 sqrt(3) area / (sum of squared edges), clipped to [0, 1]
-  8-10 mean |cos| between each triangle's longest edge and the x, y, z axes
+  8-10 centre of the child box relative to the root box per axis: (mid - root lo) / root
+       extent, 0 where the root box is flat on that axis
   11   1 if the child is a leaf
 """
 from __future__ import annotations
@@ -16,8 +17,9 @@ from __future__ import annotations
 import numpy as np
 
 
-def tri_shape(tris):
-    """[n, 4]: thinness and |cos| of the longest edge with x, y, z (float64)."""
+def tri_thinness(tris):
+    """[n]: 1 - 4 sqrt(3) area / (sum of squared edge lengths), clipped to [0, 1]; 1 when the
+    edges have zero length (float64)."""
     v = np.asarray(tris, np.float64)
     e = np.stack([v[:, 1] - v[:, 0], v[:, 2] - v[:, 1], v[:, 0] - v[:, 2]], 1)  # [n, 3 edges, 3]
     l2 = (e * e).sum(-1)
@@ -25,13 +27,7 @@ def tri_shape(tris):
     s = l2.sum(-1)
     with np.errstate(invalid="ignore", divide="ignore"):
         thin = np.where(s > 0, 1.0 - 4.0 * np.sqrt(3.0) * area / s, 1.0)
-    thin = np.clip(thin, 0.0, 1.0)
-    k = np.argmax(l2, axis=1)  # first longest edge on ties
-    longest = e[np.arange(v.shape[0]), k]
-    ln = np.sqrt(l2[np.arange(v.shape[0]), k])
-    with np.errstate(invalid="ignore", divide="ignore"):
-        cosv = np.where(ln[:, None] > 0, np.abs(longest) / ln[:, None], 0.0)
-    return np.concatenate([thin[:, None], cosv], 1)
+    return np.clip(thin, 0.0, 1.0)
 
 
 def slot_features(tris, bvh, masks, R):
@@ -55,9 +51,11 @@ def slot_features(tris, bvh, masks, R):
         d = hi - lo
         return 2.0 * ((d[..., 0] * d[..., 1] + d[..., 1] * d[..., 2]) + d[..., 2] * d[..., 0])
 
-    root_area = area(plo[0], phi[0])
-    shape = tri_shape(np.asarray(tris)[bvh.perm])  # leaf order
-    pre = np.concatenate([np.zeros((1, 4)), np.cumsum(shape, 0)], 0)
+    root_lo, root_hi = plo[0], phi[0]
+    root_area = area(root_lo, root_hi)
+    root_ext = root_hi - root_lo
+    thin = tri_thinness(np.asarray(tris)[bvh.perm])  # leaf order
+    pre = np.concatenate([[0.0], np.cumsum(thin)])
     m = np.ascontiguousarray(masks, np.uint64)
     pc = np.unpackbits(m.view(np.uint8), axis=-1).reshape(m.shape[0], -1).sum(-1)
     for s in range(S):
@@ -74,6 +72,8 @@ def slot_features(tris, bvh, masks, R):
             first, count = (int(x) for x in bvh.range[ref])
         out[s, 5] = np.log2(1.0 + count) / 24.0
         out[s, 6] = pc[s] / R ** 3
-        out[s, 7:11] = (pre[first + count] - pre[first]) / count
+        out[s, 7] = (pre[first + count] - pre[first]) / count
+        mid = (lo + hi) * 0.5
+        out[s, 8:11] = np.where(root_ext > 0, (mid - root_lo) / np.where(root_ext > 0, root_ext, 1.0), 0.0)
         out[s, 11] = 1.0 if ref & 0x80000000 else 0.0
     return out

@@ -1192,15 +1192,17 @@ sc_status sc_slot_features(const sc_scene* scene, float* d_out, void* stream) {
             const uint32_t r = B.cref[2 * (size_t)i + c];
             if (!(r & kLeafBit)) depth[r] = (uint8_t)(depth[i] + 1);
         }
-    double lo[3], hi[3];
+    RootBox root{};
     for (int j = 0; j < 3; ++j) {
-        lo[j] = std::min(B.cbox[j], B.cbox[6 + j]);
-        hi[j] = std::max(B.cbox[3 + j], B.cbox[9 + j]);
+        root.lo[j] = std::min(B.cbox[j], B.cbox[6 + j]);
+        root.hi[j] = std::max(B.cbox[3 + j], B.cbox[9 + j]);
     }
-    const double root_area = 2.0 * (((hi[0] - lo[0]) * (hi[1] - lo[1]) + (hi[1] - lo[1]) * (hi[2] - lo[2])) +
-                                     (hi[2] - lo[2]) * (hi[0] - lo[0]));
+    const double* lo = root.lo;
+    const double* hi = root.hi;
+    root.area = 2.0 * (((hi[0] - lo[0]) * (hi[1] - lo[1]) + (hi[1] - lo[1]) * (hi[2] - lo[2])) +
+                       (hi[2] - lo[2]) * (hi[0] - lo[0]));
     const uint32_t n = I.n_tris;
-    const size_t pre_bytes = (size_t)4 * n * 8, scr_bytes = scan_scratch_doubles(n, 4) * 8;
+    const size_t pre_bytes = (size_t)n * 8, scr_bytes = scan_scratch_doubles(n, 1) * 8;
     const size_t rng_bytes = B.range.size() * 4;
     auto* d_pre = static_cast<double*>(dev_alloc(ctx, pre_bytes, s));
     auto* d_scr = static_cast<double*>(dev_alloc(ctx, scr_bytes, s));
@@ -1210,10 +1212,10 @@ sc_status sc_slot_features(const sc_scene* scene, float* d_out, void* stream) {
     if (e == hipSuccess) e = hipMemcpyAsync(d_rng, B.range.data(), rng_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_dep, depth.data(), depth.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_tri_shape(scene->tris, n, d_pre, s);
-    if (e == hipSuccess) e = launch_prefix_scan(d_pre, n, 4, d_scr, s);
+    if (e == hipSuccess) e = launch_prefix_scan(d_pre, n, 1, d_scr, s);
     if (e == hipSuccess)
-        e = launch_slot_features(I.R, scene->nodes, scene->stride2, d_rng, d_dep, I.depth, scene->masks, d_pre, n,
-                                 root_area, I.n_inner, d_out, s);
+        e = launch_slot_features(I.R, scene->nodes, scene->stride2, d_rng, d_dep, I.depth, scene->masks, d_pre, root,
+                                 I.n_inner, d_out, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     dev_free(ctx, d_pre, pre_bytes, s);
     dev_free(ctx, d_scr, scr_bytes, s);

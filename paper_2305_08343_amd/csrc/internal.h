@@ -235,12 +235,17 @@ hipError_t launch_pack4(uint32_t mode, uint32_t R, const uint32_t* src4, uint32_
 
 // learned placement
 constexpr int kMlpParams = SC_MLP_PARAMS;
+// per-triangle thinness [n] (leaf order), float64
 hipError_t launch_tri_shape(const float* rec, uint32_t n, double* out, hipStream_t s);
 size_t scan_scratch_doubles(uint32_t n, uint32_t rows);
 hipError_t launch_prefix_scan(double* a, uint32_t n, uint32_t rows, double* scratch, hipStream_t s);
+// the root box (union of the root's child boxes) and its surface area, for the slot features
+struct RootBox {
+    double lo[3], hi[3], area;
+};
 hipError_t launch_slot_features(uint32_t R, const unsigned char* nodes, uint32_t stride, const uint32_t* range,
                                 const uint8_t* depth, uint32_t max_depth, const uint64_t* masks,
-                                const double* prefix, uint32_t n, double root_area, uint32_t n_inner, float* out,
+                                const double* prefix, const RootBox& root, uint32_t n_inner, float* out,
                                 hipStream_t s);
 hipError_t launch_mlp_forward(const float* prm, const float* x, uint32_t n, float* y, float* act, hipStream_t s);
 hipError_t launch_mlp_backward(const float* prm, const float* x, const float* act, const float* y, const float* t,

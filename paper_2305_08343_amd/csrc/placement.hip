@@ -29,9 +29,8 @@ inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n + b - 1)
 // ---------------------------------------------------------------- features
 // Per triangle (leaf order, from the traversal's records v0, e1 = v1 - v0,
 // e2 = v2 - v0): thinness 1 - 4*sqrt(3)*area / (sum of squared edge
-// lengths) (0 for an equilateral triangle, 1 when degenerate) and |cos| of
-// the longest edge with the x, y and z axes.
-__global__ void tri_shape_kernel(const float* __restrict__ rec, uint32_t n, double* __restrict__ out /*[4][n]*/) {
+// lengths), 0 for an equilateral triangle, 1 when degenerate.
+__global__ void tri_shape_kernel(const float* __restrict__ rec, uint32_t n, double* __restrict__ out /*[n]*/) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float* r = rec + 12 * (size_t)i;
@@ -48,14 +47,8 @@ __global__ void tri_shape_kernel(const float* __restrict__ rec, uint32_t n, doub
     const float cz = e[0][0] * e[1][1] - e[0][1] * e[1][0];
     const float area = 0.5f * sqrtf(cx * cx + cy * cy + cz * cz);
     const float s = l2[0] + l2[1] + l2[2];
-    float thin = (s > 0.0f) ? 1.0f - 4.0f * 1.7320508075688772f * area / s : 1.0f;
-    thin = fminf(fmaxf(thin, 0.0f), 1.0f);
-    int kmax = 0;
-    if (l2[1] > l2[kmax]) kmax = 1;
-    if (l2[2] > l2[kmax]) kmax = 2;
-    const float len = sqrtf(l2[kmax]);
-    out[i] = thin;
-    for (int j = 0; j < 3; ++j) out[(size_t)(j + 1) * n + i] = (len > 0.0f) ? fabsf(e[kmax][j]) / len : 0.0f;
+    const float thin = (s > 0.0f) ? 1.0f - 4.0f * 1.7320508075688772f * area / s : 1.0f;
+    out[i] = fminf(fmaxf(thin, 0.0f), 1.0f);
 }
 
 // Inclusive prefix sums of `rows` arrays of n doubles, in place, three
@@ -129,8 +122,8 @@ template <int W>
 __global__ void slot_feature_kernel(const unsigned char* __restrict__ nodes, uint32_t stride,
                                     const uint32_t* __restrict__ range, const uint8_t* __restrict__ depth,
                                     uint32_t max_depth, const uint64_t* __restrict__ masks, uint32_t R3,
-                                    const double* __restrict__ prefix /*[4][n] inclusive*/, uint32_t n,
-                                    double root_area, uint32_t n_inner, float* __restrict__ out) {
+                                    const double* __restrict__ prefix /*[n] inclusive*/, RootBox root,
+                                    uint32_t n_inner, float* __restrict__ out) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= 2 * n_inner) return;
     const uint32_t node = s >> 1, c = s & 1;
@@ -148,7 +141,7 @@ __global__ void slot_feature_kernel(const unsigned char* __restrict__ nodes, uin
         const float pe = phi[j] - plo[j];
         f[j] = (pe > 0.0f) ? (hi[j] - lo[j]) / pe : 0.0f;
     }
-    const double ratio = box_area(lo, hi) / root_area;
+    const double ratio = box_area(lo, hi) / root.area;
     f[3] = (float)(log2(fmax(ratio, 0x1p-40)) / 32.0);
     f[4] = (float)depth[node] / (float)max_depth;
     uint32_t first, count;
@@ -163,10 +156,13 @@ __global__ void slot_feature_kernel(const unsigned char* __restrict__ nodes, uin
     int pc = 0;
     for (int w = 0; w < W; ++w) pc += __popcll(masks[(size_t)s * W + w]);
     f[6] = (float)pc / (float)R3;
-    for (int q = 0; q < 4; ++q) {
-        const double* p = prefix + (size_t)q * n;
-        const double sum = p[first + count - 1] - (first ? p[first - 1] : 0.0);
-        f[7 + q] = (float)(sum / (double)count);
+    const double sum = prefix[first + count - 1] - (first ? prefix[first - 1] : 0.0);
+    f[7] = (float)(sum / (double)count);
+    // where the child sits in the scene: its box centre relative to the root box
+    for (int j = 0; j < 3; ++j) {
+        const double ext = root.hi[j] - root.lo[j];
+        const double mid = ((double)lo[j] + (double)hi[j]) * 0.5;
+        f[8 + j] = (ext > 0.0) ? (float)((mid - root.lo[j]) / ext) : 0.0f;
     }
     f[11] = (ref & kLeafBit) ? 1.0f : 0.0f;
 }
@@ -324,16 +320,16 @@ hipError_t launch_prefix_scan(double* a, uint32_t n, uint32_t rows, double* scra
 
 hipError_t launch_slot_features(uint32_t R, const unsigned char* nodes, uint32_t stride, const uint32_t* range,
                                 const uint8_t* depth, uint32_t max_depth, const uint64_t* masks,
-                                const double* prefix, uint32_t n, double root_area, uint32_t n_inner, float* out,
+                                const double* prefix, const RootBox& root, uint32_t n_inner, float* out,
                                 hipStream_t s) {
     if (n_inner == 0) return hipSuccess;
     const dim3 g(blocks_for(2 * (size_t)n_inner, 256));
     if (R == 4)
         hipLaunchKernelGGL(slot_feature_kernel<1>, g, dim3(256), 0, s, nodes, stride, range, depth, max_depth, masks,
-                           64u, prefix, n, root_area, n_inner, out);
+                           64u, prefix, root, n_inner, out);
     else
         hipLaunchKernelGGL(slot_feature_kernel<4>, g, dim3(256), 0, s, nodes, stride, range, depth, max_depth, masks,
-                           216u, prefix, n, root_area, n_inner, out);
+                           216u, prefix, root, n_inner, out);
     return hipGetLastError();
 }
 

@@ -1,20 +1,20 @@
-"""What the trained placement network gains, on a held-out scene.
+"""What the trained placement network gains, on held-out scenes.
 
 The network is trained on the GPU (the library's forward, backward and Adam
 kernels) on per-slot false-positive counts of 16 generated strand / curly /
 thin-quad scenes (50k-400k tris), then places masks at 0.5, 1 and 2 bytes
-per inner node on a held-out 1M-tri hair scene with 1M rays. Checked:
+per inner node on two held-out 1M-tri scenes (hair, curly) with 1M rays.
+Checked on each:
   * hits are identical under every placement, all masks and no masks;
   * all masks <= any placement <= no masks in tests per ray;
   * the learned placement removes tests at every budget, more at larger
     budgets, at least twice what random placement removes and at least 70% of
     what placement by the true (measured) counts removes;
-  * it stays within 0.5% (in tests per ray) of the surface-area x emptiness
-    heuristic it learns a correction to. It does NOT beat that heuristic: on
-    this scene it trails it by 0.07-0.21 tests/ray at the three budgets (the
-    twelve geometric features carry little beyond area x emptiness, while
-    placement by the true counts is about one test/ray better); the check is
-    written so that this shortfall is visible, not hidden.
+  * it removes more tests than the surface-area x emptiness heuristic it
+    learns a correction to, at every budget. The features that carry what the
+    heuristic misses are the position of the slot's box in the scene (where
+    the rays are denser and less occluded); with triangle-orientation
+    features in their place the network trailed the heuristic slightly.
 Times (rays/s) are printed, not asserted: they depend on the launch.
 """
 import numpy as np
@@ -36,25 +36,27 @@ def test_learned_placement_gain(request):
     from paper_2305_08343_amd import binding, placement, scenes
     ctx = binding.Context(0)
     specs = scenes.placement_specs(16, tri_lo=50_000, tri_hi=400_000, n_rays=131_072)
-    held = [scenes.placement_heldout(0, 1_000_000, 1_000_000)]
+    held = [scenes.placement_heldout(k, 1_000_000, 1_000_000) for k in (0, 1)]
     params, hist, res = placement.run_experiment(ctx, specs, held, epochs=15,
                                                  log=lambda m: _say(request, m))
     ctx.close()
     assert hist[-1] < hist[0]
-    ev = {(e.name, e.beta): e for e in res[0]}
-    none, full = ev[("no_masks", None)], ev[("all_masks", None)]
-    assert all(e.hits_equal for e in res[0])
-    prev = 0.0
-    for beta in (0.5, 1.0, 2.0):
-        L, Rn, T = ev[("learned", beta)], ev[("random", beta)], ev[("true_label", beta)]
-        for e in (L, Rn, T, ev[("heuristic", beta)]):
-            assert full.tests_per_ray <= e.tests_per_ray <= none.tests_per_ray
-        gain = none.tests_per_ray - L.tests_per_ray
-        assert gain > prev
-        assert gain >= 2.0 * (none.tests_per_ray - Rn.tests_per_ray)
-        assert gain >= 0.7 * (none.tests_per_ray - T.tests_per_ray)
-        H = ev[("heuristic", beta)]
-        _say(request, f"beta={beta}: learned - heuristic = {L.tests_per_ray - H.tests_per_ray:+.3f} tests/ray, "
-                      f"true counts - heuristic = {T.tests_per_ray - H.tests_per_ray:+.3f}")
-        assert L.tests_per_ray <= 1.005 * H.tests_per_ray
-        prev = gain
+    for k, evs in enumerate(res):
+        ev = {(e.name, e.beta): e for e in evs}
+        none, full = ev[("no_masks", None)], ev[("all_masks", None)]
+        assert all(e.hits_equal for e in evs)
+        prev = 0.0
+        for beta in (0.5, 1.0, 2.0):
+            L, Rn, T = ev[("learned", beta)], ev[("random", beta)], ev[("true_label", beta)]
+            H = ev[("heuristic", beta)]
+            for e in (L, Rn, T, H):
+                assert full.tests_per_ray <= e.tests_per_ray <= none.tests_per_ray
+            gain = none.tests_per_ray - L.tests_per_ray
+            assert gain > prev
+            assert gain >= 2.0 * (none.tests_per_ray - Rn.tests_per_ray)
+            assert gain >= 0.7 * (none.tests_per_ray - T.tests_per_ray)
+            _say(request, f"held-out {k} beta={beta}: learned - heuristic = "
+                          f"{L.tests_per_ray - H.tests_per_ray:+.3f} tests/ray, "
+                          f"true counts - heuristic = {T.tests_per_ray - H.tests_per_ray:+.3f}")
+            assert L.tests_per_ray < H.tests_per_ray
+            prev = gain
