@@ -280,6 +280,8 @@ def cpu_baseline(tris, rays, target_s, spec):
             kw.update(codebook=cb, cidx=idx)
         else:
             kw.update(masks=masks)
+        if mode == "sparse":
+            kw.update(placed=spec["placed"])
         kw["lut"] = oracle.raymask_lut(R)
     setup = time.perf_counter() - t0
 
@@ -314,6 +316,7 @@ def cpu_baseline(tris, rays, target_s, spec):
         deep, refs = h.deepest, h.cb_refs
     masks_txt = ("no masks (plain traversal)" if mode == "none" else
                  f"{'LUT K=' + str(spec.get('K', 4096)) if mode == 'lut' else mode} masks R={R}"
+                 f"{' on %d placed slots' % int(np.count_nonzero(spec['placed'])) if mode == 'sparse' else ''}"
                  f"{' on leaf slots' if spec.get('mask_slots') == 'leaves' else ''}"
                  f"{', masks of more than %d set bits untested' % spec['test_max'] if spec.get('test_max') else ''}"
                  f", culled")
@@ -488,10 +491,17 @@ def run_placement(args, ctx):
     specs = scenes.placement_specs(args.place_scenes)
     held = [scenes.placement_heldout(k) for k in range(args.place_heldout)]
     log(f"placement: {len(specs)} training scenes, {len(held)} held-out scenes")
-    params, hist, res = placement.run_experiment(ctx, specs, held, log=log)
+    kept = []
+    params, hist, res = placement.run_experiment(ctx, specs, held, log=log, placements_out=kept)
     total_s = time.perf_counter() - t0
     table = [[{k: v for k, v in e.__dict__.items()} for e in r] for r in res]
     head = {(e.name, e.beta): e for e in res[0]}[("learned", 1.0)]
+    # the value's trace: sparse R = 6 masks (64-byte binary nodes, 32-byte side masks) on the held-out
+    # hair scene; the timed traces write hits only
+    n_rays = held[0][1].shape[0]
+    alg = n_rays * (RAY_BYTES + HIT_BYTES) + n_rays * (head.box_per_ray / 2.0 * 64 + head.mask_per_ray * 32 +
+                                                       head.tri_per_ray * TRI_BYTES)
+    alg_gbs = alg / (head.ms * 1e-3) / 1e9
     line = {
         "metric": METRIC, "value": head.rays_per_s, "unit": "rays/s", "n_gpus": 1,
         "steps": 5, "warmup": 1, "ms_per_step": head.ms, "higher_is_better": True, "scaling": "weak",
@@ -502,9 +512,16 @@ def run_placement(args, ctx):
                                "scene with 4M rays (value); all budgets and baselines in 'placement'",
                    "n_train_scenes": len(specs)},
         "tests_per_ray": head.tests_per_ray,
+        "roofline": {"bound": "hbm", "achieved": alg_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "trace_kernel (binary, sparse masks)",
+                     "kernel_ms": head.ms, "alg_bytes_per_launch": alg, "alg_bytes_per_ray": alg / n_rays},
         "train_loss": hist, "seconds_total": total_s,
         "placement": table,
     }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, learned placement at 1 byte per inner node)")
+        spec = {"R": 6, "mode": "sparse", "width": 2, "placed": kept[0][("learned", 1.0)]}
+        line["cpu_baseline"], _ = cpu_baseline(held[0][0], held[0][1], args.cpu_seconds, spec)
     print(json.dumps(line), flush=True)
 
 

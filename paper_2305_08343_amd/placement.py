@@ -182,6 +182,7 @@ class Evaluation:
     ms: float
     rays_per_s: float
     hits_equal: bool
+    mask_per_ray: float = 0.0
 
 
 def evaluate(ctx, tris, rays_dev, placement, ref_hits, *, R: int = 6, name: str = "", beta=None,
@@ -194,8 +195,9 @@ def evaluate(ctx, tris, rays_dev, placement, ref_hits, *, R: int = 6, name: str 
         scene = binding.Scene(ctx, tris, R=R, mode=mode)
     n = rays_dev.shape[0]
     hits = torch.empty((n, 4), dtype=torch.int32, device=rays_dev.device)
-    scene.trace(rays_dev, hits=hits, extra=False)
+    extra = scene.trace(rays_dev, hits=hits, extra=True).extra
     h = hits.cpu().numpy()
+    mask_tests = float(extra[:, 0].double().sum().item()) if n else 0.0
     same = bool(ref_hits is None or ((h[:, 0] == ref_hits[:, 0]).all() and (h[:, 1] == ref_hits[:, 1]).all()))
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
@@ -209,7 +211,8 @@ def evaluate(ctx, tris, rays_dev, placement, ref_hits, *, R: int = 6, name: str 
     scene.close()
     box = h[:, 2].astype(np.float64).sum() / n
     tri = h[:, 3].astype(np.float64).sum() / n
-    return Evaluation(name, beta, int(n_masks), box + tri, box, tri, ms, n / (ms * 1e-3), same)
+    return Evaluation(name, beta, int(n_masks), box + tri, box, tri, ms, n / (ms * 1e-3), same,
+                      mask_tests / max(n, 1))
 
 
 def placeable(scores, X) -> np.ndarray:
@@ -287,9 +290,10 @@ def learned_scores(ctx, params, a: float, X) -> np.ndarray:
 
 
 def evaluate_scene(ctx, params, a, tris, rays, *, betas=(0.5, 1.0, 2.0), seed: int = 0, reps: int = 5,
-                   log=None) -> list:
+                   log=None, placements_out=None) -> list:
     """All placements of one held-out scene: learned, heuristic, random and
-    true-label at each budget, plus all masks (raw) and no masks."""
+    true-label at each budget, plus all masks (raw) and no masks. With a dict
+    `placements_out`, the uint8 placement of each (name, beta) is stored there."""
     import torch
     X, y, info = slot_dataset(ctx, tris, rays)
     S = X.shape[0]
@@ -307,6 +311,8 @@ def evaluate_scene(ctx, params, a, tris, rays, *, betas=(0.5, 1.0, 2.0), seed: i
         M = budget_masks(beta, info["n_inner"])
         for name, pl in placements(scores, M, X).items():
             out.append(evaluate(ctx, tris, rays_dev, pl, ref, name=name, beta=beta, reps=reps))
+            if placements_out is not None:
+                placements_out[(name, beta)] = pl
     if log:
         for e in out:
             log(f"  {e.name:>10} beta={e.beta}: masks {e.n_masks}, tests/ray {e.tests_per_ray:.2f}, "
@@ -315,9 +321,11 @@ def evaluate_scene(ctx, params, a, tris, rays, *, betas=(0.5, 1.0, 2.0), seed: i
 
 
 def run_experiment(ctx, train_specs, heldout, *, betas=(0.5, 1.0, 2.0), epochs: int = 30,
-                   batch: int = 4096, lr: float = 1e-3, max_slots: int = 65536, seed: int = 0, log=None):
+                   batch: int = 4096, lr: float = 1e-3, max_slots: int = 65536, seed: int = 0, log=None,
+                   placements_out=None):
     """Train on the training scenes, evaluate every placement on each held-out
-    (tris, rays) pair. Returns (params, loss history, [[Evaluation]])."""
+    (tris, rays) pair. Returns (params, loss history, [[Evaluation]]); with a list
+    `placements_out`, each held-out scene appends its {(name, beta): placement}."""
     t0 = time.time()
     X, y, a = build_training_set(ctx, train_specs, max_slots=max_slots, log=log)
     if log:
@@ -331,5 +339,9 @@ def run_experiment(ctx, train_specs, heldout, *, betas=(0.5, 1.0, 2.0), epochs: 
     for k, (tris, rays) in enumerate(heldout):
         if log:
             log(f"held-out scene {k}: {tris.shape[0]} tris, {rays.shape[0]} rays")
-        results.append(evaluate_scene(ctx, params, a, tris, rays, betas=betas, seed=seed + k, log=log))
+        kept = {} if placements_out is not None else None
+        results.append(evaluate_scene(ctx, params, a, tris, rays, betas=betas, seed=seed + k, log=log,
+                                      placements_out=kept))
+        if placements_out is not None:
+            placements_out.append(kept)
     return params, hist, results
