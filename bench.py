@@ -272,7 +272,10 @@ def cpu_baseline(tris, rays, target_s, spec):
         bvh = oracle.with_slot_boxes(bvh, b4)
     kw = dict(mode=mode, R=R, origin_bound=ob, test_max=spec.get("test_max", 0))
     if mode != "none":
-        masks = oracle.object_masks(tris, bvh, R, delta, nthreads=cores)
+        if spec.get("approx_levels"):
+            masks = oracle.approx_masks(tris, bvh, R, delta, spec["approx_levels"])
+        else:
+            masks = oracle.object_masks(tris, bvh, R, delta, nthreads=cores)
         if spec.get("mask_slots") == "leaves":
             masks = oracle.leaf_slot_masks(masks, bvh, R)
         if mode == "lut":
@@ -317,6 +320,7 @@ def cpu_baseline(tris, rays, target_s, spec):
     masks_txt = ("no masks (plain traversal)" if mode == "none" else
                  f"{'LUT K=' + str(spec.get('K', 4096)) if mode == 'lut' else mode} masks R={R}"
                  f"{' on %d placed slots' % int(np.count_nonzero(spec['placed'])) if mode == 'sparse' else ''}"
+                 f"{' built by Alg. 2 at L = %d' % spec['approx_levels'] if spec.get('approx_levels') else ''}"
                  f"{' on leaf slots' if spec.get('mask_slots') == 'leaves' else ''}"
                  f"{', masks of more than %d set bits untested' % spec['test_max'] if spec.get('test_max') else ''}"
                  f", culled")
@@ -541,7 +545,7 @@ def run_approx(args, ctx):
             ctx.set_tune(*MODES[f"raw{R}w4"]["tune"])
             sc = binding.Scene(ctx, tris, R=R, mode="raw", width=4, approx_levels=L)
             ms_masks = sc.info["ms_masks"]
-            sc.trace(rays_dev, hits=hits, extra=False)
+            ex = sc.trace(rays_dev, hits=hits, extra=True).extra.cpu().numpy()
             torch.cuda.synchronize()
             h = hits.cpu().numpy()
             evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -555,8 +559,12 @@ def run_approx(args, ctx):
             sc.close()
             tests = (h[:, 2].astype(np.float64).sum() + h[:, 3].astype(np.float64).sum()) / n
             key = f"R{R}_L{L if L else 'exact'}"
+            # the timed traces write hits only: the byte model without the mask counters
+            alg = algorithmic_bytes(h[:, 2].view(np.uint32), h[:, 3].view(np.uint32), ex[:, 0].view(np.uint32), n,
+                                    mode_spec(f"raw{R}w4")) - n * EXTRA_BYTES
             table[key] = {"mask_build_ms": ms_masks, "tests_per_ray": tests, "trace_ms": ms,
-                          "rays_per_s": n / (ms * 1e-3)}
+                          "rays_per_s": n / (ms * 1e-3), "alg_bytes_per_launch": alg,
+                          "alg_gbs": alg / (ms * 1e-3) / 1e9}
             log(f"approx {key}: masks {ms_masks:.2f} ms, {tests:.2f} tests/ray, {n / ms / 1e3:.1f} Mrays/s")
     for R in (4, 6):
         base = table[f"R{R}_L1"]
@@ -572,8 +580,18 @@ def run_approx(args, ctx):
         "config": {"workload": "approx: hair_1m (1,000,002 tris, 4,147,200 rays), 4-wide BVH, raw masks built by "
                                "Alg. 2 at L = 1..5 or exactly; value = R=6, L=3", "n_tris": int(tris.shape[0]),
                    "n_rays": n},
+        "roofline": {"bound": "hbm", "achieved": head["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": head["alg_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "trace_kernel (4-wide, raw R=6 masks)", "kernel_ms": head["trace_ms"],
+                     "alg_bytes_per_launch": head["alg_bytes_per_launch"],
+                     "alg_bytes_per_ray": head["alg_bytes_per_launch"] / n},
         "approx": table,
     }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, R=6 masks by Alg. 2 at L=3)")
+        spec = dict(mode_spec("raw6w4"))
+        spec["approx_levels"] = 3
+        line["cpu_baseline"], _ = cpu_baseline(tris, rays, args.cpu_seconds, spec)
     print(json.dumps(line), flush=True)
 
 
