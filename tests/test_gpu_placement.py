@@ -40,6 +40,29 @@ def test_slot_features_match_oracle(ctx, small_scene, small_oracle, R):
     assert np.allclose(f, ref, rtol=1e-4, atol=2e-5), np.abs(f - ref).max(0)
 
 
+@pytest.mark.parametrize("name", ["segments", "flat"])
+def test_slot_features_of_degenerate_boxes_match_oracle(ctx, name):
+    """Zero-area triangles along x (leaf boxes are segments: extent ratios 0 on y and z, areas
+    clamped at 2^-40 of the root's) and a scene flat in z (position 0 on the flat axis)."""
+    from paper_2305_08343_amd import scenes
+    tris = scenes.segment_rows(0)
+    if name == "flat":
+        tris = scenes.lattice_copies(5)
+        tris[..., 2] = np.float32(0.5)
+    print(f"[gpu] features of {name}", flush=True)
+    bvh = oracle.bvh_build(tris)
+    _, delta = oracle.default_bounds(tris)
+    m = oracle.object_masks(tris, bvh, 6, delta)
+    s = binding.Scene(ctx, tris, R=6, mode="raw")
+    f = s.features().cpu().numpy()
+    s.close()
+    ref = ofeat.slot_features(tris, bvh, m, 6)
+    assert f.shape == ref.shape
+    assert np.allclose(f, ref, rtol=1e-4, atol=2e-5), np.abs(f - ref).max(0)
+    if name == "flat":
+        assert (f[:, 10] == 0.0).all()
+
+
 def test_mlp_forward_and_gradients_match_oracle(ctx):
     import torch
     rng = np.random.default_rng(0)
