@@ -20,10 +20,12 @@
  *    they pass in; a scene owns the memory it allocates.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Traces are asynchronous on that stream and never synchronise the host;
- *    scene builds synchronise (the BVH and the codebook are built on the
- *    host).
+ *    scene builds synchronise (the BVH is built on the host, and the
+ *    codebook's selection is read back to finish it there).
  *  - An asynchronous HIP failure is reported as SC_ERR_HIP by the call that
- *    observes it.
+ *    observes it; memory that the allocator or the HIP runtime cannot provide
+ *    is SC_ERR_OOM, returned before any kernel would use the missing buffer,
+ *    and the call releases what it had allocated.
  */
 #ifndef SUBCULL_H
 #define SUBCULL_H

@@ -186,15 +186,34 @@ class Context:
     """An sc_ctx on one device; scene memory comes from torch's allocator.
 
     ``checks=True`` (or the environment variable SUBCULL_DEBUG=1 when ``checks`` is None) runs
-    the traversal kernels with device checks; ``check_flags()`` reads what failed."""
+    the traversal kernels with device checks; ``check_flags()`` reads what failed.
+    ``allocator=(alloc, free)`` routes the library's device memory through two callables instead:
+    ``alloc(nbytes, stream) -> int`` (a device address usable on the stream handle, or 0 when the
+    memory cannot be had) and ``free(ptr, nbytes, stream)``."""
 
-    def __init__(self, device: int = 0, torch_memory: bool = True, checks=None):
+    def __init__(self, device: int = 0, torch_memory: bool = True, checks=None, allocator=None):
         import torch
         lib = load()
         self.device = device
         self._keep = []
         alloc_p = None
-        if torch_memory:
+        if allocator is not None:
+            user_alloc, user_free = allocator
+
+            def _alloc(nbytes, stream, user):
+                try:
+                    return user_alloc(int(nbytes), stream or 0) or None
+                except Exception:
+                    return None
+
+            def _free(ptr, nbytes, stream, user):
+                user_free(ptr, int(nbytes), stream or 0)
+
+            fa, ff = _ALLOC_FN(_alloc), _FREE_FN(_free)
+            self._keep += [fa, ff]
+            self._alloc = sc_allocator(C.cast(fa, C.c_void_p), C.cast(ff, C.c_void_p), None)
+            alloc_p = C.byref(self._alloc)
+        elif torch_memory:
             def _alloc(nbytes, stream, user):
                 try:
                     return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream or 0)

@@ -68,8 +68,11 @@ sc_status fail(sc_status s, const std::string& msg) {
     return s;
 }
 
+// a HIP error as a status: memory the runtime could not provide is SC_ERR_OOM
+sc_status hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? SC_ERR_OOM : SC_ERR_HIP; }
+
 sc_status hip_fail(hipError_t e, const char* what) {
-    return fail(SC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return fail(hip_status(e), std::string(what) + ": " + hipGetErrorString(e));
 }
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -436,7 +439,7 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
     if (!sc->nodes || !sc->tris) return bail(SC_ERR_OOM, "scene allocation failed");
     hipError_t e = hipMemcpyAsync(sc->nodes, nodes.data(), nodes.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(sc->tris, rec.data(), rec.size() * 4, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("scene upload: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return bail(hip_status(e), std::string("scene upload: ") + hipGetErrorString(e));
 
     if (P.mode != SC_MASK_NONE) {
         st = ensure_lut(ctx, R, s);
@@ -504,12 +507,12 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         dev_free(ctx, d_perm, (size_t)n * 4, s);
         dev_free(ctx, d_range, B.range.size() * 4, s);
-        if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("object masks: ") + hipGetErrorString(e));
+        if (e != hipSuccess) return bail(hip_status(e), std::string("object masks: ") + hipGetErrorString(e));
         I.ms_masks = ms_since(t0);
 
         if (P.mode == SC_MASK_RAW) {
             e = launch_pack_raw(R, sc->masks, B.n_inner, test_max, sc->nodes, s);
-            if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("pack: ") + hipGetErrorString(e));
+            if (e != hipSuccess) return bail(hip_status(e), std::string("pack: ") + hipGetErrorString(e));
         } else {
             if (P.mode == SC_MASK_LUT) {
                 const uint32_t K = P.codebook_size;
@@ -520,7 +523,7 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                 if (!ws) return bail(SC_ERR_OOM, "codebook workspace");
                 e = select_codebook_device(sc->nodes, stride, sc->masks, S, R, K, ws, chosen, s);
                 dev_free(ctx, ws, ws_bytes, s);
-                if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("codebook: ") + hipGetErrorString(e));
+                if (e != hipSuccess) return bail(hip_status(e), std::string("codebook: ") + hipGetErrorString(e));
                 finish_codebook(chosen, R, K, cb);
                 // entries are sorted by set bits: the first one denser than test_max (the full
                 // mask by default) starts the untested ones
@@ -560,13 +563,13 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                 }
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
                 dev_free(ctx, d_req, req_bytes, s);
-                if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("compression: ") + hipGetErrorString(e));
+                if (e != hipSuccess) return bail(hip_status(e), std::string("compression: ") + hipGetErrorString(e));
                 I.ms_compress = ms_since(t0);
             } else {  // SPARSE: gather the placed masks (a full mask counts as none)
                 std::vector<uint64_t> hmasks((size_t)S * W);
                 e = hipMemcpyAsync(hmasks.data(), sc->masks, mask_bytes, hipMemcpyDeviceToHost, s);
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
-                if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("mask download: ") + hipGetErrorString(e));
+                if (e != hipSuccess) return bail(hip_status(e), std::string("mask download: ") + hipGetErrorString(e));
                 n_masked = 0;
                 for (uint32_t q = 0; q < S; ++q) {
                     if (side_of_slot[q] == kNoMask) continue;
@@ -579,14 +582,14 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
                 for (uint32_t i = 0; i < B.n_inner; ++i)
                     std::memcpy(nodes.data() + (size_t)i * stride + 56, &side_of_slot[2 * (size_t)i], 8);
                 e = hipMemcpyAsync(sc->nodes, nodes.data(), nodes.size(), hipMemcpyHostToDevice, s);
-                if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("node upload: ") + hipGetErrorString(e));
+                if (e != hipSuccess) return bail(hip_status(e), std::string("node upload: ") + hipGetErrorString(e));
                 for (uint32_t q = 0; q < S; ++q)
                     if (side_of_slot[q] != kNoMask)
                         std::memcpy(&side[(size_t)side_of_slot[q] * W], &hmasks[(size_t)q * W], W * 8);
                 sc->side_masks = scene_alloc<uint64_t>(sc, side.size() * 8, s);
                 if (!sc->side_masks) return bail(SC_ERR_OOM, "sparse mask allocation failed");
                 e = hipMemcpyAsync(sc->side_masks, side.data(), side.size() * 8, hipMemcpyHostToDevice, s);
-                if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("sparse upload: ") + hipGetErrorString(e));
+                if (e != hipSuccess) return bail(hip_status(e), std::string("sparse upload: ") + hipGetErrorString(e));
             }
         }
     }
@@ -614,7 +617,7 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
             e = hipMemcpyAsync(sc->nodes4, n4.data(), n4.size(), hipMemcpyHostToDevice, s);
             if (e == hipSuccess) e = hipMemcpyAsync(sc->src4, B4.src.data(), B4.src.size() * 4, hipMemcpyHostToDevice, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);  // n4 is a host temporary
-            if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("4-wide upload: ") + hipGetErrorString(e));
+            if (e != hipSuccess) return bail(hip_status(e), std::string("4-wide upload: ") + hipGetErrorString(e));
             if (P.mode == SC_MASK_RAW) {
                 sc->masks4 = scene_alloc<uint64_t>(sc, (size_t)B4.n4 * 4 * W * 8, s);
                 if (!sc->masks4) return bail(SC_ERR_OOM, "4-wide mask allocation failed");
@@ -622,12 +625,12 @@ sc_status sc_scene_build(sc_ctx* ctx, const float* d_tris, uint32_t n, const sc_
             if (P.mode == SC_MASK_RAW || P.mode == SC_MASK_LUT) {
                 e = launch_pack4(P.mode, R, sc->src4, B4.n4, sc->masks, sc->cidx_trace, test_max, sc->nodes4,
                                  sc->masks4, sc->quant4, s);
-                if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("4-wide pack: ") + hipGetErrorString(e));
+                if (e != hipSuccess) return bail(hip_status(e), std::string("4-wide pack: ") + hipGetErrorString(e));
             }
         }
     }
     e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return bail(SC_ERR_HIP, std::string("scene build: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return bail(hip_status(e), std::string("scene build: ") + hipGetErrorString(e));
     *out = sc;
     return SC_OK;
 }
