@@ -44,9 +44,21 @@ class Refusing:
         return sorted(self.live.values())
 
 
-def _build(ctx, tris):
+BUILDS = {
+    "lut6w4b": dict(R=6, mode="lut", K=256, width=4, bit_table=True),
+    "raw6w4": dict(R=6, mode="raw", width=4),
+    "raw4_approx3": dict(R=4, mode="raw", approx_levels=3),
+    "sparse6": dict(R=6, mode="sparse"),
+    "none4q": dict(R=6, mode="none", width=4, quantise=True),
+}
+
+
+def _build(ctx, tris, name, placement=None):
     from paper_2305_08343_amd import binding
-    return binding.Scene(ctx, tris, R=6, mode="lut", K=256, width=4, bit_table=True)
+    kw = dict(BUILDS[name])
+    if name == "sparse6":
+        kw["placement"] = placement
+    return binding.Scene(ctx, tris, **kw)
 
 
 def _same(a, b):
@@ -54,25 +66,29 @@ def _same(a, b):
         (a["t"].view(np.uint32) == b["t"].view(np.uint32)).all()
 
 
-def test_refused_allocations_in_context_build_and_trace(small_scene):
+@pytest.mark.parametrize("name", list(BUILDS))
+def test_refused_allocations_in_context_build_and_trace(small_scene, small_oracle, name):
     from paper_2305_08343_amd import binding
     tris, rays = small_scene
+    S = 2 * small_oracle["bvh"].n_inner
+    placement = (np.random.default_rng(3).random(S) < 0.3).astype(np.uint8)
+    build = lambda c: _build(c, tris, name, placement)  # noqa: E731
     # an undisturbed run: how many requests the context and the build make, and what the context keeps
     A = Refusing()
     ctx = binding.Context(0, allocator=(A.alloc, A.free))
     n_ctx = A.calls
-    s = _build(ctx, tris)
+    s = build(ctx)
     n_build = A.calls - n_ctx
     ref = s.trace(rays).numpy()
     s.close()
     kept = A.sizes()
     ctx.close()
     assert not A.live and not A.errors
-    assert n_build >= 8
-    print(f"[gpu-alloc] context {n_ctx} requests, LUT 4-wide bit-table build {n_build}", flush=True)
+    assert n_build >= 3
+    print(f"[gpu-alloc] {name}: context {n_ctx} requests, build {n_build}", flush=True)
 
     for k in range(1, n_ctx + n_build + 1):
-        print(f"[gpu-alloc] refusing request {k}", flush=True)
+        print(f"[gpu-alloc] {name}: refusing request {k}", flush=True)
         A = Refusing()
         A.refuse_at = k
         if k <= n_ctx:
@@ -83,7 +99,7 @@ def test_refused_allocations_in_context_build_and_trace(small_scene):
             continue
         ctx = binding.Context(0, allocator=(A.alloc, A.free))
         with pytest.raises(binding.SubcullError) as ei:
-            _build(ctx, tris)
+            build(ctx)
         assert ei.value.status == SC_ERR_OOM, ei.value
         # nothing of the failed scene is left: the live sizes are a part of what the context keeps
         rest = list(kept)
@@ -91,7 +107,7 @@ def test_refused_allocations_in_context_build_and_trace(small_scene):
             assert b in rest, (k, b, kept)
             rest.remove(b)
         # the context still builds, and the scene traces as in the undisturbed run
-        s = _build(ctx, tris)
+        s = build(ctx)
         assert _same(s.trace(rays).numpy(), ref)
         s.close()
         ctx.close()
@@ -100,7 +116,7 @@ def test_refused_allocations_in_context_build_and_trace(small_scene):
     # a trace whose ray-order workspace is refused fails alone: the scene keeps working
     A = Refusing()
     ctx = binding.Context(0, allocator=(A.alloc, A.free))
-    s = _build(ctx, tris)
+    s = build(ctx)
     A.refuse_at = A.calls + 1
     with pytest.raises(binding.SubcullError) as ei:
         s.trace(rays, sort=True)
@@ -108,5 +124,49 @@ def test_refused_allocations_in_context_build_and_trace(small_scene):
     assert _same(s.trace(rays, sort=True).numpy(), ref)
     assert _same(s.trace(rays).numpy(), ref)
     s.close()
+    ctx.close()
+    assert not A.live and not A.errors
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_refused_allocations_in_batched_traces(small_scene, graph):
+    """A sorted batch of two scenes: each request of sc_batch_create (descriptors, counters,
+    ray-order workspace) or of sc_trace_batch (descriptors, workspace) refused in turn."""
+    from paper_2305_08343_amd import binding, scenes
+    tris, rays = small_scene
+    tris2 = scenes.micro_scene(5, 64)
+    rays2 = np.concatenate([rays[:5000], scenes.random_rays(333, 9)])
+    A = Refusing()
+    ctx = binding.Context(0, allocator=(A.alloc, A.free))
+    s1 = binding.Scene(ctx, tris, R=4, mode="raw", width=4)
+    s2 = binding.Scene(ctx, tris2, R=4, mode="raw", width=4)
+    want = [s1.trace(rays).numpy(), s2.trace(rays2).numpy()]
+    start = A.calls
+    b = binding.Batch(ctx, [(s1, rays), (s2, rays2)], graph=graph, sort=True)
+    if not graph:
+        b.launch()
+    n_req = A.calls - start
+    b.close()
+    assert n_req >= 2
+    print(f"[gpu-alloc] batch graph={graph}: {n_req} requests", flush=True)
+    for k in range(1, n_req + 1):
+        print(f"[gpu-alloc] batch graph={graph}: refusing request {k}", flush=True)
+        A.refuse_at = A.calls + k
+        held = A.sizes()
+        with pytest.raises(binding.SubcullError) as ei:
+            b = binding.Batch(ctx, [(s1, rays), (s2, rays2)], graph=graph, sort=True)
+            b.launch()
+        assert ei.value.status == SC_ERR_OOM, ei.value
+        b = None
+        assert A.sizes() == held
+        A.refuse_at = 0
+        b = binding.Batch(ctx, [(s1, rays), (s2, rays2)], graph=graph, sort=True)
+        b.launch()
+        import torch
+        torch.cuda.synchronize()
+        assert _same(b.results(0).numpy(), want[0]) and _same(b.results(1).numpy(), want[1])
+        b.close()
+    s1.close()
+    s2.close()
     ctx.close()
     assert not A.live and not A.errors
