@@ -226,8 +226,9 @@ sc_status sc_destroy(sc_ctx* ctx); /* NULL-safe */
  *     the device: voxels of the child box that a descendant triangle
  *     overlaps, dilated by delta (Sect. 3.1.1, 3.2.1 with L = infinity);
  *  4. (LUT) selects the codebook by the importance SA(N) O_m(N) / R^3 of Eq. 2
- *     on the host, builds the requirement LUTs and compresses every mask with
- *     Alg. 3 on the device (Sect. 3.2.2-3.2.3);
+ *     on the device (the K - 1 most important distinct masks; the host pads
+ *     with the full mask and sorts the K entries), builds the requirement LUTs
+ *     and compresses every mask with Alg. 3 on the device (Sect. 3.2.2-3.2.3);
  *  5. packs the device node array; with width 4 also collapses the BVH into
  *     4-wide nodes (see sc_scene_export4) whose children take the masks and
  *     codebook indices of the binary slots they came from.
