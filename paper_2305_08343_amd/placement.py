@@ -2,8 +2,10 @@
 
 Masks cost memory (27 bytes per slot at R = 6) and a test per slab hit; most
 of the false-positive removal comes from few slots. A small MLP predicts,
-from 12 geometric features of a child slot, how many false-positive slab hits
-the slot's mask removes; masks are then placed on the highest-scoring slots
+from 12 geometric features of a child slot (its box relative to its parent
+and to the root, depth, triangle count and thinness, mask occupancy, and where
+its box sits in the scene), how many false-positive slab hits the slot's mask
+removes; masks are then placed on the highest-scoring slots
 until a budget of `beta` bytes per inner node is spent (SC_MASK_SPARSE). A
 slot without a mask is traversed exactly as in plain BVH traversal, so every
 placement returns the same hits as all masks and as no masks.
