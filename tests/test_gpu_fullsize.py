@@ -143,6 +143,25 @@ def test_hair_1m_compressed_bit_exact(request, ctx, hair):
                                origin_bound=hair["ob"], nthreads=hair["nt"]))
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("K", [64, 256])
+def test_hair_1m_compressed_r4_codebook_bit_exact(request, ctx, hair, K):
+    """64-bit masks (one word a mask: the device value sort in 2 rounds) compressed to small codebooks
+    over the 1M-triangle scene's 602,340 slots: codebook, indices and every 4th ray."""
+    from paper_2305_08343_amd import binding
+    tris, rays, bvh = hair["tris"], hair["rays"], hair["bvh"]
+    _say(request, f"hair_1m compressed R=4 K={K}: codebook, indices, every 4th ray")
+    s = binding.Scene(ctx, tris, R=4, mode="lut", K=K)
+    exp = s.export()
+    cb, idx = oracle.compress(hair["masks4"], bvh.slot_boxes(), 4, K)
+    assert (exp["codebook"] == cb).all() and (exp["cidx"] == idx).all()
+    sel = rays[::4]
+    dev = s.trace(sel).numpy()
+    s.close()
+    _compare(dev, oracle.trace(tris, bvh, sel, mode="lut", R=4, codebook=cb, cidx=idx,
+                               origin_bound=hair["ob"], nthreads=hair["nt"]))
+
+
 # ------------------------------------------------------------------- curly_12m
 @pytest.fixture(scope="module")
 def curly(request):
