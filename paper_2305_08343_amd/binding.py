@@ -234,7 +234,12 @@ class Context:
         if checks is None:
             checks = os.environ.get("SUBCULL_DEBUG") == "1"
         if checks:
-            _check(lib.sc_set_device_checks(self.handle, 1), "sc_set_device_checks")
+            try:
+                _check(lib.sc_set_device_checks(self.handle, 1), "sc_set_device_checks")
+            except SubcullError:
+                lib.sc_destroy(self.handle)  # a context that failed to start holds nothing
+                self.handle = None
+                raise
         self.checks = bool(checks)
 
     def set_device_checks(self, on: bool):
