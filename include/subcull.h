@@ -83,7 +83,9 @@ typedef struct {
     uint32_t sah_bins;      /* SAH bins per axis, 2..256 (default 32)             */
     uint32_t depth_cap;     /* max inner nodes on a root-to-leaf path, 1..64      */
     uint32_t mode;          /* sc_mask_mode                                       */
-    uint32_t codebook_size; /* K for SC_MASK_LUT: multiple of 64, 64..4096        */
+    uint32_t codebook_size; /* K for SC_MASK_LUT: multiple of 64, 64..4096; Alg. 3
+                               reads a mask in 8-bit chunks (ceil(R^3 / 8)
+                               requirement tables of 256 rows), a fixed width  */
     float delta;            /* voxel dilation; <= 0 selects the default           */
     float origin_bound;     /* masks are skipped for rays with max|o| above this;
                                <= 0 selects the default                          */
@@ -383,8 +385,10 @@ typedef struct sc_batch sc_batch;
  * scene bounds), which keeps the items' order (at most 256 items, else
  * SC_ERR_UNSUPPORTED; workspace of 16 bytes per ray plus counts from the
  * context allocator, or held by the batch for sc_batch_create).
- * Synchronises `stream` (the descriptor table uploaded for the call is
- * released afterwards); sc_batch_launch does not. */
+ * The launch shape is the context's (sc_set_tune); a replayable graph of the
+ * same launch comes from sc_batch_create. Synchronises `stream` (the
+ * descriptor table uploaded for the call is released afterwards);
+ * sc_batch_launch does not. */
 sc_status sc_trace_batch(sc_ctx* ctx, const sc_batch_item* items, uint32_t n_items, uint32_t flags,
                          void* stream);
 
