@@ -88,3 +88,50 @@ def test_trace_on_a_side_stream_from_host_rays():
     ora4 = oracle.trace4(tris, bvh, oracle.bvh4_collapse(bvh), rays, mode="raw", R=6, masks=masks, origin_bound=ob)
     assert _same(base, ora4) and all(_same(d, ora4) for d in got)
     assert sorted(ordr.tolist()) == list(range(rays.shape[0]))
+
+
+@pytest.mark.timeout(300)
+def test_two_threads_build_compressed_scenes_at_once():
+    """Two LUT scenes (device codebook selection, Alg. 3, 2-D bit table) built at the same time
+    from two host threads on their own streams: codebooks, indices and traces equal the oracle's."""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2305_08343_amd import binding, scenes
+    tris = scenes.scene_small(0)
+    rays = scenes.rays_small(96)
+    ctx = binding.Context(0)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    cfg = [dict(R=6, K=256, width=4, bit_table=True), dict(R=4, K=128, width=2, bit_table=False)]
+    results, errors = [None, None], []
+
+    def work(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                sc = binding.Scene(ctx, tris, mode="lut", stream=streams[i], **cfg[i])
+                exp = sc.export()
+                out = sc.trace(torch.from_numpy(rays).cuda(), stream=streams[i])
+                streams[i].synchronize()
+                results[i] = (exp["codebook"], exp["cidx"], out.numpy())
+                sc.close()
+        except Exception as e:  # reported below, on the main thread
+            errors.append(repr(e))
+
+    print("[gpu-conc] two threads building LUT scenes", flush=True)
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    ctx.close()
+    assert not errors, errors
+    bvh = oracle.bvh_build(tris)
+    ob, delta = oracle.default_bounds(tris)
+    b4 = oracle.bvh4_collapse(bvh)
+    for i, c in enumerate(cfg):
+        masks = oracle.object_masks(tris, bvh, c["R"], delta)
+        cb, idx = oracle.compress(masks, bvh.slot_boxes(), c["R"], c["K"])
+        got_cb, got_idx, dev = results[i]
+        assert (got_cb == cb).all() and (got_idx == idx).all()
+        kw = dict(mode="lut", R=c["R"], codebook=cb, cidx=idx, origin_bound=ob)
+        ora = oracle.trace4(tris, bvh, b4, rays, **kw) if c["width"] == 4 else oracle.trace(tris, bvh, rays, **kw)
+        assert _same(dev, ora)
